@@ -1,0 +1,140 @@
+"""Grid ordering, operator assembly and node features (oracle, float64).
+
+TEST INFRASTRUCTURE ONLY -- see oracle/__init__.py.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def morton_code(x: int, y: int, z: int, bits: int = 16) -> int:
+    """Z-order code of cell (x, y, z): bit b of x goes to bit 3b, of y to
+    3b+1, of z to 3b+2 (paper, Supplementary "Grid and ordering": cells are
+    sorted by Morton code; the 3D interleave is this build's reading)."""
+    c = 0
+    for b in range(bits):
+        c |= ((x >> b) & 1) << (3 * b)
+        c |= ((y >> b) & 1) << (3 * b + 1)
+        c |= ((z >> b) & 1) << (3 * b + 2)
+    return c
+
+
+def morton_perm(nx: int, ny: int, nz: int) -> np.ndarray:
+    """perm[i] = lexicographic id (x + nx*(y + ny*z)) of the i-th cell in
+    Morton order.  Codes are unique, so the sort needs no tie-break."""
+    ids, codes = [], []
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                ids.append(x + nx * (y + ny * z))
+                codes.append(morton_code(x, y, z))
+    order = sorted(range(len(ids)), key=lambda t: codes[t])
+    return np.array([ids[t] for t in order], dtype=np.int64)
+
+
+def cell_xyz(nx: int, ny: int, nz: int, lex: np.ndarray) -> np.ndarray:
+    lex = np.asarray(lex)
+    return np.stack([lex % nx, (lex // nx) % ny, lex // (nx * ny)], axis=-1)
+
+
+def assemble_lex(nx: int, ny: int, nz: int, rho: np.ndarray) -> sp.csr_matrix:
+    """Cell-centred 7-point variable-coefficient Poisson operator in
+    lexicographic order.
+
+    Paper, Sec. 7.1 / Supplementary "Operator assembly": A_ii = sum_j w_ij,
+    A_ij = -w_ij over cell-cell faces.  Face weight w_ij = 2/(rho_i+rho_j),
+    the harmonic mean of 1/rho.  Zero-flux boundaries everywhere except the
+    top face (z = nz-1), which carries p = 0 through a ghost cell one spacing
+    away: A_ii += 1/rho_i.  Spacing h = 1.
+    """
+    n = nx * ny * nz
+    rows, cols, vals = [], [], []
+    diag = np.zeros(n)
+
+    def lid(x, y, z):
+        return x + nx * (y + ny * z)
+
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                i = lid(x, y, z)
+                for (dx, dy, dz) in ((1, 0, 0), (0, 1, 0), (0, 0, 1)):
+                    xx, yy, zz = x + dx, y + dy, z + dz
+                    if xx >= nx or yy >= ny or zz >= nz:
+                        continue
+                    j = lid(xx, yy, zz)
+                    w = 2.0 / (rho[i] + rho[j])
+                    rows += [i, j]
+                    cols += [j, i]
+                    vals += [-w, -w]
+                    diag[i] += w
+                    diag[j] += w
+                if z == nz - 1:
+                    diag[i] += 1.0 / rho[i]
+    rows += list(range(n))
+    cols += list(range(n))
+    vals += list(diag)
+    return sp.csr_matrix((np.array(vals), (np.array(rows), np.array(cols))), shape=(n, n))
+
+
+def assemble(nx: int, ny: int, nz: int, rho_lex: np.ndarray) -> sp.csr_matrix:
+    """The operator in Morton order: A_m = P A P^T with P the Morton perm."""
+    perm = morton_perm(nx, ny, nz)
+    A = assemble_lex(nx, ny, nz, rho_lex)
+    Am = A[perm][:, perm].tocsr()
+    Am.sort_indices()
+    return Am
+
+
+def features(nx: int, ny: int, nz: int, rho_lex: np.ndarray) -> np.ndarray:
+    """Per-node encoder input [N, 20] in Morton order.
+
+    The paper (Sec. 4.1, Supplementary "Encoder") lists density, position and
+    boundary indicators per node and a 12-value per-frame summary of the
+    assembled system.  This build's definition:
+      node:   log rho, (x+1/2)/nx, (y+1/2)/ny, (z+1/2)/nz, top flag (z=nz-1),
+              side flag (x or y on the domain boundary), bottom flag (z=0),
+              log A_ii
+      global: log2(N)/16, log(rho_max/rho_min), mean and std of log rho,
+              heavy fraction (log rho above the mid-point of its range),
+              mean/std/min/max of log A_ii, nx/32, ny/32, nz/32
+    Standard deviations are population (divide by N).  Pressure is absent:
+    the frames have no previous time step.
+    """
+    n = nx * ny * nz
+    perm = morton_perm(nx, ny, nz)
+    A = assemble_lex(nx, ny, nz, rho_lex)
+    dA = A.diagonal()
+    xyz = cell_xyz(nx, ny, nz, np.arange(n))
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    lr = np.log(rho_lex)
+    la = np.log(dA)
+    node = np.stack([
+        lr,
+        (x + 0.5) / nx, (y + 0.5) / ny, (z + 0.5) / nz,
+        (z == nz - 1).astype(np.float64),
+        ((x == 0) | (x == nx - 1) | (y == 0) | (y == ny - 1)).astype(np.float64),
+        (z == 0).astype(np.float64),
+        la,
+    ], axis=1)
+    lmin, lmax = lr.min(), lr.max()
+    heavy = float(np.mean(lr > 0.5 * (lmin + lmax))) if lmax > lmin else 0.0
+    glob = np.array([
+        math.log2(n) / 16.0,
+        lmax - lmin,
+        lr.mean(), lr.std(),
+        heavy,
+        la.mean(), la.std(), la.min(), la.max(),
+        nx / 32.0, ny / 32.0, nz / 32.0,
+    ])
+    f = np.concatenate([node, np.broadcast_to(glob, (n, 12))], axis=1)
+    return f[perm]
+
+
+def positions(nx: int, ny: int, nz: int) -> np.ndarray:
+    """Integer (x, y, z) of every cell, Morton order, [N, 3] float64."""
+    perm = morton_perm(nx, ny, nz)
+    return cell_xyz(nx, ny, nz, perm).astype(np.float64)

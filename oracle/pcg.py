@@ -1,0 +1,100 @@
+"""Preconditioned conjugate gradients (oracle, float64).
+
+TEST INFRASTRUCTURE ONLY -- see oracle/__init__.py.
+
+Standard PCG (Saad 2003, Alg. 9.1; the paper's Sec. 3 convergence bound and
+Sec. 5 solve loop) with this build's run-time policy:
+
+  setup:  x = x0 (default 0), r = b - A x, z = M r, p = z, rho = r.z
+  each iteration k = 1, 2, ...:
+      q = A p;  alpha = rho / (p.q);  x += alpha p;  r -= alpha q
+      if k % recompute_every == 0:  r = b - A x     (residual replacement)
+      stop (CONVERGED) when ||r|| <= tol * ||b||
+      stop (STAGNATED) when k % 100 == 0 and ||r_k|| > 0.5 ||r_{k-100}||
+      z = M r;  rho' = r.z;  stop (NOT_SPD) unless rho' > 0 and finite
+      beta = rho' / rho;  p = z + beta p
+  iterations = number of SpMVs in the loop.
+
+The stagnation window and the Jacobi fallback are this build's additions:
+the paper enforces no SPD property on M and has no fallback.
+"""
+from __future__ import annotations
+
+import math
+from typing import Callable, Optional
+
+import numpy as np
+
+CONVERGED, NOT_SPD, STAGNATED, MAXITER, FELL_BACK = 1, 2, 4, 8, 16
+
+
+def pcg(A, b: np.ndarray, M: Optional[Callable] = None, tol: float = 1e-6,
+        max_iter: int = 10000, recompute_every: int = 25, x0: Optional[np.ndarray] = None,
+        stagnation: bool = True, bnorm: Optional[float] = None):
+    """Returns (x, iterations, flags, relres history)."""
+    b = np.asarray(b, dtype=np.float64)
+    Mf = (lambda r: r.copy()) if M is None else M
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - A @ x
+    if bnorm is None:
+        bnorm = float(np.sqrt(b @ b))
+    target = tol * bnorm
+    hist = [float(np.sqrt(r @ r)) / bnorm if bnorm > 0 else 0.0]
+    if math.sqrt(r @ r) <= target:
+        return x, 0, CONVERGED, hist
+    z = Mf(r)
+    rho = float(r @ z)
+    if not (rho > 0 and math.isfinite(rho)):
+        return x, 0, NOT_SPD, hist
+    p = z.copy()
+    k, flags = 0, 0
+    last_window = hist[0]
+    while True:
+        if k >= max_iter:
+            flags = MAXITER
+            break
+        q = A @ p
+        alpha = rho / float(p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        k += 1
+        if recompute_every and k % recompute_every == 0:
+            r = b - A @ x
+        rn = math.sqrt(float(r @ r))
+        hist.append(rn / bnorm)
+        if rn <= target:
+            flags = CONVERGED
+            break
+        if stagnation and k % 100 == 0:
+            if rn > 0.5 * last_window:
+                flags = STAGNATED
+                break
+            last_window = rn
+        z = Mf(r)
+        rho_new = float(r @ z)
+        if not (rho_new > 0 and math.isfinite(rho_new)):
+            flags = NOT_SPD
+            break
+        beta = rho_new / rho
+        rho = rho_new
+        p = z + beta * p
+    return x, k, flags, hist
+
+
+def jacobi(A) -> Callable:
+    """M = diag(A)^-1 (Jacobi preconditioner, the paper's GPU baseline)."""
+    d = np.asarray(A.diagonal(), dtype=np.float64)
+    return lambda r: r / d
+
+
+def solve_with_fallback(A, b, M: Callable, tol: float = 1e-6, max_iter: int = 10000,
+                        recompute_every: int = 25):
+    """Learned-M PCG; on NOT_SPD or STAGNATED, Jacobi-PCG warm-started from the
+    current x to the same target tol * ||b||.  Iterations add up."""
+    x, k, flags, hist = pcg(A, b, M, tol, max_iter, recompute_every)
+    if flags & (NOT_SPD | STAGNATED):
+        bn = float(np.sqrt(b @ b))
+        x, k2, f2, h2 = pcg(A, b, jacobi(A), tol, max_iter, recompute_every, x0=x,
+                            stagnation=False, bnorm=bn)
+        return x, k + k2, f2 | FELL_BACK | flags, hist + h2[1:]
+    return x, k, flags, hist
