@@ -1,0 +1,222 @@
+/*
+ * hp.h -- C ABI of the MI355X (gfx950) library for hierarchical transformer
+ * preconditioning of multiphase Poisson systems (Osborne et al., arxiv
+ * 2605.13343, "Hierarchical Transformer Preconditioning for Interactive
+ * Physics Simulation").
+ *
+ * Problem statement (paper Sec. 4 "Notation and pipeline", Sec. 5, Sec. 6.1):
+ * given a sparse SPD system A x = b whose unknowns are laid out along a
+ * space-filling curve, a network reads per-node features and the partition
+ * and emits factors of M ~ A^-1 on a weak-admissibility H-matrix partition;
+ * PCG then solves A x = b with M.  Training minimises the cosine-Hutchinson
+ * probe loss 1 - <Z, M A Z>_F / (||Z||_F ||M A Z||_F).
+ *
+ * Conventions
+ *  - Status codes, never exceptions.  hp_last_error() returns a thread-local
+ *    message for the last non-OK status of the calling thread.
+ *  - "d_" pointers are device pointers (hipMalloc'd or torch CUDA tensors on
+ *    the batch's device); "h_" / plain pointers are host memory.  The caller
+ *    owns every buffer it passes and the library never frees them.  A batch
+ *    owns only the workspaces it allocates in hp_batch_create.
+ *  - Work is enqueued on the batch's stream (the caller's hipStream_t, may be
+ *    NULL for the default stream) and calls return after enqueueing, except
+ *    where a host output is requested (hp_pcg_solve results, hp_train_step
+ *    loss): those synchronise the stream.
+ *  - Shape errors are reported before anything is enqueued.
+ *
+ * Grids and order.  Frame f is a cell-centred nx x ny x nz grid, z vertical,
+ * with N = nx ny nz unknowns in Morton order (bit b of x, y, z at bits 3b,
+ * 3b+1, 3b+2).  The library requires power-of-two dims whose Morton codes are
+ * exactly 0..N-1 (log2 nx, log2 ny in {log2 nz, log2 nz + 1}, nx >= ny), so a
+ * cell's Morton code is its row index.  Leaves are the K = N / L contiguous
+ * index ranges of length L (paper Sec. 4); K must be a power of two.
+ *
+ * Batch layout.  The frames of a batch are concatenated: frame f's nodes are
+ * rows [n0_f, n0_f + N_f) of every per-node array, its leaves [k0_f, ...),
+ * its tiles [m0_f, ...).  hp_batch_info reports all sizes.
+ */
+#ifndef HP_H
+#define HP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hp_status;
+enum {
+  HP_OK = 0,
+  HP_E_INVALID = 1,  /* bad argument (NULL where required, negative size, ...) */
+  HP_E_SHAPE = 2,    /* grid not admissible, N % L != 0, K not a power of two, L % L_s != 0 */
+  HP_E_HIP = 3,      /* a HIP runtime call failed; message names it */
+  HP_E_NOMEM = 4,    /* device allocation failed in hp_batch_create */
+  HP_E_NOT_SPD = 5,  /* solve: M lost positivity and fallback is off */
+  HP_E_NOCONV = 6,   /* solve: tolerance not reached and fallback is off */
+  HP_E_STATE = 7     /* call out of order (e.g. no weights uploaded) */
+};
+
+enum { HP_F32 = 0, HP_BF16 = 1 };                  /* factor / compute precision */
+enum { HP_PRECOND_NONE = 0, HP_PRECOND_JACOBI = 1, HP_PRECOND_HMAT = 2 };
+enum {                                             /* per-frame solve flags */
+  HP_CONVERGED = 1, HP_NOT_SPD = 2, HP_STAGNATED = 4, HP_MAXITER = 8, HP_FELL_BACK = 16
+};
+
+const char* hp_last_error(void);
+
+/* Network shape (paper Sec. 4, Supplementary "Network Architecture Details").
+ * The library supports d = 128, heads in {2, 4, 8}, leaf in {32, 64},
+ * rank = leaf / 4, edge_hidden = 32, node_feats = 8, glob_feats = 12. */
+typedef struct {
+  int32_t d, heads, layers, leaf, rank, edge_hidden, gcn, node_feats, glob_feats;
+  int32_t highways; /* 1: row/column/global highway buffers on (Sec. 4.3) */
+  int32_t offdiag;  /* 1: off-diagonal stack on (Sec. 4.2) */
+} hp_model_config;
+
+/* ------------------------------------------------------------------ host only */
+
+/* Morton order of an nx x ny x nz grid: perm[i] = x + nx (y + ny z) of the
+ * i-th cell along the curve (paper Supplementary "Grid and ordering").
+ * perm has N entries, host memory.  Any positive dims are accepted. */
+hp_status hp_morton_order(int32_t nx, int32_t ny, int32_t nz, int32_t* perm);
+
+typedef struct {
+  int32_t n, leaf, rank;   /* N, L, L_s */
+  int32_t K, J, MH;        /* leaves, levels (log2 K), unique off-diagonal tiles (K - 1) */
+  int64_t P;               /* packed width K L^2 + M_H L_s^2 + 2 N L_s + N (Sec. 4.4) */
+  int64_t off_diag, off_B, off_Ut, off_Vt, off_lam;  /* section offsets in elements */
+} hp_partition_info;
+
+/* Weak-admissibility partition at eta = 1 (paper Sec. 4, Sec. 4.2 and
+ * Supplementary "H-matrix partition"): K = N / L leaves; tile m at level j
+ * (S = 2^j leaves per side), index i within the level, m = K - K/2^j + i,
+ * rows = leaves [2iS, 2iS+S), columns = leaves [2iS+S, 2iS+2S).  Two-call
+ * idiom: with every array NULL only *info is filled.  Otherwise (host memory)
+ * tile_* have M_H entries, leaf_tile and leaf_side have K*J entries
+ * (leaf-major): leaf k at level j sits in tile leaf_tile[k*J+j] on side
+ * leaf_side[k*J+j] (0 row strip, 1 column strip).  Pure integer, bit-exact. */
+hp_status hp_build_partition(int32_t n, int32_t leaf, int32_t rank, hp_partition_info* info,
+                             int32_t* tile_level, int32_t* tile_row0, int32_t* tile_col0,
+                             int32_t* tile_span, int32_t* leaf_tile, int8_t* leaf_side);
+
+/* ------------------------------------------------------------------ batches */
+
+typedef struct hp_batch_s* hp_batch;
+
+typedef struct {
+  int32_t nframes;
+  int64_t ntot, ktot, mtot;       /* nodes, leaves, tiles over all frames */
+  int64_t sys_floats;             /* floats of the assembled-system buffer: 13 * ntot */
+  int64_t factor_bytes[2];        /* factor buffer bytes for HP_F32, HP_BF16 */
+  int64_t off_G, off_B, off_Ut, off_Vt, off_lam;   /* byte offsets, per dtype below */
+  int64_t weight_floats;          /* flat FP32 weight vector length */
+} hp_batch_info_t;
+
+/* Create a batch of nframes frames with dims[3f..3f+2] = (nx, ny, nz) (host).
+ * All frames share cfg (one leaf size L and rank L_s).  hip_stream is the
+ * caller's hipStream_t (borrowed; NULL = default stream).  Allocates every
+ * workspace the batch's calls need; later calls allocate nothing. */
+hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes, const int32_t* dims,
+                          void* hip_stream, hp_batch* out);
+hp_status hp_batch_destroy(hp_batch b);
+/* Sizes; factor offsets are given for dtype (HP_F32 or HP_BF16). */
+hp_status hp_batch_info(hp_batch b, int32_t dtype, hp_batch_info_t* info);
+/* Per-frame offsets (host arrays of nframes entries, any may be NULL). */
+hp_status hp_batch_offsets(hp_batch b, int64_t* n0, int64_t* k0, int64_t* m0);
+
+/* Assemble A for every frame (paper Sec. 7.1 and Supplementary "Operator
+ * assembly", in 3D): face weight w_ij = 2 / (rho_i + rho_j) (harmonic mean of
+ * 1/rho), A_ij = -w_ij, A_ii = sum_j w_ij, plus 1/rho_i on the top layer
+ * (Dirichlet p = 0 one spacing above), zero flux elsewhere.
+ *   d_rho [ntot]  FP32 density per node, Morton order.
+ *   d_sys [13 ntot floats] output, 8-byte aligned: FP32 [diag | wx | wy | wz |
+ *                 1/diag] (5 ntot floats; the SpMV and Jacobi read these) then
+ *                 FP64 [diag | wx | wy | wz] (4 ntot doubles; the FP64
+ *                 residual replacement reads these).  wx_i is the weight of
+ *                 the face between i and its +x neighbour (0 on the +x
+ *                 boundary), likewise wy, wz.  Computed in FP64; the FP32
+ *                 copies are rounded once. */
+hp_status hp_assemble(hp_batch b, const float* d_rho, float* d_sys);
+
+/* q = A p for every frame (FP32, 7-point stencil in Morton order). */
+hp_status hp_spmv(hp_batch b, const float* d_sys, const float* d_p, float* d_q);
+
+/* Packed factors of M, per batch (paper Sec. 4.4 "All factors pack into a
+ * single tensor"): byte sections [G: ktot L L][B: mtot Ls Ls][Ut: ntot Ls]
+ * [Vt: ntot Ls] in the factor dtype, then [lam: ntot] FP32, each section
+ * 256-byte aligned at the offsets hp_batch_info reports.  G_k = F_k F_k^T is
+ * stored (the diagonal block of M, Sec. 4.2), B_m = U_m V_m^T.  Within a
+ * section frames follow each other, so a one-frame batch holds exactly the
+ * paper's per-frame packing [K L^2][M_H L_s^2][N L_s][N L_s][N].
+ *
+ * M r = blockdiag(G_k) r + diag(lam / A_ii) r + the FMM-style far field of
+ * Sec. 5 (restriction u = Ut^T r, v = Vt^T r; strip sums; t^c = B^T s^r,
+ * t^r = B s^c; prolongation Ut sum t^r + Vt sum t^c).
+ *
+ * hp_apply: y = M r for every frame.  d_r, d_y: [ntot] FP32 (ncols must be 1
+ * here; multi-column products are internal to training).  fdtype HP_F32 or
+ * HP_BF16 selects how d_factors is read; accumulation is FP32. */
+hp_status hp_apply(hp_batch b, const float* d_sys, const void* d_factors, int32_t fdtype,
+                   const float* d_r, float* d_y, int32_t ncols);
+
+typedef struct {
+  int32_t precond;          /* HP_PRECOND_* */
+  int32_t fdtype;           /* factor dtype for HP_PRECOND_HMAT */
+  double tol;               /* stop when ||r|| <= tol ||b|| */
+  int32_t max_iter;         /* per frame, counted in SpMVs */
+  int32_t recompute_every;  /* r = b - A x in FP64 every this many iterations (0 = never) */
+  int32_t fallback;         /* 1: NOT_SPD/STAGNATED/MAXITER frames restart with Jacobi-PCG from x */
+  int32_t use_graph;        /* 1: replay a captured hipGraph per chunk of iterations */
+  int32_t chunk;            /* iterations per host check (even, >= 2) */
+  int32_t stagnation;       /* 1: STAGNATED when ||r_k|| > 0.5 ||r_{k-100}|| at k % 100 == 0 */
+} hp_solve_opts;
+
+typedef struct {
+  int32_t iters;            /* SpMVs of this frame, fallback included */
+  int32_t flags;            /* HP_CONVERGED | HP_NOT_SPD | ... */
+  double relres;            /* last recurrence ||r|| / ||b|| (FP64) */
+} hp_solve_result;
+
+/* PCG on every frame (paper Sec. 3, Sec. 5 "Single-graph capture", Sec. 6.3
+ * precision split): x0 = d_x on entry, r = b - A x0, z = M r, p = z; per
+ * iteration q = A p, alpha = rho / p.q, x += alpha p, r -= alpha q, residual
+ * replacement every recompute_every, stop at ||r|| <= tol ||b||,
+ * z = M r, rho' = r.z (flag NOT_SPD unless > 0 and finite), beta = rho'/rho,
+ * p = z + beta p.  r, z, p, q are FP32; the solution x accumulates in FP64
+ * (an FP32 x cannot hold a 1e-6 true residual on the stiffer frames); inner
+ * products, norms, alpha, beta are FP64 (products of FP32 values formed
+ * exactly in FP64, summed in a fixed order).  A residual that passes tol
+ * stops a frame only if it is a true residual b - A x (FP64, with the FP64
+ * coefficients); a passing recurrence residual forces a replacement on the
+ * next iteration.  d_b: [ntot] FP32; d_x: [ntot] FP64.  d_factors may be NULL unless precond == HMAT.
+ * res (host, nframes entries) receives per-frame results; the call
+ * synchronises the stream.  Returns HP_OK even when frames fell back; with
+ * fallback off, HP_E_NOT_SPD / HP_E_NOCONV if any frame failed. */
+hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_factors,
+                       const hp_solve_opts* opts, const float* d_b, double* d_x,
+                       hp_solve_result* res);
+
+/* ------------------------------------------------------------------ network */
+
+/* Weight vector: every tensor of the network in the order hp_weight_info
+ * reports, FP32, row-major, linear maps stored [in, out] (y = x W + b). */
+hp_status hp_weight_count(const hp_model_config* cfg, int32_t* count, int64_t* floats);
+/* name (<= 63 chars + NUL), rank-1 or rank-2 shape, offset in floats. */
+hp_status hp_weight_info(const hp_model_config* cfg, int32_t index, char* name, int32_t* rows,
+                         int32_t* cols, int64_t* offset);
+
+/* Network forward for every frame (paper Sec. 4.1-4.4): features from
+ * (rho, A), encoder MLP + GCN, diagonal and off-diagonal attention stacks
+ * with highways, decoder heads, then the packed factors (G = F F^T,
+ * B = U V^T, Ut, Vt, lam).  compute = HP_BF16 runs the GEMMs on MFMA in
+ * BF16 with FP32 accumulation and writes BF16 factors (lam FP32);
+ * HP_F32 runs everything in FP32 and writes FP32 factors.
+ *   d_weights [weight_floats] FP32; d_rho [ntot] FP32 (Morton);
+ *   d_sys from hp_assemble; d_factors per hp_batch_info(compute). */
+hp_status hp_infer_factors(hp_batch b, const float* d_weights, const float* d_rho,
+                           const float* d_sys, void* d_factors, int32_t compute);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HP_H */

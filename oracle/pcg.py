@@ -8,9 +8,11 @@ Sec. 5 solve loop) with this build's run-time policy:
   setup:  x = x0 (default 0), r = b - A x, z = M r, p = z, rho = r.z
   each iteration k = 1, 2, ...:
       q = A p;  alpha = rho / (p.q);  x += alpha p;  r -= alpha q
-      if k % recompute_every == 0:  r = b - A x     (residual replacement)
-      stop (CONVERGED) when ||r|| <= tol * ||b||
+      if k % recompute_every == 0 or forced:  r = b - A x   (residual replacement)
+      stop (CONVERGED) when ||r|| <= tol * ||b|| on a replaced (true) residual;
+          a recurrence residual that passes forces replacement next iteration
       stop (STAGNATED) when k % 100 == 0 and ||r_k|| > 0.5 ||r_{k-100}||
+      stop (MAXITER) when k == max_iter
       z = M r;  rho' = r.z;  stop (NOT_SPD) unless rho' > 0 and finite
       beta = rho' / rho;  p = z + beta p
   iterations = number of SpMVs in the loop.
@@ -48,6 +50,7 @@ def pcg(A, b: np.ndarray, M: Optional[Callable] = None, tol: float = 1e-6,
         return x, 0, NOT_SPD, hist
     p = z.copy()
     k, flags = 0, 0
+    force = False
     last_window = hist[0]
     while True:
         if k >= max_iter:
@@ -58,18 +61,25 @@ def pcg(A, b: np.ndarray, M: Optional[Callable] = None, tol: float = 1e-6,
         x = x + alpha * p
         r = r - alpha * q
         k += 1
-        if recompute_every and k % recompute_every == 0:
+        replaced = force or bool(recompute_every and k % recompute_every == 0)
+        if replaced:
             r = b - A @ x
+        force = False
         rn = math.sqrt(float(r @ r))
         hist.append(rn / bnorm)
         if rn <= target:
-            flags = CONVERGED
-            break
+            if replaced:
+                flags = CONVERGED
+                break
+            force = True   # confirm on the true residual next iteration
         if stagnation and k % 100 == 0:
             if rn > 0.5 * last_window:
                 flags = STAGNATED
                 break
             last_window = rn
+        if k >= max_iter:
+            flags = MAXITER
+            break
         z = Mf(r)
         rho_new = float(r @ z)
         if not (rho_new > 0 and math.isfinite(rho_new)):

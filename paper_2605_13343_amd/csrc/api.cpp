@@ -1,0 +1,394 @@
+// Batch object and the C entry points of the solver path.
+#include <string.h>
+
+#include <map>
+#include <tuple>
+
+#include "batch.h"
+
+namespace hp {
+
+static int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
+
+void factor_offsets(const Batch& b, int dtype, int64_t offs[5], int64_t* total) {
+  const int64_t es = dtype == HP_BF16 ? 2 : 4;
+  const int L = b.cfg.leaf, LS = b.cfg.rank;
+  int64_t o = 0;
+  offs[0] = o;
+  o = align256(o + b.ktot * L * L * es);
+  offs[1] = o;
+  o = align256(o + std::max<int64_t>(b.mtot, 1) * LS * LS * es);
+  offs[2] = o;
+  o = align256(o + b.ntot * LS * es);
+  offs[3] = o;
+  o = align256(o + b.ntot * LS * es);
+  offs[4] = o;
+  o = align256(o + b.ntot * 4);
+  *total = o;
+}
+
+Batch::~Batch() {
+  for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+  for (void* p : allocs) hipFree(p);
+  if (h_pin) hipHostFree(h_pin);
+  if (cap_stream) hipStreamDestroy(cap_stream);
+}
+
+hp_status Batch::alloc(void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
+  if (e != hipSuccess) return set_error(HP_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  allocs.push_back(*p);
+  return HP_OK;
+}
+
+LaunchGeom Batch::geom() const {
+  LaunchGeom g;
+  g.fr = d_fr;
+  g.blk2f = d_blk2f;
+  g.leaf2f = d_leaf2f;
+  g.nframes = nframes;
+  g.nblk = nblk;
+  g.ktot = ktot;
+  g.ntot = ntot;
+  g.kmax = kmax;
+  g.stream = stream;
+  return g;
+}
+
+}  // namespace hp
+
+using namespace hp;
+
+static bool supported_cfg(const hp_model_config& c, std::string* why) {
+  if (!((c.leaf == 64 && c.rank == 16) || (c.leaf == 32 && c.rank == 8))) {
+    *why = "supported (leaf, rank): (64, 16), (32, 8)";
+    return false;
+  }
+  return true;
+}
+
+extern "C" hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes, const int32_t* dims,
+                                     void* hip_stream, hp_batch* out) {
+  if (!cfg || !dims || !out || nframes <= 0) return set_error(HP_E_INVALID, "hp_batch_create: bad arguments");
+  std::string why;
+  if (!supported_cfg(*cfg, &why)) return set_error(HP_E_SHAPE, "hp_batch_create: %s", why.c_str());
+  auto* b = new hp_batch_s();
+  b->cfg = *cfg;
+  b->nframes = nframes;
+  b->stream = (hipStream_t)hip_stream;
+  const int L = cfg->leaf, LS = cfg->rank;
+  int64_t n0 = 0, k0 = 0, m0 = 0;
+  int nb0 = 0;
+  for (int f = 0; f < nframes; ++f) {
+    int nx = dims[3 * f], ny = dims[3 * f + 1], nz = dims[3 * f + 2];
+    if (!admissible_grid(nx, ny, nz, &why)) {
+      delete b;
+      return set_error(HP_E_SHAPE, "hp_batch_create: frame %d (%d x %d x %d): %s", f, nx, ny, nz, why.c_str());
+    }
+    int n = nx * ny * nz;
+    hp_partition_info pi;
+    hp_status s = hp_build_partition(n, L, LS, &pi, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (s != HP_OK) {
+      delete b;
+      return s;
+    }
+    FrameDesc F{};
+    F.n = n;
+    F.n0 = (int)n0;
+    F.K = pi.K;
+    F.k0 = (int)k0;
+    F.MH = pi.MH;
+    F.m0 = (int)m0;
+    F.J = pi.J;
+    F.nz = nz;
+    morton_masks(nx, ny, nz, &F.xm, &F.ym, &F.zm);
+    F.nb = (n + NODE_BLOCK - 1) / NODE_BLOCK;
+    F.b0 = nb0;
+    b->fr.push_back(F);
+    b->dims.push_back({nx, ny, nz});
+    n0 += n;
+    k0 += pi.K;
+    m0 += pi.MH;
+    nb0 += F.nb;
+    b->kmax = std::max(b->kmax, pi.K);
+    b->nmax = std::max(b->nmax, n);
+  }
+  if (n0 >= (1ll << 31)) {
+    delete b;
+    return set_error(HP_E_SHAPE, "hp_batch_create: more than 2^31 unknowns");
+  }
+  b->ntot = n0;
+  b->ktot = k0;
+  b->mtot = m0;
+  b->nblk = nb0;
+  std::vector<int> blk2f(nb0), leaf2f(k0);
+  for (int f = 0; f < nframes; ++f) {
+    for (int j = 0; j < b->fr[f].nb; ++j) blk2f[b->fr[f].b0 + j] = f;
+    for (int j = 0; j < b->fr[f].K; ++j) leaf2f[b->fr[f].k0 + j] = f;
+  }
+  hp_status s = HP_OK;
+  auto A = [&](void** p, size_t bytes) {
+    if (s == HP_OK) s = b->alloc(p, bytes);
+  };
+  A((void**)&b->d_fr, sizeof(FrameDesc) * nframes);
+  A((void**)&b->d_blk2f, sizeof(int) * nb0);
+  A((void**)&b->d_leaf2f, sizeof(int) * k0);
+  const size_t nf = sizeof(float) * n0;
+  A((void**)&b->x1, 2 * nf);
+  A((void**)&b->p0, nf);
+  A((void**)&b->p1, nf);
+  A((void**)&b->r, nf);
+  A((void**)&b->z, nf);
+  A((void**)&b->q, nf);
+  const size_t kf = sizeof(float) * k0 * LS;
+  A((void**)&b->uh, kf);
+  A((void**)&b->vh, kf);
+  A((void**)&b->Tr, kf);
+  A((void**)&b->Tc, kf);
+  const size_t np = sizeof(double) * std::max<int64_t>(nb0, k0);
+  A((void**)&b->part_pq, np);
+  A((void**)&b->part_rr, np);
+  A((void**)&b->part_rz, np);
+  A((void**)&b->ticket, sizeof(unsigned) * 4 * nframes);
+  A((void**)&b->n_active, sizeof(int));
+  A((void**)&b->st, sizeof(FrameState) * nframes);
+  A((void**)&b->prm, sizeof(SolveParams));
+  if (s != HP_OK) {
+    delete b;
+    return s;
+  }
+  if (hipHostMalloc((void**)&b->h_pin, 256 + sizeof(FrameState) * nframes) != hipSuccess) {
+    delete b;
+    return set_error(HP_E_NOMEM, "hipHostMalloc failed");
+  }
+  auto cp = [&](void* dst, const void* src, size_t n) {
+    if (s == HP_OK && hipMemcpy(dst, src, n, hipMemcpyHostToDevice) != hipSuccess)
+      s = set_error(HP_E_HIP, "hp_batch_create: upload failed");
+  };
+  cp(b->d_fr, b->fr.data(), sizeof(FrameDesc) * nframes);
+  cp(b->d_blk2f, blk2f.data(), sizeof(int) * nb0);
+  cp(b->d_leaf2f, leaf2f.data(), sizeof(int) * k0);
+  if (s == HP_OK && hipMemset(b->ticket, 0, sizeof(unsigned) * 4 * nframes) != hipSuccess)
+    s = set_error(HP_E_HIP, "hp_batch_create: memset failed");
+  if (s == HP_OK) s = network_alloc(*b);
+  if (s != HP_OK) {
+    delete b;
+    return s;
+  }
+  *out = b;
+  return HP_OK;
+}
+
+extern "C" hp_status hp_batch_destroy(hp_batch b) {
+  delete b;
+  return HP_OK;
+}
+
+extern "C" hp_status hp_batch_info(hp_batch b, int32_t dtype, hp_batch_info_t* info) {
+  if (!b || !info) return set_error(HP_E_INVALID, "hp_batch_info: NULL argument");
+  info->nframes = b->nframes;
+  info->ntot = b->ntot;
+  info->ktot = b->ktot;
+  info->mtot = b->mtot;
+  info->sys_floats = 13 * b->ntot;
+  int64_t offs[5], tot;
+  factor_offsets(*b, HP_F32, offs, &tot);
+  info->factor_bytes[0] = tot;
+  factor_offsets(*b, HP_BF16, offs, &tot);
+  info->factor_bytes[1] = tot;
+  factor_offsets(*b, dtype == HP_BF16 ? HP_BF16 : HP_F32, offs, &tot);
+  info->off_G = offs[0];
+  info->off_B = offs[1];
+  info->off_Ut = offs[2];
+  info->off_Vt = offs[3];
+  info->off_lam = offs[4];
+  int32_t cnt;
+  int64_t wf;
+  hp_weight_count(&b->cfg, &cnt, &wf);
+  info->weight_floats = wf;
+  return HP_OK;
+}
+
+extern "C" hp_status hp_batch_offsets(hp_batch b, int64_t* n0, int64_t* k0, int64_t* m0) {
+  if (!b) return set_error(HP_E_INVALID, "hp_batch_offsets: NULL batch");
+  for (int f = 0; f < b->nframes; ++f) {
+    if (n0) n0[f] = b->fr[f].n0;
+    if (k0) k0[f] = b->fr[f].k0;
+    if (m0) m0[f] = b->fr[f].m0;
+  }
+  return HP_OK;
+}
+
+extern "C" hp_status hp_assemble(hp_batch b, const float* d_rho, float* d_sys) {
+  if (!b || !d_rho || !d_sys) return set_error(HP_E_INVALID, "hp_assemble: NULL argument");
+  return launch_assemble(b->geom(), d_rho, d_sys);
+}
+
+extern "C" hp_status hp_spmv(hp_batch b, const float* d_sys, const float* d_p, float* d_q) {
+  if (!b || !d_sys || !d_p || !d_q) return set_error(HP_E_INVALID, "hp_spmv: NULL argument");
+  return launch_spmv(b->geom(), d_sys, d_p, d_q);
+}
+
+extern "C" hp_status hp_apply(hp_batch b, const float* d_sys, const void* d_factors, int32_t fdtype,
+                              const float* d_r, float* d_y, int32_t ncols) {
+  if (!b || !d_sys || !d_factors || !d_r || !d_y) return set_error(HP_E_INVALID, "hp_apply: NULL argument");
+  if (ncols != 1) return set_error(HP_E_INVALID, "hp_apply: ncols must be 1");
+  if (fdtype != HP_F32 && fdtype != HP_BF16) return set_error(HP_E_INVALID, "hp_apply: bad fdtype");
+  if (d_r == d_y) return set_error(HP_E_INVALID, "hp_apply: r and y must not alias");
+  int64_t offs[5], tot;
+  factor_offsets(*b, fdtype, offs, &tot);
+  return launch_apply(b->geom(), b->cfg.leaf, b->cfg.rank, fdtype, d_sys, d_factors, offs, d_r, d_y, b->uh, b->vh,
+                      b->Tr, b->Tc);
+}
+
+// ------------------------------------------------------------------ PCG driver
+
+// The pinned staging area is rewritten only after the stream has drained
+// (every pass ends with a synchronisation), so the async uploads never race.
+static hp_status run_pass(Batch* b, PcgLaunch& P, const hp_solve_opts& o, const std::vector<FrameState>& init,
+                          int nact) {
+  int* h_active = (int*)b->h_pin;
+  int* h_nact = (int*)(b->h_pin + 64);
+  SolveParams* h_prm = (SolveParams*)(b->h_pin + 128);
+  FrameState* h_st = (FrameState*)(b->h_pin + 256);
+  HP_HIP(hipStreamSynchronize(b->stream));
+  memcpy(h_st, init.data(), sizeof(FrameState) * b->nframes);
+  *h_nact = nact;
+  *h_prm = SolveParams{o.tol, o.max_iter, o.recompute_every, o.stagnation, 0};
+  HP_HIP(hipMemcpyAsync(b->st, h_st, sizeof(FrameState) * b->nframes, hipMemcpyHostToDevice, b->stream));
+  HP_HIP(hipMemcpyAsync(b->n_active, h_nact, sizeof(int), hipMemcpyHostToDevice, b->stream));
+  HP_HIP(hipMemcpyAsync(b->prm, h_prm, sizeof(SolveParams), hipMemcpyHostToDevice, b->stream));
+  HP_TRY(pcg_setup(P));
+  const int chunk = std::max(2, o.chunk + (o.chunk & 1));
+  hipGraphExec_t exec = nullptr;
+  if (o.use_graph) {
+    auto key = std::make_tuple(P.mode, P.fdtype, (const void*)P.B.sys, P.fbase, (const void*)P.B.b,
+                               (const void*)P.B.x0, chunk);
+    auto it = b->graphs.find(key);
+    if (it != b->graphs.end()) {
+      exec = it->second;
+    } else {
+      if (!b->cap_stream) HP_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+      PcgLaunch C = P;
+      C.g.stream = b->cap_stream;
+      hipGraph_t graph;
+      HP_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+      hp_status s = pcg_iterations(C, chunk);
+      hipError_t e = hipStreamEndCapture(b->cap_stream, &graph);
+      if (s != HP_OK) return s;
+      if (e != hipSuccess) return set_error(HP_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      hipGraphDestroy(graph);
+      if (e != hipSuccess) return set_error(HP_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+      b->graphs[key] = exec;
+    }
+  }
+  const int64_t max_chunks = (int64_t)o.max_iter / chunk + 2;
+  for (int64_t c = 0; c < max_chunks; ++c) {
+    HP_HIP(hipMemcpyAsync(h_active, b->n_active, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    HP_HIP(hipStreamSynchronize(b->stream));
+    if (*h_active <= 0) break;
+    if (exec) HP_HIP(hipGraphLaunch(exec, b->stream));
+    else HP_TRY(pcg_iterations(P, chunk));
+  }
+  HP_TRY(pcg_finalize(P));
+  return HP_OK;
+}
+
+extern "C" hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_factors, const hp_solve_opts* opts,
+                                  const float* d_b, double* d_x, hp_solve_result* res) {
+  if (!b || !d_sys || !opts || !d_b || !d_x || !res) return set_error(HP_E_INVALID, "hp_pcg_solve: NULL argument");
+  const hp_solve_opts o = *opts;
+  if (o.precond < 0 || o.precond > 2) return set_error(HP_E_INVALID, "hp_pcg_solve: bad precond");
+  if (o.precond == HP_PRECOND_HMAT && !d_factors)
+    return set_error(HP_E_INVALID, "hp_pcg_solve: factors required for HMAT");
+  if (o.precond == HP_PRECOND_HMAT && o.fdtype != HP_F32 && o.fdtype != HP_BF16)
+    return set_error(HP_E_INVALID, "hp_pcg_solve: bad fdtype");
+  if (!(o.tol >= 0) || o.max_iter < 0 || o.recompute_every < 0)
+    return set_error(HP_E_INVALID, "hp_pcg_solve: bad tolerance or limits");
+  if ((const void*)d_b == (const void*)d_x) return set_error(HP_E_INVALID, "hp_pcg_solve: b and x must not alias");
+  int64_t offs[5], tot;
+  factor_offsets(*b, o.precond == HP_PRECOND_HMAT ? o.fdtype : HP_F32, offs, &tot);
+  PcgLaunch P;
+  P.g = b->geom();
+  P.mode = o.precond;
+  P.L = b->cfg.leaf;
+  P.LS = b->cfg.rank;
+  P.fdtype = o.fdtype;
+  P.fbase = d_factors;
+  P.offs = offs;
+  PcgBufs& B = P.B;
+  B.sys = d_sys;
+  B.ntot = b->ntot;
+  B.b = d_b;
+  B.x0 = d_x;
+  B.x1 = b->x1;
+  B.p0 = b->p0;
+  B.p1 = b->p1;
+  B.r = b->r;
+  B.z = b->z;
+  B.q = b->q;
+  B.uh = b->uh;
+  B.vh = b->vh;
+  B.Tr = b->Tr;
+  B.Tc = b->Tc;
+  B.part_pq = b->part_pq;
+  B.part_rr = b->part_rr;
+  B.part_rz = b->part_rz;
+  B.ticket = b->ticket;
+  B.n_active = b->n_active;
+  B.st = b->st;
+  B.prm = b->prm;
+  std::vector<FrameState> init(b->nframes);
+  for (auto& s : init) {
+    memset(&s, 0, sizeof s);
+    s.rho = 1.0;
+    s.active = 1;
+  }
+  HP_TRY(run_pass(b, P, o, init, b->nframes));
+  std::vector<FrameState> out(b->nframes);
+  HP_HIP(hipMemcpyAsync(out.data(), b->st, sizeof(FrameState) * b->nframes, hipMemcpyDeviceToHost, b->stream));
+  HP_HIP(hipStreamSynchronize(b->stream));
+  bool any_fail = false;
+  for (int f = 0; f < b->nframes; ++f) {
+    res[f].iters = out[f].k;
+    res[f].flags = out[f].flags;
+    res[f].relres = out[f].bnorm > 0 ? sqrt(out[f].rr) / out[f].bnorm : 0.0;
+    if (!(out[f].flags & HP_CONVERGED)) any_fail = true;
+  }
+  if (any_fail && o.fallback && o.precond == HP_PRECOND_HMAT) {
+    std::vector<FrameState> init2(b->nframes);
+    int nact = 0;
+    for (int f = 0; f < b->nframes; ++f) {
+      memset(&init2[f], 0, sizeof(FrameState));
+      init2[f].rho = 1.0;
+      bool redo = !(out[f].flags & HP_CONVERGED);
+      init2[f].active = redo;
+      init2[f].done = !redo;
+      nact += redo;
+    }
+    hp_solve_opts o2 = o;
+    o2.precond = HP_PRECOND_JACOBI;
+    o2.stagnation = 0;
+    PcgLaunch P2 = P;
+    P2.mode = HP_PRECOND_JACOBI;
+    HP_TRY(run_pass(b, P2, o2, init2, nact));
+    std::vector<FrameState> out2(b->nframes);
+    HP_HIP(hipMemcpyAsync(out2.data(), b->st, sizeof(FrameState) * b->nframes, hipMemcpyDeviceToHost, b->stream));
+    HP_HIP(hipStreamSynchronize(b->stream));
+    any_fail = false;
+    for (int f = 0; f < b->nframes; ++f) {
+      if (!init2[f].active) continue;
+      res[f].iters += out2[f].k;
+      res[f].flags |= out2[f].flags | HP_FELL_BACK;
+      res[f].relres = out2[f].bnorm > 0 ? sqrt(out2[f].rr) / out2[f].bnorm : 0.0;
+      if (!(out2[f].flags & HP_CONVERGED)) any_fail = true;
+    }
+  }
+  if (any_fail && !o.fallback) {
+    for (int f = 0; f < b->nframes; ++f)
+      if (res[f].flags & HP_NOT_SPD) return set_error(HP_E_NOT_SPD, "hp_pcg_solve: frame %d lost positivity", f);
+    return set_error(HP_E_NOCONV, "hp_pcg_solve: tolerance not reached");
+  }
+  return HP_OK;
+}

@@ -1,0 +1,105 @@
+// The batch object behind hp_batch and the launch interfaces between the
+// host driver and the kernel translation units.
+#pragma once
+
+#include <algorithm>
+#include <array>
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "common.h"
+
+namespace hp {
+
+struct LaunchGeom {
+  const FrameDesc* fr;
+  const int* blk2f;
+  const int* leaf2f;
+  int nframes, nblk;
+  int64_t ktot, ntot;
+  int kmax;
+  hipStream_t stream;
+};
+
+struct PcgBufs {
+  const float* sys;
+  int64_t ntot;
+  const float* b;
+  double *x0, *x1;   // FP64 solution, ping-pong
+  float *p0, *p1;
+  float *r, *z, *q;
+  float *uh, *vh, *Tr, *Tc;
+  double *part_pq, *part_rr, *part_rz;
+  unsigned* ticket;
+  int* n_active;
+  FrameState* st;
+  const SolveParams* prm;
+};
+
+struct PcgLaunch {
+  LaunchGeom g;
+  PcgBufs B;
+  int mode, L, LS, fdtype;
+  const void* fbase;
+  const int64_t* offs;
+};
+
+// Device workspace of the network forward (sized at batch creation).
+struct NetWork {
+  int64_t tokens_d = 0, tokens_o = 0;  // diagonal and off-diagonal token counts
+  float* feats = nullptr;              // [ntot][32] node features, zero padded
+  void* ws = nullptr;                  // one arena for every activation buffer
+  size_t ws_bytes = 0;
+};
+
+struct Batch {
+  hp_model_config cfg{};
+  int nframes = 0;
+  std::vector<FrameDesc> fr;
+  std::vector<std::array<int, 3>> dims;
+  int64_t ntot = 0, ktot = 0, mtot = 0;
+  int nblk = 0, kmax = 0, nmax = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  FrameDesc* d_fr = nullptr;
+  int* d_blk2f = nullptr;
+  int* d_leaf2f = nullptr;
+  // solver workspace
+  double* x1 = nullptr;
+  float *p0 = nullptr, *p1 = nullptr, *r = nullptr, *z = nullptr, *q = nullptr;
+  float *uh = nullptr, *vh = nullptr, *Tr = nullptr, *Tc = nullptr;
+  double *part_pq = nullptr, *part_rr = nullptr, *part_rz = nullptr;
+  unsigned* ticket = nullptr;
+  int* n_active = nullptr;
+  // pinned host staging: [0] active count read back, [1] active count upload,
+  // then SolveParams, then nframes FrameState
+  char* h_pin = nullptr;
+  FrameState* st = nullptr;
+  SolveParams* prm = nullptr;
+  NetWork net;
+  std::map<std::tuple<int, int, const void*, const void*, const void*, const void*, int>, hipGraphExec_t> graphs;
+  std::vector<void*> allocs;
+
+  ~Batch();
+  hp_status alloc(void** p, size_t bytes);
+  LaunchGeom geom() const;
+};
+
+void factor_offsets(const Batch& b, int dtype, int64_t offs[5], int64_t* total);
+
+// solver.hip
+hp_status launch_assemble(const LaunchGeom& g, const float* rho, float* sys);
+hp_status launch_spmv(const LaunchGeom& g, const float* sys, const float* p, float* q);
+hp_status launch_apply(const LaunchGeom& g, int L, int LS, int fdtype, const float* sys, const void* fac,
+                       const int64_t* offs, const float* r, float* y, float* uh, float* vh, float* Tr, float* Tc);
+hp_status pcg_setup(const PcgLaunch& P);
+hp_status pcg_iterations(const PcgLaunch& P, int count);
+hp_status pcg_finalize(const PcgLaunch& P);
+
+// network.hip
+hp_status network_alloc(Batch& b);
+
+}  // namespace hp
+
+struct hp_batch_s : hp::Batch {};

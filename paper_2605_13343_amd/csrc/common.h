@@ -1,0 +1,120 @@
+// Internal definitions shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hp.h"
+
+namespace hp {
+
+// ---------------------------------------------------------------- errors
+hp_status set_error(hp_status code, const char* fmt, ...);
+
+#define HP_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return ::hp::set_error(HP_E_HIP, "%s failed: %s (%s:%d)", #call,                \
+                             hipGetErrorString(e_), __FILE__, __LINE__);              \
+  } while (0)
+
+#define HP_TRY(expr)                 \
+  do {                               \
+    hp_status s_ = (expr);           \
+    if (s_ != HP_OK) return s_;      \
+  } while (0)
+
+// ---------------------------------------------------------------- frames
+// One frame of a batch as the kernels see it.  Morton code == local row.
+struct FrameDesc {
+  int n, n0;        // unknowns, first row in the batch
+  int K, k0;        // leaves, first leaf
+  int MH, m0;       // tiles, first tile
+  int J;            // levels = log2 K
+  int nz;           // grid height (top layer z = nz-1)
+  unsigned xm, ym, zm;  // Morton bit masks of x, y, z within the code
+  int nb, b0;       // node blocks (of NODE_BLOCK rows) and first node block
+  int pad;
+};
+
+constexpr int NODE_BLOCK = 256;   // rows per node block
+constexpr int LEAF_THREADS = 256; // threads per leaf block
+
+// Per-frame PCG scalars (device).  Written only by the last-arriving block
+// of a kernel for that frame (ticket pattern) or by single-block kernels.
+struct FrameState {
+  double rho;     // r.z of the current residual
+  double alpha;   // rho / p.q
+  double beta;    // rho' / rho
+  double rr;      // ||r||^2
+  double target;  // (tol ||b||)^2
+  double bnorm;   // ||b||
+  double rwin;    // ||r|| at the last stagnation checkpoint
+  int k;          // iterations done
+  int flags;      // HP_* flags
+  int done;       // 1: frame stopped (converged or failed)
+  int active;     // 1: frame takes part in this solve
+  int force_rc;   // 1: next iteration replaces r by b - A x (confirmation)
+  int pad;
+};
+
+struct SolveParams {
+  double tol;
+  int max_iter, recompute_every, stagnation, pad;
+};
+
+// ---------------------------------------------------------------- bf16
+__host__ __device__ inline float bf16_to_f32(uint16_t h) {
+  union { uint32_t u; float f; } c;
+  c.u = (uint32_t)h << 16;
+  return c.f;
+}
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {  // round to nearest even
+  union { uint32_t u; float f; } c;
+  c.f = f;
+  if ((c.u & 0x7f800000u) == 0x7f800000u && (c.u & 0x007fffffu)) return 0x7fc0;  // NaN
+  c.u += 0x7fffu + ((c.u >> 16) & 1u);
+  return (uint16_t)(c.u >> 16);
+}
+
+template <typename T> __device__ inline float ldf(const T* p, int64_t i);
+template <> __device__ inline float ldf<float>(const float* p, int64_t i) { return p[i]; }
+template <> __device__ inline float ldf<uint16_t>(const uint16_t* p, int64_t i) { return bf16_to_f32(p[i]); }
+
+// ---------------------------------------------------------------- Morton neighbours
+// Neighbour of code c one step along the axis whose bits are mask; the
+// boundary wraps to the far side, where the face weight is zero.
+__device__ inline unsigned mstep_plus(unsigned c, unsigned mask) {
+  return (((c | ~mask) + 1u) & mask) | (c & ~mask);
+}
+__device__ inline unsigned mstep_minus(unsigned c, unsigned mask) {
+  return (((c & mask) - 1u) & mask) | (c & ~mask);
+}
+__device__ inline int mcoord(unsigned c, unsigned mask) {
+  int v = 0, b = 0;
+  while (mask) {
+    unsigned low = mask & (~mask + 1u);
+    if (c & low) v |= 1 << b;
+    ++b;
+    mask &= mask - 1u;
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------- host helpers
+bool admissible_grid(int nx, int ny, int nz, std::string* why);
+void morton_masks(int nx, int ny, int nz, unsigned* xm, unsigned* ym, unsigned* zm);
+
+struct WeightEntry {
+  std::string name;
+  int rows, cols;   // cols == 0 for rank-1
+  int64_t offset;
+};
+std::vector<WeightEntry> weight_layout(const hp_model_config& c);
+const WeightEntry* find_weight(const std::vector<WeightEntry>& w, const std::string& name);
+
+}  // namespace hp

@@ -1,0 +1,247 @@
+"""Thin Python binding of the C ABI in include/hp.h (ctypes; argument
+marshalling only).  Every step of the method runs in the HIP library; torch is
+used for device memory and streams.  There is no CPU fallback: the binding
+raises if libhp.so is missing or a call fails."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhp.so")
+_lib = None
+
+HP_F32, HP_BF16 = 0, 1
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_HMAT = 0, 1, 2
+CONVERGED, NOT_SPD, STAGNATED, MAXITER, FELL_BACK = 1, 2, 4, 8, 16
+
+
+class HPError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hp status {status}: {msg}")
+        self.status = status
+
+
+class ModelConfigC(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("d", "heads", "layers", "leaf", "rank", "edge_hidden", "gcn",
+                                         "node_feats", "glob_feats", "highways", "offdiag")]
+
+
+class PartitionInfo(C.Structure):
+    _fields_ = [("n", C.c_int32), ("leaf", C.c_int32), ("rank", C.c_int32), ("K", C.c_int32), ("J", C.c_int32),
+                ("MH", C.c_int32), ("P", C.c_int64), ("off_diag", C.c_int64), ("off_B", C.c_int64),
+                ("off_Ut", C.c_int64), ("off_Vt", C.c_int64), ("off_lam", C.c_int64)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("nframes", C.c_int32), ("ntot", C.c_int64), ("ktot", C.c_int64), ("mtot", C.c_int64),
+                ("sys_floats", C.c_int64), ("factor_bytes", C.c_int64 * 2), ("off_G", C.c_int64),
+                ("off_B", C.c_int64), ("off_Ut", C.c_int64), ("off_Vt", C.c_int64), ("off_lam", C.c_int64),
+                ("weight_floats", C.c_int64)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("precond", C.c_int32), ("fdtype", C.c_int32), ("tol", C.c_double), ("max_iter", C.c_int32),
+                ("recompute_every", C.c_int32), ("fallback", C.c_int32), ("use_graph", C.c_int32),
+                ("chunk", C.c_int32), ("stagnation", C.c_int32)]
+
+
+class SolveResult(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("flags", C.c_int32), ("relres", C.c_double)]
+
+
+EXPORTS = {
+    "hp_last_error": ([], C.c_char_p),
+    "hp_morton_order": ([C.c_int32, C.c_int32, C.c_int32, C.c_void_p], C.c_int32),
+    "hp_build_partition": ([C.c_int32, C.c_int32, C.c_int32, C.POINTER(PartitionInfo)] + [C.c_void_p] * 6,
+                           C.c_int32),
+    "hp_batch_create": ([C.POINTER(ModelConfigC), C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)],
+                        C.c_int32),
+    "hp_batch_destroy": ([C.c_void_p], C.c_int32),
+    "hp_batch_info": ([C.c_void_p, C.c_int32, C.POINTER(BatchInfo)], C.c_int32),
+    "hp_batch_offsets": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
+    "hp_assemble": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
+    "hp_spmv": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
+    "hp_apply": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32], C.c_int32),
+    "hp_pcg_solve": ([C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p,
+                      C.POINTER(SolveResult)], C.c_int32),
+    "hp_weight_count": ([C.POINTER(ModelConfigC), C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int32),
+    "hp_weight_info": ([C.POINTER(ModelConfigC), C.c_int32, C.c_char_p, C.POINTER(C.c_int32),
+                        C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int32),
+    "hp_infer_factors": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32], C.c_int32),
+}
+
+
+def lib():
+    """Load libhp.so (built in-tree by paper_2605_13343_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with paper_2605_13343_amd.build.build()")
+        L = C.CDLL(_LIB_PATH)
+        for name, (args, res) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise HPError(status, lib().hp_last_error().decode())
+
+
+def cfg_c(cfg) -> ModelConfigC:
+    return ModelConfigC(cfg.d, cfg.heads, cfg.layers, cfg.leaf, cfg.rank, cfg.edge_hidden, cfg.gcn,
+                        cfg.node_feats, cfg.glob_feats, int(cfg.highways), int(cfg.offdiag))
+
+
+# ------------------------------------------------------------------ host-only calls
+
+def morton_order(nx: int, ny: int, nz: int) -> np.ndarray:
+    perm = np.zeros(nx * ny * nz, dtype=np.int32)
+    _check(lib().hp_morton_order(nx, ny, nz, perm.ctypes.data))
+    return perm
+
+
+def build_partition(n: int, leaf: int, rank: int, tables: bool = True):
+    info = PartitionInfo()
+    if not tables:
+        _check(lib().hp_build_partition(n, leaf, rank, C.byref(info), *([None] * 6)))
+        return info, None
+    _check(lib().hp_build_partition(n, leaf, rank, C.byref(info), *([None] * 6)))
+    K, J, MH = info.K, info.J, info.MH
+    t = {k: np.zeros(max(MH, 1), dtype=np.int32) for k in ("level", "row0", "col0", "span")}
+    lt = np.zeros(max(K * J, 1), dtype=np.int32)
+    ls = np.zeros(max(K * J, 1), dtype=np.int8)
+    _check(lib().hp_build_partition(n, leaf, rank, C.byref(info), t["level"].ctypes.data, t["row0"].ctypes.data,
+                                    t["col0"].ctypes.data, t["span"].ctypes.data, lt.ctypes.data, ls.ctypes.data))
+    t = {k: v[:MH] for k, v in t.items()}
+    t["leaf_tile"] = lt[:K * J].reshape(K, J)
+    t["leaf_side"] = ls[:K * J].reshape(K, J)
+    return info, t
+
+
+def weight_layout(cfg) -> List[Tuple[str, Tuple[int, ...], int]]:
+    c = cfg_c(cfg)
+    cnt, fl = C.c_int32(), C.c_int64()
+    _check(lib().hp_weight_count(C.byref(c), C.byref(cnt), C.byref(fl)))
+    out = []
+    name = C.create_string_buffer(64)
+    for i in range(cnt.value):
+        r, cc, off = C.c_int32(), C.c_int32(), C.c_int64()
+        _check(lib().hp_weight_info(C.byref(c), i, name, C.byref(r), C.byref(cc), C.byref(off)))
+        shape = (r.value, cc.value) if cc.value else (r.value,)
+        out.append((name.value.decode(), shape, off.value))
+    return out
+
+
+def pack_weights(cfg, weights: Dict[str, np.ndarray]) -> np.ndarray:
+    """Flatten a name -> array dict into the library's FP32 weight vector."""
+    lay = weight_layout(cfg)
+    tot = lay[-1][2] + int(np.prod(lay[-1][1]))
+    out = np.zeros(tot, dtype=np.float32)
+    for name, shape, off in lay:
+        a = np.asarray(weights[name], dtype=np.float32)
+        if a.shape != shape:
+            raise ValueError(f"weight {name}: shape {a.shape} != {shape}")
+        out[off:off + a.size] = a.ravel()
+    return out
+
+
+# ------------------------------------------------------------------ batches (GPU)
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Batch:
+    """A batch of frames (one leaf size) with device workspaces."""
+
+    def __init__(self, cfg, dims: Sequence[Tuple[int, int, int]], stream=None):
+        import torch
+        self.cfg = cfg
+        self.dims = [tuple(int(v) for v in d) for d in dims]
+        self._c = cfg_c(cfg)
+        arr = np.array(self.dims, dtype=np.int32).reshape(-1)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib().hp_batch_create(C.byref(self._c), len(self.dims), arr.ctypes.data, C.c_void_p(stream.cuda_stream),
+                                     C.byref(h)))
+        self.h = h
+        self.info = {}
+        for dt in (HP_F32, HP_BF16):
+            bi = BatchInfo()
+            _check(lib().hp_batch_info(h, dt, C.byref(bi)))
+            self.info[dt] = bi
+        nf = len(self.dims)
+        n0, k0, m0 = (np.zeros(nf, dtype=np.int64) for _ in range(3))
+        _check(lib().hp_batch_offsets(h, n0.ctypes.data, k0.ctypes.data, m0.ctypes.data))
+        self.n0, self.k0, self.m0 = n0, k0, m0
+        self.ntot = self.info[0].ntot
+        self.ktot = self.info[0].ktot
+        self.mtot = self.info[0].mtot
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().hp_batch_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    # -- buffers
+    def new_sys(self):
+        import torch
+        return torch.zeros(self.info[0].sys_floats, dtype=torch.float32, device="cuda")
+
+    def new_factors(self, dtype: int):
+        import torch
+        return torch.zeros(self.info[dtype].factor_bytes[dtype], dtype=torch.uint8, device="cuda")
+
+    def factor_views(self, fac, dtype: int) -> Dict[str, "torch.Tensor"]:
+        """Typed views of the packed factor sections."""
+        import torch
+        bi = self.info[dtype]
+        L, LS = self.cfg.leaf, self.cfg.rank
+        et = torch.bfloat16 if dtype == HP_BF16 else torch.float32
+        es = 2 if dtype == HP_BF16 else 4
+        sec = lambda off, n, t, e: fac[off:off + n * e].view(t)
+        return {
+            "G": sec(bi.off_G, self.ktot * L * L, et, es).view(self.ktot, L, L),
+            "B": sec(bi.off_B, self.mtot * LS * LS, et, es).view(self.mtot, LS, LS),
+            "Ut": sec(bi.off_Ut, self.ntot * LS, et, es).view(self.ntot, LS),
+            "Vt": sec(bi.off_Vt, self.ntot * LS, et, es).view(self.ntot, LS),
+            "lam": sec(bi.off_lam, self.ntot, torch.float32, 4),
+        }
+
+    # -- calls
+    def assemble(self, rho, sys):
+        _check(lib().hp_assemble(self.h, _ptr(rho), _ptr(sys)))
+
+    def spmv(self, sys, p, q):
+        _check(lib().hp_spmv(self.h, _ptr(sys), _ptr(p), _ptr(q)))
+
+    def apply(self, sys, fac, dtype: int, r, y):
+        _check(lib().hp_apply(self.h, _ptr(sys), _ptr(fac), dtype, _ptr(r), _ptr(y), 1))
+
+    def pcg_solve(self, sys, fac, b, x, precond: int, fdtype: int = HP_F32, tol: float = 1e-6,
+                  max_iter: int = 10000, recompute_every: int = 25, fallback: bool = True,
+                  use_graph: bool = True, chunk: int = 16, stagnation: bool = True, raise_on_fail: bool = True):
+        """Returns [(iterations, flags, recurrence relres)] per frame.  With
+        raise_on_fail False, HP_E_NOT_SPD / HP_E_NOCONV still return results."""
+        o = SolveOpts(precond, fdtype, tol, max_iter, recompute_every, int(fallback), int(use_graph), chunk,
+                      int(stagnation))
+        res = (SolveResult * len(self.dims))()
+        st = lib().hp_pcg_solve(self.h, _ptr(sys), _ptr(fac), C.byref(o), _ptr(b), _ptr(x), res)
+        if not (st in (5, 6) and not raise_on_fail):
+            _check(st)
+        return [(r.iters, r.flags, r.relres) for r in res]
+
+    def infer_factors(self, weights, rho, sys, fac, compute: int):
+        _check(lib().hp_infer_factors(self.h, _ptr(weights), _ptr(rho), _ptr(sys), _ptr(fac), compute))

@@ -92,8 +92,9 @@ def test_pcg_exact_inverse_one_iteration():
     fr = inputs.make_frame_grid(8, 4, 4, 5)
     A = grid.assemble(fr.nx, fr.ny, fr.nz, fr.rho)
     Ainv = np.linalg.inv(A.toarray())
-    x, it, fl, _ = pcg.pcg(A, fr.b, lambda r: Ainv @ r, tol=1e-10)
-    assert it == 1 and fl == pcg.CONVERGED
+    # every iteration replaces r by b - A x, so the first residual is a true one
+    x, it, fl, h = pcg.pcg(A, fr.b, lambda r: Ainv @ r, tol=1e-10, recompute_every=1)
+    assert it == 1 and fl == pcg.CONVERGED and h[1] < 1e-13
 
 
 def test_jacobi_is_cg_on_scaled_system():
