@@ -92,6 +92,11 @@ extern "C" hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes
       delete b;
       return s;
     }
+    if ((int64_t)(pi.K - 1) * LS > 16 * LEAF_THREADS) {  // coarse stage: <= 16 tile outputs per thread
+      delete b;
+      return set_error(HP_E_SHAPE, "hp_batch_create: frame %d has %d leaves; at most %d for L_s=%d", f, pi.K,
+                       16 * LEAF_THREADS / LS + 1, LS);
+    }
     FrameDesc F{};
     F.n = n;
     F.n0 = (int)n0;
@@ -151,13 +156,13 @@ extern "C" hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes
   A((void**)&b->part_rz, np);
   A((void**)&b->ticket, sizeof(unsigned) * 4 * nframes);
   A((void**)&b->n_active, sizeof(int));
-  A((void**)&b->st, sizeof(FrameState) * nframes);
+  A((void**)&b->st, sizeof(FrameState) * 2 * nframes);
   A((void**)&b->prm, sizeof(SolveParams));
   if (s != HP_OK) {
     delete b;
     return s;
   }
-  if (hipHostMalloc((void**)&b->h_pin, 256 + sizeof(FrameState) * nframes) != hipSuccess) {
+  if (hipHostMalloc((void**)&b->h_pin, 256 + sizeof(FrameState) * 2 * nframes) != hipSuccess) {
     delete b;
     return set_error(HP_E_NOMEM, "hipHostMalloc failed");
   }
@@ -252,10 +257,10 @@ static hp_status run_pass(Batch* b, PcgLaunch& P, const hp_solve_opts& o, const 
   SolveParams* h_prm = (SolveParams*)(b->h_pin + 128);
   FrameState* h_st = (FrameState*)(b->h_pin + 256);
   HP_HIP(hipStreamSynchronize(b->stream));
-  memcpy(h_st, init.data(), sizeof(FrameState) * b->nframes);
+  for (int f = 0; f < b->nframes; ++f) h_st[2 * f] = h_st[2 * f + 1] = init[f];
   *h_nact = nact;
   *h_prm = SolveParams{o.tol, o.max_iter, o.recompute_every, o.stagnation, 0};
-  HP_HIP(hipMemcpyAsync(b->st, h_st, sizeof(FrameState) * b->nframes, hipMemcpyHostToDevice, b->stream));
+  HP_HIP(hipMemcpyAsync(b->st, h_st, sizeof(FrameState) * 2 * b->nframes, hipMemcpyHostToDevice, b->stream));
   HP_HIP(hipMemcpyAsync(b->n_active, h_nact, sizeof(int), hipMemcpyHostToDevice, b->stream));
   HP_HIP(hipMemcpyAsync(b->prm, h_prm, sizeof(SolveParams), hipMemcpyHostToDevice, b->stream));
   HP_TRY(pcg_setup(P));
@@ -292,6 +297,16 @@ static hp_status run_pass(Batch* b, PcgLaunch& P, const hp_solve_opts& o, const 
     else HP_TRY(pcg_iterations(P, chunk));
   }
   HP_TRY(pcg_finalize(P));
+  return HP_OK;
+}
+
+// Final per-frame states (slot 0 of each frame).
+static hp_status read_states(Batch* b, std::vector<FrameState>& out) {
+  std::vector<FrameState> both(2 * b->nframes);
+  HP_HIP(hipMemcpyAsync(both.data(), b->st, sizeof(FrameState) * 2 * b->nframes, hipMemcpyDeviceToHost, b->stream));
+  HP_HIP(hipStreamSynchronize(b->stream));
+  out.resize(b->nframes);
+  for (int f = 0; f < b->nframes; ++f) out[f] = both[2 * f];
   return HP_OK;
 }
 
@@ -346,12 +361,11 @@ extern "C" hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_
     s.active = 1;
   }
   HP_TRY(run_pass(b, P, o, init, b->nframes));
-  std::vector<FrameState> out(b->nframes);
-  HP_HIP(hipMemcpyAsync(out.data(), b->st, sizeof(FrameState) * b->nframes, hipMemcpyDeviceToHost, b->stream));
-  HP_HIP(hipStreamSynchronize(b->stream));
+  std::vector<FrameState> out;
+  HP_TRY(read_states(b, out));
   bool any_fail = false;
   for (int f = 0; f < b->nframes; ++f) {
-    res[f].iters = out[f].k;
+    res[f].iters = out[f].it;
     res[f].flags = out[f].flags;
     res[f].relres = out[f].bnorm > 0 ? sqrt(out[f].rr) / out[f].bnorm : 0.0;
     if (!(out[f].flags & HP_CONVERGED)) any_fail = true;
@@ -373,13 +387,12 @@ extern "C" hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_
     PcgLaunch P2 = P;
     P2.mode = HP_PRECOND_JACOBI;
     HP_TRY(run_pass(b, P2, o2, init2, nact));
-    std::vector<FrameState> out2(b->nframes);
-    HP_HIP(hipMemcpyAsync(out2.data(), b->st, sizeof(FrameState) * b->nframes, hipMemcpyDeviceToHost, b->stream));
-    HP_HIP(hipStreamSynchronize(b->stream));
+    std::vector<FrameState> out2;
+    HP_TRY(read_states(b, out2));
     any_fail = false;
     for (int f = 0; f < b->nframes; ++f) {
       if (!init2[f].active) continue;
-      res[f].iters += out2[f].k;
+      res[f].iters += out2[f].it;
       res[f].flags |= out2[f].flags | HP_FELL_BACK;
       res[f].relres = out2[f].bnorm > 0 ? sqrt(out2[f].rr) / out2[f].bnorm : 0.0;
       if (!(out2[f].flags & HP_CONVERGED)) any_fail = true;

@@ -44,22 +44,21 @@ struct FrameDesc {
 constexpr int NODE_BLOCK = 256;   // rows per node block
 constexpr int LEAF_THREADS = 256; // threads per leaf block
 
-// Per-frame PCG scalars (device).  Written only by the last-arriving block
-// of a kernel for that frame (ticket pattern) or by single-block kernels.
+// Per-frame PCG scalars (device), double-buffered by iteration parity.
 struct FrameState {
   double rho;     // r.z of the current residual
-  double alpha;   // rho / p.q
-  double beta;    // rho' / rho
-  double rr;      // ||r||^2
+  double alpha;   // last step length (record)
+  double beta;    // last rho'/rho (record)
+  double rr;      // ||r||^2 at the last check
   double target;  // (tol ||b||)^2
   double bnorm;   // ||b||
   double rwin;    // ||r|| at the last stagnation checkpoint
-  int k;          // iterations done
+  int it;         // updates done and checked
   int flags;      // HP_* flags
   int done;       // 1: frame stopped (converged or failed)
   int active;     // 1: frame takes part in this solve
-  int force_rc;   // 1: next iteration replaces r by b - A x (confirmation)
-  int pad;
+  int force_rc;   // 1: next update replaces r by b - A x (confirmation)
+  int fresh;      // 1: set up, no update yet
 };
 
 struct SolveParams {

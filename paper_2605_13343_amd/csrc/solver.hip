@@ -1,25 +1,23 @@
 // Assembly, 7-point SpMV, the H-matrix apply and the fused PCG pipeline.
 //
-// PCG (paper Sec. 3 and Sec. 5; Saad 2003 Alg. 9.1) runs as three kernels per
+// PCG (paper Sec. 3 and Sec. 5; Saad 2003 Alg. 9.1) runs as four kernels per
 // iteration for the learned preconditioner and two for Jacobi / identity:
 //
-//   k_spmv_p      node blocks: p = z + beta p_old (on the fly at the 7 stencil
-//                 points, p ping-pongs), q = A p, FP64 partials of p.q; the last
-//                 block of a frame reduces them in a fixed order -> alpha.
-//   k_update_hmat leaf blocks: x += alpha p (x ping-pongs), r -= alpha q or the
-//                 FP64 residual replacement r = b - A x, the leaf stage of M
-//                 (G_k r_k + lam r / A_ii, restriction Ut^T r, Vt^T r), FP64
-//                 partials of ||r||^2; the last block of a frame takes the
-//                 stop decisions and runs the frame's coarse stage (strip sums,
-//                 B / B^T coupling, accumulation down the levels).
-//   k_prolong     leaf blocks: z += Ut T^r + Vt T^c, FP64 partials of r.z; the
-//                 last block -> positivity check, beta = rho'/rho.
+//   k_spmv_p      node blocks: rho' = r.z, beta, p = z + beta p_old (on the fly
+//                 at the 7 stencil points, p ping-pongs), q = A p, partials of
+//                 p.q.  Jacobi / identity: also the stop checks of the last update.
+//   k_update_hmat leaf blocks: alpha, x += alpha p (FP64, x ping-pongs),
+//                 r -= alpha q or the FP64 residual replacement r = b - A x,
+//                 the leaf stage of M (G_k r_k + lam r / A_ii, restriction
+//                 Ut^T r, Vt^T r), partials of ||r||^2.
+//   k_frame_check one block per frame: stop checks; coarse stage (strip sums,
+//                 B / B^T coupling, gathering down the levels).
+//   k_prolong     leaf blocks: z += Ut T^r + Vt T^c, partials of r.z.
 //
-// Per-frame scalars live in FrameState and are written only by the last
-// block to arrive (atomic ticket per frame and kernel), so every reduction
-// has a fixed order and the solve is bit-reproducible.  Frames that stopped
-// are skipped by every kernel, which makes a fixed chunk of iterations safe
-// to replay from a hipGraph.
+// All reductions run in a fixed order (FP64), so a solve is bit-reproducible
+// and independent of how frames are batched.  Frames that stopped are skipped
+// by every kernel, which makes a fixed chunk of iterations safe to replay
+// from a hipGraph.
 #include <float.h>
 #include <math.h>
 
@@ -46,25 +44,14 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-// Ticket: returns true in every thread of the last block (of `count`) to
-// arrive for this counter; resets the counter for the next use.
-__device__ inline bool last_arrival(unsigned* ticket, unsigned count) {
-  __shared__ int is_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned t = atomicAdd(ticket, 1u);
-    is_last = (t == count - 1);
-    if (is_last) {
-      *ticket = 0;
-      __threadfence();
-    }
-  }
-  __syncthreads();
-  return is_last != 0;
+// Fixed-order sum of `count` partials (written by an earlier kernel) by the
+// whole block: thread t adds entries t, t + nt, ... in order, then the
+// fixed-order block reduction.  Every block gets the same bits.
+__device__ inline double frame_sum(const double* part, int count, double* red) {
+  double a = 0.0;
+  for (int j = threadIdx.x; j < count; j += blockDim.x) a += part[j];
+  return block_sum(a, red);
 }
-
-__device__ inline double vload(const double* p) { return *(const volatile double*)p; }
 
 // Assembled system: FP32 [diag | wx | wy | wz | 1/diag] (5 ntot floats) for
 // the SpMV and Jacobi, then FP64 [diag | wx | wy | wz] (4 ntot doubles) for the
@@ -280,66 +267,96 @@ __device__ inline float prolong_row(int64_t row0, const float* trs, const float*
 }
 
 // Coarse stage of one frame, run by one whole block (paper Sec. 5 strip
-// aggregation and coarse coupling): level sums of u and v up the dyadic
-// tree; per tile m = (j, i): t^r = B_m s^c with s^c the level-j sum of the
-// column strip, t^c = B_m^T s^r with s^r the row-strip sum; leaf k adds t^r
-// of the tile where it is on the row side and t^c where it is on the column
-// side, at every level.  lds holds 2.5 K LS floats.
+// aggregation and coarse coupling).  For every tile m = (j, i) at once:
+//   s^r = sum of u over the row strip (leaves [2iS, 2iS+S)),
+//   s^c = sum of v over the column strip (leaves [2iS+S, 2iS+2S)),
+//   t^r = B_m s^c,  t^c = B_m^T s^r;
+// then leaf k gathers T^r_k = sum of t^r over the tiles where it is on the
+// row side and T^c_k over those where it is on the column side.  Every sum
+// runs in a fixed order.  lds holds 2 K LS floats (+ LS slack).
 template <int LS, typename FT>
 __device__ void coarse_stage(const FrameDesc& F, const float* uh, const float* vh, const FT* B, float* Tr,
                              float* Tc, float* lds) {
-  const int K = F.K, J = F.J, nt = blockDim.x, t = threadIdx.x;
+  const int K = F.K, J = F.J, MH = F.MH, nt = blockDim.x, t = threadIdx.x;
   const int64_t kb = (int64_t)F.k0 * LS;
-  for (int e = t; e < K * LS; e += nt) {
-    Tr[kb + e] = 0.f;
-    Tc[kb + e] = 0.f;
-  }
-  if (J == 0) return;
-  float* Pu = lds;
-  float* Pv = Pu + (K / 2) * LS;
-  float* Qu = Pv + (K / 2) * LS;
-  float* Qv = Qu + (K / 4) * LS;
-  float* tb = Qv + (K / 4) * LS;  // [0, K/2 LS): t^r, [K/2 LS, K LS): t^c
-  const float* su = uh + kb;
-  const float* sv = vh + kb;
-  const FT* Bf = B + (int64_t)F.m0 * LS * LS;
-  for (int j = 0; j < J; ++j) {
-    const int nj = K >> (j + 1);
-    const int mb = K - (K >> j);
-    for (int o = t; o < 2 * nj * LS; o += nt) {
-      int which = o / (nj * LS), rem = o % (nj * LS), i = rem / LS, s = rem % LS;
-      const FT* Bm = Bf + (int64_t)(mb + i) * LS * LS;
-      float a = 0.f;
-      if (which == 0) {
-        const float* sc = sv + (2 * i + 1) * LS;
-#pragma unroll
-        for (int u = 0; u < LS; ++u) a = fmaf(ldf(Bm, s * LS + u), sc[u], a);
-        tb[i * LS + s] = a;
-      } else {
-        const float* sr = su + (2 * i) * LS;
-#pragma unroll
-        for (int u = 0; u < LS; ++u) a = fmaf(ldf(Bm, u * LS + s), sr[u], a);
-        tb[(K / 2) * LS + i * LS + s] = a;
-      }
-    }
-    __syncthreads();
+  if (J == 0) {
     for (int e = t; e < K * LS; e += nt) {
-      int k = e / LS, s = e % LS, i = k >> (j + 1);
-      if (((k >> j) & 1) == 0) Tr[kb + e] += tb[i * LS + s];
-      else Tc[kb + e] += tb[(K / 2) * LS + i * LS + s];
+      Tr[kb + e] = 0.f;
+      Tc[kb + e] = 0.f;
     }
-    if (j + 1 < J) {
-      float* du = (j % 2 == 0) ? Pu : Qu;
-      float* dv = (j % 2 == 0) ? Pv : Qv;
-      for (int e = t; e < nj * LS; e += nt) {
-        int bb = e / LS, s = e % LS;
-        du[e] = su[(2 * bb) * LS + s] + su[(2 * bb + 1) * LS + s];
-        dv[e] = sv[(2 * bb) * LS + s] + sv[(2 * bb + 1) * LS + s];
-      }
-      su = du;
-      sv = dv;
+    return;
+  }
+  float* su = lds;            // [K][LS] u, later strip sums s^r / t^c
+  float* sv = lds + K * LS;   // [K][LS] v, later strip sums s^c / t^r
+  for (int e = t; e < K * LS; e += nt) {
+    su[e] = uh[kb + e];
+    sv[e] = vh[kb + e];
+  }
+  __syncthreads();
+  // tile m at level j = level_of(m), index i: m = K - K/2^j + i
+  auto tile_of = [&](int m, int& j, int& i) {
+    j = 0;
+    while (m >= K - (K >> (j + 1))) ++j;
+    i = m - (K - (K >> j));
+  };
+  constexpr int MAXR = 16;  // outputs per thread per phase (MH LS <= MAXR nt)
+  float ar[MAXR], ac[MAXR];
+  int cnt = 0;
+  for (int e = t; e < MH * LS; e += nt, ++cnt) {
+    int m = e / LS, s = e % LS, j, i;
+    tile_of(m, j, i);
+    const int S = 1 << j;
+    float a = 0.f, c = 0.f;
+    for (int k = 2 * i * S; k < 2 * i * S + S; ++k) a += su[k * LS + s];
+    for (int k = 2 * i * S + S; k < 2 * i * S + 2 * S; ++k) c += sv[k * LS + s];
+    ar[cnt] = a;
+    ac[cnt] = c;
+  }
+  __syncthreads();
+  cnt = 0;
+  for (int e = t; e < MH * LS; e += nt, ++cnt) {
+    su[e] = ar[cnt];  // s^r
+    sv[e] = ac[cnt];  // s^c
+  }
+  __syncthreads();
+  const FT* Bf = B + (int64_t)F.m0 * LS * LS;
+  cnt = 0;
+  for (int e = t; e < MH * LS; e += nt, ++cnt) {
+    int m = e / LS, s = e % LS;
+    const FT* Bm = Bf + (int64_t)m * LS * LS;
+    float b_row[LS], b_col[LS];
+    if constexpr (LS % 4 == 0) load_vec<FT, LS>(Bm + s * LS, b_row);
+#pragma unroll
+    for (int u = 0; u < LS; ++u) {
+      if constexpr (LS % 4 != 0) b_row[u] = ldf(Bm, s * LS + u);
+      b_col[u] = ldf(Bm, u * LS + s);
     }
-    __syncthreads();
+    float tr = 0.f, tc = 0.f;
+#pragma unroll
+    for (int u = 0; u < LS; ++u) {
+      tr = fmaf(b_row[u], sv[m * LS + u], tr);  // t^r = B s^c
+      tc = fmaf(b_col[u], su[m * LS + u], tc);  // t^c = B^T s^r
+    }
+    ar[cnt] = tc;
+    ac[cnt] = tr;
+  }
+  __syncthreads();
+  cnt = 0;
+  for (int e = t; e < MH * LS; e += nt, ++cnt) {
+    su[e] = ar[cnt];  // t^c
+    sv[e] = ac[cnt];  // t^r
+  }
+  __syncthreads();
+  for (int e = t; e < K * LS; e += nt) {
+    int k = e / LS, s = e % LS;
+    float a = 0.f, c = 0.f;
+    for (int j = 0; j < J; ++j) {
+      int m = K - (K >> j) + (k >> (j + 1));
+      if (((k >> j) & 1) == 0) a += sv[m * LS + s];
+      else c += su[m * LS + s];
+    }
+    Tr[kb + e] = a;
+    Tc[kb + e] = c;
   }
 }
 
@@ -389,18 +406,27 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_apply_prolong(const FrameDesc*
 }
 
 // ------------------------------------------------------------------ PCG kernels
+//
+// Synchronisation is by kernel boundaries only: no kernel reads data that
+// another block of the same kernel writes.  Every block of a kernel reduces
+// the partials that the previous kernel wrote for its frame, in the same fixed
+// order, so all blocks of a frame reach bit-identical scalars and decisions;
+// the frame's first block (or the frame's single block) writes the frame
+// state.  State is double-buffered by iteration parity: an iteration at
+// parity par reads st[2f + par] in its first kernel and leaves its result in
+// st[2f + (par ^ 1)].
 
+enum { SLOT0 = 0 };
 
+__device__ inline bool is_replacement(const FrameState& s, const SolveParams& prm, int u) {
+  return s.force_rc || (prm.recompute_every > 0 && u % prm.recompute_every == 0);
+}
 
-enum { TK_SPMV = 0, TK_UPD = 1, TK_PRO = 2, TK_SETUP = 3 };
-
-// Stop decisions after the x / r update of iteration k (rr = ||r||^2).
-// Called by one thread; returns true when the frame stops.
-// A residual that passes the tolerance stops the frame only when it is a
-// true (replaced) residual; a recurrence residual that passes forces a
-// replacement on the next iteration instead.
-__device__ inline bool stop_checks(FrameState& s, const SolveParams& prm, int k, double rr, bool replaced) {
-  s.k = k;
+// Stop decisions after update u with ||r||^2 = rr.  A residual that passes the
+// tolerance stops the frame only when it is a true (replaced) residual; a
+// passing recurrence residual forces a replacement on the next update.
+__device__ inline bool stop_checks(FrameState& s, const SolveParams& prm, int u, double rr, bool replaced) {
+  s.it = u;
   s.rr = rr;
   s.force_rc = 0;
   if (rr <= s.target) {
@@ -411,34 +437,64 @@ __device__ inline bool stop_checks(FrameState& s, const SolveParams& prm, int k,
     s.force_rc = 1;
   }
   double rn = sqrt(rr);
-  if (prm.stagnation && k % 100 == 0) {
+  if (prm.stagnation && u % 100 == 0) {
     if (rn > 0.5 * s.rwin) {
       s.flags |= HP_STAGNATED;
       return true;
     }
     s.rwin = rn;
   }
-  if (k >= prm.max_iter) {
+  if (u >= prm.max_iter) {
     s.flags |= HP_MAXITER;
     return true;
   }
   return false;
 }
 
-__device__ inline void finish_frame(FrameState& s, int* n_active) {
-  s.done = 1;
-  atomicSub(n_active, 1);
-}
-
-// p = z + beta p_old; q = A p; partial p.q -> alpha in the last block.
-__global__ __launch_bounds__(NODE_BLOCK) void k_spmv_p(const FrameDesc* fr, const int* blk2f, PcgBufs B_,
+// First kernel of an iteration (node blocks): [Jacobi / identity: stop checks
+// of the previous update], positivity of rho' = r.z, beta = rho'/rho,
+// p = z + beta p_old at the 7 stencil points, q = A p, partials of p.q.
+template <bool SIMPLE>
+__global__ __launch_bounds__(NODE_BLOCK) void k_spmv_p(const FrameDesc* fr, const int* blk2f, PcgBufs B_, int par,
                                                        const float* pold, float* pnew) {
   __shared__ double red[NODE_BLOCK / 64];
   const int f = blk2f[blockIdx.x];
   const FrameDesc F = fr[f];
-  FrameState* st = B_.st + f;
-  if (st->done) return;
-  const float beta = (float)st->beta;
+  FrameState S = B_.st[2 * f + par];
+  FrameState* out = B_.st + 2 * f + (par ^ 1);
+  const bool lead = blockIdx.x == F.b0 && threadIdx.x == 0;
+  if (S.done) {
+    if (lead) *out = S;
+    return;
+  }
+  const SolveParams prm = *B_.prm;
+  if (SIMPLE && !S.fresh) {
+    const int u = S.it + 1;
+    const bool rep = is_replacement(S, prm, u);
+    const double rr = frame_sum(B_.part_rr + F.b0, F.nb, red);
+    if (stop_checks(S, prm, u, rr, rep)) {
+      if (lead) {
+        S.done = 1;
+        *out = S;
+        atomicSub(B_.n_active, 1);
+      }
+      return;
+    }
+  }
+  S.fresh = 0;
+  const double rz = SIMPLE ? frame_sum(B_.part_rz + F.b0, F.nb, red) : frame_sum(B_.part_rz + F.k0, F.K, red);
+  if (!(rz > 0.0) || !isfinite(rz)) {
+    if (lead) {
+      S.flags |= HP_NOT_SPD;
+      S.done = 1;
+      *out = S;
+      atomicSub(B_.n_active, 1);
+    }
+    return;
+  }
+  S.beta = rz / S.rho;
+  S.rho = rz;
+  const float beta = (float)S.beta;
   const float* z = B_.z;
   SysPtr s(B_.sys, B_.ntot);
   int c = (blockIdx.x - F.b0) * NODE_BLOCK + threadIdx.x;
@@ -453,17 +509,9 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_spmv_p(const FrameDesc* fr, cons
   }
   double bs = block_sum(pq, red);
   if (threadIdx.x == 0) B_.part_pq[blockIdx.x] = bs;
-  if (last_arrival(B_.ticket + 4 * f + TK_SPMV, F.nb)) {
-    if (threadIdx.x == 0) {
-      double tot = 0.0;
-      for (int j = 0; j < F.nb; ++j) tot += vload(B_.part_pq + F.b0 + j);
-      st->alpha = st->rho / tot;
-    }
-  }
+  if (lead) *out = S;
 }
 
-// Shared per-leaf x / r update.  Writes x_new, r; fills rs (LDS); returns the
-// thread's share of ||r||^2.
 // x accumulates in FP64 (x += alpha p with alpha in FP64); r, p, q are FP32.
 template <int L>
 __device__ inline double xr_update(const FrameDesc& F, int64_t row0, const PcgBufs& B_, const double* xold,
@@ -488,56 +536,86 @@ __device__ inline double xr_update(const FrameDesc& F, int64_t row0, const PcgBu
   return rr;
 }
 
+// Second kernel (leaf blocks): alpha = rho / p.q, x and r update (or FP64
+// residual replacement), leaf stage of z = M r, partials of ||r||^2.
 template <int L, int LS, typename FT>
 __global__ __launch_bounds__(LEAF_THREADS) void k_update_hmat(const FrameDesc* fr, const int* leaf2f, PcgBufs B_,
-                                                              Factors<FT> fac, const double* xold, double* xnew,
-                                                              const float* p) {
-  extern __shared__ float lds[];
+                                                              Factors<FT> fac, int par, const double* xold,
+                                                              double* xnew, const float* p) {
   __shared__ float rs[L];
   __shared__ float red[(LEAF_THREADS / 64) * 2 * LS];
   __shared__ double dred[LEAF_THREADS / 64];
-  __shared__ int stop;
   const int64_t kg = blockIdx.x;
   const int f = leaf2f[kg];
   const FrameDesc F = fr[f];
-  FrameState* st = B_.st + f;
-  if (st->done) return;
+  const FrameState S = B_.st[2 * f + (par ^ 1)];
+  if (S.done) return;
   const SolveParams prm = *B_.prm;
   const int64_t row0 = F.n0 + (kg - F.k0) * L;
-  const double alpha = st->alpha;
-  const int knext = st->k + 1;
-  const bool recompute = st->force_rc || (prm.recompute_every > 0 && knext % prm.recompute_every == 0);
-  double rr = xr_update<L>(F, row0, B_, xold, xnew, p, alpha, recompute, rs);
+  const bool rep = is_replacement(S, prm, S.it + 1);
+  const double alpha = S.rho / frame_sum(B_.part_pq + F.b0, F.nb, dred);
+  double rr = xr_update<L>(F, row0, B_, xold, xnew, p, alpha, rep, rs);
   __syncthreads();
   leaf_stage<L, LS, FT>(kg, row0, rs, fac, B_.sys + 4 * B_.ntot, B_.z, B_.uh, B_.vh, red);
   double bs = block_sum(rr, dred);
   if (threadIdx.x == 0) B_.part_rr[kg] = bs;
-  if (last_arrival(B_.ticket + 4 * f + TK_UPD, F.K)) {
-    if (threadIdx.x == 0) {
-      double tot = 0.0;
-      for (int j = 0; j < F.K; ++j) tot += vload(B_.part_rr + F.k0 + j);
-      stop = stop_checks(*st, prm, knext, tot, recompute);
-      if (stop) finish_frame(*st, B_.n_active);
-    }
-    __syncthreads();
-    if (!stop) {
-      __threadfence();
-      coarse_stage<LS, FT>(F, B_.uh, B_.vh, fac.B, B_.Tr, B_.Tc, lds);
-    }
-  }
 }
 
-// z += Ut T^r + Vt T^c; partial r.z -> positivity, beta in the last block.
+// Frame kernel (one block per frame): stop checks (or, at setup, ||b||, the
+// target and the check of r0) and, for the learned preconditioner, the coarse
+// stage.  Partials are per leaf (HMAT) or per node block (Jacobi / identity).
+template <int LS, typename FT, bool HMAT>
+__global__ __launch_bounds__(LEAF_THREADS) void k_frame_check(const FrameDesc* fr, PcgBufs B_, Factors<FT> fac,
+                                                              int slot, int setup) {
+  extern __shared__ float lds[];
+  __shared__ double dred[LEAF_THREADS / 64];
+  const int f = blockIdx.x;
+  const FrameDesc F = fr[f];
+  FrameState* sp = B_.st + 2 * f + slot;
+  FrameState S = *sp;
+  if (S.done) return;
+  const SolveParams prm = *B_.prm;
+  const double* prr = B_.part_rr + (HMAT ? F.k0 : F.b0);
+  const double* pbb = B_.part_pq + (HMAT ? F.k0 : F.b0);
+  const int np = HMAT ? F.K : F.nb;
+  const double rr = frame_sum(prr, np, dred);
+  bool stop;
+  if (setup) {
+    const double bb = frame_sum(pbb, np, dred);
+    S.bnorm = sqrt(bb);
+    S.target = (prm.tol * S.bnorm) * (prm.tol * S.bnorm);
+    S.rr = rr;
+    S.rwin = sqrt(rr);
+    S.it = 0;
+    S.fresh = 1;
+    stop = true;
+    if (rr <= S.target) S.flags |= HP_CONVERGED;
+    else if (prm.max_iter <= 0) S.flags |= HP_MAXITER;
+    else stop = false;
+  } else {
+    const int u = S.it + 1;
+    stop = stop_checks(S, prm, u, rr, is_replacement(S, prm, u));
+  }
+  if (threadIdx.x == 0) {
+    if (stop) {
+      S.done = 1;
+      atomicSub(B_.n_active, 1);
+    }
+    *sp = S;
+  }
+  if (HMAT && !stop) coarse_stage<LS, FT>(F, B_.uh, B_.vh, fac.B, B_.Tr, B_.Tc, lds);
+}
+
+// Last kernel (leaf blocks): z += Ut T^r + Vt T^c, partials of r.z.
 template <int L, int LS, typename FT>
 __global__ __launch_bounds__(LEAF_THREADS) void k_prolong(const FrameDesc* fr, const int* leaf2f, PcgBufs B_,
-                                                          Factors<FT> fac, int setup) {
+                                                          Factors<FT> fac, int slot) {
   __shared__ float trs[LS], tcs[LS];
   __shared__ double dred[LEAF_THREADS / 64];
   const int64_t kg = blockIdx.x;
   const int f = leaf2f[kg];
   const FrameDesc F = fr[f];
-  FrameState* st = B_.st + f;
-  if (st->done) return;
+  if (B_.st[2 * f + slot].done) return;
   const int64_t row0 = F.n0 + (kg - F.k0) * L;
   if (threadIdx.x < LS) {
     trs[threadIdx.x] = B_.Tr[kg * LS + threadIdx.x];
@@ -556,36 +634,20 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_prolong(const FrameDesc* fr, c
   }
   double bs = block_sum(rz, dred);
   if (threadIdx.x == 0) B_.part_rz[kg] = bs;
-  if (last_arrival(B_.ticket + 4 * f + TK_PRO, F.K)) {
-    if (threadIdx.x == 0) {
-      double tot = 0.0;
-      for (int j = 0; j < F.K; ++j) tot += vload(B_.part_rz + F.k0 + j);
-      if (!(tot > 0.0) || !isfinite(tot)) {
-        st->flags |= HP_NOT_SPD;
-        finish_frame(*st, B_.n_active);
-      } else {
-        st->beta = setup ? 0.0 : tot / st->rho;
-        st->rho = tot;
-      }
-    }
-  }
 }
 
-// Setup for the learned preconditioner: r = b - A x0 (FP64), ||b||, ||r||,
-// the leaf stage of z = M r and, in the last block, the coarse stage.  p0 = 0.
+// Setup for the learned preconditioner (leaf blocks): r = b - A x0 in FP64,
+// p0 = 0, the leaf stage of z = M r, partials of ||r||^2 and ||b||^2.
 template <int L, int LS, typename FT>
 __global__ __launch_bounds__(LEAF_THREADS) void k_setup_hmat(const FrameDesc* fr, const int* leaf2f, PcgBufs B_,
                                                              Factors<FT> fac) {
-  extern __shared__ float lds[];
   __shared__ float rs[L];
   __shared__ float red[(LEAF_THREADS / 64) * 2 * LS];
   __shared__ double dred[LEAF_THREADS / 64];
-  __shared__ int stop;
   const int64_t kg = blockIdx.x;
   const int f = leaf2f[kg];
   const FrameDesc F = fr[f];
-  FrameState* st = B_.st + f;
-  if (st->done) return;
+  if (B_.st[2 * f].done) return;
   const int64_t row0 = F.n0 + (kg - F.k0) * L;
   SysPtr s(B_.sys, B_.ntot);
   double rr = 0.0, bb = 0.0;
@@ -604,43 +666,18 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_setup_hmat(const FrameDesc* fr
   double bsum = block_sum(bb, dred);
   if (threadIdx.x == 0) {
     B_.part_rr[kg] = rsum;
-    B_.part_rz[kg] = bsum;
-  }
-  if (last_arrival(B_.ticket + 4 * f + TK_SETUP, F.K)) {
-    if (threadIdx.x == 0) {
-      double rt = 0.0, bt = 0.0;
-      for (int j = 0; j < F.K; ++j) {
-        rt += vload(B_.part_rr + F.k0 + j);
-        bt += vload(B_.part_rz + F.k0 + j);
-      }
-      const SolveParams prm = *B_.prm;
-      st->bnorm = sqrt(bt);
-      st->target = (prm.tol * st->bnorm) * (prm.tol * st->bnorm);
-      st->rr = rt;
-      st->rwin = sqrt(rt);
-      st->k = 0;
-      stop = rt <= st->target;
-      if (stop) {
-        st->flags |= HP_CONVERGED;
-        finish_frame(*st, B_.n_active);
-      }
-    }
-    __syncthreads();
-    if (!stop) {
-      __threadfence();
-      coarse_stage<LS, FT>(F, B_.uh, B_.vh, fac.B, B_.Tr, B_.Tc, lds);
-    }
+    B_.part_pq[kg] = bsum;
   }
 }
 
-// Jacobi / identity: setup over node blocks.
+// Setup for Jacobi / identity (node blocks): r = b - A x0, z, p0 = 0 and the
+// partials of ||r||^2, r.z and ||b||^2.
 template <bool JAC>
 __global__ __launch_bounds__(NODE_BLOCK) void k_setup_simple(const FrameDesc* fr, const int* blk2f, PcgBufs B_) {
   __shared__ double red[NODE_BLOCK / 64];
   const int f = blk2f[blockIdx.x];
   const FrameDesc F = fr[f];
-  FrameState* st = B_.st + f;
-  if (st->done) return;
+  if (B_.st[2 * f].done) return;
   SysPtr s(B_.sys, B_.ntot);
   int c = (blockIdx.x - F.b0) * NODE_BLOCK + threadIdx.x;
   double rr = 0.0, bb = 0.0, rz = 0.0;
@@ -661,48 +698,23 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_setup_simple(const FrameDesc* fr
     B_.part_rz[blockIdx.x] = cz;
     B_.part_pq[blockIdx.x] = b;
   }
-  if (last_arrival(B_.ticket + 4 * f + TK_SETUP, F.nb)) {
-    if (threadIdx.x == 0) {
-      double rt = 0.0, bt = 0.0, zt = 0.0;
-      for (int j = 0; j < F.nb; ++j) {
-        rt += vload(B_.part_rr + F.b0 + j);
-        zt += vload(B_.part_rz + F.b0 + j);
-        bt += vload(B_.part_pq + F.b0 + j);
-      }
-      const SolveParams prm = *B_.prm;
-      st->bnorm = sqrt(bt);
-      st->target = (prm.tol * st->bnorm) * (prm.tol * st->bnorm);
-      st->rr = rt;
-      st->rwin = sqrt(rt);
-      st->k = 0;
-      if (rt <= st->target) {
-        st->flags |= HP_CONVERGED;
-        finish_frame(*st, B_.n_active);
-      } else if (!(zt > 0.0) || !isfinite(zt)) {
-        st->flags |= HP_NOT_SPD;
-        finish_frame(*st, B_.n_active);
-      } else {
-        st->rho = zt;
-        st->beta = 0.0;
-      }
-    }
-  }
 }
 
-// Jacobi / identity iteration update over node blocks: x, r, z, ||r||^2, r.z.
+// Second kernel for Jacobi / identity (node blocks): alpha, x, r (or FP64
+// replacement), z = D^-1 r or r, partials of ||r||^2 and r.z.
 template <bool JAC>
 __global__ __launch_bounds__(NODE_BLOCK) void k_update_simple(const FrameDesc* fr, const int* blk2f, PcgBufs B_,
-                                                              const double* xold, double* xnew, const float* p) {
+                                                              int par, const double* xold, double* xnew,
+                                                              const float* p) {
   __shared__ double red[NODE_BLOCK / 64];
   const int f = blk2f[blockIdx.x];
   const FrameDesc F = fr[f];
-  FrameState* st = B_.st + f;
-  if (st->done) return;
+  const FrameState S = B_.st[2 * f + (par ^ 1)];
+  if (S.done) return;
   const SolveParams prm = *B_.prm;
-  const double alpha = st->alpha;
+  const bool rep = is_replacement(S, prm, S.it + 1);
+  const double alpha = S.rho / frame_sum(B_.part_pq + F.b0, F.nb, red);
   const float af = (float)alpha;
-  const int knext = st->k + 1;
-  const bool recompute = st->force_rc || (prm.recompute_every > 0 && knext % prm.recompute_every == 0);
   SysPtr s(B_.sys, B_.ntot);
   int c = (blockIdx.x - F.b0) * NODE_BLOCK + threadIdx.x;
   double rr = 0.0, rz = 0.0;
@@ -710,7 +722,7 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_update_simple(const FrameDesc* f
     int64_t i = F.n0 + c;
     xnew[i] = fma(alpha, (double)p[i], xold[i]);
     float ri;
-    if (recompute)
+    if (rep)
       ri = (float)resid_f64(s, F, c, (double)B_.b[i], [&](int64_t j) { return fma(alpha, (double)p[j], xold[j]); });
     else
       ri = fmaf(-af, B_.q[i], B_.r[i]);
@@ -725,32 +737,15 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_update_simple(const FrameDesc* f
     B_.part_rr[blockIdx.x] = a;
     B_.part_rz[blockIdx.x] = cz;
   }
-  if (last_arrival(B_.ticket + 4 * f + TK_UPD, F.nb)) {
-    if (threadIdx.x == 0) {
-      double rt = 0.0, zt = 0.0;
-      for (int j = 0; j < F.nb; ++j) {
-        rt += vload(B_.part_rr + F.b0 + j);
-        zt += vload(B_.part_rz + F.b0 + j);
-      }
-      if (stop_checks(*st, prm, knext, rt, recompute)) {
-        finish_frame(*st, B_.n_active);
-      } else if (!(zt > 0.0) || !isfinite(zt)) {
-        st->flags |= HP_NOT_SPD;
-        finish_frame(*st, B_.n_active);
-      } else {
-        st->beta = zt / st->rho;
-        st->rho = zt;
-      }
-    }
-  }
 }
 
-// After a pass: frames that ended on an odd iteration hold x in x1.
+// After a pass: a frame that did an odd number of updates holds x in x1.
 __global__ void k_finalize_x(const FrameDesc* fr, const int* blk2f, const FrameState* st, const double* x1,
                              double* x0) {
   const int f = blk2f[blockIdx.x];
   const FrameDesc F = fr[f];
-  if (!st[f].active || (st[f].k & 1) == 0) return;
+  const FrameState S = st[2 * f];
+  if (!S.active || (S.it & 1) == 0) return;
   int c = (blockIdx.x - F.b0) * NODE_BLOCK + threadIdx.x;
   if (c < F.n) x0[F.n0 + c] = x1[F.n0 + c];
 }
@@ -759,7 +754,7 @@ __global__ void k_finalize_x(const FrameDesc* fr, const int* blk2f, const FrameS
 
 
 
-static size_t coarse_lds_bytes(int kmax, int ls) { return (size_t)(5 * kmax * ls / 2 + ls) * sizeof(float); }
+static size_t coarse_lds_bytes(int kmax, int ls) { return (size_t)(2 * kmax * ls + ls) * sizeof(float); }
 
 hp_status launch_assemble(const LaunchGeom& g, const float* rho, float* sys) {
   hipLaunchKernelGGL(k_assemble, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, rho, sys, g.ntot);
@@ -815,25 +810,30 @@ template <int L, int LS, typename FT>
 static void hmat_setup(const PcgLaunch& P) {
   auto fac = make_factors<L, LS, FT>(P);
   const LaunchGeom& g = P.g;
-  hipLaunchKernelGGL((k_setup_hmat<L, LS, FT>), dim3(g.ktot), dim3(LEAF_THREADS), coarse_lds_bytes(g.kmax, LS),
-                     g.stream, g.fr, g.leaf2f, P.B, fac);
+  hipLaunchKernelGGL((k_setup_hmat<L, LS, FT>), dim3(g.ktot), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.leaf2f, P.B,
+                     fac);
+  hipLaunchKernelGGL((k_frame_check<LS, FT, true>), dim3(g.nframes), dim3(LEAF_THREADS), coarse_lds_bytes(g.kmax, LS),
+                     g.stream, g.fr, P.B, fac, SLOT0, 1);
   hipLaunchKernelGGL((k_prolong<L, LS, FT>), dim3(g.ktot), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.leaf2f, P.B, fac,
-                     1);
+                     SLOT0);
 }
 
 template <int L, int LS, typename FT>
-static void hmat_iter(const PcgLaunch& P, int parity) {
+static void hmat_iter(const PcgLaunch& P, int par) {
   auto fac = make_factors<L, LS, FT>(P);
   const LaunchGeom& g = P.g;
-  const float* pold = parity ? P.B.p1 : P.B.p0;
-  float* pnew = parity ? P.B.p0 : P.B.p1;
-  const double* xold = parity ? P.B.x1 : P.B.x0;
-  double* xnew = parity ? P.B.x0 : P.B.x1;
-  hipLaunchKernelGGL(k_spmv_p, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B, pold, pnew);
-  hipLaunchKernelGGL((k_update_hmat<L, LS, FT>), dim3(g.ktot), dim3(LEAF_THREADS), coarse_lds_bytes(g.kmax, LS),
-                     g.stream, g.fr, g.leaf2f, P.B, fac, xold, xnew, (const float*)pnew);
+  const float* pold = par ? P.B.p1 : P.B.p0;
+  float* pnew = par ? P.B.p0 : P.B.p1;
+  const double* xold = par ? P.B.x1 : P.B.x0;
+  double* xnew = par ? P.B.x0 : P.B.x1;
+  hipLaunchKernelGGL(k_spmv_p<false>, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B, par, pold,
+                     pnew);
+  hipLaunchKernelGGL((k_update_hmat<L, LS, FT>), dim3(g.ktot), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.leaf2f, P.B,
+                     fac, par, xold, xnew, (const float*)pnew);
+  hipLaunchKernelGGL((k_frame_check<LS, FT, true>), dim3(g.nframes), dim3(LEAF_THREADS), coarse_lds_bytes(g.kmax, LS),
+                     g.stream, g.fr, P.B, fac, par ^ 1, 0);
   hipLaunchKernelGGL((k_prolong<L, LS, FT>), dim3(g.ktot), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.leaf2f, P.B, fac,
-                     0);
+                     par ^ 1);
 }
 
 hp_status pcg_setup(const PcgLaunch& P) {
@@ -848,16 +848,20 @@ hp_status pcg_setup(const PcgLaunch& P) {
     } else {
       return set_error(HP_E_SHAPE, "pcg: unsupported (L, L_s) = (%d, %d)", P.L, P.LS);
     }
-  } else if (P.mode == HP_PRECOND_JACOBI) {
-    hipLaunchKernelGGL(k_setup_simple<true>, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B);
   } else {
-    hipLaunchKernelGGL(k_setup_simple<false>, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B);
+    if (P.mode == HP_PRECOND_JACOBI)
+      hipLaunchKernelGGL(k_setup_simple<true>, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B);
+    else
+      hipLaunchKernelGGL(k_setup_simple<false>, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B);
+    Factors<float> none{};
+    hipLaunchKernelGGL((k_frame_check<16, float, false>), dim3(g.nframes), dim3(LEAF_THREADS), 0, g.stream, g.fr, P.B,
+                       none, SLOT0, 1);
   }
   HP_HIP(hipGetLastError());
   return HP_OK;
 }
 
-// Enqueue `count` iterations (count even) starting at parity 0.
+// Enqueue `count` iterations (count even), the first at parity 0.
 hp_status pcg_iterations(const PcgLaunch& P, int count) {
   const LaunchGeom& g = P.g;
   for (int it = 0; it < count; ++it) {
@@ -877,13 +881,14 @@ hp_status pcg_iterations(const PcgLaunch& P, int count) {
       float* pnew = par ? P.B.p0 : P.B.p1;
       const double* xold = par ? P.B.x1 : P.B.x0;
       double* xnew = par ? P.B.x0 : P.B.x1;
-      hipLaunchKernelGGL(k_spmv_p, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B, pold, pnew);
+      hipLaunchKernelGGL(k_spmv_p<true>, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B, par, pold,
+                         pnew);
       if (P.mode == HP_PRECOND_JACOBI)
         hipLaunchKernelGGL(k_update_simple<true>, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B,
-                           xold, xnew, (const float*)pnew);
+                           par, xold, xnew, (const float*)pnew);
       else
-        hipLaunchKernelGGL(k_update_simple<false>, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f,
-                           P.B, xold, xnew, (const float*)pnew);
+        hipLaunchKernelGGL(k_update_simple<false>, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B,
+                           par, xold, xnew, (const float*)pnew);
     }
   }
   HP_HIP(hipGetLastError());
