@@ -216,6 +216,19 @@ hp_status hp_weight_info(const hp_model_config* cfg, int32_t index, char* name, 
 hp_status hp_infer_factors(hp_batch b, const float* d_weights, const float* d_rho,
                            const float* d_sys, void* d_factors, int32_t compute);
 
+/* ------------------------------------------------------------------ diagnostics */
+
+/* Copy `bytes` of a named internal buffer of the last hp_infer_factors call
+ * into d_dst (device, caller-owned), on the batch's stream.  Names: "feats"
+ * [ntot][32] encoder input (compute type), "glob" [nframes][12] FP32 frame
+ * summaries, "enc" [ntot][d] FP32 encoder output, "xo0" [mtot L_s][d] FP32
+ * pooled off-diagonal tokens, "xd" / "xo" [..][d] FP32 residual streams after
+ * the last layer, "desc" [mtot][L_s][L_s][4] FP32 off-diagonal pair
+ * descriptors, "frows" [ntot][L] FP32 leaf-head rows (F), "nodeh" [ntot][36]
+ * FP32 node heads (Ut | Vt | lam logit), "uv" [mtot L_s][2 L_s] FP32 (U | V).
+ * For tests; HP_E_INVALID on an unknown name or a size beyond the buffer. */
+hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, int64_t bytes);
+
 #ifdef __cplusplus
 }
 #endif

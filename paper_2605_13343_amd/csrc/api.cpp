@@ -28,6 +28,7 @@ void factor_offsets(const Batch& b, int dtype, int64_t offs[5], int64_t* total) 
 }
 
 Batch::~Batch() {
+  if (net_free && net.ws) net_free(net.ws);
   for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
   for (void* p : allocs) hipFree(p);
   if (h_pin) hipHostFree(h_pin);
@@ -106,6 +107,8 @@ extern "C" hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes
     F.m0 = (int)m0;
     F.J = pi.J;
     F.nz = nz;
+    F.nx = nx;
+    F.ny = ny;
     morton_masks(nx, ny, nz, &F.xm, &F.ym, &F.zm);
     F.nb = (n + NODE_BLOCK - 1) / NODE_BLOCK;
     F.b0 = nb0;

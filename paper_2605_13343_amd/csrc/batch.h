@@ -78,6 +78,7 @@ struct Batch {
   FrameState* st = nullptr;
   SolveParams* prm = nullptr;
   NetWork net;
+  void (*net_free)(void*) = nullptr;  // releases net.ws
   std::map<std::tuple<int, int, const void*, const void*, const void*, const void*, int>, hipGraphExec_t> graphs;
   std::vector<void*> allocs;
 

@@ -38,7 +38,7 @@ struct FrameDesc {
   int nz;           // grid height (top layer z = nz-1)
   unsigned xm, ym, zm;  // Morton bit masks of x, y, z within the code
   int nb, b0;       // node blocks (of NODE_BLOCK rows) and first node block
-  int pad;
+  int nx, ny;       // grid width and depth
 };
 
 constexpr int NODE_BLOCK = 256;   // rows per node block

@@ -1,17 +1,1043 @@
-// Network forward (filled in below the solver path).
+// Network forward of the hierarchical transformer preconditioner (paper
+// Sec. 4.1-4.4 and Supplementary "Network Architecture Details"), every
+// frame of a batch at once.
+//
+// Layout: diagonal-stream tokens are the batch's rows (Nd = ntot); off-
+// diagonal tokens are (tile, t) pairs (No = mtot * L_s).  The residual streams
+// stay FP32; GEMM inputs are BF16 (compute = HP_BF16, MFMA 32x32x16 with FP32
+// accumulation) or FP32 (compute = HP_F32, MFMA 32x32x2 in FP32).
+#include <math.h>
+#include <string.h>
+
 #include "batch.h"
 
 namespace hp {
 
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+__device__ inline float gelu_f(float x) { return 0.5f * x * (1.f + erff(x * 0.7071067811865476f)); }
+__device__ inline float softplus_f(float x) { return fmaxf(x, 0.f) + log1pf(expf(-fabsf(x))); }
+
+template <typename AT> __device__ inline AT to_act(float v);
+template <> __device__ inline float to_act<float>(float v) { return v; }
+template <> __device__ inline uint16_t to_act<uint16_t>(float v) { return f32_to_bf16(v); }
+
+__device__ inline float wave_sum_f(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------ GEMM
+// Y[M, N] = act(X[M, K] W + b) (+ resid), with W given transposed as
+// Wt[N][K] (K contiguous, K % 32 == 0).  64 x 64 block tile, four waves of
+// 32 x 32, K staged through LDS in steps of 32.
+struct GemmArgs {
+  const void* X;
+  int64_t ldx;
+  const void* Wt;
+  int K;
+  const float* bias;
+  const float* resid;
+  int64_t ldr;
+  float* Yf;
+  int64_t ldf;
+  void* Yb;
+  int64_t ldb;
+  int M, N, act;
+};
+
+template <typename AT>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
+  constexpr int BM = 64, BN = 64, BK = 32;
+  constexpr int PAD = sizeof(AT) == 2 ? 8 : 4;
+  __shared__ __attribute__((aligned(16))) AT sA[BM][BK + PAD];
+  __shared__ __attribute__((aligned(16))) AT sB[BN][BK + PAD];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const AT* X = (const AT*)a.X;
+  const AT* W = (const AT*)a.Wt;
+  f32x16_t acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  for (int k0 = 0; k0 < a.K; k0 += BK) {
+    if constexpr (sizeof(AT) == 2) {
+      const int r = tid >> 2, c = (tid & 3) * 8;
+      uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
+      if (m0 + r < a.M) va = *(const uint4*)(X + (int64_t)(m0 + r) * a.ldx + k0 + c);
+      if (n0 + r < a.N) vb = *(const uint4*)(W + (int64_t)(n0 + r) * a.K + k0 + c);
+      *(uint4*)&sA[r][c] = va;
+      *(uint4*)&sB[r][c] = vb;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int idx = tid + q * 256, r = idx >> 3, c = (idx & 7) * 4;
+        float4 va = make_float4(0, 0, 0, 0), vb = make_float4(0, 0, 0, 0);
+        if (m0 + r < a.M) va = *(const float4*)(X + (int64_t)(m0 + r) * a.ldx + k0 + c);
+        if (n0 + r < a.N) vb = *(const float4*)(W + (int64_t)(n0 + r) * a.K + k0 + c);
+        *(float4*)&sA[r][c] = va;
+        *(float4*)&sB[r][c] = vb;
+      }
+    }
+    __syncthreads();
+    if constexpr (sizeof(AT) == 2) {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 16) {
+        bf16x8_t av = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sA[wm + (lane & 31)][kk + (lane >> 5) * 8]);
+        bf16x8_t bv = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sB[wn + (lane & 31)][kk + (lane >> 5) * 8]);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 2) {
+        float av = sA[wm + (lane & 31)][kk + (lane >> 5)];
+        float bv = sB[wn + (lane & 31)][kk + (lane >> 5)];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  const int col = n0 + wn + (lane & 31);
+  if (col >= a.N) return;
+  const float bc = a.bias ? a.bias[col] : 0.f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = m0 + wm + i * 8 + (lane >> 5) * 4 + j;
+      if (row >= a.M) continue;
+      float v = acc[i * 4 + j] + bc;
+      if (a.act == 1) v = gelu_f(v);
+      if (a.resid) v += a.resid[(int64_t)row * a.ldr + col];
+      if (a.Yf) a.Yf[(int64_t)row * a.ldf + col] = v;
+      if (a.Yb) ((AT*)a.Yb)[(int64_t)row * a.ldb + col] = to_act<AT>(v);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ LayerNorm
+// One wave per row of C = 128 (eps 1e-5), FP32 in, activation type out.
+template <typename AT>
+__global__ __launch_bounds__(256) void k_layernorm128(const float* X, const float* g, const float* b, AT* Y, int M) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= M) return;
+  const float* x = X + (int64_t)row * 128;
+  float v0 = x[lane], v1 = x[lane + 64];
+  const float mu = wave_sum_f(v0 + v1) * (1.f / 128.f);
+  const float d0 = v0 - mu, d1 = v1 - mu;
+  const float var = wave_sum_f(d0 * d0 + d1 * d1) * (1.f / 128.f);
+  const float rs = rsqrtf(var + 1e-5f);
+  Y[(int64_t)row * 128 + lane] = to_act<AT>(d0 * rs * g[lane] + b[lane]);
+  Y[(int64_t)row * 128 + lane + 64] = to_act<AT>(d1 * rs * g[lane + 64] + b[lane + 64]);
+}
+
+// LayerNorm over the 4d concat [x | a | c | g] (Sec. 4.3: each token joins its
+// row, column and global highway context before the FFN).  Segment s of row
+// r is read from S_s + r * ld_s (s < 3) or from G + frame * 128; with has_ctx
+// = 0 the three context segments are zero.
+template <typename AT>
+__global__ __launch_bounds__(256) void k_ln_concat(const float* S0, int64_t ld0, const float* S1, int64_t ld1,
+                                                   const float* S2, int64_t ld2, const float* G, const int* row2f,
+                                                   const float* gam, const float* bet, AT* Y, int M, int has_ctx) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= M) return;
+  const int seg = lane >> 4, c0 = (lane & 15) * 8;
+  float v[8];
+  const float* src = nullptr;
+  if (seg == 0) src = S0 + (int64_t)row * ld0;
+  else if (has_ctx) {
+    if (seg == 1) src = S1 + (int64_t)row * ld1;
+    else if (seg == 2) src = S2 + (int64_t)row * ld2;
+    else src = G + (int64_t)row2f[row] * 128;
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = src ? src[c0 + i] : 0.f;
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) s += v[i];
+  const float mu = wave_sum_f(s) * (1.f / 512.f);
+  float q = 0.f;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) q += (v[i] - mu) * (v[i] - mu);
+  const float rs = rsqrtf(wave_sum_f(q) * (1.f / 512.f) + 1e-5f);
+  AT* y = Y + (int64_t)row * 512 + seg * 128 + c0;
+  const int gc = seg * 128 + c0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) y[i] = to_act<AT>((v[i] - mu) * rs * gam[gc + i] + bet[gc + i]);
+}
+
+// ------------------------------------------------------------------ features
+// Per-frame summary (one block per frame), this build's definition of the
+// 12 global features: log2(N)/16, log(rho_max/rho_min), mean and std of
+// log rho, heavy fraction, mean/std/min/max of log A_ii, nx/32, ny/32, nz/32.
+__global__ __launch_bounds__(256) void k_frame_stats(const FrameDesc* fr, const float* rho, const float* sys,
+                                                     int64_t ntot, float* glob) {
+  __shared__ double red[4][8];
+  const FrameDesc F = fr[blockIdx.x];
+  const double* dg8 = reinterpret_cast<const double*>(sys + 5 * ntot);
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  auto bsum = [&](double v) -> double {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if (lane == 0) red[w][0] = v;
+    __syncthreads();
+    return red[0][0] + red[1][0] + red[2][0] + red[3][0];
+  };
+  auto bmin = [&](double v, bool mx) -> double {
+    for (int o = 32; o > 0; o >>= 1) {
+      double u = __shfl_xor(v, o, 64);
+      v = mx ? fmax(v, u) : fmin(v, u);
+    }
+    __syncthreads();
+    if (lane == 0) red[w][1] = v;
+    __syncthreads();
+    double r = red[0][1];
+    for (int i = 1; i < 4; ++i) r = mx ? fmax(r, red[i][1]) : fmin(r, red[i][1]);
+    return r;
+  };
+  double sr = 0, sa = 0, mnr = 1e300, mxr = -1e300, mna = 1e300, mxa = -1e300;
+  for (int c = t; c < F.n; c += 256) {
+    double lr = log((double)rho[F.n0 + c]), la = log(dg8[F.n0 + c]);
+    sr += lr;
+    sa += la;
+    mnr = fmin(mnr, lr);
+    mxr = fmax(mxr, lr);
+    mna = fmin(mna, la);
+    mxa = fmax(mxa, la);
+  }
+  const double n = F.n;
+  const double mr = bsum(sr) / n, ma = bsum(sa) / n;
+  const double lmin = bmin(mnr, false), lmax = bmin(mxr, true);
+  const double amin = bmin(mna, false), amax = bmin(mxa, true);
+  double vr = 0, va = 0, hv = 0;
+  const double mid = 0.5 * (lmin + lmax);
+  for (int c = t; c < F.n; c += 256) {
+    double lr = log((double)rho[F.n0 + c]), la = log(dg8[F.n0 + c]);
+    vr += (lr - mr) * (lr - mr);
+    va += (la - ma) * (la - ma);
+    hv += lr > mid ? 1.0 : 0.0;
+  }
+  const double sdr = sqrt(bsum(vr) / n), sda = sqrt(bsum(va) / n), heavy = lmax > lmin ? bsum(hv) / n : 0.0;
+  if (t == 0) {
+    float* g = glob + blockIdx.x * 12;
+    g[0] = (float)(log2(n) / 16.0);
+    g[1] = (float)(lmax - lmin);
+    g[2] = (float)mr;
+    g[3] = (float)sdr;
+    g[4] = (float)heavy;
+    g[5] = (float)ma;
+    g[6] = (float)sda;
+    g[7] = (float)amin;
+    g[8] = (float)amax;
+    g[9] = F.nx / 32.f;
+    g[10] = F.ny / 32.f;
+    g[11] = F.nz / 32.f;
+  }
+}
+
+// Node features (8) + the frame summary (12), zero padded to 32 columns.
+template <typename AT>
+__global__ void k_features(const FrameDesc* fr, const int* blk2f, const float* rho, const float* sys, int64_t ntot,
+                           const float* glob, AT* out) {
+  const int f = blk2f[blockIdx.x];
+  const FrameDesc F = fr[f];
+  const int c = (blockIdx.x - F.b0) * NODE_BLOCK + threadIdx.x;
+  if (c >= F.n) return;
+  const int64_t i = F.n0 + c;
+  const double* dg8 = reinterpret_cast<const double*>(sys + 5 * ntot);
+  const int x = mcoord(c, F.xm), y = mcoord(c, F.ym), z = mcoord(c, F.zm);
+  float v[32];
+  v[0] = (float)log((double)rho[i]);
+  v[1] = (x + 0.5f) / F.nx;
+  v[2] = (y + 0.5f) / F.ny;
+  v[3] = (z + 0.5f) / F.nz;
+  v[4] = z == F.nz - 1 ? 1.f : 0.f;
+  v[5] = (x == 0 || x == F.nx - 1 || y == 0 || y == F.ny - 1) ? 1.f : 0.f;
+  v[6] = z == 0 ? 1.f : 0.f;
+  v[7] = (float)log(dg8[i]);
+  for (int j = 0; j < 12; ++j) v[8 + j] = glob[f * 12 + j];
+  for (int j = 20; j < 32; ++j) v[j] = 0.f;
+  for (int j = 0; j < 32; ++j) out[i * 32 + j] = to_act<AT>(v[j]);
+}
+
+// ------------------------------------------------------------------ encoder GCN
+// Y = D^-1 A H: y_i = h_i - sum_j (w_ij / A_ii) h_j over the 6 faces.
+// Two rows per block of 256 threads (one thread per feature).
+template <typename AT>
+__global__ __launch_bounds__(256) void k_gcn_spmm(const FrameDesc* fr, const int* node2f, const float* sys,
+                                                  int64_t ntot, const float* H, AT* Y) {
+  const int64_t i = (int64_t)blockIdx.x * 2 + (threadIdx.x >> 7);
+  if (i >= ntot) return;
+  const int col = threadIdx.x & 127;
+  const FrameDesc F = fr[node2f[i]];
+  const unsigned c = (unsigned)(i - F.n0);
+  const float *dg = sys, *wx = sys + ntot, *wy = sys + 2 * ntot, *wz = sys + 3 * ntot;
+  const float id = 1.f / dg[i];
+  const int64_t xp = F.n0 + mstep_plus(c, F.xm), xn = F.n0 + mstep_minus(c, F.xm);
+  const int64_t yp = F.n0 + mstep_plus(c, F.ym), yn = F.n0 + mstep_minus(c, F.ym);
+  const int64_t zp = F.n0 + mstep_plus(c, F.zm), zn = F.n0 + mstep_minus(c, F.zm);
+  float s = wx[i] * H[xp * 128 + col];
+  s = fmaf(wx[xn], H[xn * 128 + col], s);
+  s = fmaf(wy[i], H[yp * 128 + col], s);
+  s = fmaf(wy[yn], H[yn * 128 + col], s);
+  s = fmaf(wz[i], H[zp * 128 + col], s);
+  s = fmaf(wz[zn], H[zn * 128 + col], s);
+  Y[i * 128 + col] = to_act<AT>(H[i * 128 + col] - s * id);
+}
+
+// ------------------------------------------------------------------ edge-bias MLPs
+// MLP_e(e) = GELU(e W1 + b1) W2 + b2, e in R^4 (Sec. 4.2, Supplementary:
+// per-head bias from the edge descriptor (dx, A_ij)); W1 [4][E], W2 [E][H].
+struct EdgeW {
+  const float *w1, *b1, *w2, *b2;
+  int E, H;
+};
+
+__device__ inline void edge_mlp(const EdgeW& w, const float e[4], float* out) {
+  float hdn[64];
+  for (int k = 0; k < w.E; ++k) {
+    float s = w.b1[k];
+    for (int q = 0; q < 4; ++q) s = fmaf(e[q], w.w1[q * w.E + k], s);
+    hdn[k] = gelu_f(s);
+  }
+  for (int h = 0; h < w.H; ++h) {
+    float s = w.b2[h];
+    for (int k = 0; k < w.E; ++k) s = fmaf(hdn[k], w.w2[k * w.H + h], s);
+    out[h] = s;
+  }
+}
+
+// Within-leaf bias table with A_ij = 0: T0[h][i][j] = MLP_e((pos j - pos i)/4, 0).
+// Every leaf has the same shape, so one table per layer serves all leaves.
+__global__ void k_edge_table(EdgeW w, int L, unsigned xm, unsigned ym, unsigned zm, float* T0) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= L * L) return;
+  const int i = p / L, j = p % L;
+  float e[4] = {(mcoord(j, xm) - mcoord(i, xm)) * 0.25f, (mcoord(j, ym) - mcoord(i, ym)) * 0.25f,
+                (mcoord(j, zm) - mcoord(i, zm)) * 0.25f, 0.f};
+  float o[8];
+  edge_mlp(w, e, o);
+  for (int h = 0; h < w.H; ++h) T0[(h * L + i) * L + j] = o[h];
+}
+
+// Stencil entries of node i inside its own leaf (self and up to 6 faces):
+// nbr[i][e] = local index of j in the leaf (255: none), ahat[i][e] =
+// A_ij / sqrt(A_ii A_jj), delta code in dir[i][e] (0 self, 1..6 = +x,-x,+y,-y,+z,-z).
+__global__ void k_leaf_stencil(const FrameDesc* fr, const int* node2f, const float* sys, int64_t ntot, int L,
+                               uint8_t* nbr, float* ahat) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntot) return;
+  const FrameDesc F = fr[node2f[i]];
+  const unsigned c = (unsigned)(i - F.n0);
+  const double* d8 = reinterpret_cast<const double*>(sys + 5 * ntot);
+  const double *wx8 = d8 + ntot, *wy8 = d8 + 2 * ntot, *wz8 = d8 + 3 * ntot;
+  const unsigned leaf = c / (unsigned)L;
+  nbr[i * 7] = (uint8_t)(c % L);
+  ahat[i * 7] = 1.f;
+  const unsigned masks[3] = {F.xm, F.ym, F.zm};
+  const double* ws[3] = {wx8, wy8, wz8};
+  for (int a = 0; a < 3; ++a) {
+    for (int sgn = 0; sgn < 2; ++sgn) {
+      const int e = 1 + 2 * a + sgn;
+      const bool edge = sgn == 0 ? (c & masks[a]) == masks[a] : (c & masks[a]) == 0;
+      const unsigned cj = sgn == 0 ? mstep_plus(c, masks[a]) : mstep_minus(c, masks[a]);
+      nbr[i * 7 + e] = 255;
+      ahat[i * 7 + e] = 0.f;
+      if (edge || cj / (unsigned)L != leaf) continue;
+      const double w = sgn == 0 ? ws[a][i] : ws[a][F.n0 + cj];
+      nbr[i * 7 + e] = (uint8_t)(cj % L);
+      ahat[i * 7 + e] = (float)(-w / sqrt(d8[i] * d8[F.n0 + cj]));
+    }
+  }
+}
+
+// Per-layer corrections of the diagonal bias at the stencil entries:
+// corr[i][e][h] = MLP_e(dx_ij/4, Ahat_ij) - MLP_e(dx_ij/4, 0).
+__global__ void k_edge_corr(EdgeW w, const uint8_t* nbr, const float* ahat, int64_t ntot, float* corr) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ntot * 7) return;
+  const int e = (int)(p % 7);
+  float* o = corr + p * w.H;
+  if (nbr[p] == 255) {
+    for (int h = 0; h < w.H; ++h) o[h] = 0.f;
+    return;
+  }
+  float d[3] = {0.f, 0.f, 0.f};
+  if (e > 0) d[(e - 1) / 2] = ((e - 1) % 2 == 0) ? 0.25f : -0.25f;
+  float e1[4] = {d[0], d[1], d[2], ahat[p]}, e0[4] = {d[0], d[1], d[2], 0.f};
+  float a[8], b[8];
+  edge_mlp(w, e1, a);
+  edge_mlp(w, e0, b);
+  for (int h = 0; h < w.H; ++h) o[h] = a[h] - b[h];
+}
+
+// Off-diagonal pair descriptors (Supplementary "Off-diagonal attention
+// stack"): for tile m, row token t, column token t':
+//   (centroid(J_m^t') - centroid(I_m^t)) / 4,  mean of Ahat over I_m^t x J_m^t'.
+// One block per tile; thread (t, t').
+__global__ __launch_bounds__(256) void k_off_desc(const FrameDesc* fr, const int* tile2f, const float* sys,
+                                                  int64_t ntot, int L, int LS, float* desc) {
+  const int mg = blockIdx.x;
+  const FrameDesc F = fr[tile2f[mg]];
+  const int m = mg - F.m0, K = F.K;
+  int j = 0;
+  while (m >= K - (K >> (j + 1))) ++j;
+  const int i = m - (K - (K >> j)), S = 1 << j, r0 = 2 * i * S, c0 = r0 + S, p = L / LS;
+  const int t = threadIdx.x / LS, t2 = threadIdx.x % LS;
+  if (t >= LS) return;
+  const double* d8 = reinterpret_cast<const double*>(sys + 5 * ntot);
+  const double* w8[3] = {d8 + ntot, d8 + 2 * ntot, d8 + 3 * ntot};
+  const unsigned masks[3] = {F.xm, F.ym, F.zm};
+  double cI[3] = {0, 0, 0}, cJ[3] = {0, 0, 0}, acc = 0.0;
+  for (int k = 0; k < S; ++k) {
+    for (int l = t * p; l < (t + 1) * p; ++l) {
+      const unsigned ci = (unsigned)((r0 + k) * L + l);
+      for (int a = 0; a < 3; ++a) cI[a] += mcoord(ci, masks[a]);
+      for (int a = 0; a < 3; ++a) {
+        for (int sgn = 0; sgn < 2; ++sgn) {
+          const bool edge = sgn == 0 ? (ci & masks[a]) == masks[a] : (ci & masks[a]) == 0;
+          if (edge) continue;
+          const unsigned cj = sgn == 0 ? mstep_plus(ci, masks[a]) : mstep_minus(ci, masks[a]);
+          const int kj = cj / L, lj = cj % L;
+          if (kj < c0 || kj >= c0 + S || lj / p != t2) continue;
+          const double w = sgn == 0 ? w8[a][F.n0 + ci] : w8[a][F.n0 + cj];
+          acc += -w / sqrt(d8[F.n0 + ci] * d8[F.n0 + cj]);
+        }
+      }
+    }
+    for (int l = t2 * p; l < (t2 + 1) * p; ++l) {
+      const unsigned cj = (unsigned)((c0 + k) * L + l);
+      for (int a = 0; a < 3; ++a) cJ[a] += mcoord(cj, masks[a]);
+    }
+  }
+  const double inv = 1.0 / (double)(S * p);
+  float* o = desc + (((int64_t)mg * LS + t) * LS + t2) * 4;
+  for (int a = 0; a < 3; ++a) o[a] = (float)((cJ[a] - cI[a]) * inv * 0.25);
+  o[3] = (float)(acc * inv * inv);
+}
+
+// Off-diagonal bias per layer: bias[m][h][t][t'] = MLP_e(desc[m][t][t']).
+__global__ void k_edge_off(EdgeW w, const float* desc, int64_t npairs, int LS, float* bias) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const int64_t m = p / (LS * LS);
+  const int tt = (int)(p % (LS * LS));
+  float e[4] = {desc[p * 4], desc[p * 4 + 1], desc[p * 4 + 2], desc[p * 4 + 3]};
+  float o[8];
+  edge_mlp(w, e, o);
+  for (int h = 0; h < w.H; ++h) bias[(m * w.H + h) * LS * LS + tt] = o[h];
+}
+
+// ------------------------------------------------------------------ attention
+// One wave per (group, head): T tokens (a leaf, T = L, or a tile, T = L_s),
+// head dim 32.  S = Q K^T / sqrt(32) + bias, softmax over keys, O = P V.
+// Diagonal groups read the shared table T0[h] plus the stencil corrections
+// of their own row; tiles read a dense per-tile bias.
+template <typename AT, int T, bool DIAG>
+__global__ __launch_bounds__(64) void k_attention(const AT* qkv, AT* out, const float* bias, const float* corr,
+                                                  const uint8_t* nbr, int H) {
+  constexpr int DH = 32;
+  __shared__ float sK[T][DH + 1], sV[T][DH + 1], sB[T][T + 1];
+  const int grp = blockIdx.x, h = blockIdx.y, lane = threadIdx.x;
+  const int d = H * DH;
+  const int64_t row0 = (int64_t)grp * T;
+  for (int idx = lane; idx < T * DH; idx += 64) {
+    const int r = idx / DH, c = idx % DH;
+    const AT* q = qkv + (row0 + r) * 3 * d + h * DH + c;
+    sK[r][c] = ldf(q, d);
+    sV[r][c] = ldf(q, 2 * d);
+  }
+  const float* bt = DIAG ? bias + (int64_t)h * T * T : bias + ((int64_t)grp * H + h) * T * T;
+  for (int idx = lane; idx < T * T; idx += 64) sB[idx / T][idx % T] = bt[idx];
+  __syncthreads();
+  if (lane >= T) return;
+  const int64_t row = row0 + lane;
+  if (DIAG) {
+    for (int e = 0; e < 7; ++e) {
+      const int lj = nbr[row * 7 + e];
+      if (lj != 255) sB[lane][lj] += corr[(row * 7 + e) * H + h];
+    }
+  }
+  float q[DH];
+  const float scale = 0.17677669529663687f;  // 1/sqrt(32)
+#pragma unroll
+  for (int c = 0; c < DH; ++c) q[c] = ldf(qkv, row * 3 * d + h * DH + c) * scale;
+  float s[T];
+  float mx = -3.4e38f;
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    float a = sB[lane][j];
+#pragma unroll
+    for (int c = 0; c < DH; ++c) a = fmaf(q[c], sK[j][c], a);
+    s[j] = a;
+    mx = fmaxf(mx, a);
+  }
+  float sum = 0.f;
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    s[j] = expf(s[j] - mx);
+    sum += s[j];
+  }
+  const float inv = 1.f / sum;
+  float o[DH];
+#pragma unroll
+  for (int c = 0; c < DH; ++c) o[c] = 0.f;
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+#pragma unroll
+    for (int c = 0; c < DH; ++c) o[c] = fmaf(s[j], sV[j][c], o[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < DH; ++c) out[row * d + h * DH + c] = to_act<AT>(o[c] * inv);
+}
+
+// ------------------------------------------------------------------ strips and highways
+// Strip means for off-diagonal token (m, t): out[tok][0:128] = mean of A over
+// I_m^t (row strip), out[tok][128:256] = mean of Bsrc over J_m^t (column
+// strip).  Used for pooling (A = Bsrc = encoder output) and for the highway
+// context of off-diagonal tokens (A = r, Bsrc = c).  One block (128 threads,
+// one per feature) per token.
+template <typename OT>
+__global__ __launch_bounds__(128) void k_strip_means(const FrameDesc* fr, const int* tile2f, const float* A,
+                                                     const float* Bsrc, int L, int LS, OT* out) {
+  const int64_t tok = blockIdx.x;
+  const int mg = (int)(tok / LS), t = (int)(tok % LS);
+  const FrameDesc F = fr[tile2f[mg]];
+  const int m = mg - F.m0, K = F.K;
+  int j = 0;
+  while (m >= K - (K >> (j + 1))) ++j;
+  const int i = m - (K - (K >> j)), S = 1 << j, r0 = 2 * i * S, c0 = r0 + S, p = L / LS;
+  const int col = threadIdx.x;
+  float sa = 0.f, sb = 0.f;
+  for (int k = 0; k < S; ++k) {
+    for (int l = t * p; l < (t + 1) * p; ++l) {
+      sa += A[((int64_t)F.n0 + (int64_t)(r0 + k) * L + l) * 128 + col];
+      sb += Bsrc[((int64_t)F.n0 + (int64_t)(c0 + k) * L + l) * 128 + col];
+    }
+  }
+  const float inv = 1.f / (float)(S * p);
+  out[tok * 256 + col] = to_act<OT>(sa * inv);
+  out[tok * 256 + 128 + col] = to_act<OT>(sb * inv);
+}
+
+// Highway buffers of the diagonal tokens (Sec. 4.3): r_i (c_i) is the mean of
+// the diagonal token i and of every off-diagonal token whose row (column)
+// sub-strip contains i.  Leaf k sits at level j in tile K - K/2^j + (k >> (j+1))
+// on side (k >> j) & 1; its position l maps to sub-strip token l / p.
+__global__ __launch_bounds__(256) void k_highway_rc(const FrameDesc* fr, const int* node2f, const float* Xd,
+                                                    const float* Xo, int L, int LS, int64_t ntot, float* R,
+                                                    float* Cc) {
+  const int64_t i = (int64_t)blockIdx.x * 2 + (threadIdx.x >> 7);
+  if (i >= ntot) return;
+  const int col = threadIdx.x & 127;
+  const FrameDesc F = fr[node2f[i]];
+  const int c = (int)(i - F.n0), k = c / L, l = c % L, p = L / LS, K = F.K;
+  const float x = Xd[i * 128 + col];
+  float r = x, cc = x;
+  int nr = 1, nc = 1;
+  for (int j = 0; j < F.J; ++j) {
+    const int m = K - (K >> j) + (k >> (j + 1));
+    const float v = Xo[((int64_t)(F.m0 + m) * LS + l / p) * 128 + col];
+    if (((k >> j) & 1) == 0) {
+      r += v;
+      ++nr;
+    } else {
+      cc += v;
+      ++nc;
+    }
+  }
+  R[i * 128 + col] = r / nr;
+  Cc[i * 128 + col] = cc / nc;
+}
+
+// Column sums of 128-wide rows over chunks (first stage of the per-frame
+// global token g = mean of all tokens of the frame).
+struct SumChunk {
+  int frame, kind;  // kind 0: diagonal rows, 1: off-diagonal rows
+  int64_t row0;
+  int rows;
+};
+
+__global__ __launch_bounds__(128) void k_chunk_sums(const SumChunk* ch, const float* Xd, const float* Xo,
+                                                    float* part) {
+  const SumChunk c = ch[blockIdx.x];
+  const float* X = c.kind ? Xo : Xd;
+  float s = 0.f;
+  for (int r = 0; r < c.rows; ++r) s += X[(c.row0 + r) * 128 + threadIdx.x];
+  part[(int64_t)blockIdx.x * 128 + threadIdx.x] = s;
+}
+
+__global__ __launch_bounds__(128) void k_frame_mean(const int* chunk0, const float* part, const float* count,
+                                                    float* G) {
+  const int f = blockIdx.x;
+  float s = 0.f;
+  for (int c = chunk0[f]; c < chunk0[f + 1]; ++c) s += part[(int64_t)c * 128 + threadIdx.x];
+  G[f * 128 + threadIdx.x] = s / count[f];
+}
+
+// ------------------------------------------------------------------ heads and packing
+// G_k = F_k F_k^T (one block per leaf).  Entry (i, j) and (j, i) run the same
+// FMA sequence, so G_k is exactly symmetric.
+template <typename FT, int L>
+__global__ __launch_bounds__(256) void k_gram(const float* Frows, FT* G) {
+  __shared__ float sF[L][L + 1];
+  const int64_t kg = blockIdx.x;
+  for (int idx = threadIdx.x; idx < L * L; idx += 256) sF[idx / L][idx % L] = Frows[kg * L * L + idx];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < L * L; idx += 256) {
+    const int i = idx / L, j = idx % L;
+    float a = 0.f;
+#pragma unroll 8
+    for (int c = 0; c < L; ++c) a = fmaf(sF[i][c], sF[j][c], a);
+    G[kg * L * L + idx] = to_act<FT>(a);
+  }
+}
+
+// B_m = U_m V_m^T (one block per tile); UV rows = [U row | V row].
+template <typename FT, int LS>
+__global__ void k_uvt(const float* UV, FT* B) {
+  const int64_t m = blockIdx.x;
+  const int t = threadIdx.x / LS, t2 = threadIdx.x % LS;
+  if (t >= LS) return;
+  const float* u = UV + (m * LS + t) * (2 * LS);
+  const float* v = UV + (m * LS + t2) * (2 * LS) + LS;
+  float a = 0.f;
+  for (int s = 0; s < LS; ++s) a = fmaf(u[s], v[s], a);
+  B[(m * LS + t) * LS + t2] = to_act<FT>(a);
+}
+
+// Node heads [Ut | Vt | lam-logit] -> factor sections; lam = softplus.
+template <typename FT, int LS>
+__global__ void k_pack_nodes(const float* NH, int64_t ntot, FT* Ut, FT* Vt, float* lam) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntot) return;
+  const float* r = NH + i * 36;
+  for (int s = 0; s < LS; ++s) {
+    Ut[i * LS + s] = to_act<FT>(r[s]);
+    Vt[i * LS + s] = to_act<FT>(r[LS + s]);
+  }
+  lam[i] = softplus_f(r[2 * LS]);
+}
+
+// Weight conversion: dst[(n_off + n) * ld + k_off + k] = src[k * ncols + n].
+struct ConvDesc {
+  int64_t src, dst;
+  int rows, cols, ld, n_off, k_off, pad;
+};
+
+template <typename AT>
+__global__ void k_convert(const ConvDesc* d, const float* W, AT* out) {
+  const ConvDesc c = d[blockIdx.x];
+  for (int idx = threadIdx.x; idx < c.rows * c.cols; idx += blockDim.x) {
+    const int k = idx / c.cols, n = idx % c.cols;
+    out[c.dst + (int64_t)(c.n_off + n) * c.ld + c.k_off + k] = to_act<AT>(W[c.src + idx]);
+  }
+}
+
+// ------------------------------------------------------------------ host side
+
+struct GemmW {
+  int64_t off;  // element offset in the converted-weight arena
+  int N, K;
+};
+
+struct NetPlan {
+  std::vector<WeightEntry> lay;
+  std::vector<ConvDesc> conv;
+  int64_t arena = 0;
+  GemmW enc1, enc2, gcn[4], pool, hleaf1, hleaf2, hnode, huv;
+  GemmW qkv[2][16], o[2][16], f1[2][16], f2[2][16];
+};
+
+static int64_t woff(const NetPlan& P, const std::string& n) {
+  const WeightEntry* e = find_weight(P.lay, n);
+  return e ? e->offset : -1;
+}
+
+static NetPlan make_plan(const hp_model_config& c) {
+  NetPlan P;
+  P.lay = weight_layout(c);
+  auto gemm = [&](int N, int K) {
+    GemmW g{P.arena, N, K};
+    P.arena += (int64_t)N * K;
+    return g;
+  };
+  auto conv = [&](const GemmW& g, const std::string& name, int n_off, int k_off) {
+    const WeightEntry* e = find_weight(P.lay, name);
+    P.conv.push_back(ConvDesc{e->offset, g.off, e->rows, e->cols, g.K, n_off, k_off, 0});
+  };
+  const int d = c.d, LS = c.rank;
+  P.enc1 = gemm(d, 32);
+  conv(P.enc1, "enc1.w", 0, 0);
+  P.enc2 = gemm(d, d);
+  conv(P.enc2, "enc2.w", 0, 0);
+  for (int g = 0; g < c.gcn; ++g) {
+    P.gcn[g] = gemm(d, d);
+    conv(P.gcn[g], "gcn" + std::to_string(g) + ".w", 0, 0);
+  }
+  P.pool = gemm(d, 2 * d);
+  conv(P.pool, "pool.wr", 0, 0);
+  conv(P.pool, "pool.wc", 0, d);
+  for (int s = 0; s < 2; ++s)
+    for (int l = 0; l < c.layers; ++l) {
+      std::string p = std::string(s ? "off" : "diag") + std::to_string(l) + ".";
+      P.qkv[s][l] = gemm(3 * d, d);
+      conv(P.qkv[s][l], p + "qkv.w", 0, 0);
+      P.o[s][l] = gemm(d, d);
+      conv(P.o[s][l], p + "o.w", 0, 0);
+      P.f1[s][l] = gemm(4 * d, 4 * d);
+      conv(P.f1[s][l], p + "f1.w", 0, 0);
+      P.f2[s][l] = gemm(d, 4 * d);
+      conv(P.f2[s][l], p + "f2.w", 0, 0);
+    }
+  P.hleaf1 = gemm(d, d);
+  conv(P.hleaf1, "hleaf1.w", 0, 0);
+  P.hleaf2 = gemm(c.leaf, d);
+  conv(P.hleaf2, "hleaf2.w", 0, 0);
+  P.hnode = gemm(2 * LS + 1, d);
+  conv(P.hnode, "hut.w", 0, 0);
+  conv(P.hnode, "hvt.w", LS, 0);
+  conv(P.hnode, "hlam.w", 2 * LS, 0);
+  P.huv = gemm(2 * LS, d);
+  conv(P.huv, "hu.w", 0, 0);
+  conv(P.huv, "hv.w", LS, 0);
+  return P;
+}
+
+// Workspace of one batch (every buffer sized at creation, 4-byte activations
+// so one arena serves both precisions).
+struct NetBufs {
+  NetPlan plan;
+  int64_t Nd = 0, No = 0;
+  void* feats = nullptr;
+  float *H = nullptr, *Henc = nullptr, *R = nullptr, *C = nullptr, *Xo = nullptr, *Xo0 = nullptr;
+  void *a128 = nullptr, *b128 = nullptr, *qkv = nullptr, *u512 = nullptr, *h512 = nullptr;
+  void *ctx = nullptr, *ao128 = nullptr, *bo128 = nullptr, *qkvo = nullptr, *uo512 = nullptr, *ho512 = nullptr;
+  float *ctxf = nullptr;
+  float *Frows = nullptr, *NH = nullptr, *UV = nullptr;
+  float *T0 = nullptr, *corr = nullptr, *ahat = nullptr, *desc = nullptr, *boff = nullptr;
+  uint8_t* nbr = nullptr;
+  float *gpart = nullptr, *G = nullptr, *gcount = nullptr, *glob = nullptr, *bias_node = nullptr, *bias_uv = nullptr;
+  void* warena = nullptr;
+  ConvDesc* d_conv = nullptr;
+  int *node2f = nullptr, *tok2f = nullptr, *tile2f = nullptr, *chunk0 = nullptr;
+  SumChunk* chunks = nullptr;
+  int nchunks = 0;
+};
+
+static NetBufs* nb_of(Batch& b) { return reinterpret_cast<NetBufs*>(b.net.ws); }
+
 hp_status network_alloc(Batch& b) {
-  (void)b;
+  auto* N = new NetBufs();
+  b.net.ws = N;
+  b.net_free = [](void* p) { delete reinterpret_cast<NetBufs*>(p); };
+  const hp_model_config& c = b.cfg;
+  if (c.d != 128 || c.edge_hidden > 64 || c.heads * 32 != c.d || c.node_feats + c.glob_feats > 32 ||
+      c.gcn > 4 || c.layers > 16)
+    return set_error(HP_E_SHAPE, "network: supported d = 128, heads = 4 (head dim 32), edge_hidden <= 64, "
+                                 "gcn <= 4, layers <= 16, node_feats + glob_feats <= 32");
+  N->plan = make_plan(c);
+  const int64_t Nd = b.ntot, No = std::max<int64_t>(b.mtot, 1) * c.rank, d = c.d;
+  N->Nd = Nd;
+  N->No = No;
+  hp_status s = HP_OK;
+  auto A = [&](auto** p, size_t bytes) {
+    if (s == HP_OK) s = b.alloc((void**)p, bytes);
+  };
+  A(&N->feats, Nd * 32 * 4);
+  A(&N->H, Nd * d * 4);
+  A(&N->Henc, Nd * d * 4);
+  A(&N->R, Nd * d * 4);
+  A(&N->C, Nd * d * 4);
+  A(&N->a128, Nd * d * 4);
+  A(&N->b128, Nd * d * 4);
+  A(&N->qkv, Nd * 3 * d * 4);
+  A(&N->u512, Nd * 4 * d * 4);
+  A(&N->h512, Nd * 4 * d * 4);
+  A(&N->Xo, No * d * 4);
+  A(&N->Xo0, No * d * 4);
+  A(&N->ctx, No * 2 * d * 4);
+  A(&N->ctxf, No * 2 * d * 4);
+  A(&N->ao128, No * d * 4);
+  A(&N->bo128, No * d * 4);
+  A(&N->qkvo, No * 3 * d * 4);
+  A(&N->uo512, No * 4 * d * 4);
+  A(&N->ho512, No * 4 * d * 4);
+  A(&N->Frows, Nd * c.leaf * 4);
+  A(&N->NH, Nd * 36 * 4);
+  A(&N->UV, No * 2 * c.rank * 4);
+  A(&N->T0, (size_t)c.heads * c.leaf * c.leaf * 4);
+  A(&N->corr, Nd * 7 * c.heads * 4);
+  A(&N->ahat, Nd * 7 * 4);
+  A(&N->nbr, Nd * 7);
+  A(&N->desc, std::max<int64_t>(b.mtot, 1) * c.rank * c.rank * 4 * 4);
+  A(&N->boff, std::max<int64_t>(b.mtot, 1) * c.heads * c.rank * c.rank * 4);
+  A(&N->G, b.nframes * d * 4);
+  A(&N->gcount, b.nframes * 4);
+  A(&N->glob, b.nframes * 12 * 4);
+  A(&N->bias_node, 64 * 4);
+  A(&N->bias_uv, 64 * 4);
+  A(&N->warena, N->plan.arena * 4);
+  A(&N->d_conv, N->plan.conv.size() * sizeof(ConvDesc));
+  A(&N->node2f, Nd * 4);
+  A(&N->tok2f, No * 4);
+  A(&N->tile2f, std::max<int64_t>(b.mtot, 1) * 4);
+  A(&N->chunk0, (b.nframes + 1) * 4);
+  if (s != HP_OK) return s;
+  // maps and chunk tables
+  std::vector<int> node2f(Nd), tok2f(No, 0), tile2f(std::max<int64_t>(b.mtot, 1), 0), chunk0(b.nframes + 1);
+  std::vector<SumChunk> ch;
+  std::vector<float> cnt(b.nframes);
+  for (int f = 0; f < b.nframes; ++f) {
+    const FrameDesc& F = b.fr[f];
+    for (int i = 0; i < F.n; ++i) node2f[F.n0 + i] = f;
+    for (int m = 0; m < F.MH; ++m) {
+      tile2f[F.m0 + m] = f;
+      for (int t = 0; t < c.rank; ++t) tok2f[(int64_t)(F.m0 + m) * c.rank + t] = f;
+    }
+    chunk0[f] = (int)ch.size();
+    for (int r = 0; r < F.n; r += 128) ch.push_back(SumChunk{f, 0, (int64_t)F.n0 + r, std::min(128, F.n - r)});
+    if (c.offdiag)
+      for (int r = 0; r < F.MH * c.rank; r += 128)
+        ch.push_back(SumChunk{f, 1, (int64_t)F.m0 * c.rank + r, std::min(128, F.MH * c.rank - r)});
+    cnt[f] = (float)(F.n + (c.offdiag ? F.MH * c.rank : 0));
+  }
+  chunk0[b.nframes] = (int)ch.size();
+  N->nchunks = (int)ch.size();
+  A(&N->chunks, ch.size() * sizeof(SumChunk));
+  A(&N->gpart, ch.size() * 128 * 4);
+  if (s != HP_OK) return s;
+  auto up = [&](void* dst, const void* src, size_t n) {
+    if (s == HP_OK && hipMemcpy(dst, src, n, hipMemcpyHostToDevice) != hipSuccess)
+      s = set_error(HP_E_HIP, "network_alloc: upload failed");
+  };
+  up(N->node2f, node2f.data(), Nd * 4);
+  up(N->tok2f, tok2f.data(), No * 4);
+  up(N->tile2f, tile2f.data(), tile2f.size() * 4);
+  up(N->chunk0, chunk0.data(), chunk0.size() * 4);
+  up(N->chunks, ch.data(), ch.size() * sizeof(SumChunk));
+  up(N->gcount, cnt.data(), cnt.size() * 4);
+  up(N->d_conv, N->plan.conv.data(), N->plan.conv.size() * sizeof(ConvDesc));
+  if (s == HP_OK && hipMemset(N->warena, 0, N->plan.arena * 4) != hipSuccess)
+    s = set_error(HP_E_HIP, "network_alloc: memset failed");
+  return s;
+}
+
+template <typename AT>
+static void gemm(hipStream_t st, const void* X, int64_t ldx, const NetBufs& NB, const GemmW& w, const float* bias,
+                 const float* resid, int64_t ldr, float* Yf, int64_t ldf, void* Yb, int64_t ldb, int64_t M, int act) {
+  if (M <= 0) return;
+  GemmArgs a;
+  a.X = X;
+  a.ldx = ldx;
+  a.Wt = (const AT*)NB.warena + w.off;
+  a.K = w.K;
+  a.bias = bias;
+  a.resid = resid;
+  a.ldr = ldr;
+  a.Yf = Yf;
+  a.ldf = ldf;
+  a.Yb = Yb;
+  a.ldb = ldb;
+  a.M = (int)M;
+  a.N = w.N;
+  a.act = act;
+  dim3 grid((unsigned)((M + 63) / 64), (unsigned)((w.N + 63) / 64));
+  hipLaunchKernelGGL(k_gemm<AT>, grid, dim3(256), 0, st, a);
+}
+
+template <typename AT, typename FT>
+static hp_status forward(Batch& b, const float* W, const float* rho, const float* sys, void* fac) {
+  NetBufs& N = *nb_of(b);
+  const NetPlan& P = N.plan;
+  const hp_model_config& c = b.cfg;
+  hipStream_t st = b.stream;
+  const int64_t Nd = N.Nd, d = c.d, L = c.leaf, LS = c.rank, H = c.heads;
+  const int64_t No = b.mtot * LS;
+  const bool use_off = c.offdiag && b.mtot > 0;
+  const FrameDesc* fr = b.d_fr;
+  auto wp = [&](const std::string& n) { return W + woff(P, n); };
+  // weights -> transposed arena in the compute type
+  hipLaunchKernelGGL(k_convert<AT>, dim3((unsigned)P.conv.size()), dim3(256), 0, st, N.d_conv, W, (AT*)N.warena);
+  HP_HIP(hipMemcpyAsync(N.bias_node, wp("hut.b"), LS * 4, hipMemcpyDeviceToDevice, st));
+  HP_HIP(hipMemcpyAsync(N.bias_node + LS, wp("hvt.b"), LS * 4, hipMemcpyDeviceToDevice, st));
+  HP_HIP(hipMemcpyAsync(N.bias_node + 2 * LS, wp("hlam.b"), 4, hipMemcpyDeviceToDevice, st));
+  HP_HIP(hipMemcpyAsync(N.bias_uv, wp("hu.b"), LS * 4, hipMemcpyDeviceToDevice, st));
+  HP_HIP(hipMemcpyAsync(N.bias_uv + LS, wp("hv.b"), LS * 4, hipMemcpyDeviceToDevice, st));
+  // features and encoder (Sec. 4.1)
+  hipLaunchKernelGGL(k_frame_stats, dim3(b.nframes), dim3(256), 0, st, fr, rho, sys, b.ntot, N.glob);
+  hipLaunchKernelGGL(k_features<AT>, dim3(b.nblk), dim3(NODE_BLOCK), 0, st, fr, b.d_blk2f, rho, sys, b.ntot, N.glob,
+                     (AT*)N.feats);
+  gemm<AT>(st, N.feats, 32, N, P.enc1, wp("enc1.b"), nullptr, 0, nullptr, 0, N.a128, d, Nd, 1);
+  gemm<AT>(st, N.a128, d, N, P.enc2, wp("enc2.b"), nullptr, 0, N.H, d, N.b128, d, Nd, 0);
+  for (int g = 0; g < c.gcn; ++g) {
+    hipLaunchKernelGGL(k_gcn_spmm<AT>, dim3((unsigned)((Nd + 1) / 2)), dim3(256), 0, st, fr, N.node2f, sys, b.ntot,
+                       (const float*)N.H, (AT*)N.a128);
+    gemm<AT>(st, N.a128, d, N, P.gcn[g], wp("gcn" + std::to_string(g) + ".b"), N.H, d, N.H, d, N.b128, d, Nd, 1);
+  }
+  HP_HIP(hipMemcpyAsync(N.Henc, N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
+  // off-diagonal tokens: pooled strip means through [W_r; W_c] (Sec. 4.2)
+  if (use_off) {
+    hipLaunchKernelGGL(k_strip_means<AT>, dim3((unsigned)No), dim3(128), 0, st, fr, N.tile2f, (const float*)N.H,
+                       (const float*)N.H, (int)L, (int)LS, (AT*)N.ctx);
+    gemm<AT>(st, N.ctx, 2 * d, N, P.pool, wp("pool.b"), nullptr, 0, N.Xo, d, nullptr, 0, No, 0);
+    HP_HIP(hipMemcpyAsync(N.Xo0, N.Xo, No * d * 4, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_off_desc, dim3((unsigned)b.mtot), dim3(256), 0, st, fr, N.tile2f, sys, b.ntot, (int)L,
+                       (int)LS, N.desc);
+  }
+  hipLaunchKernelGGL(k_leaf_stencil, dim3((unsigned)((Nd + 255) / 256)), dim3(256), 0, st, fr, N.node2f, sys, b.ntot,
+                     (int)L, N.nbr, N.ahat);
+  const unsigned lowmask = (unsigned)(L - 1);
+  const FrameDesc& F0 = b.fr[0];
+  for (int l = 0; l < c.layers; ++l) {
+    for (int sidx = 0; sidx < 2; ++sidx) {
+      if (sidx == 1 && !use_off) continue;
+      const std::string p = std::string(sidx ? "off" : "diag") + std::to_string(l) + ".";
+      EdgeW ew{wp(p + "e1.w"), wp(p + "e1.b"), wp(p + "e2.w"), wp(p + "e2.b"), c.edge_hidden, (int)H};
+      float* X = sidx ? N.Xo : N.H;
+      const int64_t M = sidx ? No : Nd;
+      void* a = sidx ? N.ao128 : N.a128;
+      void* q = sidx ? N.qkvo : N.qkv;
+      void* o = sidx ? N.bo128 : N.b128;
+      hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, (const float*)X,
+                         wp(p + "ln1.g"), wp(p + "ln1.b"), (AT*)a, (int)M);
+      gemm<AT>(st, a, d, N, P.qkv[sidx][l], wp(p + "qkv.b"), nullptr, 0, nullptr, 0, q, 3 * d, M, 0);
+      if (sidx == 0) {
+        hipLaunchKernelGGL(k_edge_table, dim3((unsigned)((L * L + 63) / 64)), dim3(64), 0, st, ew, (int)L,
+                           F0.xm & lowmask, F0.ym & lowmask, F0.zm & lowmask, N.T0);
+        hipLaunchKernelGGL(k_edge_corr, dim3((unsigned)((Nd * 7 + 127) / 128)), dim3(128), 0, st, ew,
+                           (const uint8_t*)N.nbr, (const float*)N.ahat, Nd, N.corr);
+        if (L == 64)
+          hipLaunchKernelGGL((k_attention<AT, 64, true>), dim3((unsigned)b.ktot, (unsigned)H), dim3(64), 0, st,
+                             (const AT*)q, (AT*)o, (const float*)N.T0, (const float*)N.corr, (const uint8_t*)N.nbr,
+                             (int)H);
+        else
+          hipLaunchKernelGGL((k_attention<AT, 32, true>), dim3((unsigned)b.ktot, (unsigned)H), dim3(64), 0, st,
+                             (const AT*)q, (AT*)o, (const float*)N.T0, (const float*)N.corr, (const uint8_t*)N.nbr,
+                             (int)H);
+      } else {
+        const int64_t npairs = b.mtot * LS * LS;
+        hipLaunchKernelGGL(k_edge_off, dim3((unsigned)((npairs + 127) / 128)), dim3(128), 0, st, ew,
+                           (const float*)N.desc, npairs, (int)LS, N.boff);
+        if (LS == 16)
+          hipLaunchKernelGGL((k_attention<AT, 16, false>), dim3((unsigned)b.mtot, (unsigned)H), dim3(64), 0, st,
+                             (const AT*)q, (AT*)o, (const float*)N.boff, nullptr, nullptr, (int)H);
+        else
+          hipLaunchKernelGGL((k_attention<AT, 8, false>), dim3((unsigned)b.mtot, (unsigned)H), dim3(64), 0, st,
+                             (const AT*)q, (AT*)o, (const float*)N.boff, nullptr, nullptr, (int)H);
+      }
+      gemm<AT>(st, o, d, N, P.o[sidx][l], wp(p + "o.b"), X, d, X, d, nullptr, 0, M, 0);
+    }
+    // highways (Sec. 4.3)
+    if (c.highways) {
+      if (use_off) {
+        hipLaunchKernelGGL(k_highway_rc, dim3((unsigned)((Nd + 1) / 2)), dim3(256), 0, st, fr, N.node2f,
+                           (const float*)N.H, (const float*)N.Xo, (int)L, (int)LS, Nd, N.R, N.C);
+      } else {
+        HP_HIP(hipMemcpyAsync(N.R, N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
+        HP_HIP(hipMemcpyAsync(N.C, N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
+      }
+      hipLaunchKernelGGL(k_chunk_sums, dim3((unsigned)N.nchunks), dim3(128), 0, st, (const SumChunk*)N.chunks,
+                         (const float*)N.H, (const float*)N.Xo, N.gpart);
+      hipLaunchKernelGGL(k_frame_mean, dim3(b.nframes), dim3(128), 0, st, (const int*)N.chunk0,
+                         (const float*)N.gpart, (const float*)N.gcount, N.G);
+      if (use_off)
+        hipLaunchKernelGGL(k_strip_means<float>, dim3((unsigned)No), dim3(128), 0, st, fr, N.tile2f,
+                           (const float*)N.R, (const float*)N.C, (int)L, (int)LS, N.ctxf);
+    }
+    for (int sidx = 0; sidx < 2; ++sidx) {
+      if (sidx == 1 && !use_off) continue;
+      const std::string p = std::string(sidx ? "off" : "diag") + std::to_string(l) + ".";
+      float* X = sidx ? N.Xo : N.H;
+      const int64_t M = sidx ? No : Nd;
+      void* u = sidx ? N.uo512 : N.u512;
+      void* h = sidx ? N.ho512 : N.h512;
+      if (sidx == 0)
+        hipLaunchKernelGGL(k_ln_concat<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, (const float*)X, d,
+                           (const float*)N.R, d, (const float*)N.C, d, (const float*)N.G, (const int*)N.node2f,
+                           wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, (int)M, c.highways);
+      else
+        hipLaunchKernelGGL(k_ln_concat<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, (const float*)X, d,
+                           (const float*)N.ctxf, 2 * d, (const float*)(N.ctxf + d), 2 * d, (const float*)N.G,
+                           (const int*)N.tok2f, wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, (int)M, c.highways);
+      gemm<AT>(st, u, 4 * d, N, P.f1[sidx][l], wp(p + "f1.b"), nullptr, 0, nullptr, 0, h, 4 * d, M, 1);
+      gemm<AT>(st, h, 4 * d, N, P.f2[sidx][l], wp(p + "f2.b"), X, d, X, d, nullptr, 0, M, 0);
+    }
+  }
+  // heads (Sec. 4.4)
+  const char* base = (const char*)fac;
+  int64_t offs[5], tot;
+  factor_offsets(b, sizeof(FT) == 2 ? HP_BF16 : HP_F32, offs, &tot);
+  hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((Nd + 3) / 4)), dim3(256), 0, st, (const float*)N.H,
+                     wp("diaglnf.g"), wp("diaglnf.b"), (AT*)N.a128, (int)Nd);
+  gemm<AT>(st, N.a128, d, N, P.hleaf1, wp("hleaf1.b"), nullptr, 0, nullptr, 0, N.b128, d, Nd, 1);
+  gemm<AT>(st, N.b128, d, N, P.hleaf2, wp("hleaf2.b"), nullptr, 0, N.Frows, L, nullptr, 0, Nd, 0);
+  if (L == 64)
+    hipLaunchKernelGGL((k_gram<FT, 64>), dim3((unsigned)b.ktot), dim3(256), 0, st, (const float*)N.Frows,
+                       (FT*)(base + offs[0]));
+  else
+    hipLaunchKernelGGL((k_gram<FT, 32>), dim3((unsigned)b.ktot), dim3(256), 0, st, (const float*)N.Frows,
+                       (FT*)(base + offs[0]));
+  gemm<AT>(st, N.a128, d, N, P.hnode, N.bias_node, nullptr, 0, N.NH, 36, nullptr, 0, Nd, 0);
+  if (LS == 16)
+    hipLaunchKernelGGL((k_pack_nodes<FT, 16>), dim3((unsigned)((Nd + 255) / 256)), dim3(256), 0, st,
+                       (const float*)N.NH, Nd, (FT*)(base + offs[2]), (FT*)(base + offs[3]), (float*)(base + offs[4]));
+  else
+    hipLaunchKernelGGL((k_pack_nodes<FT, 8>), dim3((unsigned)((Nd + 255) / 256)), dim3(256), 0, st,
+                       (const float*)N.NH, Nd, (FT*)(base + offs[2]), (FT*)(base + offs[3]), (float*)(base + offs[4]));
+  if (b.mtot > 0) {
+    if (use_off) {
+      hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((No + 3) / 4)), dim3(256), 0, st, (const float*)N.Xo,
+                         wp("offlnf.g"), wp("offlnf.b"), (AT*)N.ao128, (int)No);
+      gemm<AT>(st, N.ao128, d, N, P.huv, N.bias_uv, nullptr, 0, N.UV, 2 * LS, nullptr, 0, No, 0);
+    } else {
+      HP_HIP(hipMemsetAsync(N.UV, 0, No * 2 * LS * 4, st));
+    }
+    if (LS == 16)
+      hipLaunchKernelGGL((k_uvt<FT, 16>), dim3((unsigned)b.mtot), dim3(256), 0, st, (const float*)N.UV,
+                         (FT*)(base + offs[1]));
+    else
+      hipLaunchKernelGGL((k_uvt<FT, 8>), dim3((unsigned)b.mtot), dim3(64), 0, st, (const float*)N.UV,
+                         (FT*)(base + offs[1]));
+  }
+  HP_HIP(hipGetLastError());
   return HP_OK;
 }
 
 }  // namespace hp
 
+using namespace hp;
+
 extern "C" hp_status hp_infer_factors(hp_batch b, const float* d_weights, const float* d_rho, const float* d_sys,
                                       void* d_factors, int32_t compute) {
-  (void)b; (void)d_weights; (void)d_rho; (void)d_sys; (void)d_factors; (void)compute;
-  return hp::set_error(HP_E_STATE, "hp_infer_factors: not built yet");
+  if (!b || !d_weights || !d_rho || !d_sys || !d_factors)
+    return set_error(HP_E_INVALID, "hp_infer_factors: NULL argument");
+  if (compute == HP_BF16) return forward<uint16_t, uint16_t>(*b, d_weights, d_rho, d_sys, d_factors);
+  if (compute == HP_F32) return forward<float, float>(*b, d_weights, d_rho, d_sys, d_factors);
+  return set_error(HP_E_INVALID, "hp_infer_factors: compute must be HP_F32 or HP_BF16");
+}
+
+extern "C" hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, int64_t bytes) {
+  if (!b || !name || !d_dst || bytes < 0) return set_error(HP_E_INVALID, "hp_debug_copy: bad arguments");
+  NetBufs& N = *nb_of(*b);
+  const void* src = nullptr;
+  int64_t cap = 0;
+  const std::string n = name;
+  const int64_t d = b->cfg.d;
+  if (n == "feats") src = N.feats, cap = N.Nd * 32 * 4;
+  else if (n == "enc") src = N.Henc, cap = N.Nd * d * 4;
+  else if (n == "xo0") src = N.Xo0, cap = N.No * d * 4;
+  else if (n == "xd") src = N.H, cap = N.Nd * d * 4;
+  else if (n == "xo") src = N.Xo, cap = N.No * d * 4;
+  else if (n == "frows") src = N.Frows, cap = N.Nd * b->cfg.leaf * 4;
+  else if (n == "nodeh") src = N.NH, cap = N.Nd * 36 * 4;
+  else if (n == "uv") src = N.UV, cap = N.No * 2 * b->cfg.rank * 4;
+  else if (n == "desc") src = N.desc, cap = std::max<int64_t>(b->mtot, 1) * b->cfg.rank * b->cfg.rank * 16;
+  else if (n == "glob") src = N.glob, cap = b->nframes * 12 * 4;
+  if (!src) return set_error(HP_E_INVALID, "hp_debug_copy: unknown buffer '%s'", name);
+  if (bytes > cap) return set_error(HP_E_INVALID, "hp_debug_copy: %lld bytes requested, buffer holds %lld",
+                                    (long long)bytes, (long long)cap);
+  HP_HIP(hipMemcpyAsync(d_dst, src, bytes, hipMemcpyDeviceToDevice, b->stream));
+  return HP_OK;
 }

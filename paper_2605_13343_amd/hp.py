@@ -71,6 +71,7 @@ EXPORTS = {
     "hp_weight_info": ([C.POINTER(ModelConfigC), C.c_int32, C.c_char_p, C.POINTER(C.c_int32),
                         C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int32),
     "hp_infer_factors": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32], C.c_int32),
+    "hp_debug_copy": ([C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64], C.c_int32),
 }
 
 

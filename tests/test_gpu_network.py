@@ -1,0 +1,151 @@
+"""GPU parity of the network forward (hp_infer_factors) against the oracle."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import hmatrix, network
+from paper_2605_13343_amd import hp, inputs
+from tests.gpu_helpers import Side, f32, relerr
+
+pytestmark = pytest.mark.gpu
+
+PLAIN, DEF = inputs.MODEL_PLAIN, inputs.MODEL_DEFAULT
+
+
+def test_weights(cfg, seed=7):
+    """Seeded init with a non-zero V head, so every path of M carries signal."""
+    w = inputs.init_weights(cfg, seed)
+    rng = np.random.default_rng(seed + 100)
+    w["hv.w"] = (rng.standard_normal(w["hv.w"].shape) * 0.02).astype(np.float32)
+    for k in list(w):
+        if k.endswith(".b"):
+            w[k] = (rng.standard_normal(w[k].shape) * 0.02).astype(np.float32)
+    return w
+
+
+test_weights.__test__ = False
+
+
+def _dbg(side, name, shape):
+    import torch
+    t = torch.zeros(int(np.prod(shape)), dtype=torch.float32, device="cuda")
+    hp._check(hp.lib().hp_debug_copy(side.B.h, name.encode(), t.data_ptr(), t.numel() * 4))
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64).reshape(shape)
+
+
+def _run(cfg, frames, compute, w):
+    import torch
+    s = Side(cfg, frames, with_net=True)
+    wt = torch.tensor(hp.pack_weights(cfg, w), device="cuda")
+    fac = s.B.new_factors(compute)
+    s.B.infer_factors(wt, s.rho, s.sys, fac, compute)
+    torch.cuda.synchronize()
+    return s, fac
+
+
+def _oracle(cfg, s, f, w, trace=None):
+    out = network.forward(cfg, {k: np.asarray(v, np.float64) for k, v in w.items()}, s.fs[f], trace=trace)
+    return {k: v.detach().numpy() for k, v in out.items()}
+
+
+@pytest.mark.parametrize("cfg,recipe,seed", [
+    (PLAIN, "plain1024", 1000),
+    (dataclasses.replace(PLAIN, layers=1), "plain1024", 1001),
+    (dataclasses.replace(PLAIN, layers=1, highways=False), "plain1024", 1002),
+    (dataclasses.replace(PLAIN, layers=1, offdiag=False), "plain1024", 1003),
+    (DEF, "precision8192", 2000),
+])
+def test_forward_fp32_matches_oracle(cfg, recipe, seed):
+    w = test_weights(cfg)
+    fr = inputs.make_frame(recipe, seed)
+    s, fac = _run(cfg, [fr], hp.HP_F32, w)
+    tr = {}
+    o = _oracle(cfg, s, 0, w, trace=tr)
+    n, d = fr.n, cfg.d
+    K, MH, L, LS = n // cfg.leaf, n // cfg.leaf - 1, cfg.leaf, cfg.rank
+    feats = _dbg(s, "feats", (n, 32))
+    from oracle import grid
+    fo = s.fs[0].feats
+    errs = {"feats": relerr(feats[:, :20], fo)}
+    errs["enc"] = relerr(_dbg(s, "enc", (n, d)), tr["enc"].detach().numpy())
+    if cfg.offdiag:
+        errs["xo0"] = relerr(_dbg(s, "xo0", (MH * LS, d)), tr["pool"].detach().numpy())
+        errs["desc"] = relerr(_dbg(s, "desc", (MH, LS, LS, 4)), s.fs[0].desc_off)
+    last = tr[f"ffn{cfg.layers - 1}"]
+    errs["xd"] = relerr(_dbg(s, "xd", (n, d)), last[0].detach().numpy())
+    if cfg.offdiag:
+        errs["xo"] = relerr(_dbg(s, "xo", (MH * LS, d)), last[1].detach().numpy())
+    G, B, Ut, Vt, lam = s.download_factors(fac, hp.HP_F32)[0]
+    errs["G"] = relerr(G, hmatrix.gram(o["F"]))
+    errs["B"] = relerr(B, hmatrix.coupling(o["U"], o["V"])) if cfg.offdiag else float(np.abs(B).max())
+    errs["Ut"] = relerr(Ut, o["Ut"])
+    errs["Vt"] = relerr(Vt, o["Vt"])
+    errs["lam"] = relerr(lam, o["lam"])
+    print(cfg, {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= 1e-4, (k, v)
+
+
+# BF16 bounds: inputs of every GEMM are rounded to 8 mantissa bits (relative
+# 2^-9); through the encoder and 4 blocks the activations carry ~1e-2 and the
+# coupling B = U V^T, a product of two such small tensors, about twice that.
+BF16_BOUND = {"enc": 2e-2, "xd": 5e-2, "G": 5e-2, "B": 1.5e-1, "Ut": 5e-2, "Vt": 5e-2, "lam": 2e-2}
+
+
+@pytest.mark.parametrize("cfg,recipe,seed", [(PLAIN, "plain1024", 1000), (DEF, "precision8192", 2000)])
+def test_forward_bf16_close_to_oracle(cfg, recipe, seed):
+    w = test_weights(cfg)
+    fr = inputs.make_frame(recipe, seed)
+    s, fac = _run(cfg, [fr], hp.HP_BF16, w)
+    tr = {}
+    o = _oracle(cfg, s, 0, w, trace=tr)
+    n, d = fr.n, cfg.d
+    G, B, Ut, Vt, lam = s.download_factors(fac, hp.HP_BF16)[0]
+    errs = {"enc": relerr(_dbg(s, "enc", (n, d)), tr["enc"].detach().numpy()),
+            "xd": relerr(_dbg(s, "xd", (n, d)), tr[f"ffn{cfg.layers - 1}"][0].detach().numpy()),
+            "G": relerr(G, hmatrix.gram(o["F"])), "B": relerr(B, hmatrix.coupling(o["U"], o["V"])),
+            "Ut": relerr(Ut, o["Ut"]), "Vt": relerr(Vt, o["Vt"]), "lam": relerr(lam, o["lam"])}
+    print("bf16 forward vs fp64 oracle", recipe, {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= BF16_BOUND[k], (k, v)
+
+
+def test_bf16_factors_precondition_like_fp32():
+    """What the BF16 path must preserve is the preconditioner: PCG with BF16
+    factors takes (almost) the iterations of PCG with FP32 factors."""
+    import torch
+    cfg = DEF
+    w = test_weights(cfg)
+    frames = [inputs.make_frame("precision8192", 2000 + i) for i in range(2)]
+    its = {}
+    for comp in (hp.HP_F32, hp.HP_BF16):
+        s, fac = _run(cfg, frames, comp, w)
+        x = torch.zeros(s.B.ntot, dtype=torch.float64, device="cuda")
+        res = s.B.pcg_solve(s.sys, fac, s.b, x, hp.PRECOND_HMAT, fdtype=comp, tol=1e-6)
+        its[comp] = [r[0] for r in res]
+        for f, xf in enumerate(s.split(x)):
+            assert np.linalg.norm(s.bo[f] - s.A[f] @ xf) / np.linalg.norm(s.bo[f]) <= 1e-6
+    print("iterations fp32 factors", its[hp.HP_F32], "bf16 factors", its[hp.HP_BF16])
+    for a, b_ in zip(its[hp.HP_F32], its[hp.HP_BF16]):
+        assert abs(a - b_) <= max(3, 0.05 * a)
+
+
+def test_forward_batched_equals_single():
+    import torch
+    cfg = DEF
+    w = test_weights(cfg, 11)
+    frames = [inputs.make_frame("batch_mixed", 4000 + i) for i in range(3)]
+    s, fac = _run(cfg, frames, hp.HP_F32, w)
+    allf = s.download_factors(fac, hp.HP_F32)
+    for f, fr in enumerate(frames):
+        s1, fac1 = _run(cfg, [fr], hp.HP_F32, w)
+        one = s1.download_factors(fac1, hp.HP_F32)[0]
+        for a, b_ in zip(allf[f], one):
+            assert np.array_equal(a, b_)
+    # and the first frame against the oracle
+    o = _oracle(cfg, s, 0, w)
+    G, B, Ut, Vt, lam = allf[0]
+    assert relerr(G, hmatrix.gram(o["F"])) <= 1e-4
+    assert relerr(Ut, o["Ut"]) <= 1e-4 and relerr(lam, o["lam"]) <= 1e-4
