@@ -229,6 +229,15 @@ hp_status hp_infer_factors(hp_batch b, const float* d_weights, const float* d_rh
  * For tests; HP_E_INVALID on an unknown name or a size beyond the buffer. */
 hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, int64_t bytes);
 
+/* Live kernel timing for roofline figures.  After hp_profile_enable(b,
+ * "gemm"), every eager launch of that kernel family on the batch stream is
+ * bracketed by HIP events (at most 4096 launches are recorded); "none" turns
+ * it off.  hp_profile_read synchronises on the last event and returns the
+ * launch count, the summed kernel time in ms and the summed algorithmic work
+ * (GEMM: 2 M N K flops per launch), then resets the counters. */
+hp_status hp_profile_enable(hp_batch b, const char* kernel);
+hp_status hp_profile_read(hp_batch b, int32_t* launches, double* total_ms, double* work);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,6 +28,7 @@ void factor_offsets(const Batch& b, int dtype, int64_t offs[5], int64_t* total) 
 }
 
 Batch::~Batch() {
+  for (hipEvent_t e : prof.ev) hipEventDestroy(e);
   if (net_free && net.ws) net_free(net.ws);
   for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
   for (void* p : allocs) hipFree(p);
@@ -406,5 +407,37 @@ extern "C" hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_
       if (res[f].flags & HP_NOT_SPD) return set_error(HP_E_NOT_SPD, "hp_pcg_solve: frame %d lost positivity", f);
     return set_error(HP_E_NOCONV, "hp_pcg_solve: tolerance not reached");
   }
+  return HP_OK;
+}
+
+extern "C" hp_status hp_profile_enable(hp_batch b, const char* kernel) {
+  if (!b || !kernel) return set_error(HP_E_INVALID, "hp_profile_enable: NULL argument");
+  const std::string k = kernel;
+  int kind = k == "gemm" ? PROF_GEMM : k == "none" ? PROF_NONE : -1;
+  if (kind < 0) return set_error(HP_E_INVALID, "hp_profile_enable: unknown kernel family '%s'", kernel);
+  if (kind != PROF_NONE && b->prof.ev.empty()) {
+    b->prof.ev.resize(2 * 4096);
+    for (auto& e : b->prof.ev) HP_HIP(hipEventCreate(&e));
+  }
+  b->prof.kind = kind;
+  b->prof.used = 0;
+  b->prof.work = 0.0;
+  return HP_OK;
+}
+
+extern "C" hp_status hp_profile_read(hp_batch b, int32_t* launches, double* total_ms, double* work) {
+  if (!b || !launches || !total_ms || !work) return set_error(HP_E_INVALID, "hp_profile_read: NULL argument");
+  double ms = 0.0;
+  if (b->prof.used > 0) HP_HIP(hipEventSynchronize(b->prof.ev[2 * b->prof.used - 1]));
+  for (int i = 0; i < b->prof.used; ++i) {
+    float t = 0.f;
+    HP_HIP(hipEventElapsedTime(&t, b->prof.ev[2 * i], b->prof.ev[2 * i + 1]));
+    ms += t;
+  }
+  *launches = b->prof.used;
+  *total_ms = ms;
+  *work = b->prof.work;
+  b->prof.used = 0;
+  b->prof.work = 0.0;
   return HP_OK;
 }

@@ -53,8 +53,19 @@ struct NetWork {
   size_t ws_bytes = 0;
 };
 
+// Live kernel timing: every launch of one kernel family is bracketed by HIP
+// events on the batch stream (eager launches only, never inside a capture).
+enum { PROF_NONE = 0, PROF_GEMM = 1, PROF_UPDATE = 2, PROF_SPMV = 3 };
+struct Prof {
+  int kind = PROF_NONE;
+  std::vector<hipEvent_t> ev;  // 2 per launch
+  int used = 0;
+  double work = 0.0;           // algorithmic flops (GEMM) or bytes (others)
+};
+
 struct Batch {
   hp_model_config cfg{};
+  Prof prof;
   int nframes = 0;
   std::vector<FrameDesc> fr;
   std::vector<std::array<int, 3>> dims;

@@ -825,9 +825,11 @@ hp_status network_alloc(Batch& b) {
 }
 
 template <typename AT>
-static void gemm(hipStream_t st, const void* X, int64_t ldx, const NetBufs& NB, const GemmW& w, const float* bias,
+static void gemm(Batch& b, const void* X, int64_t ldx, const NetBufs& NB, const GemmW& w, const float* bias,
                  const float* resid, int64_t ldr, float* Yf, int64_t ldf, void* Yb, int64_t ldb, int64_t M, int act) {
   if (M <= 0) return;
+  hipStream_t st = b.stream;
+  const bool timed = b.prof.kind == PROF_GEMM && 2 * (b.prof.used + 1) <= (int)b.prof.ev.size();
   GemmArgs a;
   a.X = X;
   a.ldx = ldx;
@@ -844,7 +846,13 @@ static void gemm(hipStream_t st, const void* X, int64_t ldx, const NetBufs& NB, 
   a.N = w.N;
   a.act = act;
   dim3 grid((unsigned)((M + 63) / 64), (unsigned)((w.N + 63) / 64));
+  if (timed) hipEventRecord(b.prof.ev[2 * b.prof.used], st);
   hipLaunchKernelGGL(k_gemm<AT>, grid, dim3(256), 0, st, a);
+  if (timed) {
+    hipEventRecord(b.prof.ev[2 * b.prof.used + 1], st);
+    b.prof.used++;
+    b.prof.work += 2.0 * (double)M * w.N * w.K;
+  }
 }
 
 template <typename AT, typename FT>
@@ -869,19 +877,19 @@ static hp_status forward(Batch& b, const float* W, const float* rho, const float
   hipLaunchKernelGGL(k_frame_stats, dim3(b.nframes), dim3(256), 0, st, fr, rho, sys, b.ntot, N.glob);
   hipLaunchKernelGGL(k_features<AT>, dim3(b.nblk), dim3(NODE_BLOCK), 0, st, fr, b.d_blk2f, rho, sys, b.ntot, N.glob,
                      (AT*)N.feats);
-  gemm<AT>(st, N.feats, 32, N, P.enc1, wp("enc1.b"), nullptr, 0, nullptr, 0, N.a128, d, Nd, 1);
-  gemm<AT>(st, N.a128, d, N, P.enc2, wp("enc2.b"), nullptr, 0, N.H, d, N.b128, d, Nd, 0);
+  gemm<AT>(b, N.feats, 32, N, P.enc1, wp("enc1.b"), nullptr, 0, nullptr, 0, N.a128, d, Nd, 1);
+  gemm<AT>(b, N.a128, d, N, P.enc2, wp("enc2.b"), nullptr, 0, N.H, d, N.b128, d, Nd, 0);
   for (int g = 0; g < c.gcn; ++g) {
     hipLaunchKernelGGL(k_gcn_spmm<AT>, dim3((unsigned)((Nd + 1) / 2)), dim3(256), 0, st, fr, N.node2f, sys, b.ntot,
                        (const float*)N.H, (AT*)N.a128);
-    gemm<AT>(st, N.a128, d, N, P.gcn[g], wp("gcn" + std::to_string(g) + ".b"), N.H, d, N.H, d, N.b128, d, Nd, 1);
+    gemm<AT>(b, N.a128, d, N, P.gcn[g], wp("gcn" + std::to_string(g) + ".b"), N.H, d, N.H, d, N.b128, d, Nd, 1);
   }
   HP_HIP(hipMemcpyAsync(N.Henc, N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
   // off-diagonal tokens: pooled strip means through [W_r; W_c] (Sec. 4.2)
   if (use_off) {
     hipLaunchKernelGGL(k_strip_means<AT>, dim3((unsigned)No), dim3(128), 0, st, fr, N.tile2f, (const float*)N.H,
                        (const float*)N.H, (int)L, (int)LS, (AT*)N.ctx);
-    gemm<AT>(st, N.ctx, 2 * d, N, P.pool, wp("pool.b"), nullptr, 0, N.Xo, d, nullptr, 0, No, 0);
+    gemm<AT>(b, N.ctx, 2 * d, N, P.pool, wp("pool.b"), nullptr, 0, N.Xo, d, nullptr, 0, No, 0);
     HP_HIP(hipMemcpyAsync(N.Xo0, N.Xo, No * d * 4, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_off_desc, dim3((unsigned)b.mtot), dim3(256), 0, st, fr, N.tile2f, sys, b.ntot, (int)L,
                        (int)LS, N.desc);
@@ -902,7 +910,7 @@ static hp_status forward(Batch& b, const float* W, const float* rho, const float
       void* o = sidx ? N.bo128 : N.b128;
       hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, (const float*)X,
                          wp(p + "ln1.g"), wp(p + "ln1.b"), (AT*)a, (int)M);
-      gemm<AT>(st, a, d, N, P.qkv[sidx][l], wp(p + "qkv.b"), nullptr, 0, nullptr, 0, q, 3 * d, M, 0);
+      gemm<AT>(b, a, d, N, P.qkv[sidx][l], wp(p + "qkv.b"), nullptr, 0, nullptr, 0, q, 3 * d, M, 0);
       if (sidx == 0) {
         hipLaunchKernelGGL(k_edge_table, dim3((unsigned)((L * L + 63) / 64)), dim3(64), 0, st, ew, (int)L,
                            F0.xm & lowmask, F0.ym & lowmask, F0.zm & lowmask, N.T0);
@@ -927,7 +935,7 @@ static hp_status forward(Batch& b, const float* W, const float* rho, const float
           hipLaunchKernelGGL((k_attention<AT, 8, false>), dim3((unsigned)b.mtot, (unsigned)H), dim3(64), 0, st,
                              (const AT*)q, (AT*)o, (const float*)N.boff, nullptr, nullptr, (int)H);
       }
-      gemm<AT>(st, o, d, N, P.o[sidx][l], wp(p + "o.b"), X, d, X, d, nullptr, 0, M, 0);
+      gemm<AT>(b, o, d, N, P.o[sidx][l], wp(p + "o.b"), X, d, X, d, nullptr, 0, M, 0);
     }
     // highways (Sec. 4.3)
     if (c.highways) {
@@ -961,8 +969,8 @@ static hp_status forward(Batch& b, const float* W, const float* rho, const float
         hipLaunchKernelGGL(k_ln_concat<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, (const float*)X, d,
                            (const float*)N.ctxf, 2 * d, (const float*)(N.ctxf + d), 2 * d, (const float*)N.G,
                            (const int*)N.tok2f, wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, (int)M, c.highways);
-      gemm<AT>(st, u, 4 * d, N, P.f1[sidx][l], wp(p + "f1.b"), nullptr, 0, nullptr, 0, h, 4 * d, M, 1);
-      gemm<AT>(st, h, 4 * d, N, P.f2[sidx][l], wp(p + "f2.b"), X, d, X, d, nullptr, 0, M, 0);
+      gemm<AT>(b, u, 4 * d, N, P.f1[sidx][l], wp(p + "f1.b"), nullptr, 0, nullptr, 0, h, 4 * d, M, 1);
+      gemm<AT>(b, h, 4 * d, N, P.f2[sidx][l], wp(p + "f2.b"), X, d, X, d, nullptr, 0, M, 0);
     }
   }
   // heads (Sec. 4.4)
@@ -971,15 +979,15 @@ static hp_status forward(Batch& b, const float* W, const float* rho, const float
   factor_offsets(b, sizeof(FT) == 2 ? HP_BF16 : HP_F32, offs, &tot);
   hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((Nd + 3) / 4)), dim3(256), 0, st, (const float*)N.H,
                      wp("diaglnf.g"), wp("diaglnf.b"), (AT*)N.a128, (int)Nd);
-  gemm<AT>(st, N.a128, d, N, P.hleaf1, wp("hleaf1.b"), nullptr, 0, nullptr, 0, N.b128, d, Nd, 1);
-  gemm<AT>(st, N.b128, d, N, P.hleaf2, wp("hleaf2.b"), nullptr, 0, N.Frows, L, nullptr, 0, Nd, 0);
+  gemm<AT>(b, N.a128, d, N, P.hleaf1, wp("hleaf1.b"), nullptr, 0, nullptr, 0, N.b128, d, Nd, 1);
+  gemm<AT>(b, N.b128, d, N, P.hleaf2, wp("hleaf2.b"), nullptr, 0, N.Frows, L, nullptr, 0, Nd, 0);
   if (L == 64)
     hipLaunchKernelGGL((k_gram<FT, 64>), dim3((unsigned)b.ktot), dim3(256), 0, st, (const float*)N.Frows,
                        (FT*)(base + offs[0]));
   else
     hipLaunchKernelGGL((k_gram<FT, 32>), dim3((unsigned)b.ktot), dim3(256), 0, st, (const float*)N.Frows,
                        (FT*)(base + offs[0]));
-  gemm<AT>(st, N.a128, d, N, P.hnode, N.bias_node, nullptr, 0, N.NH, 36, nullptr, 0, Nd, 0);
+  gemm<AT>(b, N.a128, d, N, P.hnode, N.bias_node, nullptr, 0, N.NH, 36, nullptr, 0, Nd, 0);
   if (LS == 16)
     hipLaunchKernelGGL((k_pack_nodes<FT, 16>), dim3((unsigned)((Nd + 255) / 256)), dim3(256), 0, st,
                        (const float*)N.NH, Nd, (FT*)(base + offs[2]), (FT*)(base + offs[3]), (float*)(base + offs[4]));
@@ -990,7 +998,7 @@ static hp_status forward(Batch& b, const float* W, const float* rho, const float
     if (use_off) {
       hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((No + 3) / 4)), dim3(256), 0, st, (const float*)N.Xo,
                          wp("offlnf.g"), wp("offlnf.b"), (AT*)N.ao128, (int)No);
-      gemm<AT>(st, N.ao128, d, N, P.huv, N.bias_uv, nullptr, 0, N.UV, 2 * LS, nullptr, 0, No, 0);
+      gemm<AT>(b, N.ao128, d, N, P.huv, N.bias_uv, nullptr, 0, N.UV, 2 * LS, nullptr, 0, No, 0);
     } else {
       HP_HIP(hipMemsetAsync(N.UV, 0, No * 2 * LS * 4, st));
     }

@@ -72,6 +72,9 @@ EXPORTS = {
                         C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int32),
     "hp_infer_factors": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32], C.c_int32),
     "hp_debug_copy": ([C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64], C.c_int32),
+    "hp_profile_enable": ([C.c_void_p, C.c_char_p], C.c_int32),
+    "hp_profile_read": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double)],
+                        C.c_int32),
 }
 
 
@@ -243,6 +246,14 @@ class Batch:
         if not (st in (5, 6) and not raise_on_fail):
             _check(st)
         return [(r.iters, r.flags, r.relres) for r in res]
+
+    def profile_enable(self, kernel: str):
+        _check(lib().hp_profile_enable(self.h, kernel.encode()))
+
+    def profile_read(self):
+        n, ms, work = C.c_int32(), C.c_double(), C.c_double()
+        _check(lib().hp_profile_read(self.h, C.byref(n), C.byref(ms), C.byref(work)))
+        return n.value, ms.value, work.value
 
     def infer_factors(self, weights, rho, sys, fac, compute: int):
         _check(lib().hp_infer_factors(self.h, _ptr(weights), _ptr(rho), _ptr(sys), _ptr(fac), compute))
