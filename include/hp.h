@@ -216,6 +216,41 @@ hp_status hp_weight_info(const hp_model_config* cfg, int32_t index, char* name, 
 hp_status hp_infer_factors(hp_batch b, const float* d_weights, const float* d_rho,
                            const float* d_sys, void* d_factors, int32_t compute);
 
+/* ------------------------------------------------------------------ training */
+
+/* The paper's factor set of one batch (Sec. 4.4), FP32 device arrays:
+ * F [ktot][L][L] leaf factors (diagonal block F_k F_k^T), U, V
+ * [mtot][L_s][L_s] tile factors (B_m = U_m V_m^T), Ut, Vt [ntot][L_s] node
+ * bridges, lam [ntot] Jacobi gate (M adds diag(lam) diag(A)^-1). */
+typedef struct {
+  float *F, *U, *V, *Ut, *Vt, *lam;
+} hp_factor_set;
+
+/* Allocate the training workspace of the batch (the only allocating call
+ * besides hp_batch_create).  kz = probes per system, must be 16. */
+hp_status hp_train_init(hp_batch b, int32_t kz);
+
+/* Spectrally biased probes (Sec. 6.2, Eq. 8): z = (I - omega D^-1 A)^sweeps zraw,
+ * then x = A z (the loss treats x as fixed input).  zraw, z, x: [ntot][16] FP32,
+ * row-major; zraw and z must not alias. */
+hp_status hp_probes(hp_batch b, const float* d_sys, const float* d_zraw, float* d_z, float* d_x, int32_t sweeps,
+                    float omega);
+
+/* Cosine-Hutchinson loss (Sec. 6.1, Eq. loss) of every frame f:
+ * loss_f = 1 - <Z_f, Y_f>_F / (||Z_f||_F ||Y_f||_F) with Y = M X, M from the
+ * factor set f.  h_loss [nframes] (host) receives loss_f; the call
+ * synchronises.  scale weights the objective scale * sum_f loss_f whose
+ * gradient hp_loss_bwd returns (1/nframes gives the batch mean).  Sums of
+ * <Z,Y>, ||Z||^2, ||Y||^2 are FP64 in a fixed order. */
+hp_status hp_loss_fwd(hp_batch b, const float* d_sys, const hp_factor_set* f, const float* d_x, const float* d_z,
+                      double scale, double* h_loss);
+
+/* Gradient of scale * sum_f loss_f with respect to every array of the factor
+ * set, written to grad (overwritten, FP32).  Must follow hp_loss_fwd with the
+ * same arguments on the same batch (it reuses that call's saved state). */
+hp_status hp_loss_bwd(hp_batch b, const float* d_sys, const hp_factor_set* f, const float* d_x, const float* d_z,
+                      const hp_factor_set* grad);
+
 /* ------------------------------------------------------------------ diagnostics */
 
 /* Copy `bytes` of a named internal buffer of the last hp_infer_factors call

@@ -19,7 +19,7 @@ OUT = os.path.join(PKG, "libhp.so")
 BUILD = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("HP_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["host.cpp", "api.cpp", "solver.hip", "network.hip"]
+SOURCES = ["host.cpp", "api.cpp", "solver.hip", "network.hip", "train.hip"]
 
 
 def _hipcc() -> str:

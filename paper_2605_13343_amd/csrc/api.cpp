@@ -30,6 +30,8 @@ void factor_offsets(const Batch& b, int dtype, int64_t offs[5], int64_t* total) 
 Batch::~Batch() {
   for (hipEvent_t e : prof.ev) hipEventDestroy(e);
   if (net_free && net.ws) net_free(net.ws);
+  if (train_free && train_ws) train_free(train_ws);
+  if (net_train_free && net_train) net_train_free(net_train);
   for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
   for (void* p : allocs) hipFree(p);
   if (h_pin) hipHostFree(h_pin);

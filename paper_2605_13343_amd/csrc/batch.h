@@ -90,6 +90,10 @@ struct Batch {
   SolveParams* prm = nullptr;
   NetWork net;
   void (*net_free)(void*) = nullptr;  // releases net.ws
+  void* train_ws = nullptr;             // training workspace (hp_train_init)
+  void (*train_free)(void*) = nullptr;
+  void* net_train = nullptr;            // network training workspace (first hp_train_grad)
+  void (*net_train_free)(void*) = nullptr;
   std::map<std::tuple<int, int, const void*, const void*, const void*, const void*, int>, hipGraphExec_t> graphs;
   std::vector<void*> allocs;
 
@@ -111,6 +115,14 @@ hp_status pcg_finalize(const PcgLaunch& P);
 
 // network.hip
 hp_status network_alloc(Batch& b);
+
+// train.hip
+hp_status train_ws_alloc(Batch& b);
+hp_status loss_fwd(Batch& b, const float* sys, const hp_factor_set& f, const float* X, const float* Z, double scale);
+hp_status loss_bwd(Batch& b, const float* sys, const hp_factor_set& f, const float* X, const float* Z,
+                   const hp_factor_set& g);
+hp_status probes(Batch& b, const float* sys, const float* zraw, float* z, float* x, int sweeps, float omega);
+const double* train_lossf(Batch& b);
 
 }  // namespace hp
 

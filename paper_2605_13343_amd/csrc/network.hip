@@ -44,6 +44,8 @@ struct GemmArgs {
   int64_t ldf;
   void* Yb;
   int64_t ldb;
+  float* pre;   // optional: value before the activation (after the bias)
+  int64_t ldp;
   int M, N, act;
 };
 
@@ -108,6 +110,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
       const int row = m0 + wm + i * 8 + (lane >> 5) * 4 + j;
       if (row >= a.M) continue;
       float v = acc[i * 4 + j] + bc;
+      if (a.pre) a.pre[(int64_t)row * a.ldp + col] = v;
       if (a.act == 1) v = gelu_f(v);
       if (a.resid) v += a.resid[(int64_t)row * a.ldr + col];
       if (a.Yf) a.Yf[(int64_t)row * a.ldf + col] = v;
@@ -168,8 +171,8 @@ __global__ __launch_bounds__(256) void k_ln_concat(const float* S0, int64_t ld0,
 }
 
 // ------------------------------------------------------------------ features
-// Per-frame summary (one block per frame), this build's definition of the
-// 12 global features: log2(N)/16, log(rho_max/rho_min), mean and std of
+// Per-frame summary (one block per frame), the definition used here of
+// the 12 global features: log2(N)/16, log(rho_max/rho_min), mean and std of
 // log rho, heavy fraction, mean/std/min/max of log A_ii, nx/32, ny/32, nz/32.
 __global__ __launch_bounds__(256) void k_frame_stats(const FrameDesc* fr, const float* rho, const float* sys,
                                                      int64_t ntot, float* glob) {
@@ -626,12 +629,17 @@ struct ConvDesc {
   int rows, cols, ld, n_off, k_off, pad;
 };
 
+// pad == 0 (transposed, forward):  dst[(n_off + n) * ld + k_off + k] = src[k * cols + n]
+// pad == 1 (plain, backward dX):   dst[(k_off + k) * ld + n_off + n] = src[k * cols + n]
+// Grid: (descriptor, chunk of 4096 elements).
 template <typename AT>
 __global__ void k_convert(const ConvDesc* d, const float* W, AT* out) {
   const ConvDesc c = d[blockIdx.x];
-  for (int idx = threadIdx.x; idx < c.rows * c.cols; idx += blockDim.x) {
+  const int begin = blockIdx.y * 4096, end = min(c.rows * c.cols, begin + 4096);
+  for (int idx = begin + threadIdx.x; idx < end; idx += blockDim.x) {
     const int k = idx / c.cols, n = idx % c.cols;
-    out[c.dst + (int64_t)(c.n_off + n) * c.ld + c.k_off + k] = to_act<AT>(W[c.src + idx]);
+    const int64_t o = c.pad ? (int64_t)(c.k_off + k) * c.ld + c.n_off + n : (int64_t)(c.n_off + n) * c.ld + c.k_off + k;
+    out[c.dst + o] = to_act<AT>(W[c.src + idx]);
   }
 }
 
@@ -646,8 +654,13 @@ struct NetPlan {
   std::vector<WeightEntry> lay;
   std::vector<ConvDesc> conv;
   int64_t arena = 0;
+  int maxconv = 0;  // largest descriptor (elements)
   GemmW enc1, enc2, gcn[4], pool, hleaf1, hleaf2, hnode, huv;
   GemmW qkv[2][16], o[2][16], f1[2][16], f2[2][16];
+  // plain copies W[in][out] for the input-gradient GEMMs dX = dY W^T
+  // (N = in features, K = out features padded to 32)
+  GemmW b_enc2, b_gcn[4], b_pool, b_hleaf1, b_hleaf2, b_hnode, b_huv;
+  GemmW b_qkv[2][16], b_o[2][16], b_f1[2][16], b_f2[2][16];
 };
 
 static int64_t woff(const NetPlan& P, const std::string& n) {
@@ -702,6 +715,45 @@ static NetPlan make_plan(const hp_model_config& c) {
   P.huv = gemm(2 * LS, d);
   conv(P.huv, "hu.w", 0, 0);
   conv(P.huv, "hv.w", LS, 0);
+  // backward copies
+  auto bconv = [&](const GemmW& g, const std::string& name, int n_off, int k_off) {
+    const WeightEntry* e = find_weight(P.lay, name);
+    P.conv.push_back(ConvDesc{e->offset, g.off, e->rows, e->cols, g.K, n_off, k_off, 1});
+  };
+  auto pad32 = [](int v) { return (v + 31) / 32 * 32; };
+  P.b_enc2 = gemm(d, d);
+  bconv(P.b_enc2, "enc2.w", 0, 0);
+  for (int g = 0; g < c.gcn; ++g) {
+    P.b_gcn[g] = gemm(d, d);
+    bconv(P.b_gcn[g], "gcn" + std::to_string(g) + ".w", 0, 0);
+  }
+  P.b_pool = gemm(2 * d, d);
+  bconv(P.b_pool, "pool.wr", 0, 0);
+  bconv(P.b_pool, "pool.wc", 0, d);
+  for (int s = 0; s < 2; ++s)
+    for (int l = 0; l < c.layers; ++l) {
+      std::string p = std::string(s ? "off" : "diag") + std::to_string(l) + ".";
+      P.b_qkv[s][l] = gemm(d, 3 * d);
+      bconv(P.b_qkv[s][l], p + "qkv.w", 0, 0);
+      P.b_o[s][l] = gemm(d, d);
+      bconv(P.b_o[s][l], p + "o.w", 0, 0);
+      P.b_f1[s][l] = gemm(4 * d, 4 * d);
+      bconv(P.b_f1[s][l], p + "f1.w", 0, 0);
+      P.b_f2[s][l] = gemm(4 * d, d);
+      bconv(P.b_f2[s][l], p + "f2.w", 0, 0);
+    }
+  P.b_hleaf1 = gemm(d, d);
+  bconv(P.b_hleaf1, "hleaf1.w", 0, 0);
+  P.b_hleaf2 = gemm(d, pad32(c.leaf));
+  bconv(P.b_hleaf2, "hleaf2.w", 0, 0);
+  P.b_hnode = gemm(d, 64);
+  bconv(P.b_hnode, "hut.w", 0, 0);
+  bconv(P.b_hnode, "hvt.w", LS, 0);
+  bconv(P.b_hnode, "hlam.w", 2 * LS, 0);
+  P.b_huv = gemm(d, pad32(2 * LS));
+  bconv(P.b_huv, "hu.w", 0, 0);
+  bconv(P.b_huv, "hv.w", LS, 0);
+  for (auto& cd : P.conv) P.maxconv = std::max(P.maxconv, cd.rows * cd.cols);
   return P;
 }
 
@@ -826,7 +878,8 @@ hp_status network_alloc(Batch& b) {
 
 template <typename AT>
 static void gemm(Batch& b, const void* X, int64_t ldx, const NetBufs& NB, const GemmW& w, const float* bias,
-                 const float* resid, int64_t ldr, float* Yf, int64_t ldf, void* Yb, int64_t ldb, int64_t M, int act) {
+                 const float* resid, int64_t ldr, float* Yf, int64_t ldf, void* Yb, int64_t ldb, int64_t M, int act,
+                 float* pre = nullptr, int64_t ldp = 0) {
   if (M <= 0) return;
   hipStream_t st = b.stream;
   const bool timed = b.prof.kind == PROF_GEMM && 2 * (b.prof.used + 1) <= (int)b.prof.ev.size();
@@ -842,6 +895,8 @@ static void gemm(Batch& b, const void* X, int64_t ldx, const NetBufs& NB, const 
   a.ldf = ldf;
   a.Yb = Yb;
   a.ldb = ldb;
+  a.pre = pre;
+  a.ldp = ldp;
   a.M = (int)M;
   a.N = w.N;
   a.act = act;
@@ -855,8 +910,21 @@ static void gemm(Batch& b, const void* X, int64_t ldx, const NetBufs& NB, const 
   }
 }
 
-template <typename AT, typename FT>
-static hp_status forward(Batch& b, const float* W, const float* rho, const float* sys, void* fac) {
+// Training saves of the forward pass (FP32).
+struct TrainSave {
+  float* Hg[5];                      // encoder: input of each GCN layer, then the encoder output
+  float* xin_d[17];                  // residual streams entering each layer (and after the last)
+  float* xin_o[17];
+};
+struct LayerSave {
+  float *xmid_d, *xmid_o;            // FFN residual inputs
+  float *pre_d, *pre_o;              // FFN hidden pre-activations [M][4d]
+};
+
+// Features, encoder, pooled off-diagonal tokens, descriptors and stencils.
+// With sv, the encoder's intermediate H values are saved for training.
+template <typename AT>
+static hp_status fwd_prologue(Batch& b, const float* W, const float* rho, const float* sys, TrainSave* sv) {
   NetBufs& N = *nb_of(b);
   const NetPlan& P = N.plan;
   const hp_model_config& c = b.cfg;
@@ -866,8 +934,10 @@ static hp_status forward(Batch& b, const float* W, const float* rho, const float
   const bool use_off = c.offdiag && b.mtot > 0;
   const FrameDesc* fr = b.d_fr;
   auto wp = [&](const std::string& n) { return W + woff(P, n); };
+  (void)fr; (void)use_off; (void)H; (void)No; (void)L; (void)LS;
   // weights -> transposed arena in the compute type
-  hipLaunchKernelGGL(k_convert<AT>, dim3((unsigned)P.conv.size()), dim3(256), 0, st, N.d_conv, W, (AT*)N.warena);
+  hipLaunchKernelGGL(k_convert<AT>, dim3((unsigned)P.conv.size(), (unsigned)((P.maxconv + 4095) / 4096)), dim3(256),
+                     0, st, N.d_conv, W, (AT*)N.warena);
   HP_HIP(hipMemcpyAsync(N.bias_node, wp("hut.b"), LS * 4, hipMemcpyDeviceToDevice, st));
   HP_HIP(hipMemcpyAsync(N.bias_node + LS, wp("hvt.b"), LS * 4, hipMemcpyDeviceToDevice, st));
   HP_HIP(hipMemcpyAsync(N.bias_node + 2 * LS, wp("hlam.b"), 4, hipMemcpyDeviceToDevice, st));
@@ -880,11 +950,13 @@ static hp_status forward(Batch& b, const float* W, const float* rho, const float
   gemm<AT>(b, N.feats, 32, N, P.enc1, wp("enc1.b"), nullptr, 0, nullptr, 0, N.a128, d, Nd, 1);
   gemm<AT>(b, N.a128, d, N, P.enc2, wp("enc2.b"), nullptr, 0, N.H, d, N.b128, d, Nd, 0);
   for (int g = 0; g < c.gcn; ++g) {
+    if (sv) HP_HIP(hipMemcpyAsync(sv->Hg[g], N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_gcn_spmm<AT>, dim3((unsigned)((Nd + 1) / 2)), dim3(256), 0, st, fr, N.node2f, sys, b.ntot,
                        (const float*)N.H, (AT*)N.a128);
     gemm<AT>(b, N.a128, d, N, P.gcn[g], wp("gcn" + std::to_string(g) + ".b"), N.H, d, N.H, d, N.b128, d, Nd, 1);
   }
   HP_HIP(hipMemcpyAsync(N.Henc, N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
+  if (sv) HP_HIP(hipMemcpyAsync(sv->Hg[c.gcn], N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
   // off-diagonal tokens: pooled strip means through [W_r; W_c] (Sec. 4.2)
   if (use_off) {
     hipLaunchKernelGGL(k_strip_means<AT>, dim3((unsigned)No), dim3(128), 0, st, fr, N.tile2f, (const float*)N.H,
@@ -896,83 +968,120 @@ static hp_status forward(Batch& b, const float* W, const float* rho, const float
   }
   hipLaunchKernelGGL(k_leaf_stencil, dim3((unsigned)((Nd + 255) / 256)), dim3(256), 0, st, fr, N.node2f, sys, b.ntot,
                      (int)L, N.nbr, N.ahat);
+  HP_HIP(hipGetLastError());
+  return HP_OK;
+}
+
+// One transformer block of both stacks (Sec. 4.2-4.3), in place on the
+// residual streams N.H / N.Xo.  With ls, the FFN residual inputs and the
+// FFN pre-activations are saved for the reverse pass.
+template <typename AT>
+static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, LayerSave* ls) {
+  NetBufs& N = *nb_of(b);
+  const NetPlan& P = N.plan;
+  const hp_model_config& c = b.cfg;
+  hipStream_t st = b.stream;
+  const int64_t Nd = N.Nd, d = c.d, L = c.leaf, LS = c.rank, H = c.heads;
+  const int64_t No = b.mtot * LS;
+  const bool use_off = c.offdiag && b.mtot > 0;
+  const FrameDesc* fr = b.d_fr;
+  auto wp = [&](const std::string& n) { return W + woff(P, n); };
+  (void)fr; (void)use_off; (void)H; (void)No; (void)L; (void)LS;
   const unsigned lowmask = (unsigned)(L - 1);
   const FrameDesc& F0 = b.fr[0];
-  for (int l = 0; l < c.layers; ++l) {
-    for (int sidx = 0; sidx < 2; ++sidx) {
-      if (sidx == 1 && !use_off) continue;
-      const std::string p = std::string(sidx ? "off" : "diag") + std::to_string(l) + ".";
-      EdgeW ew{wp(p + "e1.w"), wp(p + "e1.b"), wp(p + "e2.w"), wp(p + "e2.b"), c.edge_hidden, (int)H};
-      float* X = sidx ? N.Xo : N.H;
-      const int64_t M = sidx ? No : Nd;
-      void* a = sidx ? N.ao128 : N.a128;
-      void* q = sidx ? N.qkvo : N.qkv;
-      void* o = sidx ? N.bo128 : N.b128;
-      hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, (const float*)X,
-                         wp(p + "ln1.g"), wp(p + "ln1.b"), (AT*)a, (int)M);
-      gemm<AT>(b, a, d, N, P.qkv[sidx][l], wp(p + "qkv.b"), nullptr, 0, nullptr, 0, q, 3 * d, M, 0);
-      if (sidx == 0) {
-        hipLaunchKernelGGL(k_edge_table, dim3((unsigned)((L * L + 63) / 64)), dim3(64), 0, st, ew, (int)L,
-                           F0.xm & lowmask, F0.ym & lowmask, F0.zm & lowmask, N.T0);
-        hipLaunchKernelGGL(k_edge_corr, dim3((unsigned)((Nd * 7 + 127) / 128)), dim3(128), 0, st, ew,
-                           (const uint8_t*)N.nbr, (const float*)N.ahat, Nd, N.corr);
-        if (L == 64)
-          hipLaunchKernelGGL((k_attention<AT, 64, true>), dim3((unsigned)b.ktot, (unsigned)H), dim3(64), 0, st,
-                             (const AT*)q, (AT*)o, (const float*)N.T0, (const float*)N.corr, (const uint8_t*)N.nbr,
-                             (int)H);
-        else
-          hipLaunchKernelGGL((k_attention<AT, 32, true>), dim3((unsigned)b.ktot, (unsigned)H), dim3(64), 0, st,
-                             (const AT*)q, (AT*)o, (const float*)N.T0, (const float*)N.corr, (const uint8_t*)N.nbr,
-                             (int)H);
-      } else {
-        const int64_t npairs = b.mtot * LS * LS;
-        hipLaunchKernelGGL(k_edge_off, dim3((unsigned)((npairs + 127) / 128)), dim3(128), 0, st, ew,
-                           (const float*)N.desc, npairs, (int)LS, N.boff);
-        if (LS == 16)
-          hipLaunchKernelGGL((k_attention<AT, 16, false>), dim3((unsigned)b.mtot, (unsigned)H), dim3(64), 0, st,
-                             (const AT*)q, (AT*)o, (const float*)N.boff, nullptr, nullptr, (int)H);
-        else
-          hipLaunchKernelGGL((k_attention<AT, 8, false>), dim3((unsigned)b.mtot, (unsigned)H), dim3(64), 0, st,
-                             (const AT*)q, (AT*)o, (const float*)N.boff, nullptr, nullptr, (int)H);
-      }
-      gemm<AT>(b, o, d, N, P.o[sidx][l], wp(p + "o.b"), X, d, X, d, nullptr, 0, M, 0);
-    }
-    // highways (Sec. 4.3)
-    if (c.highways) {
-      if (use_off) {
-        hipLaunchKernelGGL(k_highway_rc, dim3((unsigned)((Nd + 1) / 2)), dim3(256), 0, st, fr, N.node2f,
-                           (const float*)N.H, (const float*)N.Xo, (int)L, (int)LS, Nd, N.R, N.C);
-      } else {
-        HP_HIP(hipMemcpyAsync(N.R, N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
-        HP_HIP(hipMemcpyAsync(N.C, N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
-      }
-      hipLaunchKernelGGL(k_chunk_sums, dim3((unsigned)N.nchunks), dim3(128), 0, st, (const SumChunk*)N.chunks,
-                         (const float*)N.H, (const float*)N.Xo, N.gpart);
-      hipLaunchKernelGGL(k_frame_mean, dim3(b.nframes), dim3(128), 0, st, (const int*)N.chunk0,
-                         (const float*)N.gpart, (const float*)N.gcount, N.G);
-      if (use_off)
-        hipLaunchKernelGGL(k_strip_means<float>, dim3((unsigned)No), dim3(128), 0, st, fr, N.tile2f,
-                           (const float*)N.R, (const float*)N.C, (int)L, (int)LS, N.ctxf);
-    }
-    for (int sidx = 0; sidx < 2; ++sidx) {
-      if (sidx == 1 && !use_off) continue;
-      const std::string p = std::string(sidx ? "off" : "diag") + std::to_string(l) + ".";
-      float* X = sidx ? N.Xo : N.H;
-      const int64_t M = sidx ? No : Nd;
-      void* u = sidx ? N.uo512 : N.u512;
-      void* h = sidx ? N.ho512 : N.h512;
-      if (sidx == 0)
-        hipLaunchKernelGGL(k_ln_concat<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, (const float*)X, d,
-                           (const float*)N.R, d, (const float*)N.C, d, (const float*)N.G, (const int*)N.node2f,
-                           wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, (int)M, c.highways);
+  for (int sidx = 0; sidx < 2; ++sidx) {
+    if (sidx == 1 && !use_off) continue;
+    const std::string p = std::string(sidx ? "off" : "diag") + std::to_string(l) + ".";
+    EdgeW ew{wp(p + "e1.w"), wp(p + "e1.b"), wp(p + "e2.w"), wp(p + "e2.b"), c.edge_hidden, (int)H};
+    float* X = sidx ? N.Xo : N.H;
+    const int64_t M = sidx ? No : Nd;
+    void* a = sidx ? N.ao128 : N.a128;
+    void* q = sidx ? N.qkvo : N.qkv;
+    void* o = sidx ? N.bo128 : N.b128;
+    hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, (const float*)X,
+                       wp(p + "ln1.g"), wp(p + "ln1.b"), (AT*)a, (int)M);
+    gemm<AT>(b, a, d, N, P.qkv[sidx][l], wp(p + "qkv.b"), nullptr, 0, nullptr, 0, q, 3 * d, M, 0);
+    if (sidx == 0) {
+      hipLaunchKernelGGL(k_edge_table, dim3((unsigned)((L * L + 63) / 64)), dim3(64), 0, st, ew, (int)L,
+                         F0.xm & lowmask, F0.ym & lowmask, F0.zm & lowmask, N.T0);
+      hipLaunchKernelGGL(k_edge_corr, dim3((unsigned)((Nd * 7 + 127) / 128)), dim3(128), 0, st, ew,
+                         (const uint8_t*)N.nbr, (const float*)N.ahat, Nd, N.corr);
+      if (L == 64)
+        hipLaunchKernelGGL((k_attention<AT, 64, true>), dim3((unsigned)b.ktot, (unsigned)H), dim3(64), 0, st,
+                           (const AT*)q, (AT*)o, (const float*)N.T0, (const float*)N.corr, (const uint8_t*)N.nbr,
+                           (int)H);
       else
-        hipLaunchKernelGGL(k_ln_concat<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, (const float*)X, d,
-                           (const float*)N.ctxf, 2 * d, (const float*)(N.ctxf + d), 2 * d, (const float*)N.G,
-                           (const int*)N.tok2f, wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, (int)M, c.highways);
-      gemm<AT>(b, u, 4 * d, N, P.f1[sidx][l], wp(p + "f1.b"), nullptr, 0, nullptr, 0, h, 4 * d, M, 1);
-      gemm<AT>(b, h, 4 * d, N, P.f2[sidx][l], wp(p + "f2.b"), X, d, X, d, nullptr, 0, M, 0);
+        hipLaunchKernelGGL((k_attention<AT, 32, true>), dim3((unsigned)b.ktot, (unsigned)H), dim3(64), 0, st,
+                           (const AT*)q, (AT*)o, (const float*)N.T0, (const float*)N.corr, (const uint8_t*)N.nbr,
+                           (int)H);
+    } else {
+      const int64_t npairs = b.mtot * LS * LS;
+      hipLaunchKernelGGL(k_edge_off, dim3((unsigned)((npairs + 127) / 128)), dim3(128), 0, st, ew,
+                         (const float*)N.desc, npairs, (int)LS, N.boff);
+      if (LS == 16)
+        hipLaunchKernelGGL((k_attention<AT, 16, false>), dim3((unsigned)b.mtot, (unsigned)H), dim3(64), 0, st,
+                           (const AT*)q, (AT*)o, (const float*)N.boff, nullptr, nullptr, (int)H);
+      else
+        hipLaunchKernelGGL((k_attention<AT, 8, false>), dim3((unsigned)b.mtot, (unsigned)H), dim3(64), 0, st,
+                           (const AT*)q, (AT*)o, (const float*)N.boff, nullptr, nullptr, (int)H);
     }
+    gemm<AT>(b, o, d, N, P.o[sidx][l], wp(p + "o.b"), X, d, X, d, nullptr, 0, M, 0);
   }
+  // highways (Sec. 4.3)
+  if (c.highways) {
+    if (use_off) {
+      hipLaunchKernelGGL(k_highway_rc, dim3((unsigned)((Nd + 1) / 2)), dim3(256), 0, st, fr, N.node2f,
+                         (const float*)N.H, (const float*)N.Xo, (int)L, (int)LS, Nd, N.R, N.C);
+    } else {
+      HP_HIP(hipMemcpyAsync(N.R, N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
+      HP_HIP(hipMemcpyAsync(N.C, N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
+    }
+    hipLaunchKernelGGL(k_chunk_sums, dim3((unsigned)N.nchunks), dim3(128), 0, st, (const SumChunk*)N.chunks,
+                       (const float*)N.H, (const float*)N.Xo, N.gpart);
+    hipLaunchKernelGGL(k_frame_mean, dim3(b.nframes), dim3(128), 0, st, (const int*)N.chunk0,
+                       (const float*)N.gpart, (const float*)N.gcount, N.G);
+    if (use_off)
+      hipLaunchKernelGGL(k_strip_means<float>, dim3((unsigned)No), dim3(128), 0, st, fr, N.tile2f,
+                         (const float*)N.R, (const float*)N.C, (int)L, (int)LS, N.ctxf);
+  }
+  for (int sidx = 0; sidx < 2; ++sidx) {
+    if (sidx == 1 && !use_off) continue;
+    const std::string p = std::string(sidx ? "off" : "diag") + std::to_string(l) + ".";
+    float* X = sidx ? N.Xo : N.H;
+    const int64_t M = sidx ? No : Nd;
+    void* u = sidx ? N.uo512 : N.u512;
+    void* h = sidx ? N.ho512 : N.h512;
+    if (sidx == 0)
+      hipLaunchKernelGGL(k_ln_concat<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, (const float*)X, d,
+                         (const float*)N.R, d, (const float*)N.C, d, (const float*)N.G, (const int*)N.node2f,
+                         wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, (int)M, c.highways);
+    else
+      hipLaunchKernelGGL(k_ln_concat<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, (const float*)X, d,
+                         (const float*)N.ctxf, 2 * d, (const float*)(N.ctxf + d), 2 * d, (const float*)N.G,
+                         (const int*)N.tok2f, wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, (int)M, c.highways);
+    if (ls) HP_HIP(hipMemcpyAsync(sidx ? ls->xmid_o : ls->xmid_d, X, M * d * 4, hipMemcpyDeviceToDevice, st));
+    gemm<AT>(b, u, 4 * d, N, P.f1[sidx][l], wp(p + "f1.b"), nullptr, 0, nullptr, 0, h, 4 * d, M, 1,
+             ls ? (sidx ? ls->pre_o : ls->pre_d) : nullptr, 4 * d);
+    gemm<AT>(b, h, 4 * d, N, P.f2[sidx][l], wp(p + "f2.b"), X, d, X, d, nullptr, 0, M, 0);
+  }
+  HP_HIP(hipGetLastError());
+  return HP_OK;
+}
+
+template <typename AT, typename FT>
+static hp_status forward(Batch& b, const float* W, const float* rho, const float* sys, void* fac) {
+  HP_TRY(fwd_prologue<AT>(b, W, rho, sys, nullptr));
+  for (int l = 0; l < b.cfg.layers; ++l) HP_TRY(layer_fwd<AT>(b, W, sys, l, nullptr));
+  NetBufs& N = *nb_of(b);
+  const NetPlan& P = N.plan;
+  const hp_model_config& c = b.cfg;
+  hipStream_t st = b.stream;
+  const int64_t Nd = N.Nd, d = c.d, L = c.leaf, LS = c.rank, H = c.heads;
+  const int64_t No = b.mtot * LS;
+  const bool use_off = c.offdiag && b.mtot > 0;
+  const FrameDesc* fr = b.d_fr;
+  auto wp = [&](const std::string& n) { return W + woff(P, n); };
+  (void)fr; (void)use_off; (void)H; (void)No; (void)L; (void)LS;
   // heads (Sec. 4.4)
   const char* base = (const char*)fac;
   int64_t offs[5], tot;

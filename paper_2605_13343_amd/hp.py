@@ -48,6 +48,10 @@ class SolveOpts(C.Structure):
                 ("chunk", C.c_int32), ("stagnation", C.c_int32)]
 
 
+class FactorSet(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("F", "U", "V", "Ut", "Vt", "lam")]
+
+
 class SolveResult(C.Structure):
     _fields_ = [("iters", C.c_int32), ("flags", C.c_int32), ("relres", C.c_double)]
 
@@ -73,6 +77,12 @@ EXPORTS = {
     "hp_infer_factors": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32], C.c_int32),
     "hp_debug_copy": ([C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64], C.c_int32),
     "hp_profile_enable": ([C.c_void_p, C.c_char_p], C.c_int32),
+    "hp_train_init": ([C.c_void_p, C.c_int32], C.c_int32),
+    "hp_probes": ([C.c_void_p] * 5 + [C.c_int32, C.c_float], C.c_int32),
+    "hp_loss_fwd": ([C.c_void_p, C.c_void_p, C.POINTER(FactorSet), C.c_void_p, C.c_void_p, C.c_double,
+                     C.c_void_p], C.c_int32),
+    "hp_loss_bwd": ([C.c_void_p, C.c_void_p, C.POINTER(FactorSet), C.c_void_p, C.c_void_p, C.POINTER(FactorSet)],
+                    C.c_int32),
     "hp_profile_read": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double)],
                         C.c_int32),
 }
@@ -255,5 +265,85 @@ class Batch:
         _check(lib().hp_profile_read(self.h, C.byref(n), C.byref(ms), C.byref(work)))
         return n.value, ms.value, work.value
 
+    # -- training objective
+    def train_init(self, kz: int = 16):
+        _check(lib().hp_train_init(self.h, kz))
+
+    def new_factor_set(self):
+        import torch
+        L, LS = self.cfg.leaf, self.cfg.rank
+        z = lambda *s: torch.zeros(*s, dtype=torch.float32, device="cuda")
+        m = max(self.mtot, 1)
+        return dict(F=z(self.ktot, L, L), U=z(m, LS, LS), V=z(m, LS, LS), Ut=z(self.ntot, LS), Vt=z(self.ntot, LS),
+                    lam=z(self.ntot))
+
+    @staticmethod
+    def _fs(d):
+        return FactorSet(*(d[k].data_ptr() for k in ("F", "U", "V", "Ut", "Vt", "lam")))
+
+    def probes(self, sys, zraw, z, x, sweeps: int = 2, omega: float = 0.6):
+        _check(lib().hp_probes(self.h, _ptr(sys), _ptr(zraw), _ptr(z), _ptr(x), sweeps, omega))
+
+    def loss_fwd(self, sys, fset, x, z, scale: float):
+        out = np.zeros(len(self.dims), dtype=np.float64)
+        fs = self._fs(fset)
+        _check(lib().hp_loss_fwd(self.h, _ptr(sys), C.byref(fs), _ptr(x), _ptr(z), scale, out.ctypes.data))
+        return out
+
+    def loss_bwd(self, sys, fset, x, z, gset):
+        fs, gs = self._fs(fset), self._fs(gset)
+        _check(lib().hp_loss_bwd(self.h, _ptr(sys), C.byref(fs), _ptr(x), _ptr(z), C.byref(gs)))
+
     def infer_factors(self, weights, rho, sys, fac, compute: int):
         _check(lib().hp_infer_factors(self.h, _ptr(weights), _ptr(rho), _ptr(sys), _ptr(fac), compute))
+
+
+FACTOR_NAMES = ("F", "U", "V", "Ut", "Vt", "lam")
+
+
+def cosine_hutchinson_loss(batch: Batch, sys, x, z, F, U, V, Ut, Vt, lam):
+    """Batch-mean cosine-Hutchinson loss as a differentiable torch function of
+    the factor set; forward and backward run the library's kernels."""
+    return _CosLoss.apply(batch, sys, x, z, F, U, V, Ut, Vt, lam)
+
+
+def _make_cosloss():
+    import torch
+
+    class CosLoss(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, batch, sys, x, z, F, U, V, Ut, Vt, lam):
+            fset = dict(F=F.contiguous(), U=U.contiguous(), V=V.contiguous(), Ut=Ut.contiguous(),
+                        Vt=Vt.contiguous(), lam=lam.contiguous())
+            nf = len(batch.dims)
+            losses = batch.loss_fwd(sys, fset, x, z, 1.0 / nf)
+            ctx.batch, ctx.sys = batch, sys
+            ctx.save_for_backward(x, z, *(fset[k] for k in FACTOR_NAMES))
+            return torch.tensor(float(losses.mean()), dtype=torch.float64, device=F.device)
+
+        @staticmethod
+        def backward(ctx, gout):
+            x, z, *fs = ctx.saved_tensors
+            fset = dict(zip(FACTOR_NAMES, fs))
+            batch = ctx.batch
+            g = float(gout)
+            nf = len(batch.dims)
+            batch.loss_fwd(ctx.sys, fset, x, z, g / nf)   # recompute the forward state
+            gset = {k: torch.empty_like(v) for k, v in fset.items()}
+            batch.loss_bwd(ctx.sys, fset, x, z, gset)
+            return (None, None, None, None) + tuple(gset[k] for k in FACTOR_NAMES)
+
+    return CosLoss
+
+
+class _Lazy:
+    def __init__(self):
+        self.cls = None
+
+    def apply(self, *a):
+        if self.cls is None:
+            self.cls = _make_cosloss()
+        return self.cls.apply(*a)
+
+
+_CosLoss = _Lazy()
