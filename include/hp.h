@@ -251,6 +251,45 @@ hp_status hp_loss_fwd(hp_batch b, const float* d_sys, const hp_factor_set* f, co
 hp_status hp_loss_bwd(hp_batch b, const float* d_sys, const hp_factor_set* f, const float* d_x, const float* d_z,
                       const hp_factor_set* grad);
 
+/* Gradient of the batch-mean cosine-Hutchinson loss with respect to every
+ * network weight (Sec. 6.1-6.3): probes from zraw as hp_probes, the forward
+ * pass of hp_infer_factors in the compute type (HP_F32 or HP_BF16; the heads
+ * emit an FP32 factor set), the loss, and the reverse pass through heads,
+ * transformer blocks (each recomputed from its saved input), pooling and
+ * encoder.  d_weights: flat FP32 weights in hp_weight_info order; d_rho,
+ * d_sys as for hp_infer_factors; d_zraw [ntot][16] FP32; d_grad (device,
+ * caller-owned, overwritten) the FP32 gradient in the weight layout.
+ * h_loss (host, optional) receives the batch-mean loss and the call then
+ * synchronises.  The first call allocates the training workspace (saved
+ * activations of every layer; about 5 KB per node at d = 128).  Reductions
+ * over rows use fixed chunking, so the result is bit-reproducible.
+ * Errors: HP_E_SHAPE for models with edge_hidden > 32 or heads > 8. */
+hp_status hp_train_grad(hp_batch b, const float* d_weights, const float* d_rho, const float* d_sys,
+                        const float* d_zraw, int32_t sweeps, float omega, int32_t compute, float* d_grad,
+                        double* h_loss);
+
+/* AdamW with decoupled weight decay after a global l2-norm clip (Supplementary
+ * "Optimizer and schedule"; PyTorch semantics: clip factor
+ * min(1, clip / (||g|| + 1e-6)), bias-corrected moments, step counts from 1).
+ * Updates d_weights, d_m, d_v (FP32, n = hp_weight_count total) in place on
+ * the batch's stream; h_gnorm (host, optional) receives the pre-clip norm and
+ * the call then synchronises.  clip <= 0 disables clipping. */
+typedef struct {
+  double lr, beta1, beta2, eps, weight_decay, clip;
+  int32_t step;
+} hp_adamw_opts;
+hp_status hp_adamw_step(hp_batch b, float* d_weights, const float* d_grad, float* d_m, float* d_v, int64_t n,
+                        const hp_adamw_opts* opt, double* h_gnorm);
+
+/* One training step (Sec. 6.3): hp_train_grad into d_grad (caller-owned
+ * scratch of hp_batch_info weight_floats floats, overwritten) followed by
+ * hp_adamw_step on d_weights / d_m / d_v.  h_loss and h_gnorm (host,
+ * optional) receive the batch-mean loss at the weights before the update and
+ * the pre-clip gradient norm; requesting either synchronises the stream. */
+hp_status hp_train_step(hp_batch b, float* d_weights, float* d_grad, float* d_m, float* d_v, const float* d_rho,
+                        const float* d_sys, const float* d_zraw, int32_t sweeps, float omega, int32_t compute,
+                        const hp_adamw_opts* opt, double* h_loss, double* h_gnorm);
+
 /* ------------------------------------------------------------------ diagnostics */
 
 /* Copy `bytes` of a named internal buffer of the last hp_infer_factors call
@@ -263,6 +302,13 @@ hp_status hp_loss_bwd(hp_batch b, const float* d_sys, const hp_factor_set* f, co
  * FP32 node heads (Ut | Vt | lam logit), "uv" [mtot L_s][2 L_s] FP32 (U | V).
  * For tests; HP_E_INVALID on an unknown name or a size beyond the buffer. */
 hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, int64_t bytes);
+
+/* Test switches of one batch.  "attention_valu" (0/1): with BF16 compute, run
+ * the within-leaf attention on the vector ALUs instead of the matrix cores;
+ * "gemm_small_tiles" (0/1): run every BF16 GEMM on the 64 x 64 tile kernel
+ * instead of the 128 x 128 double-buffered one (the tests compare the
+ * variants).  HP_E_INVALID on an unknown name. */
+hp_status hp_debug_set(hp_batch b, const char* name, int32_t value);
 
 /* Live kernel timing for roofline figures.  After hp_profile_enable(b,
  * "gemm"), every eager launch of that kernel family on the batch stream is

@@ -50,6 +50,8 @@ LaunchGeom Batch::geom() const {
   g.fr = d_fr;
   g.blk2f = d_blk2f;
   g.leaf2f = d_leaf2f;
+  g.cblk = d_cblk;
+  g.ncblk = ncblk;
   g.nframes = nframes;
   g.nblk = nblk;
   g.ktot = ktot;
@@ -96,11 +98,6 @@ extern "C" hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes
       delete b;
       return s;
     }
-    if ((int64_t)(pi.K - 1) * LS > 16 * LEAF_THREADS) {  // coarse stage: <= 16 tile outputs per thread
-      delete b;
-      return set_error(HP_E_SHAPE, "hp_batch_create: frame %d has %d leaves; at most %d for L_s=%d", f, pi.K,
-                       16 * LEAF_THREADS / LS + 1, LS);
-    }
     FrameDesc F{};
     F.n = n;
     F.n0 = (int)n0;
@@ -133,10 +130,14 @@ extern "C" hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes
   b->mtot = m0;
   b->nblk = nb0;
   std::vector<int> blk2f(nb0), leaf2f(k0);
+  std::vector<int2> cblk;
   for (int f = 0; f < nframes; ++f) {
     for (int j = 0; j < b->fr[f].nb; ++j) blk2f[b->fr[f].b0 + j] = f;
     for (int j = 0; j < b->fr[f].K; ++j) leaf2f[b->fr[f].k0 + j] = f;
+    if (b->fr[f].MH == 0) cblk.push_back(make_int2(f, -1));
+    for (int m = 0; m < b->fr[f].MH; ++m) cblk.push_back(make_int2(f, m));
   }
+  b->ncblk = (int)cblk.size();
   hp_status s = HP_OK;
   auto A = [&](void** p, size_t bytes) {
     if (s == HP_OK) s = b->alloc(p, bytes);
@@ -144,6 +145,7 @@ extern "C" hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes
   A((void**)&b->d_fr, sizeof(FrameDesc) * nframes);
   A((void**)&b->d_blk2f, sizeof(int) * nb0);
   A((void**)&b->d_leaf2f, sizeof(int) * k0);
+  A((void**)&b->d_cblk, sizeof(int2) * cblk.size());
   const size_t nf = sizeof(float) * n0;
   A((void**)&b->x1, 2 * nf);
   A((void**)&b->p0, nf);
@@ -179,6 +181,7 @@ extern "C" hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes
   cp(b->d_fr, b->fr.data(), sizeof(FrameDesc) * nframes);
   cp(b->d_blk2f, blk2f.data(), sizeof(int) * nb0);
   cp(b->d_leaf2f, leaf2f.data(), sizeof(int) * k0);
+  cp(b->d_cblk, cblk.data(), sizeof(int2) * cblk.size());
   if (s == HP_OK && hipMemset(b->ticket, 0, sizeof(unsigned) * 4 * nframes) != hipSuccess)
     s = set_error(HP_E_HIP, "hp_batch_create: memset failed");
   if (s == HP_OK) s = network_alloc(*b);
@@ -410,6 +413,20 @@ extern "C" hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_
     return set_error(HP_E_NOCONV, "hp_pcg_solve: tolerance not reached");
   }
   return HP_OK;
+}
+
+extern "C" hp_status hp_debug_set(hp_batch b, const char* name, int32_t value) {
+  if (!b || !name) return set_error(HP_E_INVALID, "hp_debug_set: NULL argument");
+  const std::string n = name;
+  if (n == "attention_valu") {
+    b->attn_valu = value != 0;
+    return HP_OK;
+  }
+  if (n == "gemm_small_tiles") {
+    b->gemm_small = value != 0;
+    return HP_OK;
+  }
+  return set_error(HP_E_INVALID, "hp_debug_set: unknown option '%s'", name);
 }
 
 extern "C" hp_status hp_profile_enable(hp_batch b, const char* kernel) {

@@ -16,7 +16,8 @@ struct LaunchGeom {
   const FrameDesc* fr;
   const int* blk2f;
   const int* leaf2f;
-  int nframes, nblk;
+  const int2* cblk;  // coarse blocks: (frame, tile), tile -1 for a frame without tiles
+  int nframes, nblk, ncblk;
   int64_t ktot, ntot;
   int kmax;
   hipStream_t stream;
@@ -76,6 +77,8 @@ struct Batch {
   FrameDesc* d_fr = nullptr;
   int* d_blk2f = nullptr;
   int* d_leaf2f = nullptr;
+  int2* d_cblk = nullptr;
+  int ncblk = 0;
   // solver workspace
   double* x1 = nullptr;
   float *p0 = nullptr, *p1 = nullptr, *r = nullptr, *z = nullptr, *q = nullptr;
@@ -92,6 +95,8 @@ struct Batch {
   void (*net_free)(void*) = nullptr;  // releases net.ws
   void* train_ws = nullptr;             // training workspace (hp_train_init)
   void (*train_free)(void*) = nullptr;
+  int attn_valu = 0;                    // diagnostics: BF16 leaf attention on the vector ALUs
+  int gemm_small = 0;                   // diagnostics: BF16 GEMMs on the 64 x 64 tile kernel only
   void* net_train = nullptr;            // network training workspace (first hp_train_grad)
   void (*net_train_free)(void*) = nullptr;
   std::map<std::tuple<int, int, const void*, const void*, const void*, const void*, int>, hipGraphExec_t> graphs;

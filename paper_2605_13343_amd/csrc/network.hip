@@ -119,6 +119,95 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   }
 }
 
+// BF16 GEMM for the wide layers (N > 64): 128 x 128 block tile, four waves of
+// 64 x 64 (2 x 2 MFMA 32x32x16 tiles, so each LDS operand read feeds two
+// MFMAs), K in steps of 32 through two LDS buffers: the next step's global
+// loads are issued before the current step's MFMAs and stored to the other
+// buffer after them, one barrier per step.  The 1-D grid is remapped so that
+// the blocks one XCD receives are consecutive (row tile, column tile) pairs:
+// the column tiles of a row tile share that XCD's L2 copy of the X rows.
+__global__ __launch_bounds__(256) void k_gemm_wide(GemmArgs a, int tiles_n) {
+  constexpr int BM = 128, BN = 128, BK = 32, LDK = BK + 8;
+  __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM][LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN][LDK];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int nblk = (int)gridDim.x, id = (int)blockIdx.x;
+  const int lin = (nblk % 8 == 0) ? (id % 8) * (nblk / 8) + id / 8 : id;
+  const int m0 = (lin / tiles_n) * BM, n0 = (lin % tiles_n) * BN;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const uint16_t* X = (const uint16_t*)a.X;
+  const uint16_t* W = (const uint16_t*)a.Wt;
+  // global -> register staging: 2 x 16 B of X and of W per thread and step
+  const int lr = tid >> 2, lc = (tid & 3) * 8;  // rows lr and lr + 64, columns lc..lc+7
+  uint4 ra[2], rb[2];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int r = lr + 64 * q;
+      ra[q] = (m0 + r < a.M) ? *(const uint4*)(X + (int64_t)(m0 + r) * a.ldx + k0 + lc) : make_uint4(0, 0, 0, 0);
+      rb[q] = (n0 + r < a.N) ? *(const uint4*)(W + (int64_t)(n0 + r) * a.K + k0 + lc) : make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      *(uint4*)&sA[buf][lr + 64 * q][lc] = ra[q];
+      *(uint4*)&sB[buf][lr + 64 * q][lc] = rb[q];
+    }
+  };
+  f32x16_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
+  const int nk = a.K / BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      bf16x8_t av[2], bv[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        av[i] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sA[buf][wm + 32 * i + (lane & 31)][kk + (lane >> 5) * 8]);
+        bv[i] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sB[buf][wn + 32 * i + (lane & 31)][kk + (lane >> 5) * 8]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int col = n0 + wn + 32 * j + (lane & 31);
+    if (col >= a.N) continue;
+    const float bc = a.bias ? a.bias[col] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int row = m0 + wm + 32 * i + r * 8 + (lane >> 5) * 4 + c;
+          if (row >= a.M) continue;
+          float v = acc[i][j][r * 4 + c] + bc;
+          if (a.pre) a.pre[(int64_t)row * a.ldp + col] = v;
+          if (a.act == 1) v = gelu_f(v);
+          if (a.resid) v += a.resid[(int64_t)row * a.ldr + col];
+          if (a.Yf) a.Yf[(int64_t)row * a.ldf + col] = v;
+          if (a.Yb) ((uint16_t*)a.Yb)[(int64_t)row * a.ldb + col] = f32_to_bf16(v);
+        }
+  }
+}
+
 // ------------------------------------------------------------------ LayerNorm
 // One wave per row of C = 128 (eps 1e-5), FP32 in, activation type out.
 template <typename AT>
@@ -378,12 +467,22 @@ __global__ void k_edge_corr(EdgeW w, const uint8_t* nbr, const float* ahat, int6
 // Off-diagonal pair descriptors (Supplementary "Off-diagonal attention
 // stack"): for tile m, row token t, column token t':
 //   (centroid(J_m^t') - centroid(I_m^t)) / 4,  mean of Ahat over I_m^t x J_m^t'.
-// One block per tile; thread (t, t').
-__global__ __launch_bounds__(256) void k_off_desc(const FrameDesc* fr, const int* tile2f, const float* sys,
-                                                  int64_t ntot, int L, int LS, float* desc) {
-  const int mg = blockIdx.x;
-  const FrameDesc F = fr[tile2f[mg]];
-  const int m = mg - F.m0, K = F.K;
+// The strip pairs of a tile are split into chunks of at most DESC_CHUNK
+// leaves a side (a big tile's serial loop would otherwise dominate): one
+// block per chunk, thread (t, t'), FP64 partial sums
+// [chunk][t][t'][cI x, y, z | cJ x, y, z | sum Ahat]; a second kernel adds
+// a tile's chunks in order.
+constexpr int DESC_CHUNK = 4;
+struct DescChunk {
+  int tile;   // global tile index
+  int k0, k1; // leaf range [k0, k1) inside the strips
+};
+
+__global__ __launch_bounds__(256) void k_off_desc_part(const FrameDesc* fr, const int* tile2f, const DescChunk* ch,
+                                                       const float* sys, int64_t ntot, int L, int LS, double* part) {
+  const DescChunk c = ch[blockIdx.x];
+  const FrameDesc F = fr[tile2f[c.tile]];
+  const int m = c.tile - F.m0, K = F.K;
   int j = 0;
   while (m >= K - (K >> (j + 1))) ++j;
   const int i = m - (K - (K >> j)), S = 1 << j, r0 = 2 * i * S, c0 = r0 + S, p = L / LS;
@@ -393,7 +492,7 @@ __global__ __launch_bounds__(256) void k_off_desc(const FrameDesc* fr, const int
   const double* w8[3] = {d8 + ntot, d8 + 2 * ntot, d8 + 3 * ntot};
   const unsigned masks[3] = {F.xm, F.ym, F.zm};
   double cI[3] = {0, 0, 0}, cJ[3] = {0, 0, 0}, acc = 0.0;
-  for (int k = 0; k < S; ++k) {
+  for (int k = c.k0; k < c.k1; ++k) {
     for (int l = t * p; l < (t + 1) * p; ++l) {
       const unsigned ci = (unsigned)((r0 + k) * L + l);
       for (int a = 0; a < 3; ++a) cI[a] += mcoord(ci, masks[a]);
@@ -414,10 +513,34 @@ __global__ __launch_bounds__(256) void k_off_desc(const FrameDesc* fr, const int
       for (int a = 0; a < 3; ++a) cJ[a] += mcoord(cj, masks[a]);
     }
   }
+  double* o = part + ((int64_t)blockIdx.x * LS * LS + t * LS + t2) * 7;
+  for (int a = 0; a < 3; ++a) {
+    o[a] = cI[a];
+    o[3 + a] = cJ[a];
+  }
+  o[6] = acc;
+}
+
+// desc of tile (block) mg from its chunks [chunk0[mg], chunk0[mg + 1]).
+__global__ __launch_bounds__(256) void k_off_desc_final(const FrameDesc* fr, const int* tile2f, const int* chunk0,
+                                                        const double* part, int L, int LS, float* desc) {
+  const int mg = blockIdx.x;
+  const FrameDesc F = fr[tile2f[mg]];
+  const int m = mg - F.m0, K = F.K;
+  int j = 0;
+  while (m >= K - (K >> (j + 1))) ++j;
+  const int S = 1 << j, p = L / LS;
+  const int t = threadIdx.x / LS, t2 = threadIdx.x % LS;
+  if (t >= LS) return;
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int c = chunk0[mg]; c < chunk0[mg + 1]; ++c) {
+    const double* o = part + ((int64_t)c * LS * LS + t * LS + t2) * 7;
+    for (int q = 0; q < 7; ++q) v[q] += o[q];
+  }
   const double inv = 1.0 / (double)(S * p);
-  float* o = desc + (((int64_t)mg * LS + t) * LS + t2) * 4;
-  for (int a = 0; a < 3; ++a) o[a] = (float)((cJ[a] - cI[a]) * inv * 0.25);
-  o[3] = (float)(acc * inv * inv);
+  float* out = desc + (((int64_t)mg * LS + t) * LS + t2) * 4;
+  for (int a = 0; a < 3; ++a) out[a] = (float)((v[3 + a] - v[a]) * inv * 0.25);
+  out[3] = (float)(v[6] * inv * inv);
 }
 
 // Off-diagonal bias per layer: bias[m][h][t][t'] = MLP_e(desc[m][t][t']).
@@ -522,6 +645,126 @@ __global__ __launch_bounds__(128) void k_strip_means(const FrameDesc* fr, const 
   const float inv = 1.f / (float)(S * p);
   out[tok * 256 + col] = to_act<OT>(sa * inv);
   out[tok * 256 + 128 + col] = to_act<OT>(sb * inv);
+}
+
+// Within-leaf attention on the matrix cores (BF16 operands, FP32
+// accumulation): one wave per (leaf, head), the four heads of a leaf in one
+// block.  The wave forms S^T = K Q^T (keys as rows, queries as columns, so a
+// lane owns one query and half of its keys), adds scale and bias, takes the
+// softmax with one cross-lane step (lane l and l ^ 32 share a query), and
+// forms O^T = V^T P^T.  The key order inside each 16-wide MFMA step is
+// permuted so that the B operand of the second product is exactly the P
+// values a lane already holds: step (a, s), slot e of half hh is key
+// 32a + 16s + 8(e/4) + 4hh + e%4, and V^T is read from LDS in that order.
+template <int T>
+__global__ __launch_bounds__(256) void k_attention_mfma(const uint16_t* qkv, uint16_t* out, const float* T0,
+                                                       const float* corr, const uint8_t* nbr) {
+  constexpr int DH = 32, H = 4, D = H * DH, NT = T / 32, VP = T + 8;
+  __shared__ __attribute__((aligned(16))) uint16_t sVt[H][DH][VP];
+  const int h = threadIdx.x >> 6, lane = threadIdx.x & 63, hh = lane >> 5, c32 = lane & 31;
+  const int64_t row0 = (int64_t)blockIdx.x * T;
+  const uint16_t* base = qkv + row0 * 3 * D + h * DH;
+  // V^T into LDS: lane -> key rows, 16 B chunks
+  for (int idx = lane; idx < T * 4; idx += 64) {
+    const int key = idx >> 2, c0 = (idx & 3) * 8;
+    const uint4 v = *(const uint4*)(base + (int64_t)key * 3 * D + 2 * D + c0);
+    const uint16_t* pv = (const uint16_t*)&v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sVt[h][c0 + e][key] = pv[e];
+  }
+  __syncthreads();
+  // S^T tiles: acc[a][b] = K[32a..][:] Q[32b..][:]^T
+  f32x16_t S[NT][NT];
+#pragma unroll
+  for (int a = 0; a < NT; ++a)
+#pragma unroll
+    for (int b = 0; b < NT; ++b)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) S[a][b][q] = 0.f;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    bf16x8_t kop[NT], qop[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int64_t r = 32 * t + c32;
+      kop[t] = __builtin_bit_cast(bf16x8_t, *(const uint4*)(base + r * 3 * D + D + 16 * s + 8 * hh));
+      qop[t] = __builtin_bit_cast(bf16x8_t, *(const uint4*)(base + r * 3 * D + 16 * s + 8 * hh));
+    }
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+      for (int b = 0; b < NT; ++b) S[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kop[a], qop[b], S[a][b], 0, 0, 0);
+  }
+  const float scale = 0.17677669529663687f;  // 1/sqrt(32)
+#pragma unroll
+  for (int b = 0; b < NT; ++b) {
+    const int q = 32 * b + c32;
+    const int64_t row = row0 + q;
+    const float* bt = T0 + ((int64_t)h * T + q) * T;
+    int lj[7];
+    float cv[7];
+#pragma unroll
+    for (int e = 0; e < 7; ++e) {
+      lj[e] = nbr[row * 7 + e];
+      cv[e] = corr[(row * 7 + e) * H + h];
+    }
+    float mx = -3.4e38f;
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k0 = 32 * a + 8 * i + 4 * hh;
+        const float4 bv = *(const float4*)(bt + k0);
+        const float bj[4] = {bv.x, bv.y, bv.z, bv.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float v = fmaf(S[a][b][4 * i + j], scale, bj[j]);
+#pragma unroll
+          for (int e = 0; e < 7; ++e) v += (lj[e] == k0 + j) ? cv[e] : 0.f;
+          S[a][b][4 * i + j] = v;
+          mx = fmaxf(mx, v);
+        }
+      }
+    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    float sum = 0.f;
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+      for (int q2 = 0; q2 < 16; ++q2) {
+        const float p = expf(S[a][b][q2] - mx);
+        S[a][b][q2] = p;
+        sum += p;
+      }
+    sum += __shfl_xor(sum, 32, 64);
+    f32x16_t O;
+#pragma unroll
+    for (int q2 = 0; q2 < 16; ++q2) O[q2] = 0.f;
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        bf16x8_t pb, vb;
+        const int kb = 32 * a + 16 * s + 4 * hh;
+        uint16_t vv[8];
+        *(uint2*)&vv[0] = *(const uint2*)&sVt[h][c32][kb];
+        *(uint2*)&vv[4] = *(const uint2*)&sVt[h][c32][kb + 8];
+        vb = __builtin_bit_cast(bf16x8_t, *(const uint4*)vv);
+        uint16_t pp[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) pp[e] = f32_to_bf16(S[a][b][8 * s + e]);
+        pb = __builtin_bit_cast(bf16x8_t, *(const uint4*)pp);
+        O = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vb, pb, O, 0, 0, 0);
+      }
+    const float inv = 1.f / sum;
+    uint16_t* orow = out + row * D + h * DH;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      uint16_t o4[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) o4[j] = f32_to_bf16(O[4 * i + j] * inv);
+      *(uint2*)(orow + 8 * i + 4 * hh) = *(const uint2*)o4;
+    }
+  }
 }
 
 // Highway buffers of the diagonal tokens (Sec. 4.3): r_i (c_i) is the mean of
@@ -631,15 +874,26 @@ struct ConvDesc {
 
 // pad == 0 (transposed, forward):  dst[(n_off + n) * ld + k_off + k] = src[k * cols + n]
 // pad == 1 (plain, backward dX):   dst[(k_off + k) * ld + n_off + n] = src[k * cols + n]
-// Grid: (descriptor, chunk of 4096 elements).
+// One block per 64 x 64 tile (desc, k0, n0) of a source matrix, staged in LDS
+// so that both the FP32 reads and the compute-type writes are row-contiguous.
 template <typename AT>
-__global__ void k_convert(const ConvDesc* d, const float* W, AT* out) {
-  const ConvDesc c = d[blockIdx.x];
-  const int begin = blockIdx.y * 4096, end = min(c.rows * c.cols, begin + 4096);
-  for (int idx = begin + threadIdx.x; idx < end; idx += blockDim.x) {
-    const int k = idx / c.cols, n = idx % c.cols;
+__global__ __launch_bounds__(256) void k_convert(const ConvDesc* d, const int4* tiles, const float* W, AT* out) {
+  __shared__ float t[64][65];
+  const int4 tl = tiles[blockIdx.x];
+  const ConvDesc c = d[tl.x];
+  const int k0 = tl.y, n0 = tl.z;
+  for (int e = threadIdx.x; e < 4096; e += 256) {
+    const int kk = e >> 6, nn = e & 63, k = k0 + kk, n = n0 + nn;
+    t[kk][nn] = (k < c.rows && n < c.cols) ? W[c.src + (int64_t)k * c.cols + n] : 0.f;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 4096; e += 256) {
+    const int hi = e >> 6, lo = e & 63;
+    // pad 0: rows of the output are n (hi), k (lo) contiguous; pad 1: rows k, n contiguous
+    const int kk = c.pad ? hi : lo, nn = c.pad ? lo : hi, k = k0 + kk, n = n0 + nn;
+    if (k >= c.rows || n >= c.cols) continue;
     const int64_t o = c.pad ? (int64_t)(c.k_off + k) * c.ld + c.n_off + n : (int64_t)(c.n_off + n) * c.ld + c.k_off + k;
-    out[c.dst + o] = to_act<AT>(W[c.src + idx]);
+    out[c.dst + o] = to_act<AT>(t[kk][nn]);
   }
 }
 
@@ -654,7 +908,8 @@ struct NetPlan {
   std::vector<WeightEntry> lay;
   std::vector<ConvDesc> conv;
   int64_t arena = 0;
-  int maxconv = 0;  // largest descriptor (elements)
+  std::vector<int4> tiles;  // (descriptor, k0, n0) conversion tiles, forward copies first
+  int ntiles_fwd = 0;
   GemmW enc1, enc2, gcn[4], pool, hleaf1, hleaf2, hnode, huv;
   GemmW qkv[2][16], o[2][16], f1[2][16], f2[2][16];
   // plain copies W[in][out] for the input-gradient GEMMs dX = dY W^T
@@ -753,7 +1008,12 @@ static NetPlan make_plan(const hp_model_config& c) {
   P.b_huv = gemm(d, pad32(2 * LS));
   bconv(P.b_huv, "hu.w", 0, 0);
   bconv(P.b_huv, "hv.w", LS, 0);
-  for (auto& cd : P.conv) P.maxconv = std::max(P.maxconv, cd.rows * cd.cols);
+  for (int i = 0; i < (int)P.conv.size(); ++i) {
+    const ConvDesc& cd = P.conv[i];
+    for (int k0 = 0; k0 < cd.rows; k0 += 64)
+      for (int n0 = 0; n0 < cd.cols; n0 += 64) P.tiles.push_back(make_int4(i, k0, n0, 0));
+    if (cd.pad == 0) P.ntiles_fwd = (int)P.tiles.size();
+  }
   return P;
 }
 
@@ -773,9 +1033,14 @@ struct NetBufs {
   float *gpart = nullptr, *G = nullptr, *gcount = nullptr, *glob = nullptr, *bias_node = nullptr, *bias_uv = nullptr;
   void* warena = nullptr;
   ConvDesc* d_conv = nullptr;
+  int4* d_tiles = nullptr;
   int *node2f = nullptr, *tok2f = nullptr, *tile2f = nullptr, *chunk0 = nullptr;
   SumChunk* chunks = nullptr;
   int nchunks = 0;
+  DescChunk* desc_chunks = nullptr;
+  int* desc_chunk0 = nullptr;
+  double* desc_part = nullptr;
+  int ndesc_chunks = 0;
 };
 
 static NetBufs* nb_of(Batch& b) { return reinterpret_cast<NetBufs*>(b.net.ws); }
@@ -832,6 +1097,7 @@ hp_status network_alloc(Batch& b) {
   A(&N->bias_uv, 64 * 4);
   A(&N->warena, N->plan.arena * 4);
   A(&N->d_conv, N->plan.conv.size() * sizeof(ConvDesc));
+  A(&N->d_tiles, N->plan.tiles.size() * sizeof(int4));
   A(&N->node2f, Nd * 4);
   A(&N->tok2f, No * 4);
   A(&N->tile2f, std::max<int64_t>(b.mtot, 1) * 4);
@@ -857,6 +1123,23 @@ hp_status network_alloc(Batch& b) {
   }
   chunk0[b.nframes] = (int)ch.size();
   N->nchunks = (int)ch.size();
+  std::vector<DescChunk> dch;
+  std::vector<int> dch0(std::max<int64_t>(b.mtot, 1) + 1, 0);
+  for (int f = 0; f < b.nframes; ++f) {
+    const FrameDesc& F = b.fr[f];
+    for (int m = 0; m < F.MH; ++m) {
+      int j = 0;
+      while (m >= F.K - (F.K >> (j + 1))) ++j;
+      dch0[F.m0 + m] = (int)dch.size();
+      for (int k = 0; k < (1 << j); k += DESC_CHUNK)
+        dch.push_back(DescChunk{F.m0 + m, k, std::min(1 << j, k + DESC_CHUNK)});
+    }
+  }
+  dch0[b.mtot] = (int)dch.size();
+  N->ndesc_chunks = (int)dch.size();
+  A(&N->desc_chunks, std::max<size_t>(dch.size(), 1) * sizeof(DescChunk));
+  A(&N->desc_chunk0, dch0.size() * sizeof(int));
+  A(&N->desc_part, std::max<size_t>(dch.size(), 1) * c.rank * c.rank * 7 * sizeof(double));
   A(&N->chunks, ch.size() * sizeof(SumChunk));
   A(&N->gpart, ch.size() * 128 * 4);
   if (s != HP_OK) return s;
@@ -869,8 +1152,11 @@ hp_status network_alloc(Batch& b) {
   up(N->tile2f, tile2f.data(), tile2f.size() * 4);
   up(N->chunk0, chunk0.data(), chunk0.size() * 4);
   up(N->chunks, ch.data(), ch.size() * sizeof(SumChunk));
+  if (!dch.empty()) up(N->desc_chunks, dch.data(), dch.size() * sizeof(DescChunk));
+  up(N->desc_chunk0, dch0.data(), dch0.size() * sizeof(int));
   up(N->gcount, cnt.data(), cnt.size() * 4);
   up(N->d_conv, N->plan.conv.data(), N->plan.conv.size() * sizeof(ConvDesc));
+  up(N->d_tiles, N->plan.tiles.data(), N->plan.tiles.size() * sizeof(int4));
   if (s == HP_OK && hipMemset(N->warena, 0, N->plan.arena * 4) != hipSuccess)
     s = set_error(HP_E_HIP, "network_alloc: memset failed");
   return s;
@@ -900,9 +1186,14 @@ static void gemm(Batch& b, const void* X, int64_t ldx, const NetBufs& NB, const 
   a.M = (int)M;
   a.N = w.N;
   a.act = act;
-  dim3 grid((unsigned)((M + 63) / 64), (unsigned)((w.N + 63) / 64));
   if (timed) hipEventRecord(b.prof.ev[2 * b.prof.used], st);
-  hipLaunchKernelGGL(k_gemm<AT>, grid, dim3(256), 0, st, a);
+  if (sizeof(AT) == 2 && w.N > 64 && !b.gemm_small) {
+    const int tn = (w.N + 127) / 128, tm = (int)((M + 127) / 128);
+    hipLaunchKernelGGL(k_gemm_wide, dim3((unsigned)(tm * tn)), dim3(256), 0, st, a, tn);
+  } else {
+    dim3 grid((unsigned)((M + 63) / 64), (unsigned)((w.N + 63) / 64));
+    hipLaunchKernelGGL(k_gemm<AT>, grid, dim3(256), 0, st, a);
+  }
   if (timed) {
     hipEventRecord(b.prof.ev[2 * b.prof.used + 1], st);
     b.prof.used++;
@@ -936,8 +1227,10 @@ static hp_status fwd_prologue(Batch& b, const float* W, const float* rho, const 
   auto wp = [&](const std::string& n) { return W + woff(P, n); };
   (void)fr; (void)use_off; (void)H; (void)No; (void)L; (void)LS;
   // weights -> transposed arena in the compute type
-  hipLaunchKernelGGL(k_convert<AT>, dim3((unsigned)P.conv.size(), (unsigned)((P.maxconv + 4095) / 4096)), dim3(256),
-                     0, st, N.d_conv, W, (AT*)N.warena);
+  // (training also converts the plain copies its input-gradient GEMMs read)
+  const int ntiles = sv ? (int)P.tiles.size() : P.ntiles_fwd;
+  hipLaunchKernelGGL(k_convert<AT>, dim3((unsigned)ntiles), dim3(256), 0, st, N.d_conv, (const int4*)N.d_tiles, W,
+                     (AT*)N.warena);
   HP_HIP(hipMemcpyAsync(N.bias_node, wp("hut.b"), LS * 4, hipMemcpyDeviceToDevice, st));
   HP_HIP(hipMemcpyAsync(N.bias_node + LS, wp("hvt.b"), LS * 4, hipMemcpyDeviceToDevice, st));
   HP_HIP(hipMemcpyAsync(N.bias_node + 2 * LS, wp("hlam.b"), 4, hipMemcpyDeviceToDevice, st));
@@ -963,8 +1256,10 @@ static hp_status fwd_prologue(Batch& b, const float* W, const float* rho, const 
                        (const float*)N.H, (int)L, (int)LS, (AT*)N.ctx);
     gemm<AT>(b, N.ctx, 2 * d, N, P.pool, wp("pool.b"), nullptr, 0, N.Xo, d, nullptr, 0, No, 0);
     HP_HIP(hipMemcpyAsync(N.Xo0, N.Xo, No * d * 4, hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_off_desc, dim3((unsigned)b.mtot), dim3(256), 0, st, fr, N.tile2f, sys, b.ntot, (int)L,
-                       (int)LS, N.desc);
+    hipLaunchKernelGGL(k_off_desc_part, dim3((unsigned)N.ndesc_chunks), dim3(256), 0, st, fr, N.tile2f,
+                       (const DescChunk*)N.desc_chunks, sys, b.ntot, (int)L, (int)LS, N.desc_part);
+    hipLaunchKernelGGL(k_off_desc_final, dim3((unsigned)b.mtot), dim3(256), 0, st, fr, N.tile2f,
+                       (const int*)N.desc_chunk0, (const double*)N.desc_part, (int)L, (int)LS, N.desc);
   }
   hipLaunchKernelGGL(k_leaf_stencil, dim3((unsigned)((Nd + 255) / 256)), dim3(256), 0, st, fr, N.node2f, sys, b.ntot,
                      (int)L, N.nbr, N.ahat);
@@ -1006,14 +1301,22 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
                          F0.xm & lowmask, F0.ym & lowmask, F0.zm & lowmask, N.T0);
       hipLaunchKernelGGL(k_edge_corr, dim3((unsigned)((Nd * 7 + 127) / 128)), dim3(128), 0, st, ew,
                          (const uint8_t*)N.nbr, (const float*)N.ahat, Nd, N.corr);
-      if (L == 64)
+      if (sizeof(AT) == 2 && !b.attn_valu) {
+        if (L == 64)
+          hipLaunchKernelGGL(k_attention_mfma<64>, dim3((unsigned)b.ktot), dim3(256), 0, st, (const uint16_t*)q,
+                             (uint16_t*)o, (const float*)N.T0, (const float*)N.corr, (const uint8_t*)N.nbr);
+        else
+          hipLaunchKernelGGL(k_attention_mfma<32>, dim3((unsigned)b.ktot), dim3(256), 0, st, (const uint16_t*)q,
+                             (uint16_t*)o, (const float*)N.T0, (const float*)N.corr, (const uint8_t*)N.nbr);
+      } else if (L == 64) {
         hipLaunchKernelGGL((k_attention<AT, 64, true>), dim3((unsigned)b.ktot, (unsigned)H), dim3(64), 0, st,
                            (const AT*)q, (AT*)o, (const float*)N.T0, (const float*)N.corr, (const uint8_t*)N.nbr,
                            (int)H);
-      else
+      } else {
         hipLaunchKernelGGL((k_attention<AT, 32, true>), dim3((unsigned)b.ktot, (unsigned)H), dim3(64), 0, st,
                            (const AT*)q, (AT*)o, (const float*)N.T0, (const float*)N.corr, (const uint8_t*)N.nbr,
                            (int)H);
+      }
     } else {
       const int64_t npairs = b.mtot * LS * LS;
       hipLaunchKernelGGL(k_edge_off, dim3((unsigned)((npairs + 127) / 128)), dim3(128), 0, st, ew,
@@ -1158,3 +1461,7 @@ extern "C" hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, in
   HP_HIP(hipMemcpyAsync(d_dst, src, bytes, hipMemcpyDeviceToDevice, b->stream));
   return HP_OK;
 }
+
+// Reverse pass and training step.
+#include "net_backward.h"
+#include "net_train.h"

@@ -10,9 +10,11 @@
 //                 r -= alpha q or the FP64 residual replacement r = b - A x,
 //                 the leaf stage of M (G_k r_k + lam r / A_ii, restriction
 //                 Ut^T r, Vt^T r), partials of ||r||^2.
-//   k_frame_check one block per frame: stop checks; coarse stage (strip sums,
-//                 B / B^T coupling, gathering down the levels).
-//   k_prolong     leaf blocks: z += Ut T^r + Vt T^c, partials of r.z.
+//   k_coarse_check coarse blocks (one per tile): stop checks (redundant in
+//                 every block of the frame), then the tile's coupling: strip
+//                 sums s^r, s^c, t^r = B s^c, t^c = B^T s^r.
+//   k_prolong     leaf blocks: gather T^r, T^c down the levels,
+//                 z += Ut T^r + Vt T^c, partials of r.z.
 //
 // All reductions run in a fixed order (FP64), so a solve is bit-reproducible
 // and independent of how frames are batched.  Frames that stopped are skipped
@@ -266,98 +268,73 @@ __device__ inline float prolong_row(int64_t row0, const float* trs, const float*
   return yrow + a;
 }
 
-// Coarse stage of one frame, run by one whole block (paper Sec. 5 strip
-// aggregation and coarse coupling).  For every tile m = (j, i) at once:
+// Coarse coupling of one tile (paper Sec. 5 strip aggregation and coarse
+// coupling), run by one whole block.  Tile m = (j, i), S = 2^j leaves a side:
 //   s^r = sum of u over the row strip (leaves [2iS, 2iS+S)),
 //   s^c = sum of v over the column strip (leaves [2iS+S, 2iS+2S)),
-//   t^r = B_m s^c,  t^c = B_m^T s^r;
-// then leaf k gathers T^r_k = sum of t^r over the tiles where it is on the
-// row side and T^c_k over those where it is on the column side.  Every sum
-// runs in a fixed order.  lds holds 2 K LS floats (+ LS slack).
+//   t^r = B_m s^c,  t^c = B_m^T s^r,
+// written to tr / tc [tile][LS].  The strip sums run in a fixed order
+// (NCH interleaved chunks of leaves, then the chunks in order).
 template <int LS, typename FT>
-__device__ void coarse_stage(const FrameDesc& F, const float* uh, const float* vh, const FT* B, float* Tr,
-                             float* Tc, float* lds) {
-  const int K = F.K, J = F.J, MH = F.MH, nt = blockDim.x, t = threadIdx.x;
-  const int64_t kb = (int64_t)F.k0 * LS;
-  if (J == 0) {
-    for (int e = t; e < K * LS; e += nt) {
-      Tr[kb + e] = 0.f;
-      Tc[kb + e] = 0.f;
-    }
-    return;
+__device__ void tile_couple(const FrameDesc& F, int m, const float* uh, const float* vh, const FT* B, float* tr,
+                            float* tc) {
+  constexpr int NCH = LEAF_THREADS / LS;
+  __shared__ float pr[NCH][LS], pc[NCH][LS], sr[LS], sc[LS];
+  const int K = F.K, t = threadIdx.x;
+  int j = 0;
+  while (m >= K - (K >> (j + 1))) ++j;
+  const int i = m - (K - (K >> j)), S = 1 << j;
+  const int s = t % LS, ch = t / LS;
+  const int64_t lr = (int64_t)F.k0 + 2 * i * S, lc = lr + S;
+  float a = 0.f, c = 0.f;
+  for (int k = ch; k < S; k += NCH) {
+    a += uh[(lr + k) * LS + s];
+    c += vh[(lc + k) * LS + s];
   }
-  float* su = lds;            // [K][LS] u, later strip sums s^r / t^c
-  float* sv = lds + K * LS;   // [K][LS] v, later strip sums s^c / t^r
-  for (int e = t; e < K * LS; e += nt) {
-    su[e] = uh[kb + e];
-    sv[e] = vh[kb + e];
+  pr[ch][s] = a;
+  pc[ch][s] = c;
+  __syncthreads();
+  if (t < LS) {
+    float x = 0.f;
+    for (int q = 0; q < NCH; ++q) x += pr[q][t];
+    sr[t] = x;
+  } else if (t < 2 * LS) {
+    float x = 0.f;
+    for (int q = 0; q < NCH; ++q) x += pc[q][t - LS];
+    sc[t - LS] = x;
   }
   __syncthreads();
-  // tile m at level j = level_of(m), index i: m = K - K/2^j + i
-  auto tile_of = [&](int m, int& j, int& i) {
-    j = 0;
-    while (m >= K - (K >> (j + 1))) ++j;
-    i = m - (K - (K >> j));
-  };
-  constexpr int MAXR = 16;  // outputs per thread per phase (MH LS <= MAXR nt)
-  float ar[MAXR], ac[MAXR];
-  int cnt = 0;
-  for (int e = t; e < MH * LS; e += nt, ++cnt) {
-    int m = e / LS, s = e % LS, j, i;
-    tile_of(m, j, i);
-    const int S = 1 << j;
-    float a = 0.f, c = 0.f;
-    for (int k = 2 * i * S; k < 2 * i * S + S; ++k) a += su[k * LS + s];
-    for (int k = 2 * i * S + S; k < 2 * i * S + 2 * S; ++k) c += sv[k * LS + s];
-    ar[cnt] = a;
-    ac[cnt] = c;
-  }
-  __syncthreads();
-  cnt = 0;
-  for (int e = t; e < MH * LS; e += nt, ++cnt) {
-    su[e] = ar[cnt];  // s^r
-    sv[e] = ac[cnt];  // s^c
-  }
-  __syncthreads();
-  const FT* Bf = B + (int64_t)F.m0 * LS * LS;
-  cnt = 0;
-  for (int e = t; e < MH * LS; e += nt, ++cnt) {
-    int m = e / LS, s = e % LS;
-    const FT* Bm = Bf + (int64_t)m * LS * LS;
-    float b_row[LS], b_col[LS];
-    if constexpr (LS % 4 == 0) load_vec<FT, LS>(Bm + s * LS, b_row);
+  const int64_t mg = (int64_t)F.m0 + m;
+  const FT* Bm = B + mg * LS * LS;
+  if (t < LS) {
+    float x = 0.f;
 #pragma unroll
-    for (int u = 0; u < LS; ++u) {
-      if constexpr (LS % 4 != 0) b_row[u] = ldf(Bm, s * LS + u);
-      b_col[u] = ldf(Bm, u * LS + s);
-    }
-    float tr = 0.f, tc = 0.f;
+    for (int u = 0; u < LS; ++u) x = fmaf(ldf(Bm, t * LS + u), sc[u], x);
+    tr[mg * LS + t] = x;
+  } else if (t < 2 * LS) {
+    const int q = t - LS;
+    float x = 0.f;
 #pragma unroll
-    for (int u = 0; u < LS; ++u) {
-      tr = fmaf(b_row[u], sv[m * LS + u], tr);  // t^r = B s^c
-      tc = fmaf(b_col[u], su[m * LS + u], tc);  // t^c = B^T s^r
-    }
-    ar[cnt] = tc;
-    ac[cnt] = tr;
+    for (int u = 0; u < LS; ++u) x = fmaf(ldf(Bm, u * LS + q), sr[u], x);
+    tc[mg * LS + q] = x;
   }
-  __syncthreads();
-  cnt = 0;
-  for (int e = t; e < MH * LS; e += nt, ++cnt) {
-    su[e] = ar[cnt];  // t^c
-    sv[e] = ac[cnt];  // t^r
+}
+
+// Gather of leaf kg (global index) for entry s < LS: T^r = sum of t^r over the
+// tiles where the leaf is on the row side, T^c over those where it is on the
+// column side, levels in increasing order.
+template <int LS>
+__device__ inline void gather_leaf(const FrameDesc& F, int64_t kg, int s, const float* tr, const float* tc,
+                                   float& Tr, float& Tc) {
+  const int k = (int)(kg - F.k0), K = F.K;
+  float a = 0.f, c = 0.f;
+  for (int j = 0; j < F.J; ++j) {
+    const int64_t m = (int64_t)F.m0 + K - (K >> j) + (k >> (j + 1));
+    if (((k >> j) & 1) == 0) a += tr[m * LS + s];
+    else c += tc[m * LS + s];
   }
-  __syncthreads();
-  for (int e = t; e < K * LS; e += nt) {
-    int k = e / LS, s = e % LS;
-    float a = 0.f, c = 0.f;
-    for (int j = 0; j < J; ++j) {
-      int m = K - (K >> j) + (k >> (j + 1));
-      if (((k >> j) & 1) == 0) a += sv[m * LS + s];
-      else c += su[m * LS + s];
-    }
-    Tr[kb + e] = a;
-    Tc[kb + e] = c;
-  }
+  Tr = a;
+  Tc = c;
 }
 
 // ------------------------------------------------------------------ standalone apply
@@ -376,27 +353,27 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_apply_leaf(const FrameDesc* fr
   leaf_stage<L, LS, FT>(kg, row0, rs, fac, sys + 4 * ntot, y, uh, vh, red);
 }
 
+// One block per coarse block (a tile, or a placeholder for a frame without
+// tiles).
 template <int LS, typename FT>
-__global__ __launch_bounds__(LEAF_THREADS) void k_apply_coarse(const FrameDesc* fr, Factors<FT> fac,
-                                                               const float* uh, const float* vh, float* Tr,
-                                                               float* Tc) {
-  extern __shared__ float lds[];
-  const FrameDesc F = fr[blockIdx.x];
-  coarse_stage<LS, FT>(F, uh, vh, fac.B, Tr, Tc, lds);
+__global__ __launch_bounds__(LEAF_THREADS) void k_apply_coarse(const FrameDesc* fr, const int2* cblk,
+                                                               Factors<FT> fac, const float* uh, const float* vh,
+                                                               float* tr, float* tc) {
+  const int2 cb = cblk[blockIdx.x];
+  if (cb.y < 0) return;
+  const FrameDesc F = fr[cb.x];
+  tile_couple<LS, FT>(F, cb.y, uh, vh, fac.B, tr, tc);
 }
 
 template <int L, int LS, typename FT>
 __global__ __launch_bounds__(LEAF_THREADS) void k_apply_prolong(const FrameDesc* fr, const int* leaf2f,
-                                                                Factors<FT> fac, const float* Tr,
-                                                                const float* Tc, float* y) {
+                                                                Factors<FT> fac, const float* tr,
+                                                                const float* tc, float* y) {
   __shared__ float trs[LS], tcs[LS];
   const int64_t kg = blockIdx.x;
   const FrameDesc F = fr[leaf2f[kg]];
   const int64_t row0 = F.n0 + (kg - F.k0) * L;
-  if (threadIdx.x < LS) {
-    trs[threadIdx.x] = Tr[kg * LS + threadIdx.x];
-    tcs[threadIdx.x] = Tc[kg * LS + threadIdx.x];
-  }
+  if (threadIdx.x < LS) gather_leaf<LS>(F, kg, threadIdx.x, tr, tc, trs[threadIdx.x], tcs[threadIdx.x]);
   __syncthreads();
   constexpr int TPR = LEAF_THREADS / L;
   int row = threadIdx.x / TPR;
@@ -411,12 +388,13 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_apply_prolong(const FrameDesc*
 // another block of the same kernel writes.  Every block of a kernel reduces
 // the partials that the previous kernel wrote for its frame, in the same fixed
 // order, so all blocks of a frame reach bit-identical scalars and decisions;
-// the frame's first block (or the frame's single block) writes the frame
-// state.  State is double-buffered by iteration parity: an iteration at
-// parity par reads st[2f + par] in its first kernel and leaves its result in
-// st[2f + (par ^ 1)].
+// the frame's lead block writes the frame state, always to the slot that no
+// block of that kernel reads.  Jacobi / identity: an iteration at parity par
+// reads st[2f + par] in its first kernel and leaves its result in
+// st[2f + (par ^ 1)].  Learned preconditioner: k_spmv_p reads slot 0 and
+// writes slot 1, k_update_hmat reads slot 1, k_coarse_check reads slot 1 and
+// writes slot 0, k_prolong reads slot 0.
 
-enum { SLOT0 = 0 };
 
 __device__ inline bool is_replacement(const FrameState& s, const SolveParams& prm, int u) {
   return s.force_rc || (prm.recompute_every > 0 && u % prm.recompute_every == 0);
@@ -455,13 +433,13 @@ __device__ inline bool stop_checks(FrameState& s, const SolveParams& prm, int u,
 // of the previous update], positivity of rho' = r.z, beta = rho'/rho,
 // p = z + beta p_old at the 7 stencil points, q = A p, partials of p.q.
 template <bool SIMPLE>
-__global__ __launch_bounds__(NODE_BLOCK) void k_spmv_p(const FrameDesc* fr, const int* blk2f, PcgBufs B_, int par,
-                                                       const float* pold, float* pnew) {
+__global__ __launch_bounds__(NODE_BLOCK) void k_spmv_p(const FrameDesc* fr, const int* blk2f, PcgBufs B_, int rd,
+                                                       int wr, const float* pold, float* pnew) {
   __shared__ double red[NODE_BLOCK / 64];
   const int f = blk2f[blockIdx.x];
   const FrameDesc F = fr[f];
-  FrameState S = B_.st[2 * f + par];
-  FrameState* out = B_.st + 2 * f + (par ^ 1);
+  FrameState S = B_.st[2 * f + rd];
+  FrameState* out = B_.st + 2 * f + wr;
   const bool lead = blockIdx.x == F.b0 && threadIdx.x == 0;
   if (S.done) {
     if (lead) *out = S;
@@ -540,15 +518,15 @@ __device__ inline double xr_update(const FrameDesc& F, int64_t row0, const PcgBu
 // residual replacement), leaf stage of z = M r, partials of ||r||^2.
 template <int L, int LS, typename FT>
 __global__ __launch_bounds__(LEAF_THREADS) void k_update_hmat(const FrameDesc* fr, const int* leaf2f, PcgBufs B_,
-                                                              Factors<FT> fac, int par, const double* xold,
-                                                              double* xnew, const float* p) {
+                                                              Factors<FT> fac, const double* xold, double* xnew,
+                                                              const float* p) {
   __shared__ float rs[L];
   __shared__ float red[(LEAF_THREADS / 64) * 2 * LS];
   __shared__ double dred[LEAF_THREADS / 64];
   const int64_t kg = blockIdx.x;
   const int f = leaf2f[kg];
   const FrameDesc F = fr[f];
-  const FrameState S = B_.st[2 * f + (par ^ 1)];
+  const FrameState S = B_.st[2 * f + 1];
   if (S.done) return;
   const SolveParams prm = *B_.prm;
   const int64_t row0 = F.n0 + (kg - F.k0) * L;
@@ -561,27 +539,61 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_update_hmat(const FrameDesc* f
   if (threadIdx.x == 0) B_.part_rr[kg] = bs;
 }
 
-// Frame kernel (one block per frame): stop checks (or, at setup, ||b||, the
-// target and the check of r0) and, for the learned preconditioner, the coarse
-// stage.  Partials are per leaf (HMAT) or per node block (Jacobi / identity).
-template <int LS, typename FT, bool HMAT>
-__global__ __launch_bounds__(LEAF_THREADS) void k_frame_check(const FrameDesc* fr, PcgBufs B_, Factors<FT> fac,
-                                                              int slot, int setup) {
-  extern __shared__ float lds[];
+// Setup check for Jacobi / identity (one block per frame): ||b||, the target
+// and the check of r0 from the node-block partials.
+__global__ __launch_bounds__(LEAF_THREADS) void k_frame_setup(const FrameDesc* fr, PcgBufs B_) {
   __shared__ double dred[LEAF_THREADS / 64];
   const int f = blockIdx.x;
   const FrameDesc F = fr[f];
-  FrameState* sp = B_.st + 2 * f + slot;
+  FrameState* sp = B_.st + 2 * f;
   FrameState S = *sp;
   if (S.done) return;
   const SolveParams prm = *B_.prm;
-  const double* prr = B_.part_rr + (HMAT ? F.k0 : F.b0);
-  const double* pbb = B_.part_pq + (HMAT ? F.k0 : F.b0);
-  const int np = HMAT ? F.K : F.nb;
-  const double rr = frame_sum(prr, np, dred);
+  const double rr = frame_sum(B_.part_rr + F.b0, F.nb, dred);
+  const double bb = frame_sum(B_.part_pq + F.b0, F.nb, dred);
+  S.bnorm = sqrt(bb);
+  S.target = (prm.tol * S.bnorm) * (prm.tol * S.bnorm);
+  S.rr = rr;
+  S.rwin = sqrt(rr);
+  S.it = 0;
+  S.fresh = 1;
+  bool stop = true;
+  if (rr <= S.target) S.flags |= HP_CONVERGED;
+  else if (prm.max_iter <= 0) S.flags |= HP_MAXITER;
+  else stop = false;
+  if (threadIdx.x == 0) {
+    if (stop) {
+      S.done = 1;
+      atomicSub(B_.n_active, 1);
+    }
+    *sp = S;
+  }
+}
+
+// Third kernel of the learned preconditioner (coarse blocks: one per tile,
+// a placeholder block for a frame without tiles): the stop checks of the
+// update (or, at setup, ||b||, the target and the check of r0) from the
+// per-leaf partials, computed by every block of the frame; the frame's lead
+// block (its first) writes the state.  A frame that goes on then couples the
+// block's tile.
+template <int LS, typename FT>
+__global__ __launch_bounds__(LEAF_THREADS) void k_coarse_check(const FrameDesc* fr, const int2* cblk, PcgBufs B_,
+                                                               Factors<FT> fac, int setup) {
+  __shared__ double dred[LEAF_THREADS / 64];
+  const int2 cb = cblk[blockIdx.x];
+  const int f = cb.x;
+  const bool lead = cb.y <= 0 && threadIdx.x == 0;
+  const FrameDesc F = fr[f];
+  FrameState S = B_.st[2 * f + 1];
+  if (S.done) {
+    if (lead) B_.st[2 * f] = S;
+    return;
+  }
+  const SolveParams prm = *B_.prm;
+  const double rr = frame_sum(B_.part_rr + F.k0, F.K, dred);
   bool stop;
   if (setup) {
-    const double bb = frame_sum(pbb, np, dred);
+    const double bb = frame_sum(B_.part_pq + F.k0, F.K, dred);
     S.bnorm = sqrt(bb);
     S.target = (prm.tol * S.bnorm) * (prm.tol * S.bnorm);
     S.rr = rr;
@@ -596,31 +608,28 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_frame_check(const FrameDesc* f
     const int u = S.it + 1;
     stop = stop_checks(S, prm, u, rr, is_replacement(S, prm, u));
   }
-  if (threadIdx.x == 0) {
-    if (stop) {
-      S.done = 1;
-      atomicSub(B_.n_active, 1);
-    }
-    *sp = S;
+  if (stop) S.done = 1;
+  if (lead) {
+    B_.st[2 * f] = S;
+    if (stop) atomicSub(B_.n_active, 1);
   }
-  if (HMAT && !stop) coarse_stage<LS, FT>(F, B_.uh, B_.vh, fac.B, B_.Tr, B_.Tc, lds);
+  if (stop || cb.y < 0) return;
+  tile_couple<LS, FT>(F, cb.y, B_.uh, B_.vh, fac.B, B_.Tr, B_.Tc);
 }
 
-// Last kernel (leaf blocks): z += Ut T^r + Vt T^c, partials of r.z.
+// Last kernel (leaf blocks): gather T^r, T^c, z += Ut T^r + Vt T^c,
+// partials of r.z.
 template <int L, int LS, typename FT>
 __global__ __launch_bounds__(LEAF_THREADS) void k_prolong(const FrameDesc* fr, const int* leaf2f, PcgBufs B_,
-                                                          Factors<FT> fac, int slot) {
+                                                          Factors<FT> fac) {
   __shared__ float trs[LS], tcs[LS];
   __shared__ double dred[LEAF_THREADS / 64];
   const int64_t kg = blockIdx.x;
   const int f = leaf2f[kg];
   const FrameDesc F = fr[f];
-  if (B_.st[2 * f + slot].done) return;
+  if (B_.st[2 * f].done) return;
   const int64_t row0 = F.n0 + (kg - F.k0) * L;
-  if (threadIdx.x < LS) {
-    trs[threadIdx.x] = B_.Tr[kg * LS + threadIdx.x];
-    tcs[threadIdx.x] = B_.Tc[kg * LS + threadIdx.x];
-  }
+  if (threadIdx.x < LS) gather_leaf<LS>(F, kg, threadIdx.x, B_.Tr, B_.Tc, trs[threadIdx.x], tcs[threadIdx.x]);
   __syncthreads();
   constexpr int TPR = LEAF_THREADS / L;
   const int row = threadIdx.x / TPR;
@@ -754,7 +763,6 @@ __global__ void k_finalize_x(const FrameDesc* fr, const int* blk2f, const FrameS
 
 
 
-static size_t coarse_lds_bytes(int kmax, int ls) { return (size_t)(2 * kmax * ls + ls) * sizeof(float); }
 
 hp_status launch_assemble(const LaunchGeom& g, const float* rho, float* sys) {
   hipLaunchKernelGGL(k_assemble, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, rho, sys, g.ntot);
@@ -776,8 +784,8 @@ static hp_status apply_t(const LaunchGeom& g, const float* sys, const void* fbas
                   (const FT*)(base + offs[3]), (const float*)(base + offs[4])};
   hipLaunchKernelGGL((k_apply_leaf<L, LS, FT>), dim3(g.ktot), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.leaf2f, sys,
                      g.ntot, fac, r, y, uh, vh);
-  hipLaunchKernelGGL((k_apply_coarse<LS, FT>), dim3(g.nframes), dim3(LEAF_THREADS), coarse_lds_bytes(g.kmax, LS),
-                     g.stream, g.fr, fac, uh, vh, Tr, Tc);
+  hipLaunchKernelGGL((k_apply_coarse<LS, FT>), dim3(g.ncblk), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.cblk, fac,
+                     uh, vh, Tr, Tc);
   hipLaunchKernelGGL((k_apply_prolong<L, LS, FT>), dim3(g.ktot), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.leaf2f,
                      fac, Tr, Tc, y);
   HP_HIP(hipGetLastError());
@@ -812,10 +820,9 @@ static void hmat_setup(const PcgLaunch& P) {
   const LaunchGeom& g = P.g;
   hipLaunchKernelGGL((k_setup_hmat<L, LS, FT>), dim3(g.ktot), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.leaf2f, P.B,
                      fac);
-  hipLaunchKernelGGL((k_frame_check<LS, FT, true>), dim3(g.nframes), dim3(LEAF_THREADS), coarse_lds_bytes(g.kmax, LS),
-                     g.stream, g.fr, P.B, fac, SLOT0, 1);
-  hipLaunchKernelGGL((k_prolong<L, LS, FT>), dim3(g.ktot), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.leaf2f, P.B, fac,
-                     SLOT0);
+  hipLaunchKernelGGL((k_coarse_check<LS, FT>), dim3(g.ncblk), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.cblk, P.B,
+                     fac, 1);
+  hipLaunchKernelGGL((k_prolong<L, LS, FT>), dim3(g.ktot), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.leaf2f, P.B, fac);
 }
 
 template <int L, int LS, typename FT>
@@ -826,14 +833,13 @@ static void hmat_iter(const PcgLaunch& P, int par) {
   float* pnew = par ? P.B.p0 : P.B.p1;
   const double* xold = par ? P.B.x1 : P.B.x0;
   double* xnew = par ? P.B.x0 : P.B.x1;
-  hipLaunchKernelGGL(k_spmv_p<false>, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B, par, pold,
+  hipLaunchKernelGGL(k_spmv_p<false>, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B, 0, 1, pold,
                      pnew);
   hipLaunchKernelGGL((k_update_hmat<L, LS, FT>), dim3(g.ktot), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.leaf2f, P.B,
-                     fac, par, xold, xnew, (const float*)pnew);
-  hipLaunchKernelGGL((k_frame_check<LS, FT, true>), dim3(g.nframes), dim3(LEAF_THREADS), coarse_lds_bytes(g.kmax, LS),
-                     g.stream, g.fr, P.B, fac, par ^ 1, 0);
-  hipLaunchKernelGGL((k_prolong<L, LS, FT>), dim3(g.ktot), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.leaf2f, P.B, fac,
-                     par ^ 1);
+                     fac, xold, xnew, (const float*)pnew);
+  hipLaunchKernelGGL((k_coarse_check<LS, FT>), dim3(g.ncblk), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.cblk, P.B,
+                     fac, 0);
+  hipLaunchKernelGGL((k_prolong<L, LS, FT>), dim3(g.ktot), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.leaf2f, P.B, fac);
 }
 
 hp_status pcg_setup(const PcgLaunch& P) {
@@ -853,9 +859,7 @@ hp_status pcg_setup(const PcgLaunch& P) {
       hipLaunchKernelGGL(k_setup_simple<true>, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B);
     else
       hipLaunchKernelGGL(k_setup_simple<false>, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B);
-    Factors<float> none{};
-    hipLaunchKernelGGL((k_frame_check<16, float, false>), dim3(g.nframes), dim3(LEAF_THREADS), 0, g.stream, g.fr, P.B,
-                       none, SLOT0, 1);
+    hipLaunchKernelGGL(k_frame_setup, dim3(g.nframes), dim3(LEAF_THREADS), 0, g.stream, g.fr, P.B);
   }
   HP_HIP(hipGetLastError());
   return HP_OK;
@@ -881,8 +885,8 @@ hp_status pcg_iterations(const PcgLaunch& P, int count) {
       float* pnew = par ? P.B.p0 : P.B.p1;
       const double* xold = par ? P.B.x1 : P.B.x0;
       double* xnew = par ? P.B.x0 : P.B.x1;
-      hipLaunchKernelGGL(k_spmv_p<true>, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B, par, pold,
-                         pnew);
+      hipLaunchKernelGGL(k_spmv_p<true>, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B, par,
+                         par ^ 1, pold, pnew);
       if (P.mode == HP_PRECOND_JACOBI)
         hipLaunchKernelGGL(k_update_simple<true>, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B,
                            par, xold, xnew, (const float*)pnew);

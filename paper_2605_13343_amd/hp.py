@@ -52,6 +52,11 @@ class FactorSet(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("F", "U", "V", "Ut", "Vt", "lam")]
 
 
+class AdamWOpts(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("weight_decay", C.c_double), ("clip", C.c_double), ("step", C.c_int32)]
+
+
 class SolveResult(C.Structure):
     _fields_ = [("iters", C.c_int32), ("flags", C.c_int32), ("relres", C.c_double)]
 
@@ -77,12 +82,17 @@ EXPORTS = {
     "hp_infer_factors": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32], C.c_int32),
     "hp_debug_copy": ([C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64], C.c_int32),
     "hp_profile_enable": ([C.c_void_p, C.c_char_p], C.c_int32),
+    "hp_debug_set": ([C.c_void_p, C.c_char_p, C.c_int32], C.c_int32),
     "hp_train_init": ([C.c_void_p, C.c_int32], C.c_int32),
     "hp_probes": ([C.c_void_p] * 5 + [C.c_int32, C.c_float], C.c_int32),
     "hp_loss_fwd": ([C.c_void_p, C.c_void_p, C.POINTER(FactorSet), C.c_void_p, C.c_void_p, C.c_double,
                      C.c_void_p], C.c_int32),
     "hp_loss_bwd": ([C.c_void_p, C.c_void_p, C.POINTER(FactorSet), C.c_void_p, C.c_void_p, C.POINTER(FactorSet)],
                     C.c_int32),
+    "hp_train_grad": ([C.c_void_p] * 5 + [C.c_int32, C.c_float, C.c_int32, C.c_void_p, C.c_void_p], C.c_int32),
+    "hp_train_step": ([C.c_void_p] * 8 + [C.c_int32, C.c_float, C.c_int32, C.POINTER(AdamWOpts), C.c_void_p,
+                                            C.c_void_p], C.c_int32),
+    "hp_adamw_step": ([C.c_void_p] * 5 + [C.c_int64, C.POINTER(AdamWOpts), C.c_void_p], C.c_int32),
     "hp_profile_read": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double)],
                         C.c_int32),
 }
@@ -257,6 +267,9 @@ class Batch:
             _check(st)
         return [(r.iters, r.flags, r.relres) for r in res]
 
+    def debug_set(self, name: str, value: int):
+        _check(lib().hp_debug_set(self.h, name.encode(), int(value)))
+
     def profile_enable(self, kernel: str):
         _check(lib().hp_profile_enable(self.h, kernel.encode()))
 
@@ -296,6 +309,35 @@ class Batch:
 
     def infer_factors(self, weights, rho, sys, fac, compute: int):
         _check(lib().hp_infer_factors(self.h, _ptr(weights), _ptr(rho), _ptr(sys), _ptr(fac), compute))
+
+    def train_grad(self, weights, rho, sys, zraw, grad, compute: int, sweeps: int = 2, omega: float = 0.6,
+                   want_loss: bool = True):
+        """Gradient of the batch-mean loss w.r.t. the flat weights into grad;
+        returns the loss (synchronising) when want_loss."""
+        out = C.c_double(0.0)
+        _check(lib().hp_train_grad(self.h, _ptr(weights), _ptr(rho), _ptr(sys), _ptr(zraw), sweeps, omega, compute,
+                                   _ptr(grad), C.byref(out) if want_loss else None))
+        return out.value if want_loss else None
+
+    def train_step(self, weights, grad, m, v, rho, sys, zraw, step: int, compute: int, lr: float = 1e-3,
+                   betas=(0.9, 0.999), eps: float = 1e-8, weight_decay: float = 1e-4, clip: float = 1.0,
+                   sweeps: int = 2, omega: float = 0.6, want_loss: bool = True):
+        """One step: gradient at the current weights, then AdamW.  Returns
+        (loss, pre-clip gradient norm) when want_loss (synchronising)."""
+        o = AdamWOpts(lr, betas[0], betas[1], eps, weight_decay, clip, step)
+        lo, gn = C.c_double(0.0), C.c_double(0.0)
+        _check(lib().hp_train_step(self.h, _ptr(weights), _ptr(grad), _ptr(m), _ptr(v), _ptr(rho), _ptr(sys),
+                                   _ptr(zraw), sweeps, omega, compute, C.byref(o),
+                                   C.byref(lo) if want_loss else None, C.byref(gn) if want_loss else None))
+        return (lo.value, gn.value) if want_loss else None
+
+    def adamw_step(self, weights, grad, m, v, step: int, lr: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8,
+                   weight_decay: float = 1e-4, clip: float = 1.0, want_norm: bool = False):
+        o = AdamWOpts(lr, betas[0], betas[1], eps, weight_decay, clip, step)
+        out = C.c_double(0.0)
+        _check(lib().hp_adamw_step(self.h, _ptr(weights), _ptr(grad), _ptr(m), _ptr(v), int(weights.numel()),
+                                   C.byref(o), C.byref(out) if want_norm else None))
+        return out.value if want_norm else None
 
 
 FACTOR_NAMES = ("F", "U", "V", "Ut", "Vt", "lam")

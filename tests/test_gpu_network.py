@@ -149,3 +149,47 @@ def test_forward_batched_equals_single():
     G, B, Ut, Vt, lam = allf[0]
     assert relerr(G, hmatrix.gram(o["F"])) <= 1e-4
     assert relerr(Ut, o["Ut"]) <= 1e-4 and relerr(lam, o["lam"]) <= 1e-4
+
+
+@pytest.mark.parametrize("cfg,recipe,seed", [(PLAIN, "plain1024", 1000), (DEF, "precision8192", 2000)])
+def test_bf16_leaf_attention_matrix_cores_match_vector_alus(cfg, recipe, seed):
+    """The MFMA leaf attention (key order permuted inside each step, P rounded
+    to BF16 for the second product) computes what the vector-ALU kernel
+    computes: residual streams after the last layer agree to the BF16
+    rounding of P (2^-9 relative, accumulated over the layers)."""
+    import torch
+    w = test_weights(cfg)
+    fr = inputs.make_frame(recipe, seed)
+    s = Side(cfg, [fr], with_net=True)
+    wt = torch.tensor(hp.pack_weights(cfg, w), device="cuda")
+    out = {}
+    for valu in (1, 0):
+        s.B.debug_set("attention_valu", valu)
+        fac = s.B.new_factors(hp.HP_BF16)
+        s.B.infer_factors(wt, s.rho, s.sys, fac, hp.HP_BF16)
+        torch.cuda.synchronize()
+        out[valu] = (_dbg(s, "xd", (fr.n, cfg.d)), s.download_factors(fac, hp.HP_BF16)[0])
+    e_xd = relerr(out[0][0], out[1][0])
+    e_G = relerr(out[0][1][0], out[1][1][0])
+    print(f"mfma vs valu attention: xd {e_xd:.2e}  G {e_G:.2e}")
+    assert e_xd <= 1e-2 and e_G <= 2e-2
+
+
+@pytest.mark.parametrize("cfg,recipe,seed", [(PLAIN, "plain1024", 1000), (DEF, "precision8192", 2000)])
+def test_bf16_wide_gemm_equals_small_tile_gemm(cfg, recipe, seed):
+    """The 128 x 128 double-buffered GEMM runs the same MFMA sequence along K
+    as the 64 x 64 kernel, so the whole BF16 forward is bit-identical."""
+    import torch
+    w = test_weights(cfg)
+    frs = [inputs.make_frame(recipe, seed), inputs.make_frame(recipe, seed + 1)]
+    s = Side(cfg, frs, with_net=True)
+    wt = torch.tensor(hp.pack_weights(cfg, w), device="cuda")
+    out = {}
+    for small in (1, 0):
+        s.B.debug_set("gemm_small_tiles", small)
+        fac = s.B.new_factors(hp.HP_BF16)
+        s.B.infer_factors(wt, s.rho, s.sys, fac, hp.HP_BF16)
+        torch.cuda.synchronize()
+        out[small] = (_dbg(s, "xd", (s.B.ntot, cfg.d)), fac.clone())
+    assert np.array_equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1])

@@ -25,6 +25,24 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, s), s
 
 
+def _prototype_arity():
+    """Parameter count of every function the header declares."""
+    txt = open(os.path.join(ROOT, "include", "hp.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    out = {}
+    for m in re.finditer(r"^\s*(?:hp_status|const char\*)\s+(hp_\w+)\s*\(([^)]*)\)\s*;", txt, re.M):
+        args = m.group(2).strip()
+        out[m.group(1)] = 0 if args in ("", "void") else len(args.split(","))
+    return out
+
+
+def test_binding_argument_counts_match_header():
+    ar = _prototype_arity()
+    assert set(hp.EXPORTS) <= set(ar), sorted(set(hp.EXPORTS) - set(ar))
+    for name, (args, _) in hp.EXPORTS.items():
+        assert len(args) == ar[name], (name, len(args), ar[name])
+
+
 @pytest.mark.parametrize("dims", [(16, 8, 8), (16, 16, 8), (32, 16, 16), (5, 3, 2), (1, 1, 1)])
 def test_morton_order_bit_exact(dims):
     assert np.array_equal(hp.morton_order(*dims), grid.morton_perm(*dims))
