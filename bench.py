@@ -48,6 +48,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=N_FRAMES)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--method-only", action="store_true",
+                    help="time only the BF16 batched method (for counter runs under rocprofv3)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU design is "
@@ -72,6 +76,14 @@ def main() -> int:
         return rho, b
 
     wt = torch.tensor(hp.pack_weights(cfg, w), device="cuda")
+    if args.calib_copy_mib > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch
+        # scale the same counters of the library's kernels to HBM bytes
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---------------------------------------------------------------- batched BF16 method
     B = hp.Batch(cfg, dims, stream)
@@ -117,19 +129,47 @@ def main() -> int:
     torch.cuda.synchronize()
     infer_ms = e0.elapsed_time(e1) / 3
 
-    # ---------------------------------------------------------------- roofline of the dominant kernel
-    # k_gemm (BF16 MFMA): every GEMM launch of one inference, timed with HIP
+    if args.method_only:
+        print(json.dumps({"metric": "ms/frame (BF16 batched method only; counter run)", "value": round(ms_frame, 4),
+                          "unit": "ms/frame", "steps": args.steps, "iterations_mean": float(np.mean(iters)),
+                          "inference_ms_per_batch": round(infer_ms, 4)}))
+        return 0
+
+    # ---------------------------------------------------------------- rooflines
+    # GEMMs (BF16 MFMA): every GEMM launch of one inference, timed with HIP
     # events on the batch stream; algorithmic work 2 M N K per launch.
     B.profile_enable("gemm")
     B.infer_factors(wt, rho, sys_, fac, hp.HP_BF16)
     n_gemm, gemm_ms, gemm_flops = B.profile_read()
     B.profile_enable("none")
-    achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
-                "kernel": "k_gemm<bf16> (MFMA 32x32x16, FP32 accumulation)", "launches": n_gemm,
-                "avg_launch_us": round(gemm_ms * 1e3 / max(n_gemm, 1), 2),
-                "flops_per_inference": gemm_flops}
+    gemm_tf = gemm_flops / (gemm_ms * 1e-3) / 1e12
+    gemm_roof = {"bound": "mfma", "achieved": round(gemm_tf, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                 "frac": round(gemm_tf / PEAK_BF16_TFLOPS, 4), "traffic": None,
+                 "kernel": "k_gemm_wide + k_gemm<bf16> (MFMA 32x32x16, FP32 accumulation)", "launches": n_gemm,
+                 "avg_launch_us": round(gemm_ms * 1e3 / max(n_gemm, 1), 2), "ms_per_inference": round(gemm_ms, 4),
+                 "flops_per_inference": gemm_flops}
+    # PCG kernels (HBM): an eager 20-iteration solve with every frame active,
+    # each k_update_hmat / k_spmv_p launch timed with HIP events; algorithmic
+    # bytes per launch as stated in the library header.
+    pcg_roofs = {}
+    for fam, kname in (("update", "k_update_hmat<64, 16, bf16>"), ("spmv", "k_spmv_p<false>")):
+        x.zero_()
+        B.profile_enable(fam)
+        B.pcg_solve(sys_, fac, b, x, hp.PRECOND_HMAT, fdtype=hp.HP_BF16, tol=0.0, max_iter=20, fallback=False,
+                    use_graph=False, stagnation=False, raise_on_fail=False)
+        n_l, l_ms, l_bytes = B.profile_read()
+        B.profile_enable("none")
+        gbs = l_bytes / (l_ms * 1e-3) / 1e9
+        pcg_roofs[fam] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                          "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None, "kernel": kname, "launches": n_l,
+                          "avg_launch_us": round(l_ms * 1e3 / max(n_l, 1), 2),
+                          "bytes_per_launch": l_bytes / max(n_l, 1)}
+    # the dominant kernel of a step: GEMM time per inference against the
+    # update kernel's time over the step's iterations
+    upd_ms_step = pcg_roofs["update"]["avg_launch_us"] * 1e-3 * float(np.max(iters))
+    roofline = dict(gemm_roof) if gemm_ms >= upd_ms_step else dict(pcg_roofs["update"])
+    roofline["others"] = {"gemm": gemm_roof, "pcg_update": pcg_roofs["update"], "pcg_spmv": pcg_roofs["spmv"]}
+    roofline["others"] = {k: v for k, v in roofline["others"].items() if v["kernel"] != roofline["kernel"]}
 
     # ---------------------------------------------------------------- Jacobi, batched
     def jac_step():

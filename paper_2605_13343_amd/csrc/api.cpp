@@ -285,6 +285,7 @@ static hp_status run_pass(Batch* b, PcgLaunch& P, const hp_solve_opts& o, const 
       if (!b->cap_stream) HP_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
       PcgLaunch C = P;
       C.g.stream = b->cap_stream;
+      C.prof = nullptr;
       hipGraph_t graph;
       HP_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
       hp_status s = pcg_iterations(C, chunk);
@@ -341,6 +342,7 @@ extern "C" hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_
   P.fdtype = o.fdtype;
   P.fbase = d_factors;
   P.offs = offs;
+  if (!o.use_graph) P.prof = &b->prof;
   PcgBufs& B = P.B;
   B.sys = d_sys;
   B.ntot = b->ntot;
@@ -432,7 +434,8 @@ extern "C" hp_status hp_debug_set(hp_batch b, const char* name, int32_t value) {
 extern "C" hp_status hp_profile_enable(hp_batch b, const char* kernel) {
   if (!b || !kernel) return set_error(HP_E_INVALID, "hp_profile_enable: NULL argument");
   const std::string k = kernel;
-  int kind = k == "gemm" ? PROF_GEMM : k == "none" ? PROF_NONE : -1;
+  int kind = k == "gemm" ? PROF_GEMM : k == "update" ? PROF_UPDATE : k == "spmv" ? PROF_SPMV : k == "none" ? PROF_NONE
+                                                                                                          : -1;
   if (kind < 0) return set_error(HP_E_INVALID, "hp_profile_enable: unknown kernel family '%s'", kernel);
   if (kind != PROF_NONE && b->prof.ev.empty()) {
     b->prof.ev.resize(2 * 4096);

@@ -38,22 +38,6 @@ struct PcgBufs {
   const SolveParams* prm;
 };
 
-struct PcgLaunch {
-  LaunchGeom g;
-  PcgBufs B;
-  int mode, L, LS, fdtype;
-  const void* fbase;
-  const int64_t* offs;
-};
-
-// Device workspace of the network forward (sized at batch creation).
-struct NetWork {
-  int64_t tokens_d = 0, tokens_o = 0;  // diagonal and off-diagonal token counts
-  float* feats = nullptr;              // [ntot][32] node features, zero padded
-  void* ws = nullptr;                  // one arena for every activation buffer
-  size_t ws_bytes = 0;
-};
-
 // Live kernel timing: every launch of one kernel family is bracketed by HIP
 // events on the batch stream (eager launches only, never inside a capture).
 enum { PROF_NONE = 0, PROF_GEMM = 1, PROF_UPDATE = 2, PROF_SPMV = 3 };
@@ -62,6 +46,23 @@ struct Prof {
   std::vector<hipEvent_t> ev;  // 2 per launch
   int used = 0;
   double work = 0.0;           // algorithmic flops (GEMM) or bytes (others)
+};
+
+struct PcgLaunch {
+  LaunchGeom g;
+  PcgBufs B;
+  int mode, L, LS, fdtype;
+  const void* fbase;
+  const int64_t* offs;
+  Prof* prof = nullptr;  // eager launches only (never set while capturing)
+};
+
+// Device workspace of the network forward (sized at batch creation).
+struct NetWork {
+  int64_t tokens_d = 0, tokens_o = 0;  // diagonal and off-diagonal token counts
+  float* feats = nullptr;              // [ntot][32] node features, zero padded
+  void* ws = nullptr;                  // one arena for every activation buffer
+  size_t ws_bytes = 0;
 };
 
 struct Batch {

@@ -446,7 +446,18 @@ __global__ void k_leaf_stencil(const FrameDesc* fr, const int* node2f, const flo
 
 // Per-layer corrections of the diagonal bias at the stencil entries:
 // corr[i][e][h] = MLP_e(dx_ij/4, Ahat_ij) - MLP_e(dx_ij/4, 0).
-__global__ void k_edge_corr(EdgeW w, const uint8_t* nbr, const float* ahat, int64_t ntot, float* corr) {
+__global__ __launch_bounds__(128) void k_edge_corr(EdgeW w, const uint8_t* nbr, const float* ahat, int64_t ntot,
+                                                   float* corr) {
+  // MLP_e(dx_e, 0) depends on the stencil slot only: 7 evaluations per block
+  __shared__ float base[7][8];
+  if (threadIdx.x < 7) {
+    const int e = threadIdx.x;
+    float d[3] = {0.f, 0.f, 0.f};
+    if (e > 0) d[(e - 1) / 2] = ((e - 1) % 2 == 0) ? 0.25f : -0.25f;
+    const float e0[4] = {d[0], d[1], d[2], 0.f};
+    edge_mlp(w, e0, base[e]);
+  }
+  __syncthreads();
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= ntot * 7) return;
   const int e = (int)(p % 7);
@@ -457,11 +468,10 @@ __global__ void k_edge_corr(EdgeW w, const uint8_t* nbr, const float* ahat, int6
   }
   float d[3] = {0.f, 0.f, 0.f};
   if (e > 0) d[(e - 1) / 2] = ((e - 1) % 2 == 0) ? 0.25f : -0.25f;
-  float e1[4] = {d[0], d[1], d[2], ahat[p]}, e0[4] = {d[0], d[1], d[2], 0.f};
-  float a[8], b[8];
+  const float e1[4] = {d[0], d[1], d[2], ahat[p]};
+  float a[8];
   edge_mlp(w, e1, a);
-  edge_mlp(w, e0, b);
-  for (int h = 0; h < w.H; ++h) o[h] = a[h] - b[h];
+  for (int h = 0; h < w.H; ++h) o[h] = a[h] - base[e][h];
 }
 
 // Off-diagonal pair descriptors (Supplementary "Off-diagonal attention

@@ -833,10 +833,29 @@ static void hmat_iter(const PcgLaunch& P, int par) {
   float* pnew = par ? P.B.p0 : P.B.p1;
   const double* xold = par ? P.B.x1 : P.B.x0;
   double* xnew = par ? P.B.x0 : P.B.x1;
+  // live timing (eager only): algorithmic bytes of an iteration without
+  // residual replacement, every frame active
+  auto timed = [&](int kind) {
+    Prof* pr = P.prof;
+    if (!pr || pr->kind != kind || 2 * (pr->used + 1) > (int)pr->ev.size()) return false;
+    hipEventRecord(pr->ev[2 * pr->used], g.stream);
+    return true;
+  };
+  auto done = [&](double bytes) {
+    Prof* pr = P.prof;
+    hipEventRecord(pr->ev[2 * pr->used + 1], g.stream);
+    pr->used++;
+    pr->work += bytes;
+  };
+  bool t = timed(PROF_SPMV);
   hipLaunchKernelGGL(k_spmv_p<false>, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, P.B, 0, 1, pold,
                      pnew);
+  if (t) done(32.0 * (double)g.ntot);  // z, p_old, 4 coefficients in; p, q out
+  t = timed(PROF_UPDATE);
   hipLaunchKernelGGL((k_update_hmat<L, LS, FT>), dim3(g.ktot), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.leaf2f, P.B,
                      fac, xold, xnew, (const float*)pnew);
+  // per node p, q, r, x, lam, 1/diag in, x, r, z out (44 B); per leaf G, Ut, Vt in, u, v out
+  if (t) done((double)g.ktot * (44.0 * L + (double)sizeof(FT) * (L * L + 2 * L * LS) + 8.0 * LS));
   hipLaunchKernelGGL((k_coarse_check<LS, FT>), dim3(g.ncblk), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.cblk, P.B,
                      fac, 0);
   hipLaunchKernelGGL((k_prolong<L, LS, FT>), dim3(g.ktot), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.leaf2f, P.B, fac);

@@ -12,7 +12,9 @@ relative threshold 5e-3, floor max(1e-3 lr, 1e-6)).
 Validation solves held-out frames with PCG and the learned preconditioner and
 reports mean iterations beside Jacobi-PCG, which is what training is for.
 
-    python -m paper_2605_13343_amd.train --steps 2000 --out weights/trained_L64.npz
+    python -m paper_2605_13343_amd.train --steps 3000 \
+        --mix train4096:32,precision8192:16,largest16384:8 \
+        --val train4096:3900,precision8192:2000,largest16384:7000 --out weights/trained_L64.npz
 """
 from __future__ import annotations
 
@@ -88,43 +90,52 @@ class Validator:
         return {"hmat_iters": it, "fell_back": fell, "not_spd": spd, "jacobi_iters": self.jacobi[0]}
 
 
-def train(cfg=inputs.MODEL_DEFAULT, steps: int = 2000, batch: int = 32, recipe: str = "train4096",
-          lr: float = 1e-3, compute: int = hp.HP_BF16, seed_base: int = 3_000_000, init_seed: int = 7,
-          log_every: int = 20, val_every: int = 200, val_recipe: str = "train4096",
-          val_seeds: Optional[List[int]] = None, init: Optional[Dict[str, np.ndarray]] = None,
-          plateau: bool = True, warmup: int = 0, extra_val: Optional[Dict[str, List[int]]] = None,
-          log=print) -> Dict:
+# Seed bases of the training draws per recipe (disjoint from every
+# validation and benchmark seed).
+SEED_BASE = {"train4096": 3_000_000, "precision8192": 5_000_000, "largest16384": 6_000_000,
+             "plain1024": 8_000_000}
+
+
+def train(cfg=inputs.MODEL_DEFAULT, steps: int = 2000, mix=(("train4096", 32),), lr: float = 2e-4,
+          compute: int = hp.HP_BF16, init_seed: int = 7, log_every: int = 20, val_every: int = 200,
+          val: Optional[Dict[str, List[int]]] = None, init: Optional[Dict[str, np.ndarray]] = None,
+          plateau: bool = True, warmup: int = 0, log=print) -> Dict:
+    """Train for `steps` steps; step s draws a fresh batch of mix[s % len(mix)]
+    = (recipe, systems per batch) with seeds SEED_BASE[recipe] + batch * k + i
+    (k counts that recipe's batches)."""
     import torch
-    rc = inputs.RECIPES[recipe]
-    if len(rc.grids) != 1:
-        raise ValueError("training batches use one grid shape per recipe")
-    dims = [rc.grids[0]] * batch
-    perm = hp.morton_order(*rc.grids[0])
-    n = int(np.prod(rc.grids[0]))
-    B = hp.Batch(cfg, dims)
-    sys_ = B.new_sys()
+    trainers = []
+    for recipe, batch in mix:
+        rc = inputs.RECIPES[recipe]
+        if len(rc.grids) != 1:
+            raise ValueError("training batches use one grid shape per recipe")
+        B = hp.Batch(cfg, [rc.grids[0]] * batch)
+        trainers.append({"recipe": recipe, "rc": rc, "batch": batch, "B": B, "sys": B.new_sys(),
+                         "perm": hp.morton_order(*rc.grids[0]), "n": int(np.prod(rc.grids[0])), "count": 0})
     w0 = init if init is not None else inputs.init_weights(cfg, init_seed)
     flat = torch.tensor(hp.pack_weights(cfg, w0), device="cuda")
     grad, m, v = torch.zeros_like(flat), torch.zeros_like(flat), torch.zeros_like(flat)
-    vals = {val_recipe: Validator(cfg, val_recipe, val_seeds if val_seeds is not None
-                                  else [3900 + f for f in range(20)])}
-    for rname, seeds in (extra_val or {}).items():
-        vals[rname] = Validator(cfg, rname, seeds)
+    val = val if val is not None else {"train4096": [3900 + f for f in range(20)]}
+    vals = {rname: Validator(cfg, rname, seeds) for rname, seeds in val.items()}
     validate = lambda: {k: vv(flat) for k, vv in vals.items()}
     sched = Plateau(lr)
     cur_lr = lr * (1.0 / warmup if warmup > 0 else 1.0)
-    hist = {"step": [], "loss": [], "lr": [], "val": [], "gnorm": []}
+    hist = {"step": [], "loss": [], "lr": [], "val": [], "gnorm": [], "mix": [list(x) for x in mix]}
     v0 = validate()
     hist["val"].append((0, v0))
     log(json.dumps({"step": 0, "val": v0}))
     window, t0 = [], time.time()
     for step in range(1, steps + 1):
-        seeds = [seed_base + batch * (step - 1) + i for i in range(batch)]
-        frames = [inputs.make_frame(rc, s) for s in seeds]
-        rho = torch.tensor(np.concatenate([f.rho[perm] for f in frames]).astype(np.float32), device="cuda")
-        zr = torch.tensor(np.concatenate([inputs.rademacher(n, 16, s + 7_000_000) for s in seeds]), device="cuda")
-        B.assemble(rho, sys_)
-        loss, gn = B.train_step(flat, grad, m, v, rho, sys_, zr, step, compute, lr=cur_lr)
+        T = trainers[(step - 1) % len(trainers)]
+        base = SEED_BASE.get(T["recipe"], 9_000_000) + T["batch"] * T["count"]
+        T["count"] += 1
+        seeds = [base + i for i in range(T["batch"])]
+        frames = [inputs.make_frame(T["rc"], sd) for sd in seeds]
+        rho = torch.tensor(np.concatenate([f.rho[T["perm"]] for f in frames]).astype(np.float32), device="cuda")
+        zr = torch.tensor(np.concatenate([inputs.rademacher(T["n"], 16, sd + 7_000_000) for sd in seeds]),
+                          device="cuda")
+        T["B"].assemble(rho, T["sys"])
+        loss, gn = T["B"].train_step(flat, grad, m, v, rho, T["sys"], zr, step, compute, lr=cur_lr)
         if not np.isfinite(loss):
             raise FloatingPointError(f"loss is {loss} at step {step}")
         window.append(loss)
@@ -154,17 +165,17 @@ def train(cfg=inputs.MODEL_DEFAULT, steps: int = 2000, batch: int = 32, recipe: 
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--batch", type=int, default=32)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=2e-4)
     ap.add_argument("--warmup", type=int, default=0, help="linear warm-up steps (0: none)")
-    ap.add_argument("--val-bench", action="store_true",
-                    help="also validate on the precision workload frames (N = 8,192, seeds 2000..2019)")
-    ap.add_argument("--recipe", default="train4096")
+    ap.add_argument("--mix", default="train4096:32",
+                    help="comma-separated recipe:systems batches, used in turn (e.g. "
+                         "train4096:32,precision8192:16,largest16384:8)")
     ap.add_argument("--leaf", type=int, default=64)
     ap.add_argument("--fp32", action="store_true", help="FP32 compute instead of BF16")
     ap.add_argument("--no-plateau", action="store_true")
     ap.add_argument("--val-every", type=int, default=200)
-    ap.add_argument("--val-recipe", default="train4096")
+    ap.add_argument("--val", default="train4096:3900",
+                    help="comma-separated recipe:first_seed validation sets of 20 frames each")
     ap.add_argument("--init", default=None, help="start from these weights (npz)")
     ap.add_argument("--out", default=None, help="write the trained weights here (npz)")
     ap.add_argument("--history", default=None, help="write the loss/validation history here (json)")
@@ -174,10 +185,10 @@ def main(argv=None) -> int:
     if a.init:
         z = np.load(a.init, allow_pickle=False)
         init = {k: z[k] for k in z.files}
-    r = train(cfg, steps=a.steps, batch=a.batch, recipe=a.recipe, lr=a.lr,
-              compute=hp.HP_F32 if a.fp32 else hp.HP_BF16, plateau=not a.no_plateau, val_every=a.val_every,
-              val_recipe=a.val_recipe, init=init, warmup=a.warmup,
-              extra_val={"precision8192": list(range(2000, 2020))} if a.val_bench else None,
+    mix = [(t.split(":")[0], int(t.split(":")[1])) for t in a.mix.split(",")]
+    val = {t.split(":")[0]: list(range(int(t.split(":")[1]), int(t.split(":")[1]) + 20)) for t in a.val.split(",")}
+    r = train(cfg, steps=a.steps, mix=mix, lr=a.lr, compute=hp.HP_F32 if a.fp32 else hp.HP_BF16,
+              plateau=not a.no_plateau, val_every=a.val_every, val=val, init=init, warmup=a.warmup,
               log=lambda s: print(s, flush=True))
     if a.out:
         os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
