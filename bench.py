@@ -106,15 +106,16 @@ def main() -> int:
     for _ in range(args.warmup):
         res = step()
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
+    evs[0].record(stream)
+    for k in range(args.steps):
         res = step()
-    ev1.record(stream)
+        evs[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / args.steps
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+    ms_per_step = evs[0].elapsed_time(evs[-1]) / args.steps
     iters = [r[0] for r in res]
     flags = [r[1] for r in res]
     relres = [r[2] for r in res]
@@ -167,6 +168,8 @@ def main() -> int:
     # the dominant kernel of a step: GEMM time per inference against the
     # update kernel's time over the step's iterations
     upd_ms_step = pcg_roofs["update"]["avg_launch_us"] * 1e-3 * float(np.max(iters))
+    for r in [gemm_roof] + list(pcg_roofs.values()):
+        r["traffic"] = _traffic(r["kernel"])
     roofline = dict(gemm_roof) if gemm_ms >= upd_ms_step else dict(pcg_roofs["update"])
     roofline["others"] = {"gemm": gemm_roof, "pcg_update": pcg_roofs["update"], "pcg_spmv": pcg_roofs["spmv"]}
     roofline["others"] = {k: v for k, v in roofline["others"].items() if v["kernel"] != roofline["kernel"]}
@@ -238,6 +241,7 @@ def main() -> int:
         },
         "legs": {
             "bf16_batched_ms_per_frame": round(ms_frame, 4),
+            "bf16_ms_per_frame_p50_p90": [round(float(np.percentile(step_ms, q)) / len(frames), 4) for q in (50, 90)],
             "bf16_inference_ms_per_batch": round(infer_ms, 4),
             "bf16_iterations_mean": float(np.mean(iters)),
             "bf16_iterations_max": int(max(iters)),
@@ -252,10 +256,34 @@ def main() -> int:
             "wall_ms_per_step": round(wall, 4),
         },
         "roofline": roofline,
+        "autotune": B.autotune_report(),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
     return 0
+
+
+def _traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/hbm_traffic_counters.txt: FETCH_SIZE and WRITE_SIZE runs of
+    rocprofv3, scaled by a plain copy of known size), or None when there is
+    none or when the kernel's source file changed since the counters were
+    taken (its SHA-256 is recorded beside the figures)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_counters.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if not line.startswith("kernel="):
+            continue
+        kv = dict(t.split("=", 1) for t in line.strip().split(" | "))
+        if kv.get("kernel") != kernel:
+            continue
+        src = os.path.join(ROOT, kv["source"])
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != kv["source_sha256"]:
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    return None
 
 
 def _cpu_baseline(cfg, w, fr):

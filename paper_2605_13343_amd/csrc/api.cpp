@@ -428,7 +428,30 @@ extern "C" hp_status hp_debug_set(hp_batch b, const char* name, int32_t value) {
     b->gemm_small = value != 0;
     return HP_OK;
   }
+  if (n == "gemm_autotune") {
+    b->gemm_autotune = value != 0;
+    return HP_OK;
+  }
   return set_error(HP_E_INVALID, "hp_debug_set: unknown option '%s'", name);
+}
+
+extern "C" hp_status hp_autotune_report(hp_batch b, char* buf, int64_t len, int32_t* entries) {
+  if (!b || (!buf && len > 0) || len < 0) return set_error(HP_E_INVALID, "hp_autotune_report: bad arguments");
+  std::string out;
+  char line[160];
+  for (const auto& kv : b->gemm_pick) {
+    snprintf(line, sizeof line, "gemm N=%d K=%d M=%lld tile=%s small_us=%.2f wide_us=%.2f\n",
+             std::get<0>(kv.first), std::get<1>(kv.first), (long long)std::get<2>(kv.first),
+             kv.second.pick ? "128x128" : "64x64", kv.second.us_small, kv.second.us_wide);
+    out += line;
+  }
+  if (entries) *entries = (int32_t)b->gemm_pick.size();
+  if (len > 0) {
+    const size_t n = std::min<size_t>(out.size(), (size_t)len - 1);
+    memcpy(buf, out.data(), n);
+    buf[n] = 0;
+  }
+  return HP_OK;
 }
 
 extern "C" hp_status hp_profile_enable(hp_batch b, const char* kernel) {

@@ -65,6 +65,13 @@ struct NetWork {
   size_t ws_bytes = 0;
 };
 
+// Autotuner record of one GEMM shape: the chosen tile kernel (0: 64 x 64,
+// 1: 128 x 128) and the measured average launch time of each.
+struct GemmPick {
+  int pick;
+  float us_small, us_wide;
+};
+
 struct Batch {
   hp_model_config cfg{};
   Prof prof;
@@ -98,6 +105,8 @@ struct Batch {
   void (*train_free)(void*) = nullptr;
   int attn_valu = 0;                    // diagnostics: BF16 leaf attention on the vector ALUs
   int gemm_small = 0;                   // diagnostics: BF16 GEMMs on the 64 x 64 tile kernel only
+  int gemm_autotune = 1;                // time both tile kernels on a shape's first call
+  std::map<std::tuple<int, int, int64_t>, GemmPick> gemm_pick;
   void* net_train = nullptr;            // network training workspace (first hp_train_grad)
   void (*net_train_free)(void*) = nullptr;
   std::map<std::tuple<int, int, const void*, const void*, const void*, const void*, int>, hipGraphExec_t> graphs;

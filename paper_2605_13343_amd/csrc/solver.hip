@@ -183,40 +183,50 @@ __device__ inline void load_vec(const FT* p, float* out) {
 // Leaf stage of y = M r for leaf kg (global index) whose rows start at row0:
 //   y = G_k r_k + lam r / A_ii        -> y[row0 .. row0+L)
 //   u = Ut_k^T r_k,  v = Vt_k^T r_k   -> uh[kg], vh[kg]
-// rs: r_k in LDS (L floats).  Returns nothing; all threads take part.
+// split into load() (this thread's slice of G, Ut, Vt and the Jacobi gate,
+// independent of r, so kernels issue it before their reductions) and
+// apply() (rs: r_k in LDS; all threads take part).
 template <int L, int LS, typename FT>
-__device__ inline void leaf_stage(int64_t kg, int64_t row0, const float* rs, const Factors<FT>& fac,
-                                  const float* idg, float* y, float* uh, float* vh, float* red) {
-  constexpr int TPR = LEAF_THREADS / L;  // threads per row
-  constexpr int CPT = L / TPR;           // columns per thread
-  const int t = threadIdx.x;
-  {
-    int row = t / TPR, c0 = (t % TPR) * CPT;
-    float g[CPT];
+struct LeafPre {
+  static constexpr int TPR = LEAF_THREADS / L;   // threads per row (G product)
+  static constexpr int CPT = L / TPR;            // columns per thread
+  static constexpr int GR = LEAF_THREADS / LS;   // row groups (restriction)
+  static constexpr int RPG = L / GR;             // rows per group
+  static_assert(RPG >= 1, "leaf too small for the restriction layout");
+  float g[CPT], u[RPG], v[RPG], gate;
+
+  __device__ inline void load(int64_t kg, int64_t row0, const Factors<FT>& fac, const float* idg) {
+    const int t = threadIdx.x, row = t / TPR, c0 = (t % TPR) * CPT;
     load_vec<FT, CPT>(fac.G + (kg * L + row) * L + c0, g);
-    float a = 0.f;
+    const int s = t % LS, grp = t / LS;
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) a = fmaf(g[c], rs[c0 + c], a);
-#pragma unroll
-    for (int o = TPR / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-    if (t % TPR == 0) {
-      int64_t i = row0 + row;
-      y[i] = fmaf(fac.lam[i] * idg[i], rs[row], a);
+    for (int j = 0; j < RPG; ++j) {
+      const int64_t l = row0 + grp * RPG + j;
+      u[j] = ldf(fac.Ut, l * LS + s);
+      v[j] = ldf(fac.Vt, l * LS + s);
     }
+    gate = (t % TPR == 0) ? fac.lam[row0 + row] * idg[row0 + row] : 0.f;
   }
-  // restriction: thread -> (s, row group)
-  {
-    constexpr int G = LEAF_THREADS / LS;     // row groups
-    constexpr int RPG = L / G;               // rows per group
-    static_assert(RPG >= 1, "leaf too small for the restriction layout");
-    int s = t % LS, g = t / LS;
+
+  __device__ inline void apply(int64_t kg, int64_t row0, const float* rs, float* y, float* uh, float* vh,
+                               float* red) const {
+    const int t = threadIdx.x;
+    {
+      const int row = t / TPR, c0 = (t % TPR) * CPT;
+      float a = 0.f;
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) a = fmaf(g[c], rs[c0 + c], a);
+#pragma unroll
+      for (int o = TPR / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+      if (t % TPR == 0) y[row0 + row] = fmaf(gate, rs[row], a);
+    }
+    const int s = t % LS, grp = t / LS;
     float au = 0.f, av = 0.f;
 #pragma unroll
     for (int j = 0; j < RPG; ++j) {
-      int l = g * RPG + j;
-      float rl = rs[l];
-      au = fmaf(ldf(fac.Ut, (row0 + l) * LS + s), rl, au);
-      av = fmaf(ldf(fac.Vt, (row0 + l) * LS + s), rl, av);
+      const float rl = rs[grp * RPG + j];
+      au = fmaf(u[j], rl, au);
+      av = fmaf(v[j], rl, av);
     }
     // reduce the groups held inside one wave (lanes s + LS*q)
 #pragma unroll
@@ -224,7 +234,7 @@ __device__ inline void leaf_stage(int64_t kg, int64_t row0, const float* rs, con
       au += __shfl_xor(au, o, 64);
       av += __shfl_xor(av, o, 64);
     }
-    int w = t >> 6;
+    const int w = t >> 6;
     if ((t & 63) < LS) {
       red[w * 2 * LS + s] = au;
       red[w * 2 * LS + LS + s] = av;
@@ -237,36 +247,57 @@ __device__ inline void leaf_stage(int64_t kg, int64_t row0, const float* rs, con
       else vh[kg * LS + t - LS] = acc;
     }
   }
+};
+
+template <int L, int LS, typename FT>
+__device__ inline void leaf_stage(int64_t kg, int64_t row0, const float* rs, const Factors<FT>& fac,
+                                  const float* idg, float* y, float* uh, float* vh, float* red) {
+  LeafPre<L, LS, FT> pre;
+  pre.load(kg, row0, fac, idg);
+  pre.apply(kg, row0, rs, y, uh, vh, red);
 }
 
-// Prolongation for leaf kg: y[rows] += Ut_k T^r + Vt_k T^c.  Returns the
-// updated value of row (t / TPR) in the lane with t % TPR == 0, else 0; the
+// Prolongation for leaf kg: y[rows] += Ut_k T^r + Vt_k T^c.  load() reads
+// this thread's Ut, Vt entries (row t / TPR, entries s0 ..), apply() returns
+// the updated value of the row in the lane with t % TPR == 0, else 0; the
 // caller passes the row's current y value in yrow (lane t % TPR == 0).
 template <int L, int LS, typename FT>
-__device__ inline float prolong_row(int64_t row0, const float* trs, const float* tcs, const Factors<FT>& fac,
-                                    float yrow) {
-  constexpr int TPR = LEAF_THREADS / L;
-  constexpr int SPT = LS / TPR;  // coarse entries per thread
-  const int t = threadIdx.x;
-  int row = t / TPR, s0 = (t % TPR) * SPT;
-  float a = 0.f;
-  if constexpr (SPT >= 4) {
-    float u[SPT], v[SPT];
-    load_vec<FT, SPT>(fac.Ut + (row0 + row) * LS + s0, u);
-    load_vec<FT, SPT>(fac.Vt + (row0 + row) * LS + s0, v);
+struct ProlongPre {
+  static constexpr int TPR = LEAF_THREADS / L;
+  static constexpr int SPT = LS / TPR;  // coarse entries per thread
+  float u[SPT], v[SPT];
+
+  __device__ inline void load(int64_t row0, const Factors<FT>& fac) {
+    const int t = threadIdx.x, row = t / TPR, s0 = (t % TPR) * SPT;
+    if constexpr (SPT >= 4) {
+      load_vec<FT, SPT>(fac.Ut + (row0 + row) * LS + s0, u);
+      load_vec<FT, SPT>(fac.Vt + (row0 + row) * LS + s0, v);
+    } else {
 #pragma unroll
-    for (int s = 0; s < SPT; ++s) a = fmaf(u[s], trs[s0 + s], fmaf(v[s], tcs[s0 + s], a));
-  } else {
-#pragma unroll
-    for (int s = 0; s < SPT; ++s) {
-      a = fmaf(ldf(fac.Ut, (row0 + row) * LS + s0 + s), trs[s0 + s], a);
-      a = fmaf(ldf(fac.Vt, (row0 + row) * LS + s0 + s), tcs[s0 + s], a);
+      for (int s = 0; s < SPT; ++s) {
+        u[s] = ldf(fac.Ut, (row0 + row) * LS + s0 + s);
+        v[s] = ldf(fac.Vt, (row0 + row) * LS + s0 + s);
+      }
     }
   }
+
+  __device__ inline float apply(const float* trs, const float* tcs, float yrow) const {
+    const int s0 = (threadIdx.x % TPR) * SPT;
+    float a = 0.f;
 #pragma unroll
-  for (int o = TPR / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-  return yrow + a;
-}
+    for (int s = 0; s < SPT; ++s) {
+      if constexpr (SPT >= 4) {
+        a = fmaf(u[s], trs[s0 + s], fmaf(v[s], tcs[s0 + s], a));
+      } else {
+        a = fmaf(u[s], trs[s0 + s], a);
+        a = fmaf(v[s], tcs[s0 + s], a);
+      }
+    }
+#pragma unroll
+    for (int o = TPR / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    return yrow + a;
+  }
+};
 
 // Coarse coupling of one tile (paper Sec. 5 strip aggregation and coarse
 // coupling), run by one whole block.  Tile m = (j, i), S = 2^j leaves a side:
@@ -274,51 +305,68 @@ __device__ inline float prolong_row(int64_t row0, const float* trs, const float*
 //   s^c = sum of v over the column strip (leaves [2iS+S, 2iS+2S)),
 //   t^r = B_m s^c,  t^c = B_m^T s^r,
 // written to tr / tc [tile][LS].  The strip sums run in a fixed order
-// (NCH interleaved chunks of leaves, then the chunks in order).
+// (NCH interleaved chunks of leaves, then the chunks in order).  load() takes
+// the per-thread chunk sums and the B entries (no barrier, so a kernel can
+// issue it ahead of its reductions); finish() reduces and multiplies.
 template <int LS, typename FT>
-__device__ void tile_couple(const FrameDesc& F, int m, const float* uh, const float* vh, const FT* B, float* tr,
-                            float* tc) {
-  constexpr int NCH = LEAF_THREADS / LS;
-  __shared__ float pr[NCH][LS], pc[NCH][LS], sr[LS], sc[LS];
-  const int K = F.K, t = threadIdx.x;
-  int j = 0;
-  while (m >= K - (K >> (j + 1))) ++j;
-  const int i = m - (K - (K >> j)), S = 1 << j;
-  const int s = t % LS, ch = t / LS;
-  const int64_t lr = (int64_t)F.k0 + 2 * i * S, lc = lr + S;
-  float a = 0.f, c = 0.f;
-  for (int k = ch; k < S; k += NCH) {
-    a += uh[(lr + k) * LS + s];
-    c += vh[(lc + k) * LS + s];
-  }
-  pr[ch][s] = a;
-  pc[ch][s] = c;
-  __syncthreads();
-  if (t < LS) {
-    float x = 0.f;
-    for (int q = 0; q < NCH; ++q) x += pr[q][t];
-    sr[t] = x;
-  } else if (t < 2 * LS) {
-    float x = 0.f;
-    for (int q = 0; q < NCH; ++q) x += pc[q][t - LS];
-    sc[t - LS] = x;
-  }
-  __syncthreads();
-  const int64_t mg = (int64_t)F.m0 + m;
-  const FT* Bm = B + mg * LS * LS;
-  if (t < LS) {
-    float x = 0.f;
+struct TilePre {
+  static constexpr int NCH = LEAF_THREADS / LS;
+  float a, c, b[LS];
+  int64_t mg;
+
+  __device__ inline void load(const FrameDesc& F, int m, const float* uh, const float* vh, const FT* B) {
+    const int K = F.K, t = threadIdx.x;
+    int j = 0;
+    while (m >= K - (K >> (j + 1))) ++j;
+    const int i = m - (K - (K >> j)), S = 1 << j;
+    const int s = t % LS, ch = t / LS;
+    const int64_t lr = (int64_t)F.k0 + 2 * i * S, lc = lr + S;
+    a = 0.f;
+    c = 0.f;
+    for (int k = ch; k < S; k += NCH) {
+      a += uh[(lr + k) * LS + s];
+      c += vh[(lc + k) * LS + s];
+    }
+    mg = (int64_t)F.m0 + m;
+    const FT* Bm = B + mg * LS * LS;
+    if (t < LS) {
 #pragma unroll
-    for (int u = 0; u < LS; ++u) x = fmaf(ldf(Bm, t * LS + u), sc[u], x);
-    tr[mg * LS + t] = x;
-  } else if (t < 2 * LS) {
-    const int q = t - LS;
-    float x = 0.f;
+      for (int u = 0; u < LS; ++u) b[u] = ldf(Bm, t * LS + u);   // row t of B
+    } else if (t < 2 * LS) {
 #pragma unroll
-    for (int u = 0; u < LS; ++u) x = fmaf(ldf(Bm, u * LS + q), sr[u], x);
-    tc[mg * LS + q] = x;
+      for (int u = 0; u < LS; ++u) b[u] = ldf(Bm, u * LS + (t - LS));   // column of B
+    }
   }
-}
+
+  __device__ inline void finish(float* tr, float* tc) const {
+    __shared__ float pr[NCH][LS], pc[NCH][LS], sr[LS], sc[LS];
+    const int t = threadIdx.x, s = t % LS, ch = t / LS;
+    pr[ch][s] = a;
+    pc[ch][s] = c;
+    __syncthreads();
+    if (t < LS) {
+      float x = 0.f;
+      for (int q = 0; q < NCH; ++q) x += pr[q][t];
+      sr[t] = x;
+    } else if (t < 2 * LS) {
+      float x = 0.f;
+      for (int q = 0; q < NCH; ++q) x += pc[q][t - LS];
+      sc[t - LS] = x;
+    }
+    __syncthreads();
+    if (t < LS) {
+      float x = 0.f;
+#pragma unroll
+      for (int u = 0; u < LS; ++u) x = fmaf(b[u], sc[u], x);
+      tr[mg * LS + t] = x;
+    } else if (t < 2 * LS) {
+      float x = 0.f;
+#pragma unroll
+      for (int u = 0; u < LS; ++u) x = fmaf(b[u], sr[u], x);
+      tc[mg * LS + t - LS] = x;
+    }
+  }
+};
 
 // Gather of leaf kg (global index) for entry s < LS: T^r = sum of t^r over the
 // tiles where the leaf is on the row side, T^c over those where it is on the
@@ -362,7 +410,9 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_apply_coarse(const FrameDesc* 
   const int2 cb = cblk[blockIdx.x];
   if (cb.y < 0) return;
   const FrameDesc F = fr[cb.x];
-  tile_couple<LS, FT>(F, cb.y, uh, vh, fac.B, tr, tc);
+  TilePre<LS, FT> pre;
+  pre.load(F, cb.y, uh, vh, fac.B);
+  pre.finish(tr, tc);
 }
 
 template <int L, int LS, typename FT>
@@ -373,12 +423,14 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_apply_prolong(const FrameDesc*
   const int64_t kg = blockIdx.x;
   const FrameDesc F = fr[leaf2f[kg]];
   const int64_t row0 = F.n0 + (kg - F.k0) * L;
+  ProlongPre<L, LS, FT> pre;
+  pre.load(row0, fac);
+  constexpr int TPR = LEAF_THREADS / L;
+  const int row = threadIdx.x / TPR;
+  const float yr = (threadIdx.x % TPR == 0) ? y[row0 + row] : 0.f;
   if (threadIdx.x < LS) gather_leaf<LS>(F, kg, threadIdx.x, tr, tc, trs[threadIdx.x], tcs[threadIdx.x]);
   __syncthreads();
-  constexpr int TPR = LEAF_THREADS / L;
-  int row = threadIdx.x / TPR;
-  float yr = (threadIdx.x % TPR == 0) ? y[row0 + row] : 0.f;
-  float v = prolong_row<L, LS, FT>(row0, trs, tcs, fac, yr);
+  const float v = pre.apply(trs, tcs, yr);
   if (threadIdx.x % TPR == 0) y[row0 + row] = v;
 }
 
@@ -446,6 +498,30 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_spmv_p(const FrameDesc* fr, cons
     return;
   }
   const SolveParams prm = *B_.prm;
+  // stencil operands (independent of beta) before the reductions
+  const int c = (blockIdx.x - F.b0) * NODE_BLOCK + threadIdx.x;
+  const bool own = c < F.n;
+  float zv[7], pv[7], cf[7];
+  if (own) {
+    const unsigned cu = (unsigned)c;
+    const int64_t nb[7] = {F.n0 + c,
+                           F.n0 + mstep_plus(cu, F.xm), F.n0 + mstep_minus(cu, F.xm),
+                           F.n0 + mstep_plus(cu, F.ym), F.n0 + mstep_minus(cu, F.ym),
+                           F.n0 + mstep_plus(cu, F.zm), F.n0 + mstep_minus(cu, F.zm)};
+    SysPtr sp(B_.sys, B_.ntot);
+    cf[0] = sp.dg[nb[0]];
+    cf[1] = -sp.wx[nb[0]];
+    cf[2] = -sp.wx[nb[2]];
+    cf[3] = -sp.wy[nb[0]];
+    cf[4] = -sp.wy[nb[4]];
+    cf[5] = -sp.wz[nb[0]];
+    cf[6] = -sp.wz[nb[6]];
+#pragma unroll
+    for (int e = 0; e < 7; ++e) {
+      zv[e] = B_.z[nb[e]];
+      pv[e] = pold[nb[e]];
+    }
+  }
   if (SIMPLE && !S.fresh) {
     const int u = S.it + 1;
     const bool rep = is_replacement(S, prm, u);
@@ -473,17 +549,18 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_spmv_p(const FrameDesc* fr, cons
   S.beta = rz / S.rho;
   S.rho = rz;
   const float beta = (float)S.beta;
-  const float* z = B_.z;
-  SysPtr s(B_.sys, B_.ntot);
-  int c = (blockIdx.x - F.b0) * NODE_BLOCK + threadIdx.x;
   double pq = 0.0;
-  if (c < F.n) {
-    auto P = [&](int64_t j) { return fmaf(beta, pold[j], z[j]); };
-    float qi = stencil_f32(s, F, c, P);
-    float pi = P(F.n0 + c);
-    pnew[F.n0 + c] = pi;
+  if (own) {
+    // the same operation order as stencil_f32 with p = z + beta p_old
+    float P[7];
+#pragma unroll
+    for (int e = 0; e < 7; ++e) P[e] = fmaf(beta, pv[e], zv[e]);
+    float qi = cf[0] * P[0];
+#pragma unroll
+    for (int e = 1; e < 7; ++e) qi = fmaf(cf[e], P[e], qi);
+    pnew[F.n0 + c] = P[0];
     B_.q[F.n0 + c] = qi;
-    pq = (double)pi * (double)qi;
+    pq = (double)P[0] * (double)qi;
   }
   double bs = block_sum(pq, red);
   if (threadIdx.x == 0) B_.part_pq[blockIdx.x] = bs;
@@ -491,25 +568,46 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_spmv_p(const FrameDesc* fr, cons
 }
 
 // x accumulates in FP64 (x += alpha p with alpha in FP64); r, p, q are FP32.
+// NodePre holds thread l's p, q, r, x (l < L), loaded before the reductions.
+struct NodePre {
+  float p, q, r;
+  double x;
+};
+
 template <int L>
-__device__ inline double xr_update(const FrameDesc& F, int64_t row0, const PcgBufs& B_, const double* xold,
-                                   double* xnew, const float* p, double alpha, bool recompute, float* rs) {
-  SysPtr s(B_.sys, B_.ntot);
-  const float af = (float)alpha;
+__device__ inline NodePre xr_load(int64_t row0, const PcgBufs& B_, const double* xold, const float* p) {
+  NodePre n{0.f, 0.f, 0.f, 0.0};
+  if (threadIdx.x < L) {
+    const int64_t i = row0 + threadIdx.x;
+    n.p = p[i];
+    n.q = B_.q[i];
+    n.r = B_.r[i];
+    n.x = xold[i];
+  }
+  return n;
+}
+
+template <int L>
+__device__ inline double xr_update(const FrameDesc& F, int64_t row0, const PcgBufs& B_, const NodePre& n,
+                                   const double* xold, double* xnew, const float* p, double alpha, bool recompute,
+                                   float* rs) {
+  static_assert(L <= LEAF_THREADS, "one row per thread");
   double rr = 0.0;
-  for (int l = threadIdx.x; l < L; l += blockDim.x) {
-    int64_t i = row0 + l;
-    xnew[i] = fma(alpha, (double)p[i], xold[i]);
+  const int l = threadIdx.x;
+  if (l < L) {
+    const int64_t i = row0 + l;
+    xnew[i] = fma(alpha, (double)n.p, n.x);
     float ri;
     if (recompute) {
-      unsigned c = (unsigned)(i - F.n0);
+      SysPtr s(B_.sys, B_.ntot);
+      const unsigned c = (unsigned)(i - F.n0);
       ri = (float)resid_f64(s, F, c, (double)B_.b[i], [&](int64_t j) { return fma(alpha, (double)p[j], xold[j]); });
     } else {
-      ri = fmaf(-af, B_.q[i], B_.r[i]);
+      ri = fmaf(-(float)alpha, n.q, n.r);
     }
     B_.r[i] = ri;
     rs[l] = ri;
-    rr += (double)ri * (double)ri;
+    rr = (double)ri * (double)ri;
   }
   return rr;
 }
@@ -528,13 +626,17 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_update_hmat(const FrameDesc* f
   const FrameDesc F = fr[f];
   const FrameState S = B_.st[2 * f + 1];
   if (S.done) return;
-  const SolveParams prm = *B_.prm;
   const int64_t row0 = F.n0 + (kg - F.k0) * L;
+  // everything that does not depend on alpha, ahead of the reduction
+  LeafPre<L, LS, FT> pre;
+  pre.load(kg, row0, fac, B_.sys + 4 * B_.ntot);
+  const NodePre np = xr_load<L>(row0, B_, xold, p);
+  const SolveParams prm = *B_.prm;
   const bool rep = is_replacement(S, prm, S.it + 1);
   const double alpha = S.rho / frame_sum(B_.part_pq + F.b0, F.nb, dred);
-  double rr = xr_update<L>(F, row0, B_, xold, xnew, p, alpha, rep, rs);
+  double rr = xr_update<L>(F, row0, B_, np, xold, xnew, p, alpha, rep, rs);
   __syncthreads();
-  leaf_stage<L, LS, FT>(kg, row0, rs, fac, B_.sys + 4 * B_.ntot, B_.z, B_.uh, B_.vh, red);
+  pre.apply(kg, row0, rs, B_.z, B_.uh, B_.vh, red);
   double bs = block_sum(rr, dred);
   if (threadIdx.x == 0) B_.part_rr[kg] = bs;
 }
@@ -589,6 +691,8 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_coarse_check(const FrameDesc* 
     if (lead) B_.st[2 * f] = S;
     return;
   }
+  TilePre<LS, FT> pre;
+  if (cb.y >= 0) pre.load(F, cb.y, B_.uh, B_.vh, fac.B);  // ahead of the reductions
   const SolveParams prm = *B_.prm;
   const double rr = frame_sum(B_.part_rr + F.k0, F.K, dred);
   bool stop;
@@ -614,7 +718,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_coarse_check(const FrameDesc* 
     if (stop) atomicSub(B_.n_active, 1);
   }
   if (stop || cb.y < 0) return;
-  tile_couple<LS, FT>(F, cb.y, B_.uh, B_.vh, fac.B, B_.Tr, B_.Tc);
+  pre.finish(B_.Tr, B_.Tc);
 }
 
 // Last kernel (leaf blocks): gather T^r, T^c, z += Ut T^r + Vt T^c,
@@ -629,17 +733,20 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_prolong(const FrameDesc* fr, c
   const FrameDesc F = fr[f];
   if (B_.st[2 * f].done) return;
   const int64_t row0 = F.n0 + (kg - F.k0) * L;
-  if (threadIdx.x < LS) gather_leaf<LS>(F, kg, threadIdx.x, B_.Tr, B_.Tc, trs[threadIdx.x], tcs[threadIdx.x]);
-  __syncthreads();
   constexpr int TPR = LEAF_THREADS / L;
   const int row = threadIdx.x / TPR;
   const bool lead = threadIdx.x % TPR == 0;
+  ProlongPre<L, LS, FT> pre;
+  pre.load(row0, fac);
   float zr = lead ? B_.z[row0 + row] : 0.f;
-  zr = prolong_row<L, LS, FT>(row0, trs, tcs, fac, zr);
+  const float rr = lead ? B_.r[row0 + row] : 0.f;
+  if (threadIdx.x < LS) gather_leaf<LS>(F, kg, threadIdx.x, B_.Tr, B_.Tc, trs[threadIdx.x], tcs[threadIdx.x]);
+  __syncthreads();
+  zr = pre.apply(trs, tcs, zr);
   double rz = 0.0;
   if (lead) {
     B_.z[row0 + row] = zr;
-    rz = (double)B_.r[row0 + row] * (double)zr;
+    rz = (double)rr * (double)zr;
   }
   double bs = block_sum(rz, dred);
   if (threadIdx.x == 0) B_.part_rz[kg] = bs;

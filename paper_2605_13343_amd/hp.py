@@ -83,6 +83,7 @@ EXPORTS = {
     "hp_debug_copy": ([C.c_void_p, C.c_char_p, C.c_void_p, C.c_int64], C.c_int32),
     "hp_profile_enable": ([C.c_void_p, C.c_char_p], C.c_int32),
     "hp_debug_set": ([C.c_void_p, C.c_char_p, C.c_int32], C.c_int32),
+    "hp_autotune_report": ([C.c_void_p, C.c_char_p, C.c_int64, C.POINTER(C.c_int32)], C.c_int32),
     "hp_train_init": ([C.c_void_p, C.c_int32], C.c_int32),
     "hp_probes": ([C.c_void_p] * 5 + [C.c_int32, C.c_float], C.c_int32),
     "hp_loss_fwd": ([C.c_void_p, C.c_void_p, C.POINTER(FactorSet), C.c_void_p, C.c_void_p, C.c_double,
@@ -269,6 +270,12 @@ class Batch:
 
     def debug_set(self, name: str, value: int):
         _check(lib().hp_debug_set(self.h, name.encode(), int(value)))
+
+    def autotune_report(self) -> List[str]:
+        buf = C.create_string_buffer(1 << 16)
+        n = C.c_int32(0)
+        _check(lib().hp_autotune_report(self.h, buf, len(buf), C.byref(n)))
+        return [ln for ln in buf.value.decode().splitlines() if ln]
 
     def profile_enable(self, kernel: str):
         _check(lib().hp_profile_enable(self.h, kernel.encode()))

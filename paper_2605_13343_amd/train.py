@@ -174,6 +174,9 @@ def main(argv=None) -> int:
     ap.add_argument("--fp32", action="store_true", help="FP32 compute instead of BF16")
     ap.add_argument("--no-plateau", action="store_true")
     ap.add_argument("--val-every", type=int, default=200)
+    ap.add_argument("--log-every", type=int, default=0,
+                    help="optimizer steps per logged loss (the plateau rule's unit); default 20 per recipe "
+                         "of the mix, so every window holds whole cycles")
     ap.add_argument("--val", default="train4096:3900",
                     help="comma-separated recipe:first_seed validation sets of 20 frames each")
     ap.add_argument("--init", default=None, help="start from these weights (npz)")
@@ -187,8 +190,10 @@ def main(argv=None) -> int:
         init = {k: z[k] for k in z.files}
     mix = [(t.split(":")[0], int(t.split(":")[1])) for t in a.mix.split(",")]
     val = {t.split(":")[0]: list(range(int(t.split(":")[1]), int(t.split(":")[1]) + 20)) for t in a.val.split(",")}
+    log_every = a.log_every if a.log_every > 0 else 20 * len(mix)
     r = train(cfg, steps=a.steps, mix=mix, lr=a.lr, compute=hp.HP_F32 if a.fp32 else hp.HP_BF16,
               plateau=not a.no_plateau, val_every=a.val_every, val=val, init=init, warmup=a.warmup,
+              log_every=log_every,
               log=lambda s: print(s, flush=True))
     if a.out:
         os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)

@@ -148,3 +148,28 @@ def test_training_steps_reduce_loss():
     print("losses", [round(v, 5) for v in losses[::5]], losses[-1])
     assert all(math.isfinite(v) for v in losses)
     assert np.mean(losses[-5:]) < 0.8 * losses[0]
+
+
+def test_weight_gradient_matches_central_differences():
+    """Directional derivative of the GPU loss (FP32 compute) by central
+    differences with h = 1e-3 against the GPU gradient."""
+    import torch
+    s, w, flat, zraw, zr = _setup(PLAIN, [("plain1024", 1000)])
+    grad = torch.zeros_like(flat)
+    s.B.train_grad(flat, s.rho, s.sys, zr, grad, hp.HP_F32)
+    g = grad.double().cpu().numpy()
+    rng = np.random.default_rng(5)
+    scratch = torch.zeros_like(flat)
+    for trial in range(3):
+        # the gradient's own direction, then random ones
+        d = g.copy() if trial == 0 else rng.standard_normal(flat.numel())
+        d /= np.linalg.norm(d)
+        h = 1e-3
+        dt = torch.tensor(d, dtype=torch.float32, device="cuda")
+        lp = s.B.train_grad(flat + h * dt, s.rho, s.sys, zr, scratch, hp.HP_F32)
+        lm = s.B.train_grad(flat - h * dt, s.rho, s.sys, zr, scratch, hp.HP_F32)
+        fd = (lp - lm) / (2 * h)
+        an = float(g @ d)
+        print(f"direction {trial}: central difference {fd:.6e}  gradient {an:.6e}")
+        # FP32 forward noise (~1e-7 of the loss) over 2h, plus O(h^2) truncation
+        assert abs(fd - an) <= 1e-4 * np.linalg.norm(g) + 1e-3 * abs(an)
