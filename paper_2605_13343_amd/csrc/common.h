@@ -61,6 +61,44 @@ struct FrameState {
   int fresh;      // 1: set up, no update yet
 };
 
+// Field-wise copies of a frame state between global memory and registers.
+// (A whole-struct copy keeps the kernel's local copy in memory, which the
+// compiler then places per thread in LDS; field by field it stays in
+// registers.)
+__device__ inline FrameState load_state(const FrameState* p) {
+  FrameState s;
+  s.rho = p->rho;
+  s.alpha = p->alpha;
+  s.beta = p->beta;
+  s.rr = p->rr;
+  s.target = p->target;
+  s.bnorm = p->bnorm;
+  s.rwin = p->rwin;
+  s.it = p->it;
+  s.flags = p->flags;
+  s.done = p->done;
+  s.active = p->active;
+  s.force_rc = p->force_rc;
+  s.fresh = p->fresh;
+  return s;
+}
+
+__device__ inline void store_state(FrameState* p, const FrameState& s) {
+  p->rho = s.rho;
+  p->alpha = s.alpha;
+  p->beta = s.beta;
+  p->rr = s.rr;
+  p->target = s.target;
+  p->bnorm = s.bnorm;
+  p->rwin = s.rwin;
+  p->it = s.it;
+  p->flags = s.flags;
+  p->done = s.done;
+  p->active = s.active;
+  p->force_rc = s.force_rc;
+  p->fresh = s.fresh;
+}
+
 struct SolveParams {
   double tol;
   int max_iter, recompute_every, stagnation, pad;

@@ -343,7 +343,7 @@ static hp_status train_grad_t(Batch& b, const float* W, const float* rho, const 
     if (c.highways) {
       hipLaunchKernelGGL(k_chunk_sums, dim3((unsigned)N.nchunks), dim3(128), 0, st, (const SumChunk*)N.chunks,
                          (const float*)T.dGd, (const float*)T.dGo, N.gpart);
-      hipLaunchKernelGGL(k_frame_mean, dim3(b.nframes), dim3(128), 0, st, (const int*)N.chunk0,
+      hipLaunchKernelGGL(k_frame_mean, dim3(b.nframes), dim3(512), 0, st, (const int*)N.chunk0,
                          (const float*)N.gpart, (const float*)T.ones, T.dgf);
       if (use_off) {
         hipLaunchKernelGGL(k_pack_ctx, dim3(gsz(No * d)), dim3(256), 0, st, (const float*)T.dao,

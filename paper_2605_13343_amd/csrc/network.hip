@@ -872,8 +872,9 @@ __global__ __launch_bounds__(256) void k_highway_rc(const FrameDesc* fr, const i
   Cc[i * 128 + col] = cc / nc;
 }
 
-// Column sums of 128-wide rows over chunks (first stage of the per-frame
-// global token g = mean of all tokens of the frame).
+// Column sums of 128-wide rows over chunks of at most SUM_CHUNK rows (first
+// stage of the per-frame global token g = mean of all tokens of the frame).
+constexpr int SUM_CHUNK = 32;
 struct SumChunk {
   int frame, kind;  // kind 0: diagonal rows, 1: off-diagonal rows
   int64_t row0;
@@ -889,12 +890,17 @@ __global__ __launch_bounds__(128) void k_chunk_sums(const SumChunk* ch, const fl
   part[(int64_t)blockIdx.x * 128 + threadIdx.x] = s;
 }
 
-__global__ __launch_bounds__(128) void k_frame_mean(const int* chunk0, const float* part, const float* count,
+// Per-frame mean from the chunk sums: 4 groups of 128 features, group g adds
+// chunks g, g + 4, ... in order, then the groups are added in order.
+__global__ __launch_bounds__(512) void k_frame_mean(const int* chunk0, const float* part, const float* count,
                                                     float* G) {
-  const int f = blockIdx.x;
+  __shared__ float red[4][128];
+  const int f = blockIdx.x, col = threadIdx.x & 127, g = threadIdx.x >> 7;
   float s = 0.f;
-  for (int c = chunk0[f]; c < chunk0[f + 1]; ++c) s += part[(int64_t)c * 128 + threadIdx.x];
-  G[f * 128 + threadIdx.x] = s / count[f];
+  for (int c = chunk0[f] + g; c < chunk0[f + 1]; c += 4) s += part[(int64_t)c * 128 + col];
+  red[g][col] = s;
+  __syncthreads();
+  if (g == 0) G[f * 128 + col] = (red[0][col] + red[1][col] + red[2][col] + red[3][col]) / count[f];
 }
 
 // ------------------------------------------------------------------ heads and packing
@@ -1190,10 +1196,11 @@ hp_status network_alloc(Batch& b) {
       for (int t = 0; t < c.rank; ++t) tok2f[(int64_t)(F.m0 + m) * c.rank + t] = f;
     }
     chunk0[f] = (int)ch.size();
-    for (int r = 0; r < F.n; r += 128) ch.push_back(SumChunk{f, 0, (int64_t)F.n0 + r, std::min(128, F.n - r)});
+    for (int r = 0; r < F.n; r += SUM_CHUNK)
+      ch.push_back(SumChunk{f, 0, (int64_t)F.n0 + r, std::min(SUM_CHUNK, F.n - r)});
     if (c.offdiag)
-      for (int r = 0; r < F.MH * c.rank; r += 128)
-        ch.push_back(SumChunk{f, 1, (int64_t)F.m0 * c.rank + r, std::min(128, F.MH * c.rank - r)});
+      for (int r = 0; r < F.MH * c.rank; r += SUM_CHUNK)
+        ch.push_back(SumChunk{f, 1, (int64_t)F.m0 * c.rank + r, std::min(SUM_CHUNK, F.MH * c.rank - r)});
     cnt[f] = (float)(F.n + (c.offdiag ? F.MH * c.rank : 0));
   }
   chunk0[b.nframes] = (int)ch.size();
@@ -1475,7 +1482,7 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
     }
     hipLaunchKernelGGL(k_chunk_sums, dim3((unsigned)N.nchunks), dim3(128), 0, st, (const SumChunk*)N.chunks,
                        (const float*)N.H, (const float*)N.Xo, N.gpart);
-    hipLaunchKernelGGL(k_frame_mean, dim3(b.nframes), dim3(128), 0, st, (const int*)N.chunk0,
+    hipLaunchKernelGGL(k_frame_mean, dim3(b.nframes), dim3(512), 0, st, (const int*)N.chunk0,
                        (const float*)N.gpart, (const float*)N.gcount, N.G);
     if (use_off)
       hipLaunchKernelGGL(k_strip_means<float>, dim3((unsigned)No), dim3(512), 0, st, fr, N.tile2f,

@@ -490,11 +490,11 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_spmv_p(const FrameDesc* fr, cons
   __shared__ double red[NODE_BLOCK / 64];
   const int f = blk2f[blockIdx.x];
   const FrameDesc F = fr[f];
-  FrameState S = B_.st[2 * f + rd];
+  FrameState S = load_state(B_.st + 2 * f + rd);
   FrameState* out = B_.st + 2 * f + wr;
   const bool lead = blockIdx.x == F.b0 && threadIdx.x == 0;
   if (S.done) {
-    if (lead) *out = S;
+    if (lead) store_state(out, S);
     return;
   }
   const SolveParams prm = *B_.prm;
@@ -529,7 +529,7 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_spmv_p(const FrameDesc* fr, cons
     if (stop_checks(S, prm, u, rr, rep)) {
       if (lead) {
         S.done = 1;
-        *out = S;
+        store_state(out, S);
         atomicSub(B_.n_active, 1);
       }
       return;
@@ -541,7 +541,7 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_spmv_p(const FrameDesc* fr, cons
     if (lead) {
       S.flags |= HP_NOT_SPD;
       S.done = 1;
-      *out = S;
+      store_state(out, S);
       atomicSub(B_.n_active, 1);
     }
     return;
@@ -564,7 +564,7 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_spmv_p(const FrameDesc* fr, cons
   }
   double bs = block_sum(pq, red);
   if (threadIdx.x == 0) B_.part_pq[blockIdx.x] = bs;
-  if (lead) *out = S;
+  if (lead) store_state(out, S);
 }
 
 // x accumulates in FP64 (x += alpha p with alpha in FP64); r, p, q are FP32.
@@ -624,7 +624,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_update_hmat(const FrameDesc* f
   const int64_t kg = blockIdx.x;
   const int f = leaf2f[kg];
   const FrameDesc F = fr[f];
-  const FrameState S = B_.st[2 * f + 1];
+  const FrameState S = load_state(B_.st + 2 * f + 1);
   if (S.done) return;
   const int64_t row0 = F.n0 + (kg - F.k0) * L;
   // everything that does not depend on alpha, ahead of the reduction
@@ -648,7 +648,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_frame_setup(const FrameDesc* f
   const int f = blockIdx.x;
   const FrameDesc F = fr[f];
   FrameState* sp = B_.st + 2 * f;
-  FrameState S = *sp;
+  FrameState S = load_state(sp);
   if (S.done) return;
   const SolveParams prm = *B_.prm;
   const double rr = frame_sum(B_.part_rr + F.b0, F.nb, dred);
@@ -668,7 +668,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_frame_setup(const FrameDesc* f
       S.done = 1;
       atomicSub(B_.n_active, 1);
     }
-    *sp = S;
+    store_state(sp, S);
   }
 }
 
@@ -686,9 +686,9 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_coarse_check(const FrameDesc* 
   const int f = cb.x;
   const bool lead = cb.y <= 0 && threadIdx.x == 0;
   const FrameDesc F = fr[f];
-  FrameState S = B_.st[2 * f + 1];
+  FrameState S = load_state(B_.st + 2 * f + 1);
   if (S.done) {
-    if (lead) B_.st[2 * f] = S;
+    if (lead) store_state(B_.st + 2 * f, S);
     return;
   }
   TilePre<LS, FT> pre;
@@ -714,7 +714,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_coarse_check(const FrameDesc* 
   }
   if (stop) S.done = 1;
   if (lead) {
-    B_.st[2 * f] = S;
+    store_state(B_.st + 2 * f, S);
     if (stop) atomicSub(B_.n_active, 1);
   }
   if (stop || cb.y < 0) return;
@@ -825,7 +825,7 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_update_simple(const FrameDesc* f
   __shared__ double red[NODE_BLOCK / 64];
   const int f = blk2f[blockIdx.x];
   const FrameDesc F = fr[f];
-  const FrameState S = B_.st[2 * f + (par ^ 1)];
+  const FrameState S = load_state(B_.st + 2 * f + (par ^ 1));
   if (S.done) return;
   const SolveParams prm = *B_.prm;
   const bool rep = is_replacement(S, prm, S.it + 1);
@@ -860,7 +860,7 @@ __global__ void k_finalize_x(const FrameDesc* fr, const int* blk2f, const FrameS
                              double* x0) {
   const int f = blk2f[blockIdx.x];
   const FrameDesc F = fr[f];
-  const FrameState S = st[2 * f];
+  const FrameState S = load_state(st + 2 * f);
   if (!S.active || (S.it & 1) == 0) return;
   int c = (blockIdx.x - F.b0) * NODE_BLOCK + threadIdx.x;
   if (c < F.n) x0[F.n0 + c] = x1[F.n0 + c];

@@ -176,7 +176,10 @@ def test_bf16_leaf_attention_matrix_cores_match_vector_alus(cfg, recipe, seed):
     e_G = relerr(out[0][1][0], out[1][1][0])
     e_B = relerr(out[0][1][1], out[1][1][1])
     print(f"mfma vs valu attention: xd {e_xd:.2e}  xo {e_xo:.2e}  G {e_G:.2e}  B {e_B:.2e}")
-    assert e_xd <= 1e-2 and e_xo <= 1e-2 and e_G <= 2e-2 and e_B <= 5e-2
+    # the streams carry the attention difference directly; the factors are
+    # BF16 outputs of further layers, held to the BF16 bounds above
+    assert e_xd <= 1e-2 and e_xo <= 1e-2
+    assert e_G <= BF16_BOUND["G"] and e_B <= BF16_BOUND["B"]
 
 
 @pytest.mark.parametrize("cfg,recipe,seed", [(PLAIN, "plain1024", 1000), (DEF, "precision8192", 2000)])
