@@ -33,7 +33,7 @@ __device__ inline float wave_sum_f(float v) {
 // ------------------------------------------------------------------ GEMM
 // Y[M, N] = act(X[M, K] W + b) (+ resid), with W given transposed as
 // Wt[N][K] (K contiguous, K % 32 == 0).  64 x 64 block tile, four waves of
-// 32 x 32, K staged through LDS in steps of 32.
+// 32 x 32, K staged through two LDS buffers in steps of 32.
 struct GemmArgs {
   const void* X;
   int64_t ldx;
@@ -55,51 +55,68 @@ template <typename AT>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   constexpr int BM = 64, BN = 64, BK = 32;
   constexpr int PAD = sizeof(AT) == 2 ? 8 : 4;
-  __shared__ __attribute__((aligned(16))) AT sA[BM][BK + PAD];
-  __shared__ __attribute__((aligned(16))) AT sB[BN][BK + PAD];
+  constexpr int NV = sizeof(AT) == 2 ? 1 : 2;  // 16-byte loads per thread and operand
+  __shared__ __attribute__((aligned(16))) AT sA[2][BM][BK + PAD];
+  __shared__ __attribute__((aligned(16))) AT sB[2][BN][BK + PAD];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  // 1-D grid, remapped so that one XCD receives consecutive (row tile,
+  // column tile) pairs, column fastest: the column tiles of a row tile share
+  // that XCD's L2 copy of the X rows instead of fetching them again
+  const int tiles_n = (a.N + BN - 1) / BN, nblk = (int)gridDim.x, id = (int)blockIdx.x;
+  const int lin = (nblk % 8 == 0) ? (id % 8) * (nblk / 8) + id / 8 : id;
+  const int m0 = (lin / tiles_n) * BM, n0 = (lin % tiles_n) * BN;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const AT* X = (const AT*)a.X;
   const AT* W = (const AT*)a.Wt;
+  // two-stage pipeline: the next K step's global loads are issued before the
+  // current step's MFMAs and stored to the other LDS buffer after them
+  uint4 ra[NV], rb[NV];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int idx = tid + q * 256;
+      const int r = sizeof(AT) == 2 ? idx >> 2 : idx >> 3;
+      const int c = sizeof(AT) == 2 ? (idx & 3) * 8 : (idx & 7) * 4;
+      ra[q] = (m0 + r < a.M) ? *(const uint4*)(X + (int64_t)(m0 + r) * a.ldx + k0 + c) : make_uint4(0, 0, 0, 0);
+      rb[q] = (n0 + r < a.N) ? *(const uint4*)(W + (int64_t)(n0 + r) * a.K + k0 + c) : make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int idx = tid + q * 256;
+      const int r = sizeof(AT) == 2 ? idx >> 2 : idx >> 3;
+      const int c = sizeof(AT) == 2 ? (idx & 3) * 8 : (idx & 7) * 4;
+      *(uint4*)&sA[buf][r][c] = ra[q];
+      *(uint4*)&sB[buf][r][c] = rb[q];
+    }
+  };
   f32x16_t acc;
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-  for (int k0 = 0; k0 < a.K; k0 += BK) {
-    if constexpr (sizeof(AT) == 2) {
-      const int r = tid >> 2, c = (tid & 3) * 8;
-      uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
-      if (m0 + r < a.M) va = *(const uint4*)(X + (int64_t)(m0 + r) * a.ldx + k0 + c);
-      if (n0 + r < a.N) vb = *(const uint4*)(W + (int64_t)(n0 + r) * a.K + k0 + c);
-      *(uint4*)&sA[r][c] = va;
-      *(uint4*)&sB[r][c] = vb;
-    } else {
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int idx = tid + q * 256, r = idx >> 3, c = (idx & 7) * 4;
-        float4 va = make_float4(0, 0, 0, 0), vb = make_float4(0, 0, 0, 0);
-        if (m0 + r < a.M) va = *(const float4*)(X + (int64_t)(m0 + r) * a.ldx + k0 + c);
-        if (n0 + r < a.N) vb = *(const float4*)(W + (int64_t)(n0 + r) * a.K + k0 + c);
-        *(float4*)&sA[r][c] = va;
-        *(float4*)&sB[r][c] = vb;
-      }
-    }
-    __syncthreads();
+  const int nk = a.K / BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * BK);
     if constexpr (sizeof(AT) == 2) {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 16) {
-        bf16x8_t av = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sA[wm + (lane & 31)][kk + (lane >> 5) * 8]);
-        bf16x8_t bv = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sB[wn + (lane & 31)][kk + (lane >> 5) * 8]);
+        bf16x8_t av = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sA[buf][wm + (lane & 31)][kk + (lane >> 5) * 8]);
+        bf16x8_t bv = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sB[buf][wn + (lane & 31)][kk + (lane >> 5) * 8]);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
       }
     } else {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 2) {
-        float av = sA[wm + (lane & 31)][kk + (lane >> 5)];
-        float bv = sB[wn + (lane & 31)][kk + (lane >> 5)];
+        float av = sA[buf][wm + (lane & 31)][kk + (lane >> 5)];
+        float bv = sB[buf][wn + (lane & 31)][kk + (lane >> 5)];
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
       }
     }
+    if (kt + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
   }
   const int col = n0 + wn + (lane & 31);
@@ -388,30 +405,46 @@ struct EdgeW {
   int E, H;
 };
 
-__device__ inline void edge_mlp(const EdgeW& w, const float e[4], float* out) {
-  float hdn[64];
-  for (int k = 0; k < w.E; ++k) {
-    float s = w.b1[k];
-    for (int q = 0; q < 4; ++q) s = fmaf(e[q], w.w1[q * w.E + k], s);
-    hdn[k] = gelu_f(s);
-  }
-  for (int h = 0; h < w.H; ++h) {
-    float s = w.b2[h];
-    for (int k = 0; k < w.E; ++k) s = fmaf(hdn[k], w.w2[k * w.H + h], s);
-    out[h] = s;
+// The edge MLP's parameters [W1 (4E) | b1 (E) | W2 (E H) | b2 (H)] are
+// contiguous in the weight vector; each block stages them in LDS once.
+constexpr int EDGE_MAX_FLOATS = 5 * 64 + 64 * 8 + 8;
+
+__device__ inline void edge_stage(const EdgeW& w, float* sw) {
+  const int n = 5 * w.E + w.E * w.H + w.H;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) sw[q] = w.w1[q];
+  __syncthreads();
+}
+
+// MLP_e(e) from the staged parameters; out[h] for h < H (8 slots).  The
+// hidden units are folded into the output sums one at a time (no hidden
+// array), in the same order as a hidden-then-output evaluation.
+__device__ inline void edge_mlp(const float* sw, int E, int H, const float e[4], float out[8]) {
+  const float *w1 = sw, *b1 = sw + 4 * E, *w2 = sw + 5 * E, *b2 = sw + 5 * E + E * H;
+#pragma unroll
+  for (int h = 0; h < 8; ++h) out[h] = h < H ? b2[h] : 0.f;
+  for (int k = 0; k < E; ++k) {
+    float s = b1[k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s = fmaf(e[q], w1[q * E + k], s);
+    const float g = gelu_f(s);
+#pragma unroll
+    for (int h = 0; h < 8; ++h)
+      if (h < H) out[h] = fmaf(g, w2[k * H + h], out[h]);
   }
 }
 
 // Within-leaf bias table with A_ij = 0: T0[h][i][j] = MLP_e((pos j - pos i)/4, 0).
 // Every leaf has the same shape, so one table per layer serves all leaves.
 __global__ void k_edge_table(EdgeW w, int L, unsigned xm, unsigned ym, unsigned zm, float* T0) {
+  __shared__ float sw[EDGE_MAX_FLOATS];
+  edge_stage(w, sw);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= L * L) return;
   const int i = p / L, j = p % L;
   float e[4] = {(mcoord(j, xm) - mcoord(i, xm)) * 0.25f, (mcoord(j, ym) - mcoord(i, ym)) * 0.25f,
                 (mcoord(j, zm) - mcoord(i, zm)) * 0.25f, 0.f};
   float o[8];
-  edge_mlp(w, e, o);
+  edge_mlp(sw, w.E, w.H, e, o);
   for (int h = 0; h < w.H; ++h) T0[(h * L + i) * L + j] = o[h];
 }
 
@@ -452,12 +485,14 @@ __global__ __launch_bounds__(128) void k_edge_corr(EdgeW w, const uint8_t* nbr, 
                                                    float* corr) {
   // MLP_e(dx_e, 0) depends on the stencil slot only: 7 evaluations per block
   __shared__ float base[7][8];
+  __shared__ float sw[EDGE_MAX_FLOATS];
+  edge_stage(w, sw);
   if (threadIdx.x < 7) {
     const int e = threadIdx.x;
     float d[3] = {0.f, 0.f, 0.f};
     if (e > 0) d[(e - 1) / 2] = ((e - 1) % 2 == 0) ? 0.25f : -0.25f;
     const float e0[4] = {d[0], d[1], d[2], 0.f};
-    edge_mlp(w, e0, base[e]);
+    edge_mlp(sw, w.E, w.H, e0, base[e]);
   }
   __syncthreads();
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -472,7 +507,7 @@ __global__ __launch_bounds__(128) void k_edge_corr(EdgeW w, const uint8_t* nbr, 
   if (e > 0) d[(e - 1) / 2] = ((e - 1) % 2 == 0) ? 0.25f : -0.25f;
   const float e1[4] = {d[0], d[1], d[2], ahat[p]};
   float a[8];
-  edge_mlp(w, e1, a);
+  edge_mlp(sw, w.E, w.H, e1, a);
   for (int h = 0; h < w.H; ++h) o[h] = a[h] - base[e][h];
 }
 
@@ -557,13 +592,15 @@ __global__ __launch_bounds__(256) void k_off_desc_final(const FrameDesc* fr, con
 
 // Off-diagonal bias per layer: bias[m][h][t][t'] = MLP_e(desc[m][t][t']).
 __global__ void k_edge_off(EdgeW w, const float* desc, int64_t npairs, int LS, float* bias) {
+  __shared__ float sw[EDGE_MAX_FLOATS];
+  edge_stage(w, sw);
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npairs) return;
   const int64_t m = p / (LS * LS);
   const int tt = (int)(p % (LS * LS));
   float e[4] = {desc[p * 4], desc[p * 4 + 1], desc[p * 4 + 2], desc[p * 4 + 3]};
   float o[8];
-  edge_mlp(w, e, o);
+  edge_mlp(sw, w.E, w.H, e, o);
   for (int h = 0; h < w.H; ++h) bias[(m * w.H + h) * LS * LS + tt] = o[h];
 }
 
@@ -846,30 +883,135 @@ __global__ __launch_bounds__(256) void k_attention_tile_mfma(const uint16_t* qkv
 // the diagonal token i and of every off-diagonal token whose row (column)
 // sub-strip contains i.  Leaf k sits at level j in tile K - K/2^j + (k >> (j+1))
 // on side (k >> j) & 1; its position l maps to sub-strip token l / p.
-__global__ __launch_bounds__(256) void k_highway_rc(const FrameDesc* fr, const int* node2f, const float* Xd,
-                                                    const float* Xo, int L, int LS, int64_t ntot, float* R,
-                                                    float* Cc) {
+// The highway buffers by (leaf k, sub-strip t) groups.  The off-diagonal
+// tokens a node reads depend only on its leaf and its sub-strip t = l / p, so
+// per group:  gx = sum of the p diagonal tokens,  rs (cs) = sum over the
+// levels where the leaf is on the row (column) side of token t of that
+// level's tile.  Then r_i = (x_i + rs) / n_r and c_i = (x_i + cs) / n_c, with
+// n_r (n_c) = 1 + the number of row (column) levels of the leaf, and the
+// off-diagonal tokens' context sums (gx + p rs) / n_r over a strip's leaves.
+// One block per leaf: 4 groups of sub-strips x 128 features.
+__device__ inline void leaf_sides(int k, int J, int& nr, int& nc) {
+  nr = 1;
+  nc = 1;
+  for (int j = 0; j < J; ++j) {
+    if (((k >> j) & 1) == 0) ++nr;
+    else ++nc;
+  }
+}
+
+__global__ __launch_bounds__(512) void k_hw_groups(const FrameDesc* fr, const int* leaf2f, const float* Xd,
+                                                   const float* Xo, int L, int LS, float* gx, float* rs,
+                                                   float* cs) {
+  const int64_t kg = blockIdx.x;
+  const FrameDesc F = fr[leaf2f[kg]];
+  const int k = (int)(kg - F.k0), K = F.K, p = L / LS, col = threadIdx.x & 127;
+  for (int t = threadIdx.x >> 7; t < LS; t += 4) {
+    float a = 0.f, r = 0.f, c = 0.f;
+    for (int q = 0; q < p; ++q) a += Xd[((int64_t)F.n0 + (int64_t)k * L + t * p + q) * 128 + col];
+    for (int j = 0; j < F.J; ++j) {
+      const int m = K - (K >> j) + (k >> (j + 1));
+      const float v = Xo[((int64_t)(F.m0 + m) * LS + t) * 128 + col];
+      if (((k >> j) & 1) == 0) r += v;
+      else c += v;
+    }
+    const int64_t o = (kg * LS + t) * 128 + col;
+    gx[o] = a;
+    rs[o] = r;
+    cs[o] = c;
+  }
+}
+
+// Off-diagonal token context from the groups: for token (m, t) the mean of r
+// over I_m^t and of c over J_m^t, i.e. the sums of (gx + p rs) / n_r over the
+// row strip's leaves (resp. (gx + p cs) / n_c over the column strip's) divided
+// by S p.  One block (128 features) per token, leaves added in order.
+__global__ __launch_bounds__(128) void k_hw_context(const FrameDesc* fr, const int* tile2f, const float* gx,
+                                                    const float* rs, const float* cs, int L, int LS, float* out) {
+  const int64_t tok = blockIdx.x;
+  const int mg = (int)(tok / LS), t = (int)(tok % LS);
+  const FrameDesc F = fr[tile2f[mg]];
+  const int m = mg - F.m0, K = F.K;
+  int j = 0;
+  while (m >= K - (K >> (j + 1))) ++j;
+  const int i = m - (K - (K >> j)), S = 1 << j, r0 = 2 * i * S, c0 = r0 + S, p = L / LS;
+  const int col = threadIdx.x;
+  float sa = 0.f, sb = 0.f;
+  for (int q = 0; q < S; ++q) {
+    int nr, nc, nr2, nc2;
+    leaf_sides(r0 + q, F.J, nr, nc);
+    leaf_sides(c0 + q, F.J, nr2, nc2);
+    const int64_t ia = (((int64_t)F.k0 + r0 + q) * LS + t) * 128 + col;
+    const int64_t ib = (((int64_t)F.k0 + c0 + q) * LS + t) * 128 + col;
+    sa += (gx[ia] + (float)p * rs[ia]) / (float)nr;
+    sb += (gx[ib] + (float)p * cs[ib]) / (float)nc2;
+  }
+  const float inv = 1.f / (float)(S * p);
+  out[tok * 256 + col] = sa * inv;
+  out[tok * 256 + 128 + col] = sb * inv;
+}
+
+// r, c of the diagonal tokens written out (the reverse pass reads them).
+__global__ __launch_bounds__(256) void k_hw_materialize(const FrameDesc* fr, const int* node2f, const float* Xd,
+                                                        const float* rs, const float* cs, int L, int LS,
+                                                        int64_t ntot, float* R, float* Cc) {
   const int64_t i = (int64_t)blockIdx.x * 2 + (threadIdx.x >> 7);
   if (i >= ntot) return;
   const int col = threadIdx.x & 127;
   const FrameDesc F = fr[node2f[i]];
-  const int c = (int)(i - F.n0), k = c / L, l = c % L, p = L / LS, K = F.K;
+  const int c = (int)(i - F.n0), k = c / L, l = c % L, p = L / LS;
+  int nr, nc;
+  leaf_sides(k, F.J, nr, nc);
+  const int64_t gi = (((int64_t)F.k0 + k) * LS + l / p) * 128 + col;
   const float x = Xd[i * 128 + col];
-  float r = x, cc = x;
-  int nr = 1, nc = 1;
-  for (int j = 0; j < F.J; ++j) {
-    const int m = K - (K >> j) + (k >> (j + 1));
-    const float v = Xo[((int64_t)(F.m0 + m) * LS + l / p) * 128 + col];
-    if (((k >> j) & 1) == 0) {
-      r += v;
-      ++nr;
-    } else {
-      cc += v;
-      ++nc;
+  R[i * 128 + col] = (x + rs[gi]) / (float)nr;
+  Cc[i * 128 + col] = (x + cs[gi]) / (float)nc;
+}
+
+// LN([x | r | c | g]) of the diagonal tokens with r, c formed on the fly from
+// the group sums (one wave per row, as k_ln_concat).
+template <typename AT>
+__global__ __launch_bounds__(256) void k_ln_hw_diag(const FrameDesc* fr, const int* node2f, const float* X,
+                                                    const float* rs, const float* cs, const float* G, int L, int LS,
+                                                    const float* gam, const float* bet, AT* Y, int M) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= M) return;
+  const int f = node2f[row];
+  const FrameDesc F = fr[f];
+  const int c = row - F.n0, k = c / L, l = c % L, p = L / LS;
+  const int seg = lane >> 4, c0 = (lane & 15) * 8;
+  float v[8];
+  if (seg == 3) {
+    const float4* g4 = (const float4*)(G + (int64_t)f * 128 + c0);
+    const float4 a = g4[0], b = g4[1];
+    v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+  } else {
+    const float4* x4 = (const float4*)(X + (int64_t)row * 128 + c0);
+    const float4 a = x4[0], b = x4[1];
+    v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+    if (seg > 0) {
+      int nr, nc;
+      leaf_sides(k, F.J, nr, nc);
+      const float n = (float)(seg == 1 ? nr : nc);
+      const float4* h4 = (const float4*)((seg == 1 ? rs : cs) + (((int64_t)F.k0 + k) * LS + l / p) * 128 + c0);
+      const float4 ha = h4[0], hb = h4[1];
+      const float h[8] = {ha.x, ha.y, ha.z, ha.w, hb.x, hb.y, hb.z, hb.w};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = (v[q] + h[q]) / n;
     }
   }
-  R[i * 128 + col] = r / nr;
-  Cc[i * 128 + col] = cc / nc;
+  float sm = 0.f;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) sm += v[q];
+  const float mu = wave_sum_f(sm) * (1.f / 512.f);
+  float qv = 0.f;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) qv += (v[q] - mu) * (v[q] - mu);
+  const float rsd = rsqrtf(wave_sum_f(qv) * (1.f / 512.f) + 1e-5f);
+  AT* y = Y + (int64_t)row * 512 + seg * 128 + c0;
+  const int gc = seg * 128 + c0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) y[q] = to_act<AT>((v[q] - mu) * rsd * gam[gc + q] + bet[gc + q]);
 }
 
 // Column sums of 128-wide rows over chunks of at most SUM_CHUNK rows (first
@@ -1108,6 +1250,7 @@ struct NetBufs {
   void *a128 = nullptr, *b128 = nullptr, *qkv = nullptr, *u512 = nullptr, *h512 = nullptr;
   void *ctx = nullptr, *ao128 = nullptr, *bo128 = nullptr, *qkvo = nullptr, *uo512 = nullptr, *ho512 = nullptr;
   float *ctxf = nullptr;
+  float *hgx = nullptr, *hrs = nullptr, *hcs = nullptr;  // highway group sums [ktot L_s][128]
   float *Frows = nullptr, *NH = nullptr, *UV = nullptr;
   float *T0 = nullptr, *corr = nullptr, *ahat = nullptr, *desc = nullptr, *boff = nullptr;
   uint8_t* nbr = nullptr;
@@ -1157,6 +1300,9 @@ hp_status network_alloc(Batch& b) {
   A(&N->Xo0, No * d * 4);
   A(&N->ctx, No * 2 * d * 4);
   A(&N->ctxf, No * 2 * d * 4);
+  A(&N->hgx, b.ktot * c.rank * d * 4);
+  A(&N->hrs, b.ktot * c.rank * d * 4);
+  A(&N->hcs, b.ktot * c.rank * d * 4);
   A(&N->ao128, No * d * 4);
   A(&N->bo128, No * d * 4);
   A(&N->qkvo, No * 3 * d * 4);
@@ -1248,12 +1394,10 @@ static void launch_gemm(int kind, const GemmArgs& a, bool bf16, hipStream_t st) 
   if (kind == 1) {
     const int tn = (a.N + 127) / 128, tm = (a.M + 127) / 128;
     hipLaunchKernelGGL(k_gemm_wide, dim3((unsigned)(tm * tn)), dim3(256), 0, st, a, tn);
-  } else if (bf16) {
-    hipLaunchKernelGGL(k_gemm<uint16_t>, dim3((unsigned)((a.M + 63) / 64), (unsigned)((a.N + 63) / 64)), dim3(256),
-                       0, st, a);
   } else {
-    hipLaunchKernelGGL(k_gemm<float>, dim3((unsigned)((a.M + 63) / 64), (unsigned)((a.N + 63) / 64)), dim3(256),
-                       0, st, a);
+    const unsigned nb = (unsigned)(((a.M + 63) / 64) * ((a.N + 63) / 64));
+    if (bf16) hipLaunchKernelGGL(k_gemm<uint16_t>, dim3(nb), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_gemm<float>, dim3(nb), dim3(256), 0, st, a);
   }
 }
 
@@ -1474,8 +1618,12 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
   // highways (Sec. 4.3)
   if (c.highways) {
     if (use_off) {
-      hipLaunchKernelGGL(k_highway_rc, dim3((unsigned)((Nd + 1) / 2)), dim3(256), 0, st, fr, N.node2f,
-                         (const float*)N.H, (const float*)N.Xo, (int)L, (int)LS, Nd, N.R, N.C);
+      hipLaunchKernelGGL(k_hw_groups, dim3((unsigned)b.ktot), dim3(512), 0, st, fr, b.d_leaf2f, (const float*)N.H,
+                         (const float*)N.Xo, (int)L, (int)LS, N.hgx, N.hrs, N.hcs);
+      if (ls)  // the reverse pass reads r and c
+        hipLaunchKernelGGL(k_hw_materialize, dim3((unsigned)((Nd + 1) / 2)), dim3(256), 0, st, fr, N.node2f,
+                           (const float*)N.H, (const float*)N.hrs, (const float*)N.hcs, (int)L, (int)LS, Nd, N.R,
+                           N.C);
     } else {
       HP_HIP(hipMemcpyAsync(N.R, N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
       HP_HIP(hipMemcpyAsync(N.C, N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
@@ -1485,8 +1633,8 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
     hipLaunchKernelGGL(k_frame_mean, dim3(b.nframes), dim3(512), 0, st, (const int*)N.chunk0,
                        (const float*)N.gpart, (const float*)N.gcount, N.G);
     if (use_off)
-      hipLaunchKernelGGL(k_strip_means<float>, dim3((unsigned)No), dim3(512), 0, st, fr, N.tile2f,
-                         (const float*)N.R, (const float*)N.C, (int)L, (int)LS, N.ctxf);
+      hipLaunchKernelGGL(k_hw_context, dim3((unsigned)No), dim3(128), 0, st, fr, N.tile2f, (const float*)N.hgx,
+                         (const float*)N.hrs, (const float*)N.hcs, (int)L, (int)LS, N.ctxf);
   }
   for (int sidx = 0; sidx < 2; ++sidx) {
     if (sidx == 1 && !use_off) continue;
@@ -1495,7 +1643,11 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
     const int64_t M = sidx ? No : Nd;
     void* u = sidx ? N.uo512 : N.u512;
     void* h = sidx ? N.ho512 : N.h512;
-    if (sidx == 0)
+    if (sidx == 0 && c.highways && use_off)
+      hipLaunchKernelGGL(k_ln_hw_diag<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, fr, N.node2f,
+                         (const float*)X, (const float*)N.hrs, (const float*)N.hcs, (const float*)N.G, (int)L,
+                         (int)LS, wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, (int)M);
+    else if (sidx == 0)
       hipLaunchKernelGGL(k_ln_concat<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, (const float*)X, d,
                          (const float*)N.R, d, (const float*)N.C, d, (const float*)N.G, (const int*)N.node2f,
                          wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, (int)M, c.highways);
