@@ -306,16 +306,28 @@ hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, int64_t bytes
 /* Test switches of one batch.  "attention_valu" (0/1): with BF16 compute, run
  * the within-leaf attention on the vector ALUs instead of the matrix cores;
  * "gemm_small_tiles" (0/1): run every BF16 GEMM on the 64 x 64 tile kernel
- * instead of the 128 x 128 double-buffered one (the tests compare the
- * variants).  HP_E_INVALID on an unknown name. */
+ * (the tests compare the variants); "gemm_autotune" (0/1, default 1): time
+ * both tile kernels on the first call of each BF16 GEMM shape and keep the
+ * faster (off: the 128 x 128 kernel).  HP_E_INVALID on an unknown name. */
 hp_status hp_debug_set(hp_batch b, const char* name, int32_t value);
 
+/* The GEMM autotuner's records of this batch, one text line per shape
+ * ("gemm N=.. K=.. M=.. tile=.. small_us=.. wide_us=.."), written into buf
+ * (host, len bytes, always NUL-terminated when len > 0; truncated if short).
+ * *entries (optional) receives the number of shapes. */
+hp_status hp_autotune_report(hp_batch b, char* buf, int64_t len, int32_t* entries);
+
 /* Live kernel timing for roofline figures.  After hp_profile_enable(b,
- * "gemm"), every eager launch of that kernel family on the batch stream is
- * bracketed by HIP events (at most 4096 launches are recorded); "none" turns
- * it off.  hp_profile_read synchronises on the last event and returns the
- * launch count, the summed kernel time in ms and the summed algorithmic work
- * (GEMM: 2 M N K flops per launch), then resets the counters. */
+ * family), every eager launch of that kernel family on the batch stream is
+ * bracketed by HIP events (at most 4096 launches are recorded): "gemm" (the
+ * network's GEMMs; work = 2 M N K flops per launch), "update" (the PCG
+ * x/r/leaf-stage kernel of the learned preconditioner; work = its algorithmic
+ * HBM bytes with every frame active: 44 B per node plus G, Ut, Vt per leaf)
+ * and "spmv" (the PCG SpMV kernel; 32 B per node).  PCG launches are timed
+ * only in solves with use_graph = 0.  "none" turns timing off.
+ * hp_profile_read synchronises on the last event and returns the launch
+ * count, the summed kernel time in ms and the summed work, then resets the
+ * counters. */
 hp_status hp_profile_enable(hp_batch b, const char* kernel);
 hp_status hp_profile_read(hp_batch b, int32_t* launches, double* total_ms, double* work);
 

@@ -730,31 +730,31 @@ __global__ __launch_bounds__(256) void k_attention_mfma(const uint16_t* qkv, uin
     for (int e = 0; e < 8; ++e) sVt[h][c0 + e][key] = pv[e];
   }
   __syncthreads();
-  // S^T tiles: acc[a][b] = K[32a..][:] Q[32b..][:]^T
-  f32x16_t S[NT][NT];
+  // K operands of both key tiles and both 16-wide steps stay in registers;
+  // the query tiles are processed one at a time (fewer live accumulators)
+  bf16x8_t kop[2][NT];
 #pragma unroll
-  for (int a = 0; a < NT; ++a)
+  for (int s = 0; s < 2; ++s)
 #pragma unroll
-    for (int b = 0; b < NT; ++b)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) S[a][b][q] = 0.f;
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    bf16x8_t kop[NT], qop[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int64_t r = 32 * t + c32;
-      kop[t] = __builtin_bit_cast(bf16x8_t, *(const uint4*)(base + r * 3 * D + D + 16 * s + 8 * hh));
-      qop[t] = __builtin_bit_cast(bf16x8_t, *(const uint4*)(base + r * 3 * D + 16 * s + 8 * hh));
-    }
+    for (int t = 0; t < NT; ++t)
+      kop[s][t] = __builtin_bit_cast(bf16x8_t,
+                                     *(const uint4*)(base + (int64_t)(32 * t + c32) * 3 * D + D + 16 * s + 8 * hh));
+  const float scale = 0.17677669529663687f;  // 1/sqrt(32)
+#pragma unroll 1
+  for (int b = 0; b < NT; ++b) {
+    // S^T tiles of this query tile: S[a] = K[32a..][:] Q[32b..][:]^T
+    f32x16_t S[NT];
 #pragma unroll
     for (int a = 0; a < NT; ++a)
 #pragma unroll
-      for (int b = 0; b < NT; ++b) S[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kop[a], qop[b], S[a][b], 0, 0, 0);
-  }
-  const float scale = 0.17677669529663687f;  // 1/sqrt(32)
+      for (int q2 = 0; q2 < 16; ++q2) S[a][q2] = 0.f;
 #pragma unroll
-  for (int b = 0; b < NT; ++b) {
+    for (int s = 0; s < 2; ++s) {
+      const bf16x8_t qop =
+          __builtin_bit_cast(bf16x8_t, *(const uint4*)(base + (int64_t)(32 * b + c32) * 3 * D + 16 * s + 8 * hh));
+#pragma unroll
+      for (int a = 0; a < NT; ++a) S[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kop[s][a], qop, S[a], 0, 0, 0);
+    }
     const int q = 32 * b + c32;
     const int64_t row = row0 + q;
     const float* bt = T0 + ((int64_t)h * T + q) * T;
@@ -775,10 +775,10 @@ __global__ __launch_bounds__(256) void k_attention_mfma(const uint16_t* qkv, uin
         const float bj[4] = {bv.x, bv.y, bv.z, bv.w};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          float v = fmaf(S[a][b][4 * i + j], scale, bj[j]);
+          float v = fmaf(S[a][4 * i + j], scale, bj[j]);
 #pragma unroll
           for (int e = 0; e < 7; ++e) v += (lj[e] == k0 + j) ? cv[e] : 0.f;
-          S[a][b][4 * i + j] = v;
+          S[a][4 * i + j] = v;
           mx = fmaxf(mx, v);
         }
       }
@@ -788,8 +788,8 @@ __global__ __launch_bounds__(256) void k_attention_mfma(const uint16_t* qkv, uin
     for (int a = 0; a < NT; ++a)
 #pragma unroll
       for (int q2 = 0; q2 < 16; ++q2) {
-        const float p = expf(S[a][b][q2] - mx);
-        S[a][b][q2] = p;
+        const float p = expf(S[a][q2] - mx);
+        S[a][q2] = p;
         sum += p;
       }
     sum += __shfl_xor(sum, 32, 64);
@@ -808,7 +808,7 @@ __global__ __launch_bounds__(256) void k_attention_mfma(const uint16_t* qkv, uin
         vb = __builtin_bit_cast(bf16x8_t, *(const uint4*)vv);
         uint16_t pp[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) pp[e] = f32_to_bf16(S[a][b][8 * s + e]);
+        for (int e = 0; e < 8; ++e) pp[e] = f32_to_bf16(S[a][8 * s + e]);
         pb = __builtin_bit_cast(bf16x8_t, *(const uint4*)pp);
         O = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vb, pb, O, 0, 0, 0);
       }
@@ -885,11 +885,12 @@ __global__ __launch_bounds__(256) void k_attention_tile_mfma(const uint16_t* qkv
 // on side (k >> j) & 1; its position l maps to sub-strip token l / p.
 // The highway buffers by (leaf k, sub-strip t) groups.  The off-diagonal
 // tokens a node reads depend only on its leaf and its sub-strip t = l / p, so
-// per group:  gx = sum of the p diagonal tokens,  rs (cs) = sum over the
-// levels where the leaf is on the row (column) side of token t of that
-// level's tile.  Then r_i = (x_i + rs) / n_r and c_i = (x_i + cs) / n_c, with
-// n_r (n_c) = 1 + the number of row (column) levels of the leaf, and the
-// off-diagonal tokens' context sums (gx + p rs) / n_r over a strip's leaves.
+// per group:  rs (cs) = sum over the levels where the leaf is on the row
+// (column) side of token t of that level's tile.  Then r_i = (x_i + rs) / n_r
+// and c_i = (x_i + cs) / n_c, with n_r (n_c) = 1 + the number of row (column)
+// levels of the leaf; and the group sums of r and c, hr = (gx + p rs) / n_r
+// and hc = (gx + p cs) / n_c with gx the sum of the p diagonal tokens, feed
+// the off-diagonal tokens' context.
 // One block per leaf: 4 groups of sub-strips x 128 features.
 __device__ inline void leaf_sides(int k, int J, int& nr, int& nc) {
   nr = 1;
@@ -901,11 +902,13 @@ __device__ inline void leaf_sides(int k, int J, int& nr, int& nc) {
 }
 
 __global__ __launch_bounds__(512) void k_hw_groups(const FrameDesc* fr, const int* leaf2f, const float* Xd,
-                                                   const float* Xo, int L, int LS, float* gx, float* rs,
-                                                   float* cs) {
+                                                   const float* Xo, int L, int LS, float* rs, float* cs, float* hr,
+                                                   float* hc) {
   const int64_t kg = blockIdx.x;
   const FrameDesc F = fr[leaf2f[kg]];
   const int k = (int)(kg - F.k0), K = F.K, p = L / LS, col = threadIdx.x & 127;
+  int nr, nc;
+  leaf_sides(k, F.J, nr, nc);
   for (int t = threadIdx.x >> 7; t < LS; t += 4) {
     float a = 0.f, r = 0.f, c = 0.f;
     for (int q = 0; q < p; ++q) a += Xd[((int64_t)F.n0 + (int64_t)k * L + t * p + q) * 128 + col];
@@ -916,18 +919,20 @@ __global__ __launch_bounds__(512) void k_hw_groups(const FrameDesc* fr, const in
       else c += v;
     }
     const int64_t o = (kg * LS + t) * 128 + col;
-    gx[o] = a;
     rs[o] = r;
     cs[o] = c;
+    hr[o] = (a + (float)p * r) / (float)nr;   // sum of r over the group
+    hc[o] = (a + (float)p * c) / (float)nc;   // sum of c over the group
   }
 }
 
 // Off-diagonal token context from the groups: for token (m, t) the mean of r
-// over I_m^t and of c over J_m^t, i.e. the sums of (gx + p rs) / n_r over the
-// row strip's leaves (resp. (gx + p cs) / n_c over the column strip's) divided
-// by S p.  One block (128 features) per token, leaves added in order.
-__global__ __launch_bounds__(128) void k_hw_context(const FrameDesc* fr, const int* tile2f, const float* gx,
-                                                    const float* rs, const float* cs, int L, int LS, float* out) {
+// over I_m^t (the group sums hr of the row strip's leaves, divided by S p) and
+// of c over J_m^t (hc of the column strip's leaves).  4 groups of leaves x
+// 128 features, groups added in order.
+__global__ __launch_bounds__(512) void k_hw_context(const FrameDesc* fr, const int* tile2f, const float* hr,
+                                                    const float* hc, int L, int LS, float* out) {
+  __shared__ float red[2][4][128];
   const int64_t tok = blockIdx.x;
   const int mg = (int)(tok / LS), t = (int)(tok % LS);
   const FrameDesc F = fr[tile2f[mg]];
@@ -935,20 +940,19 @@ __global__ __launch_bounds__(128) void k_hw_context(const FrameDesc* fr, const i
   int j = 0;
   while (m >= K - (K >> (j + 1))) ++j;
   const int i = m - (K - (K >> j)), S = 1 << j, r0 = 2 * i * S, c0 = r0 + S, p = L / LS;
-  const int col = threadIdx.x;
+  const int col = threadIdx.x & 127, g = threadIdx.x >> 7;
   float sa = 0.f, sb = 0.f;
-  for (int q = 0; q < S; ++q) {
-    int nr, nc, nr2, nc2;
-    leaf_sides(r0 + q, F.J, nr, nc);
-    leaf_sides(c0 + q, F.J, nr2, nc2);
-    const int64_t ia = (((int64_t)F.k0 + r0 + q) * LS + t) * 128 + col;
-    const int64_t ib = (((int64_t)F.k0 + c0 + q) * LS + t) * 128 + col;
-    sa += (gx[ia] + (float)p * rs[ia]) / (float)nr;
-    sb += (gx[ib] + (float)p * cs[ib]) / (float)nc2;
+  for (int q = g; q < S; q += 4) {
+    sa += hr[(((int64_t)F.k0 + r0 + q) * LS + t) * 128 + col];
+    sb += hc[(((int64_t)F.k0 + c0 + q) * LS + t) * 128 + col];
   }
-  const float inv = 1.f / (float)(S * p);
-  out[tok * 256 + col] = sa * inv;
-  out[tok * 256 + 128 + col] = sb * inv;
+  red[0][g][col] = sa;
+  red[1][g][col] = sb;
+  __syncthreads();
+  if (g < 2) {
+    const float v = red[g][0][col] + red[g][1][col] + red[g][2][col] + red[g][3][col];
+    out[tok * 256 + 128 * g + col] = v / (float)(S * p);
+  }
 }
 
 // r, c of the diagonal tokens written out (the reverse pass reads them).
@@ -1250,7 +1254,7 @@ struct NetBufs {
   void *a128 = nullptr, *b128 = nullptr, *qkv = nullptr, *u512 = nullptr, *h512 = nullptr;
   void *ctx = nullptr, *ao128 = nullptr, *bo128 = nullptr, *qkvo = nullptr, *uo512 = nullptr, *ho512 = nullptr;
   float *ctxf = nullptr;
-  float *hgx = nullptr, *hrs = nullptr, *hcs = nullptr;  // highway group sums [ktot L_s][128]
+  float *hrs = nullptr, *hcs = nullptr, *hhr = nullptr, *hhc = nullptr;  // highway group sums [ktot L_s][128]
   float *Frows = nullptr, *NH = nullptr, *UV = nullptr;
   float *T0 = nullptr, *corr = nullptr, *ahat = nullptr, *desc = nullptr, *boff = nullptr;
   uint8_t* nbr = nullptr;
@@ -1300,9 +1304,10 @@ hp_status network_alloc(Batch& b) {
   A(&N->Xo0, No * d * 4);
   A(&N->ctx, No * 2 * d * 4);
   A(&N->ctxf, No * 2 * d * 4);
-  A(&N->hgx, b.ktot * c.rank * d * 4);
   A(&N->hrs, b.ktot * c.rank * d * 4);
   A(&N->hcs, b.ktot * c.rank * d * 4);
+  A(&N->hhr, b.ktot * c.rank * d * 4);
+  A(&N->hhc, b.ktot * c.rank * d * 4);
   A(&N->ao128, No * d * 4);
   A(&N->bo128, No * d * 4);
   A(&N->qkvo, No * 3 * d * 4);
@@ -1619,7 +1624,7 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
   if (c.highways) {
     if (use_off) {
       hipLaunchKernelGGL(k_hw_groups, dim3((unsigned)b.ktot), dim3(512), 0, st, fr, b.d_leaf2f, (const float*)N.H,
-                         (const float*)N.Xo, (int)L, (int)LS, N.hgx, N.hrs, N.hcs);
+                         (const float*)N.Xo, (int)L, (int)LS, N.hrs, N.hcs, N.hhr, N.hhc);
       if (ls)  // the reverse pass reads r and c
         hipLaunchKernelGGL(k_hw_materialize, dim3((unsigned)((Nd + 1) / 2)), dim3(256), 0, st, fr, N.node2f,
                            (const float*)N.H, (const float*)N.hrs, (const float*)N.hcs, (int)L, (int)LS, Nd, N.R,
@@ -1633,8 +1638,8 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
     hipLaunchKernelGGL(k_frame_mean, dim3(b.nframes), dim3(512), 0, st, (const int*)N.chunk0,
                        (const float*)N.gpart, (const float*)N.gcount, N.G);
     if (use_off)
-      hipLaunchKernelGGL(k_hw_context, dim3((unsigned)No), dim3(128), 0, st, fr, N.tile2f, (const float*)N.hgx,
-                         (const float*)N.hrs, (const float*)N.hcs, (int)L, (int)LS, N.ctxf);
+      hipLaunchKernelGGL(k_hw_context, dim3((unsigned)No), dim3(512), 0, st, fr, N.tile2f, (const float*)N.hhr,
+                         (const float*)N.hhc, (int)L, (int)LS, N.ctxf);
   }
   for (int sidx = 0; sidx < 2; ++sidx) {
     if (sidx == 1 && !use_off) continue;
