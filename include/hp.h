@@ -305,14 +305,22 @@ hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, int64_t bytes
 
 /* Test switches of one batch.  "attention_valu" (0/1): with BF16 compute, run
  * the within-leaf attention on the vector ALUs instead of the matrix cores;
- * "gemm_small_tiles" (0/1): run every BF16 GEMM on the 64 x 64 tile kernel
- * (the tests compare the variants); "gemm_autotune" (0/1, default 1): time
- * both tile kernels on the first call of each BF16 GEMM shape and keep the
- * faster (off: the 128 x 128 kernel).  HP_E_INVALID on an unknown name. */
+ * "gemm_variant" (-1 or 0..9, default -1): run every BF16 GEMM whose K the
+ * variant's K step divides on that tile variant (block tile x K step, "w8":
+ * 8 waves, "pf2": loads two K steps ahead; 0: 64x64x32, 1: 128x128x32, 2:
+ * 64x64x64, 3: 128x64x64, 4: 128x128x32w8, 5: 256x128x32w8, 6:
+ * 128x128x32w8pf2, 7: 256x128x32w8pf2, 8: 64x64x64pf2, 9: 128x128x64w8;
+ * other GEMMs on variant 0), -1 lets the autotuner choose (the tests
+ * compare the variants); "gemm_small_tiles" (0/1): the same as gemm_variant
+ * 0 / -1; "gemm_autotune" (0/1, default 1): time every variant on the first
+ * call of each BF16 GEMM shape, writing to a scratch buffer, and keep the
+ * fastest (off: the 128 x 128 x 32 kernel).  HP_E_INVALID on an unknown name
+ * or a variant out of range. */
 hp_status hp_debug_set(hp_batch b, const char* name, int32_t value);
 
 /* The GEMM autotuner's records of this batch, one text line per shape
- * ("gemm N=.. K=.. M=.. tile=.. small_us=.. wide_us=.."), written into buf
+ * ("gemm N=.. K=.. M=.. tile=<chosen> us=<variant>:<us>,..", the mean time
+ * of each timed variant in microseconds), written into buf
  * (host, len bytes, always NUL-terminated when len > 0; truncated if short).
  * *entries (optional) receives the number of shapes. */
 hp_status hp_autotune_report(hp_batch b, char* buf, int64_t len, int32_t* entries);
@@ -320,7 +328,9 @@ hp_status hp_autotune_report(hp_batch b, char* buf, int64_t len, int32_t* entrie
 /* Live kernel timing for roofline figures.  After hp_profile_enable(b,
  * family), every eager launch of that kernel family on the batch stream is
  * bracketed by HIP events (at most 4096 launches are recorded): "gemm" (the
- * network's GEMMs; work = 2 M N K flops per launch), "update" (the PCG
+ * network's GEMMs; work = 2 M N K flops per launch), "gemm_bytes" (the same
+ * launches; work = their algorithmic HBM bytes: X, W, the bias and every
+ * output and residual operand once), "update" (the PCG
  * x/r/leaf-stage kernel of the learned preconditioner; work = its algorithmic
  * HBM bytes with every frame active: 44 B per node plus G, Ut, Vt per leaf)
  * and "spmv" (the PCG SpMV kernel; 32 B per node).  PCG launches are timed

@@ -425,7 +425,14 @@ extern "C" hp_status hp_debug_set(hp_batch b, const char* name, int32_t value) {
     return HP_OK;
   }
   if (n == "gemm_small_tiles") {
-    b->gemm_small = value != 0;
+    b->gemm_variant = value != 0 ? 0 : -1;
+    return HP_OK;
+  }
+  if (n == "gemm_variant") {
+    if (value < -1 || value >= gemm_variant_count())
+      return set_error(HP_E_INVALID, "hp_debug_set: gemm_variant %d outside [-1, %d)", (int)value,
+                       gemm_variant_count());
+    b->gemm_variant = value;
     return HP_OK;
   }
   if (n == "gemm_autotune") {
@@ -440,10 +447,16 @@ extern "C" hp_status hp_autotune_report(hp_batch b, char* buf, int64_t len, int3
   std::string out;
   char line[160];
   for (const auto& kv : b->gemm_pick) {
-    snprintf(line, sizeof line, "gemm N=%d K=%d M=%lld tile=%s small_us=%.2f wide_us=%.2f\n",
-             std::get<0>(kv.first), std::get<1>(kv.first), (long long)std::get<2>(kv.first),
-             kv.second.pick ? "128x128" : "64x64", kv.second.us_small, kv.second.us_wide);
+    snprintf(line, sizeof line, "gemm N=%d K=%d M=%lld tile=%s us=", std::get<0>(kv.first), std::get<1>(kv.first),
+             (long long)std::get<2>(kv.first), gemm_variant_name(kv.second.pick));
     out += line;
+    for (size_t v = 0; v < kv.second.us.size(); ++v) {
+      if (kv.second.us[v] < 0.f) continue;
+      snprintf(line, sizeof line, "%s%s:%.2f", out.back() == '=' ? "" : ",", gemm_variant_name((int)v),
+               kv.second.us[v]);
+      out += line;
+    }
+    out += "\n";
   }
   if (entries) *entries = (int32_t)b->gemm_pick.size();
   if (len > 0) {
@@ -457,8 +470,12 @@ extern "C" hp_status hp_autotune_report(hp_batch b, char* buf, int64_t len, int3
 extern "C" hp_status hp_profile_enable(hp_batch b, const char* kernel) {
   if (!b || !kernel) return set_error(HP_E_INVALID, "hp_profile_enable: NULL argument");
   const std::string k = kernel;
-  int kind = k == "gemm" ? PROF_GEMM : k == "update" ? PROF_UPDATE : k == "spmv" ? PROF_SPMV : k == "none" ? PROF_NONE
-                                                                                                          : -1;
+  int kind = k == "gemm"         ? PROF_GEMM
+             : k == "gemm_bytes" ? PROF_GEMM_BYTES
+             : k == "update"     ? PROF_UPDATE
+             : k == "spmv"       ? PROF_SPMV
+             : k == "none"       ? PROF_NONE
+                                 : -1;
   if (kind < 0) return set_error(HP_E_INVALID, "hp_profile_enable: unknown kernel family '%s'", kernel);
   if (kind != PROF_NONE && b->prof.ev.empty()) {
     b->prof.ev.resize(2 * 4096);

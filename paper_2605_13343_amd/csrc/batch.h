@@ -40,7 +40,7 @@ struct PcgBufs {
 
 // Live kernel timing: every launch of one kernel family is bracketed by HIP
 // events on the batch stream (eager launches only, never inside a capture).
-enum { PROF_NONE = 0, PROF_GEMM = 1, PROF_UPDATE = 2, PROF_SPMV = 3 };
+enum { PROF_NONE = 0, PROF_GEMM = 1, PROF_UPDATE = 2, PROF_SPMV = 3, PROF_GEMM_BYTES = 4 };
 struct Prof {
   int kind = PROF_NONE;
   std::vector<hipEvent_t> ev;  // 2 per launch
@@ -68,9 +68,11 @@ struct NetWork {
 // Autotuner record of one GEMM shape: the chosen tile kernel (0: 64 x 64,
 // 1: 128 x 128) and the measured average launch time of each.
 struct GemmPick {
-  int pick;
-  float us_small, us_wide;
+  int pick = 1;
+  std::vector<float> us;  // per variant, -1 where the variant's K step does not divide K
 };
+int gemm_variant_count();
+const char* gemm_variant_name(int v);
 
 struct Batch {
   hp_model_config cfg{};
@@ -104,7 +106,7 @@ struct Batch {
   void* train_ws = nullptr;             // training workspace (hp_train_init)
   void (*train_free)(void*) = nullptr;
   int attn_valu = 0;                    // diagnostics: BF16 leaf attention on the vector ALUs
-  int gemm_small = 0;                   // diagnostics: BF16 GEMMs on the 64 x 64 tile kernel only
+  int gemm_variant = -1;                // diagnostics: BF16 GEMMs forced onto one tile variant (-1: autotuned)
   int gemm_autotune = 1;                // time both tile kernels on a shape's first call
   std::map<std::tuple<int, int, int64_t>, GemmPick> gemm_pick;
   void* net_train = nullptr;            // network training workspace (first hp_train_grad)

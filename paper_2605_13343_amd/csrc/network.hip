@@ -51,6 +51,134 @@ struct GemmArgs {
   int M, N, act;
 };
 
+// GELU of the BF16 path: erf by Abramowitz & Stegun, Handbook of
+// Mathematical Functions, formula 7.1.26 (a rational function of t = 1 / (1 +
+// p z) times exp(-z^2), absolute error at most 1.5e-7, far below the BF16
+// rounding of the value that follows); one exp and one reciprocal, no
+// branches.  The FP32 path keeps the library erff.
+__device__ inline float gelu_bf16path(float x) {
+  const float z = fabsf(x) * 0.7071067811865476f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, z, 1.f));
+  const float poly =
+      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
+  const float e = 1.f - poly * __expf(-z * z);
+  return 0.5f * x * (1.f + copysignf(e, x));
+}
+
+template <typename AT> __device__ inline float gemm_gelu(float v);
+template <> __device__ inline float gemm_gelu<float>(float v) { return gelu_f(v); }
+template <> __device__ inline float gemm_gelu<uint16_t>(float v) { return gelu_bf16path(v); }
+
+// Epilogue of one 32 x 32 output fragment that the MFMA produced transposed
+// (W as the first operand): the lane holds output row `row` and, for q = 0..3,
+// the four consecutive columns cb + 8 q .. cb + 8 q + 3 in acc[4 q .. 4 q + 3]
+// (cb = fragment column + 4 (lane / 32)).  Four-wide vector loads and stores
+// where every operand's leading dimension and base allow them.
+// Two floats to packed BF16, round to nearest even (the hardware conversion).
+__device__ inline uint32_t pack_bf16x2(float lo, float hi) {
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  typedef float f32x2_t __attribute__((ext_vector_type(2)));
+  const f32x2_t v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
+
+template <typename AT>
+__device__ inline void gemm_epilogue(const GemmArgs& a, const f32x16_t& acc, int row, int cb, bool vec) {
+  if (row >= a.M) return;
+  const int64_t r = row;
+  // row bases formed once; the columns below are 32-bit offsets from them
+  float* pre = a.pre ? a.pre + r * a.ldp : nullptr;
+  const float* res = a.resid ? a.resid + r * a.ldr : nullptr;
+  float* yf = a.Yf ? a.Yf + r * a.ldf : nullptr;
+  AT* yb = a.Yb ? (AT*)a.Yb + r * a.ldb : nullptr;
+  const bool gelu = a.act == 1;
+  // presence tests on the (uniform) kernel arguments, not on the row pointers
+  const bool has_pre = a.pre != nullptr, has_res = a.resid != nullptr, has_yf = a.Yf != nullptr,
+             has_yb = a.Yb != nullptr;
+  if (vec && cb + 27 < a.N) {
+    // every column of the fragment in range: the bias and residual loads of
+    // all four column groups are issued together, then one wait
+    float bv[16], rv[16];
+    if (a.bias) {
+      if (((uintptr_t)a.bias & 15) == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float4 t = *(const float4*)(a.bias + cb + 8 * q);
+          bv[4 * q] = t.x;
+          bv[4 * q + 1] = t.y;
+          bv[4 * q + 2] = t.z;
+          bv[4 * q + 3] = t.w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) bv[4 * q + c] = a.bias[cb + 8 * q + c];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) bv[e] = 0.f;
+    }
+    if (has_res) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 t = *(const float4*)(res + cb + 8 * q);
+        rv[4 * q] = t.x;
+        rv[4 * q + 1] = t.y;
+        rv[4 * q + 2] = t.z;
+        rv[4 * q + 3] = t.w;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c0 = cb + 8 * q;
+      float v[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] = acc[4 * q + c] + bv[4 * q + c];
+      if (has_pre) *(float4*)(pre + c0) = make_float4(v[0], v[1], v[2], v[3]);
+      if (gelu) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = gemm_gelu<AT>(v[c]);
+      }
+      if (has_res) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] += rv[4 * q + c];
+      }
+      if (has_yf) *(float4*)(yf + c0) = make_float4(v[0], v[1], v[2], v[3]);
+      if (has_yb) {
+        if constexpr (sizeof(AT) == 2)
+          *(uint2*)(yb + c0) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+        else
+          *(float4*)(yb + c0) = make_float4(v[0], v[1], v[2], v[3]);
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int col = cb + 8 * q + c;
+      if (col >= a.N) break;
+      float x = acc[4 * q + c] + (a.bias ? a.bias[col] : 0.f);
+      if (has_pre) pre[col] = x;
+      if (gelu) x = gemm_gelu<AT>(x);
+      if (has_res) x += res[col];
+      if (has_yf) yf[col] = x;
+      if (has_yb) yb[col] = to_act<AT>(x);
+    }
+  }
+}
+
+// Whether every output and the residual admit the four-wide accesses of the
+// epilogue (leading dimensions multiples of 4, 16-byte aligned bases).
+__device__ inline bool gemm_vec_ok(const GemmArgs& a, int act_bytes) {
+  auto ok = [](const void* p, int64_t ld, int eb) {
+    return !p || ((ld & 3) == 0 && ((uintptr_t)p & (uintptr_t)(4 * eb - 1)) == 0);
+  };
+  return ok(a.resid, a.ldr, 4) && ok(a.Yf, a.ldf, 4) && ok(a.pre, a.ldp, 4) && ok(a.Yb, a.ldb, act_bytes);
+}
+
 template <typename AT>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   constexpr int BM = 64, BN = 64, BK = 32;
@@ -106,141 +234,183 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
       for (int kk = 0; kk < BK; kk += 16) {
         bf16x8_t av = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sA[buf][wm + (lane & 31)][kk + (lane >> 5) * 8]);
         bf16x8_t bv = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sB[buf][wn + (lane & 31)][kk + (lane >> 5) * 8]);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bv, av, acc, 0, 0, 0);
       }
     } else {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 2) {
         float av = sA[buf][wm + (lane & 31)][kk + (lane >> 5)];
         float bv = sB[buf][wn + (lane & 31)][kk + (lane >> 5)];
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(bv, av, acc, 0, 0, 0);
       }
     }
     if (kt + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
   }
-  const int col = n0 + wn + (lane & 31);
-  if (col >= a.N) return;
-  const float bc = a.bias ? a.bias[col] : 0.f;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = m0 + wm + i * 8 + (lane >> 5) * 4 + j;
-      if (row >= a.M) continue;
-      float v = acc[i * 4 + j] + bc;
-      if (a.pre) a.pre[(int64_t)row * a.ldp + col] = v;
-      if (a.act == 1) v = gelu_f(v);
-      if (a.resid) v += a.resid[(int64_t)row * a.ldr + col];
-      if (a.Yf) a.Yf[(int64_t)row * a.ldf + col] = v;
-      if (a.Yb) ((AT*)a.Yb)[(int64_t)row * a.ldb + col] = to_act<AT>(v);
-    }
-  }
+  gemm_epilogue<AT>(a, acc, m0 + wm + (lane & 31), n0 + wn + 4 * (lane >> 5), gemm_vec_ok(a, (int)sizeof(AT)));
 }
 
-// BF16 GEMM for the wide layers (N > 64): 128 x 128 block tile, four waves of
-// 64 x 64 (2 x 2 MFMA 32x32x16 tiles, so each LDS operand read feeds two
-// MFMAs), K in steps of 32 through two LDS buffers: the next step's global
-// loads are issued before the current step's MFMAs and stored to the other
-// buffer after them, one barrier per step.  The 1-D grid is remapped so that
-// the blocks one XCD receives are consecutive (row tile, column tile) pairs:
-// the column tiles of a row tile share that XCD's L2 copy of the X rows.
-__global__ __launch_bounds__(256) void k_gemm_wide(GemmArgs a, int tiles_n) {
-  constexpr int BM = 128, BN = 128, BK = 32, LDK = BK + 8;
+// BF16 tile-kernel family: a BM x BN block tile of (BM/WM) x (BN/WN) waves,
+// each wave WM x WN in 32 x 32 MFMA fragments, K staged through two LDS
+// buffers in steps of BK.  Global loads run PF steps ahead of the MFMAs (PF =
+// 1: the next step's loads are issued before the current step's MFMAs; PF =
+// 2: two register sets, so a step's loads have two steps of MFMAs to land
+// before they are written to LDS).  Every member issues, per output element,
+// the same MFMA sequence along K (k ascending in steps of 16) and the same
+// epilogue, so all of them give bit-identical results; the autotuner picks
+// one per shape.  1-D grid with the XCD-aware, column-fastest tile order.
+template <int BM, int BN, int BK, int WM, int WN, int PF>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_bt(GemmArgs a, int tiles_n) {
+  constexpr int NWN = BN / WN, NT = (BM / WM) * NWN * 64, LDK = BK + 8, KC = BK / 8;
+  // 16-byte chunks per thread and operand (the last round may leave threads idle)
+  constexpr int CA = (BM * KC + NT - 1) / NT, CB = (BN * KC + NT - 1) / NT, FM = WM / 32, FN = WN / 32;
+  static_assert(PF == 1 || PF == 2, "prefetch depth 1 or 2");
   __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM][LDK];
   __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN][LDK];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int nblk = (int)gridDim.x, id = (int)blockIdx.x;
   const int lin = (nblk % 8 == 0) ? (id % 8) * (nblk / 8) + id / 8 : id;
   const int m0 = (lin / tiles_n) * BM, n0 = (lin % tiles_n) * BN;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int wm = (wave / NWN) * WM, wn = (wave % NWN) * WN;
   const uint16_t* X = (const uint16_t*)a.X;
   const uint16_t* W = (const uint16_t*)a.Wt;
-  // global -> register staging: 2 x 16 B of X and of W per thread and step
-  const int lr = tid >> 2, lc = (tid & 3) * 8;  // rows lr and lr + 64, columns lc..lc+7
-  uint4 ra[2], rb[2];
-  auto gload = [&](int k0) {
+  uint4 ra[PF][CA], rb[PF][CB];
+  auto gload = [&](uint4(&xa)[CA], uint4(&xb)[CB], int k0) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int r = lr + 64 * q;
-      ra[q] = (m0 + r < a.M) ? *(const uint4*)(X + (int64_t)(m0 + r) * a.ldx + k0 + lc) : make_uint4(0, 0, 0, 0);
-      rb[q] = (n0 + r < a.N) ? *(const uint4*)(W + (int64_t)(n0 + r) * a.K + k0 + lc) : make_uint4(0, 0, 0, 0);
+    for (int q = 0; q < CA; ++q) {
+      const int idx = tid + q * NT, r = idx / KC, c = (idx % KC) * 8;
+      if (BM * KC % NT != 0 && idx >= BM * KC) break;
+      xa[q] = (m0 + r < a.M) ? *(const uint4*)(X + (int64_t)(m0 + r) * a.ldx + k0 + c) : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      const int idx = tid + q * NT, r = idx / KC, c = (idx % KC) * 8;
+      if (BN * KC % NT != 0 && idx >= BN * KC) break;
+      xb[q] = (n0 + r < a.N) ? *(const uint4*)(W + (int64_t)(n0 + r) * a.K + k0 + c) : make_uint4(0, 0, 0, 0);
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](const uint4(&xa)[CA], const uint4(&xb)[CB], int buf) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      *(uint4*)&sA[buf][lr + 64 * q][lc] = ra[q];
-      *(uint4*)&sB[buf][lr + 64 * q][lc] = rb[q];
+    for (int q = 0; q < CA; ++q) {
+      const int idx = tid + q * NT;
+      if (BM * KC % NT != 0 && idx >= BM * KC) break;
+      *(uint4*)&sA[buf][idx / KC][(idx % KC) * 8] = xa[q];
+    }
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      const int idx = tid + q * NT;
+      if (BN * KC % NT != 0 && idx >= BN * KC) break;
+      *(uint4*)&sB[buf][idx / KC][(idx % KC) * 8] = xb[q];
     }
   };
-  f32x16_t acc[2][2];
+  f32x16_t acc[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
       for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
-  const int nk = a.K / BK;
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BK);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
-      bf16x8_t av[2], bv[2];
+      bf16x8_t av[FM], bv[FN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < FM; ++i)
         av[i] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sA[buf][wm + 32 * i + (lane & 31)][kk + (lane >> 5) * 8]);
-        bv[i] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sB[buf][wn + 32 * i + (lane & 31)][kk + (lane >> 5) * 8]);
-      }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < FN; ++j)
+        bv[j] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sB[buf][wn + 32 * j + (lane & 31)][kk + (lane >> 5) * 8]);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bv[j], av[i], acc[i][j], 0, 0, 0);
     }
-    if (kt + 1 < nk) sstore(buf ^ 1);
+  };
+  const int nk = a.K / BK;
+  if constexpr (PF == 1) {
+    gload(ra[0], rb[0], 0);
+    sstore(ra[0], rb[0], 0);
     __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) gload(ra[0], rb[0], (kt + 1) * BK);
+      compute(buf);
+      if (kt + 1 < nk) sstore(ra[0], rb[0], buf ^ 1);
+      __syncthreads();
+    }
+  } else {
+    // step s lives in LDS buffer s & 1 and in register set s & 1
+    gload(ra[0], rb[0], 0);
+    if (nk > 1) gload(ra[1], rb[1], BK);
+    sstore(ra[0], rb[0], 0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; kt += 2) {
+      if (kt + 2 < nk) gload(ra[0], rb[0], (kt + 2) * BK);
+      compute(0);
+      if (kt + 1 < nk) sstore(ra[1], rb[1], 1);
+      __syncthreads();
+      if (kt + 1 >= nk) break;
+      if (kt + 3 < nk) gload(ra[1], rb[1], (kt + 3) * BK);
+      compute(1);
+      if (kt + 2 < nk) sstore(ra[0], rb[0], 0);
+      __syncthreads();
+    }
   }
+  const bool vec = gemm_vec_ok(a, 2);
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int col = n0 + wn + 32 * j + (lane & 31);
-    if (col >= a.N) continue;
-    const float bc = a.bias ? a.bias[col] : 0.f;
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int row = m0 + wm + 32 * i + r * 8 + (lane >> 5) * 4 + c;
-          if (row >= a.M) continue;
-          float v = acc[i][j][r * 4 + c] + bc;
-          if (a.pre) a.pre[(int64_t)row * a.ldp + col] = v;
-          if (a.act == 1) v = gelu_f(v);
-          if (a.resid) v += a.resid[(int64_t)row * a.ldr + col];
-          if (a.Yf) a.Yf[(int64_t)row * a.ldf + col] = v;
-          if (a.Yb) ((uint16_t*)a.Yb)[(int64_t)row * a.ldb + col] = f32_to_bf16(v);
-        }
-  }
+    for (int j = 0; j < FN; ++j)
+      gemm_epilogue<uint16_t>(a, acc[i][j], m0 + wm + 32 * i + (lane & 31), n0 + wn + 32 * j + 4 * (lane >> 5), vec);
 }
 
 // ------------------------------------------------------------------ LayerNorm
-// One wave per row of C = 128 (eps 1e-5), FP32 in, activation type out.
+// Eight consecutive values of a row: loaded with two 16-byte loads when the
+// address allows, stored as one 16-byte BF16 pack (or two FP32 float4).
+__device__ inline void load8(const float* p, float (&v)[8]) {
+  if (((uintptr_t)p & 15) == 0) {
+    const float4 a = ((const float4*)p)[0], b = ((const float4*)p)[1];
+    v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = p[i];
+  }
+}
+template <typename AT>
+__device__ inline void store8(AT* y, const float (&v)[8]) {
+  if constexpr (sizeof(AT) == 2) {
+    if (((uintptr_t)y & 15) == 0) {
+      *(uint4*)y = make_uint4(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]), pack_bf16x2(v[4], v[5]),
+                              pack_bf16x2(v[6], v[7]));
+      return;
+    }
+  } else {
+    if (((uintptr_t)y & 15) == 0) {
+      ((float4*)y)[0] = make_float4(v[0], v[1], v[2], v[3]);
+      ((float4*)y)[1] = make_float4(v[4], v[5], v[6], v[7]);
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) y[i] = to_act<AT>(v[i]);
+}
+
+// One wave per row of C = 128 (eps 1e-5), FP32 in, activation type out; lane
+// l holds columns 2 l and 2 l + 1 (one 8-byte load, one packed store).
 template <typename AT>
 __global__ __launch_bounds__(256) void k_layernorm128(const float* X, const float* g, const float* b, AT* Y, int M) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (row >= M) return;
-  const float* x = X + (int64_t)row * 128;
-  float v0 = x[lane], v1 = x[lane + 64];
-  const float mu = wave_sum_f(v0 + v1) * (1.f / 128.f);
-  const float d0 = v0 - mu, d1 = v1 - mu;
+  const float2 x = *(const float2*)(X + (int64_t)row * 128 + 2 * lane);
+  const float mu = wave_sum_f(x.x + x.y) * (1.f / 128.f);
+  const float d0 = x.x - mu, d1 = x.y - mu;
   const float var = wave_sum_f(d0 * d0 + d1 * d1) * (1.f / 128.f);
   const float rs = rsqrtf(var + 1e-5f);
-  Y[(int64_t)row * 128 + lane] = to_act<AT>(d0 * rs * g[lane] + b[lane]);
-  Y[(int64_t)row * 128 + lane + 64] = to_act<AT>(d1 * rs * g[lane + 64] + b[lane + 64]);
+  const float y0 = d0 * rs * g[2 * lane] + b[2 * lane], y1 = d1 * rs * g[2 * lane + 1] + b[2 * lane + 1];
+  if constexpr (sizeof(AT) == 2)
+    *(uint32_t*)(Y + (int64_t)row * 128 + 2 * lane) = pack_bf16x2(y0, y1);
+  else
+    *(float2*)(Y + (int64_t)row * 128 + 2 * lane) = make_float2(y0, y1);
 }
 
 // LayerNorm over the 4d concat [x | a | c | g] (Sec. 4.3: each token joins its
@@ -262,8 +432,12 @@ __global__ __launch_bounds__(256) void k_ln_concat(const float* S0, int64_t ld0,
     else if (seg == 2) src = S2 + (int64_t)row * ld2;
     else src = G + (int64_t)row2f[row] * 128;
   }
+  if (src) {
+    load8(src + c0, v);
+  } else {
 #pragma unroll
-  for (int i = 0; i < 8; ++i) v[i] = src ? src[c0 + i] : 0.f;
+    for (int i = 0; i < 8; ++i) v[i] = 0.f;
+  }
   float s = 0.f;
 #pragma unroll
   for (int i = 0; i < 8; ++i) s += v[i];
@@ -272,10 +446,13 @@ __global__ __launch_bounds__(256) void k_ln_concat(const float* S0, int64_t ld0,
 #pragma unroll
   for (int i = 0; i < 8; ++i) q += (v[i] - mu) * (v[i] - mu);
   const float rs = rsqrtf(wave_sum_f(q) * (1.f / 512.f) + 1e-5f);
-  AT* y = Y + (int64_t)row * 512 + seg * 128 + c0;
   const int gc = seg * 128 + c0;
+  float gm[8], bt[8], o[8];
+  load8(gam + gc, gm);
+  load8(bet + gc, bt);
 #pragma unroll
-  for (int i = 0; i < 8; ++i) y[i] = to_act<AT>((v[i] - mu) * rs * gam[gc + i] + bet[gc + i]);
+  for (int i = 0; i < 8; ++i) o[i] = (v[i] - mu) * rs * gm[i] + bt[i];
+  store8<AT>(Y + (int64_t)row * 512 + gc, o);
 }
 
 // ------------------------------------------------------------------ features
@@ -901,17 +1078,13 @@ __device__ inline void leaf_sides(int k, int J, int& nr, int& nc) {
   }
 }
 
-__global__ __launch_bounds__(512) void k_hw_groups(const FrameDesc* fr, const int* leaf2f, const float* Xd,
-                                                   const float* Xo, int L, int LS, float* rs, float* cs, float* hr,
-                                                   float* hc) {
+__global__ __launch_bounds__(512) void k_hw_groups(const FrameDesc* fr, const int* leaf2f, const float* Xo, int LS,
+                                                   float* rs, float* cs) {
   const int64_t kg = blockIdx.x;
   const FrameDesc F = fr[leaf2f[kg]];
-  const int k = (int)(kg - F.k0), K = F.K, p = L / LS, col = threadIdx.x & 127;
-  int nr, nc;
-  leaf_sides(k, F.J, nr, nc);
+  const int k = (int)(kg - F.k0), K = F.K, col = threadIdx.x & 127;
   for (int t = threadIdx.x >> 7; t < LS; t += 4) {
-    float a = 0.f, r = 0.f, c = 0.f;
-    for (int q = 0; q < p; ++q) a += Xd[((int64_t)F.n0 + (int64_t)k * L + t * p + q) * 128 + col];
+    float r = 0.f, c = 0.f;
     for (int j = 0; j < F.J; ++j) {
       const int m = K - (K >> j) + (k >> (j + 1));
       const float v = Xo[((int64_t)(F.m0 + m) * LS + t) * 128 + col];
@@ -921,37 +1094,73 @@ __global__ __launch_bounds__(512) void k_hw_groups(const FrameDesc* fr, const in
     const int64_t o = (kg * LS + t) * 128 + col;
     rs[o] = r;
     cs[o] = c;
-    hr[o] = (a + (float)p * r) / (float)nr;   // sum of r over the group
-    hc[o] = (a + (float)p * c) / (float)nc;   // sum of c over the group
   }
 }
 
-// Off-diagonal token context from the groups: for token (m, t) the mean of r
-// over I_m^t (the group sums hr of the row strip's leaves, divided by S p) and
-// of c over J_m^t (hc of the column strip's leaves).  4 groups of leaves x
-// 128 features, groups added in order.
-__global__ __launch_bounds__(512) void k_hw_context(const FrameDesc* fr, const int* tile2f, const float* hr,
-                                                    const float* hc, int L, int LS, float* out) {
-  __shared__ float red[2][4][128];
-  const int64_t tok = blockIdx.x;
-  const int mg = (int)(tok / LS), t = (int)(tok % LS);
-  const FrameDesc F = fr[tile2f[mg]];
-  const int m = mg - F.m0, K = F.K;
-  int j = 0;
-  while (m >= K - (K >> (j + 1))) ++j;
-  const int i = m - (K - (K >> j)), S = 1 << j, r0 = 2 * i * S, c0 = r0 + S, p = L / LS;
-  const int col = threadIdx.x & 127, g = threadIdx.x >> 7;
-  float sa = 0.f, sb = 0.f;
-  for (int q = g; q < S; q += 4) {
-    sa += hr[(((int64_t)F.k0 + r0 + q) * LS + t) * 128 + col];
-    sb += hc[(((int64_t)F.k0 + c0 + q) * LS + t) * 128 + col];
+// Off-diagonal token context (the mean of r over I_m^t and of c over J_m^t)
+// from the group sums hr, hc of r and c: tile (j, i) of a frame has the row
+// strip of leaves [2 i S, 2 i S + S) and the column strip [2 i S + S, 2 i S +
+// 2 S), S = 2^j, so its strip sums are the dyadic block sums D_j[2 i] of hr and
+// D_j[2 i + 1] of hc, with D_0 the leaves and D_{j+1}[q] = D_j[2 q] + D_j[2 q +
+// 1].  Lower levels: one block per (aligned chunk of C = min(16, K) leaves,
+// t), threads (side, feature); the block builds D_0 .. D_log2(C) of its chunk
+// in registers, writes the context of every tile that lies inside the chunk,
+// and the chunk total.  Upper levels (2 S > C): per (frame, t), strip sums
+// of the chunk totals in chunk order.  Each context entry is divided by S p.
+constexpr int STRIP_CHUNK = 16;
+
+// One level of the chunk tree: the context of the level's tiles inside the
+// chunk (v holds the blocks of size S), then the fold to blocks of size 2 S.
+template <int S>
+__device__ inline void strip_level(float (&v)[STRIP_CHUNK], int C, int leaf0, int j, const FrameDesc& F, int t,
+                                   int LS, int side, int col, int p, float* out) {
+#pragma unroll
+  for (int il = 0; il < STRIP_CHUNK / (2 * S); ++il) {
+    if (il < C / (2 * S)) {
+      const int m = F.K - (F.K >> j) + leaf0 / (2 * S) + il;
+      out[((int64_t)(F.m0 + m) * LS + t) * 256 + 128 * side + col] = v[2 * il + side] / (float)(S * p);
+    }
   }
-  red[0][g][col] = sa;
-  red[1][g][col] = sb;
-  __syncthreads();
-  if (g < 2) {
-    const float v = red[g][0][col] + red[g][1][col] + red[g][2][col] + red[g][3][col];
-    out[tok * 256 + 128 * g + col] = v / (float)(S * p);
+#pragma unroll
+  for (int q = 0; q < STRIP_CHUNK / (2 * S); ++q) v[q] = v[2 * q] + v[2 * q + 1];
+}
+
+__global__ __launch_bounds__(256) void k_hw_strips_lo(const FrameDesc* fr, const int2* tab, const float* hr,
+                                                      const float* hc, int L, int LS, float* out, float* tot) {
+  const int2 e = tab[blockIdx.x];
+  const int t = blockIdx.y, side = threadIdx.x >> 7, col = threadIdx.x & 127, p = L / LS;
+  const FrameDesc F = fr[e.x];
+  const int C = min(STRIP_CHUNK, F.K), leaf0 = e.y * C;
+  const float* H = side ? hc : hr;
+  float v[STRIP_CHUNK];
+#pragma unroll
+  for (int q = 0; q < STRIP_CHUNK; ++q)
+    v[q] = q < C ? H[(((int64_t)F.k0 + leaf0 + q) * LS + t) * 128 + col] : 0.f;
+  static_assert(STRIP_CHUNK == 16, "four tree levels per chunk");
+  if (2 <= C) strip_level<1>(v, C, leaf0, 0, F, t, LS, side, col, p, out);
+  if (4 <= C) strip_level<2>(v, C, leaf0, 1, F, t, LS, side, col, p, out);
+  if (8 <= C) strip_level<4>(v, C, leaf0, 2, F, t, LS, side, col, p, out);
+  if (16 <= C) strip_level<8>(v, C, leaf0, 3, F, t, LS, side, col, p, out);
+  tot[(((int64_t)blockIdx.x) * LS + t) * 256 + 128 * side + col] = v[0];
+}
+
+__global__ __launch_bounds__(256) void k_hw_strips_hi(const FrameDesc* fr, const int* chunk0, const float* tot,
+                                                      int L, int LS, float* out) {
+  const int f = blockIdx.x, t = blockIdx.y, side = threadIdx.x >> 7, col = threadIdx.x & 127, p = L / LS;
+  const FrameDesc F = fr[f];
+  const int K = F.K, C = min(STRIP_CHUNK, K);
+  const float* T = tot + ((int64_t)chunk0[f] * LS + t) * 256 + 128 * side + col;
+  int j = 0;
+  while ((2 << j) <= C) ++j;  // first level whose tiles span more than one chunk
+  for (; j < F.J; ++j) {
+    const int S = 1 << j, nc = S / C;
+    for (int i = 0; i < (K >> (j + 1)); ++i) {
+      const int c0 = (2 * i * S + side * S) / C;
+      float sum = 0.f;
+      for (int q = 0; q < nc; ++q) sum += T[(int64_t)(c0 + q) * LS * 256];
+      const int m = K - (K >> j) + i;
+      out[((int64_t)(F.m0 + m) * LS + t) * 256 + 128 * side + col] = sum / (float)(S * p);
+    }
   }
 }
 
@@ -973,35 +1182,36 @@ __global__ __launch_bounds__(256) void k_hw_materialize(const FrameDesc* fr, con
 }
 
 // LN([x | r | c | g]) of the diagonal tokens with r, c formed on the fly from
-// the group sums (one wave per row, as k_ln_concat).
+// the level sums (one wave per row, as k_ln_concat).  A block's four rows are
+// the p = 4 tokens of one (leaf, sub-strip) group, so the block also writes
+// the group's sums of r and of c (fixed order over the four rows), which the
+// off-diagonal context is built from.
 template <typename AT>
 __global__ __launch_bounds__(256) void k_ln_hw_diag(const FrameDesc* fr, const int* node2f, const float* X,
                                                     const float* rs, const float* cs, const float* G, int L, int LS,
-                                                    const float* gam, const float* bet, AT* Y, int M) {
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (row >= M) return;
+                                                    const float* gam, const float* bet, AT* Y, float* hr, float* hc) {
+  __shared__ float rc[2][4][128];
+  const int w = threadIdx.x >> 6, row = blockIdx.x * 4 + w, lane = threadIdx.x & 63;
   const int f = node2f[row];
   const FrameDesc F = fr[f];
   const int c = row - F.n0, k = c / L, l = c % L, p = L / LS;
   const int seg = lane >> 4, c0 = (lane & 15) * 8;
   float v[8];
   if (seg == 3) {
-    const float4* g4 = (const float4*)(G + (int64_t)f * 128 + c0);
-    const float4 a = g4[0], b = g4[1];
-    v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+    load8(G + (int64_t)f * 128 + c0, v);
   } else {
-    const float4* x4 = (const float4*)(X + (int64_t)row * 128 + c0);
-    const float4 a = x4[0], b = x4[1];
-    v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+    load8(X + (int64_t)row * 128 + c0, v);
     if (seg > 0) {
       int nr, nc;
       leaf_sides(k, F.J, nr, nc);
       const float n = (float)(seg == 1 ? nr : nc);
-      const float4* h4 = (const float4*)((seg == 1 ? rs : cs) + (((int64_t)F.k0 + k) * LS + l / p) * 128 + c0);
-      const float4 ha = h4[0], hb = h4[1];
-      const float h[8] = {ha.x, ha.y, ha.z, ha.w, hb.x, hb.y, hb.z, hb.w};
+      float h[8];
+      load8((seg == 1 ? rs : cs) + (((int64_t)F.k0 + k) * LS + l / p) * 128 + c0, h);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = (v[q] + h[q]) / n;
+      for (int q = 0; q < 8; ++q) {
+        v[q] = (v[q] + h[q]) / n;
+        rc[seg - 1][w][c0 + q] = v[q];
+      }
     }
   }
   float sm = 0.f;
@@ -1012,10 +1222,19 @@ __global__ __launch_bounds__(256) void k_ln_hw_diag(const FrameDesc* fr, const i
 #pragma unroll
   for (int q = 0; q < 8; ++q) qv += (v[q] - mu) * (v[q] - mu);
   const float rsd = rsqrtf(wave_sum_f(qv) * (1.f / 512.f) + 1e-5f);
-  AT* y = Y + (int64_t)row * 512 + seg * 128 + c0;
   const int gc = seg * 128 + c0;
+  float gm[8], bt[8], o[8];
+  load8(gam + gc, gm);
+  load8(bet + gc, bt);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) y[q] = to_act<AT>((v[q] - mu) * rsd * gam[gc + q] + bet[gc + q]);
+  for (int q = 0; q < 8; ++q) o[q] = (v[q] - mu) * rsd * gm[q] + bt[q];
+  store8<AT>(Y + (int64_t)row * 512 + gc, o);
+  __syncthreads();
+  // group sums: thread (side, feature) adds the four rows in order
+  const int side = threadIdx.x >> 7, col = threadIdx.x & 127;
+  const int row0 = blockIdx.x * 4, cg = row0 - F.n0;
+  const int64_t grp = ((int64_t)F.k0 + cg / L) * LS + (cg % L) / p;
+  (side ? hc : hr)[grp * 128 + col] = ((rc[side][0][col] + rc[side][1][col]) + rc[side][2][col]) + rc[side][3][col];
 }
 
 // Column sums of 128-wide rows over chunks of at most SUM_CHUNK rows (first
@@ -1255,6 +1474,10 @@ struct NetBufs {
   void *ctx = nullptr, *ao128 = nullptr, *bo128 = nullptr, *qkvo = nullptr, *uo512 = nullptr, *ho512 = nullptr;
   float *ctxf = nullptr;
   float *hrs = nullptr, *hcs = nullptr, *hhr = nullptr, *hhc = nullptr;  // highway group sums [ktot L_s][128]
+  int2* strip_tab = nullptr;   // (frame, chunk) of the context tree's lower levels
+  int nstrip = 0;
+  int* strip0 = nullptr;       // first chunk of each frame [nframes]
+  float* strip_tot = nullptr;  // chunk totals [nstrip][L_s][2][128]
   float *Frows = nullptr, *NH = nullptr, *UV = nullptr;
   float *T0 = nullptr, *corr = nullptr, *ahat = nullptr, *desc = nullptr, *boff = nullptr;
   uint8_t* nbr = nullptr;
@@ -1308,6 +1531,18 @@ hp_status network_alloc(Batch& b) {
   A(&N->hcs, b.ktot * c.rank * d * 4);
   A(&N->hhr, b.ktot * c.rank * d * 4);
   A(&N->hhc, b.ktot * c.rank * d * 4);
+  std::vector<int2> stab;
+  std::vector<int> strip0(b.nframes, 0);
+  for (int f = 0; f < b.nframes; ++f) {
+    strip0[f] = (int)stab.size();
+    if (b.fr[f].MH == 0) continue;
+    const int C = std::min(STRIP_CHUNK, b.fr[f].K);
+    for (int q = 0; q < b.fr[f].K / C; ++q) stab.push_back(make_int2(f, q));
+  }
+  N->nstrip = (int)stab.size();
+  A(&N->strip_tab, std::max<size_t>(stab.size(), 1) * sizeof(int2));
+  A(&N->strip0, std::max(b.nframes, 1) * 4);
+  A(&N->strip_tot, std::max<size_t>(stab.size(), 1) * c.rank * 2 * d * 4);
   A(&N->ao128, No * d * 4);
   A(&N->bo128, No * d * 4);
   A(&N->qkvo, No * 3 * d * 4);
@@ -1385,6 +1620,8 @@ hp_status network_alloc(Batch& b) {
   up(N->tile2f, tile2f.data(), tile2f.size() * 4);
   up(N->chunk0, chunk0.data(), chunk0.size() * 4);
   up(N->chunks, ch.data(), ch.size() * sizeof(SumChunk));
+  if (!stab.empty()) up(N->strip_tab, stab.data(), stab.size() * sizeof(int2));
+  if (b.nframes > 0) up(N->strip0, strip0.data(), strip0.size() * 4);
   if (!dch.empty()) up(N->desc_chunks, dch.data(), dch.size() * sizeof(DescChunk));
   up(N->desc_chunk0, dch0.data(), dch0.size() * sizeof(int));
   up(N->gcount, cnt.data(), cnt.size() * 4);
@@ -1395,59 +1632,111 @@ hp_status network_alloc(Batch& b) {
   return s;
 }
 
+// BF16 GEMM variants, indexed by the autotuner's "kind": block tile BM x BN,
+// K step BK (K must be a multiple of it), waves.
+struct GemmVar {
+  const char* name;
+  int bk;
+};
+static const GemmVar kGemmVars[] = {
+    {"64x64x32", 32},       {"128x128x32", 32},      {"64x64x64", 64},          {"128x64x64", 64},
+    {"128x128x32w8", 32},   {"256x128x32w8", 32},    {"128x128x32w8pf2", 32},   {"256x128x32w8pf2", 32},
+    {"64x64x64pf2", 64},    {"128x128x64w8", 64},
+};
+constexpr int kNumGemmVars = (int)(sizeof(kGemmVars) / sizeof(kGemmVars[0]));
+int gemm_variant_count() { return kNumGemmVars; }
+const char* gemm_variant_name(int v) { return v >= 0 && v < kNumGemmVars ? kGemmVars[v].name : "?"; }
+static bool gemm_variant_fits(int v, int K) { return v >= 0 && v < kNumGemmVars && K % kGemmVars[v].bk == 0; }
+
+template <int BM, int BN, int BK, int WM, int WN, int PF = 1>
+static void launch_bt(const GemmArgs& a, hipStream_t st) {
+  const int tn = (a.N + BN - 1) / BN, tm = (a.M + BM - 1) / BM;
+  hipLaunchKernelGGL((k_gemm_bt<BM, BN, BK, WM, WN, PF>), dim3((unsigned)(tm * tn)), dim3((BM / WM) * (BN / WN) * 64),
+                     0, st, a, tn);
+}
+
 static void launch_gemm(int kind, const GemmArgs& a, bool bf16, hipStream_t st) {
-  if (kind == 1) {
-    const int tn = (a.N + 127) / 128, tm = (a.M + 127) / 128;
-    hipLaunchKernelGGL(k_gemm_wide, dim3((unsigned)(tm * tn)), dim3(256), 0, st, a, tn);
-  } else {
+  if (!bf16) {
     const unsigned nb = (unsigned)(((a.M + 63) / 64) * ((a.N + 63) / 64));
-    if (bf16) hipLaunchKernelGGL(k_gemm<uint16_t>, dim3(nb), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(k_gemm<float>, dim3(nb), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_gemm<float>, dim3(nb), dim3(256), 0, st, a);
+    return;
+  }
+  switch (kind) {
+    case 1: launch_bt<128, 128, 32, 64, 64>(a, st); break;
+    case 2: launch_bt<64, 64, 64, 32, 32>(a, st); break;
+    case 3: launch_bt<128, 64, 64, 64, 32>(a, st); break;
+    case 4: launch_bt<128, 128, 32, 64, 32>(a, st); break;
+    case 5: launch_bt<256, 128, 32, 64, 64>(a, st); break;
+    case 6: launch_bt<128, 128, 32, 64, 32, 2>(a, st); break;
+    case 7: launch_bt<256, 128, 32, 64, 64, 2>(a, st); break;
+    case 8: launch_bt<64, 64, 64, 32, 32, 2>(a, st); break;
+    case 9: launch_bt<128, 128, 64, 64, 32>(a, st); break;
+    default: {
+      const unsigned nb = (unsigned)(((a.M + 63) / 64) * ((a.N + 63) / 64));
+      hipLaunchKernelGGL(k_gemm<uint16_t>, dim3(nb), dim3(256), 0, st, a);
+    }
   }
 }
 
 // GEMM tile autotuner (BF16, N > 64): the first call of a shape (N, K, M) on
-// a batch times both tile kernels (one warm launch, then 3 timed launches
-// each) and keeps the faster.  The two kernels compute bit-identical results
-// and a call that does not read its own output is idempotent, so tuning
-// leaves exactly the single call's result.  A call that reads its output (a
-// residual added in place, or X as output) is not timed: it takes the choice of the same
-// (N, M) at the nearest K, else the 128 x 128 kernel.
+// a batch times every variant whose K step divides K (one warm launch, then
+// 3 timed launches each) with the call's outputs redirected to a scratch
+// buffer, so tuning never touches the call's own outputs (in-place residual
+// calls included); the call then runs once with the fastest.  All variants
+// compute bit-identical results.  Under stream capture, with tuning off, or if
+// the scratch buffer cannot be had, a shape takes the choice recorded for the
+// same (N, M) at the nearest K, else the 128 x 128 kernel.
 static int gemm_choice(Batch& b, const GemmArgs& a, hipStream_t st) {
   const auto key = std::make_tuple(a.N, a.K, (int64_t)a.M);
   auto it = b.gemm_pick.find(key);
   if (it != b.gemm_pick.end()) return it->second.pick;
-  const bool in_place = (a.resid && (a.resid == a.Yf || (const void*)a.resid == a.Yb)) ||
-                        a.X == (const void*)a.Yf || a.X == a.Yb;
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  hipStreamIsCapturing(st, &cs);
-  if (in_place || !b.gemm_autotune || cs != hipStreamCaptureStatusNone) {
+  auto fallback = [&]() {
     int best = 1, dk = 1 << 30;
     for (const auto& kv : b.gemm_pick)
       if (std::get<0>(kv.first) == a.N && std::get<2>(kv.first) == (int64_t)a.M &&
-          std::abs(std::get<1>(kv.first) - a.K) < dk) {
+          std::abs(std::get<1>(kv.first) - a.K) < dk && gemm_variant_fits(kv.second.pick, a.K)) {
         dk = std::abs(std::get<1>(kv.first) - a.K);
         best = kv.second.pick;
       }
     return best;
+  };
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipStreamIsCapturing(st, &cs);
+  if (!b.gemm_autotune || cs != hipStreamCaptureStatusNone) return fallback();
+  size_t need = 0;
+  if (a.Yf) need = std::max(need, (size_t)a.M * (size_t)a.ldf * 4);
+  if (a.Yb) need = std::max(need, (size_t)a.M * (size_t)a.ldb * 2);
+  if (a.pre) need = std::max(need, (size_t)a.M * (size_t)a.ldp * 4);
+  void* scratch = nullptr;
+  if (need == 0 || hipMalloc(&scratch, need) != hipSuccess) {
+    (void)hipGetLastError();
+    return fallback();
   }
+  GemmArgs t = a;
+  if (t.Yf) t.Yf = (float*)scratch;
+  if (t.Yb) t.Yb = scratch;
+  if (t.pre) t.pre = (float*)scratch;
   hipEvent_t ev[2];
   hipEventCreate(&ev[0]);
   hipEventCreate(&ev[1]);
-  float us[2] = {0.f, 0.f};
-  for (int kind = 0; kind < 2; ++kind) {
-    launch_gemm(kind, a, true, st);
+  GemmPick g;
+  g.pick = 1;
+  g.us.assign(kNumGemmVars, -1.f);
+  for (int kind = 0; kind < kNumGemmVars; ++kind) {
+    if (!gemm_variant_fits(kind, a.K)) continue;
+    launch_gemm(kind, t, true, st);
     hipEventRecord(ev[0], st);
-    for (int r = 0; r < 3; ++r) launch_gemm(kind, a, true, st);
+    for (int r = 0; r < 3; ++r) launch_gemm(kind, t, true, st);
     hipEventRecord(ev[1], st);
     hipEventSynchronize(ev[1]);
     float ms = 0.f;
     hipEventElapsedTime(&ms, ev[0], ev[1]);
-    us[kind] = ms * 1e3f / 3.f;
+    g.us[kind] = ms * 1e3f / 3.f;
+    if (g.us[kind] < g.us[g.pick] || g.us[g.pick] < 0.f) g.pick = kind;
   }
   hipEventDestroy(ev[0]);
   hipEventDestroy(ev[1]);
-  GemmPick g{us[1] <= us[0] ? 1 : 0, us[0], us[1]};
+  hipFree(scratch);
   b.gemm_pick[key] = g;
   return g.pick;
 }
@@ -1477,14 +1766,23 @@ static void gemm(Batch& b, const void* X, int64_t ldx, const NetBufs& NB, const 
   a.act = act;
   const bool bf16 = sizeof(AT) == 2;
   int kind = 0;
-  if (bf16 && w.N > 64 && !b.gemm_small) kind = gemm_choice(b, a, st);
-  const bool timed = b.prof.kind == PROF_GEMM && 2 * (b.prof.used + 1) <= (int)b.prof.ev.size();
+  if (bf16 && w.N > 64)
+    kind = gemm_variant_fits(b.gemm_variant, a.K) ? b.gemm_variant : b.gemm_variant >= 0 ? 0 : gemm_choice(b, a, st);
+  const bool timed = (b.prof.kind == PROF_GEMM || b.prof.kind == PROF_GEMM_BYTES) &&
+                     2 * (b.prof.used + 1) <= (int)b.prof.ev.size();
   if (timed) hipEventRecord(b.prof.ev[2 * b.prof.used], st);
   launch_gemm(kind, a, bf16, st);
   if (timed) {
     hipEventRecord(b.prof.ev[2 * b.prof.used + 1], st);
     b.prof.used++;
-    b.prof.work += 2.0 * (double)M * w.N * w.K;
+    if (b.prof.kind == PROF_GEMM) {
+      b.prof.work += 2.0 * (double)M * w.N * w.K;
+    } else {
+      // algorithmic HBM bytes: X and W once, bias, and each output / residual once
+      const double s = (double)sizeof(AT), mn = (double)M * w.N;
+      b.prof.work += s * ((double)M * w.K + (double)w.N * w.K) + (bias ? 4.0 * w.N : 0.0) + (resid ? 4.0 * mn : 0.0) +
+                     (Yf ? 4.0 * mn : 0.0) + (Yb ? s * mn : 0.0) + (pre ? 4.0 * mn : 0.0);
+    }
   }
 }
 
@@ -1623,8 +1921,8 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
   // highways (Sec. 4.3)
   if (c.highways) {
     if (use_off) {
-      hipLaunchKernelGGL(k_hw_groups, dim3((unsigned)b.ktot), dim3(512), 0, st, fr, b.d_leaf2f, (const float*)N.H,
-                         (const float*)N.Xo, (int)L, (int)LS, N.hrs, N.hcs, N.hhr, N.hhc);
+      hipLaunchKernelGGL(k_hw_groups, dim3((unsigned)b.ktot), dim3(512), 0, st, fr, b.d_leaf2f, (const float*)N.Xo,
+                         (int)LS, N.hrs, N.hcs);
       if (ls)  // the reverse pass reads r and c
         hipLaunchKernelGGL(k_hw_materialize, dim3((unsigned)((Nd + 1) / 2)), dim3(256), 0, st, fr, N.node2f,
                            (const float*)N.H, (const float*)N.hrs, (const float*)N.hcs, (int)L, (int)LS, Nd, N.R,
@@ -1637,9 +1935,6 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
                        (const float*)N.H, (const float*)N.Xo, N.gpart);
     hipLaunchKernelGGL(k_frame_mean, dim3(b.nframes), dim3(512), 0, st, (const int*)N.chunk0,
                        (const float*)N.gpart, (const float*)N.gcount, N.G);
-    if (use_off)
-      hipLaunchKernelGGL(k_hw_context, dim3((unsigned)No), dim3(512), 0, st, fr, N.tile2f, (const float*)N.hhr,
-                         (const float*)N.hhc, (int)L, (int)LS, N.ctxf);
   }
   for (int sidx = 0; sidx < 2; ++sidx) {
     if (sidx == 1 && !use_off) continue;
@@ -1648,10 +1943,19 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
     const int64_t M = sidx ? No : Nd;
     void* u = sidx ? N.uo512 : N.u512;
     void* h = sidx ? N.ho512 : N.h512;
+    if (sidx == 1 && c.highways && N.nstrip > 0) {
+      // context of the off-diagonal tokens from the group sums the diagonal
+      // LayerNorm wrote (taken before the diagonal FFN)
+      hipLaunchKernelGGL(k_hw_strips_lo, dim3((unsigned)N.nstrip, (unsigned)LS), dim3(256), 0, st, fr,
+                         (const int2*)N.strip_tab, (const float*)N.hhr, (const float*)N.hhc, (int)L, (int)LS, N.ctxf,
+                         N.strip_tot);
+      hipLaunchKernelGGL(k_hw_strips_hi, dim3((unsigned)b.nframes, (unsigned)LS), dim3(256), 0, st, fr,
+                         (const int*)N.strip0, (const float*)N.strip_tot, (int)L, (int)LS, N.ctxf);
+    }
     if (sidx == 0 && c.highways && use_off)
-      hipLaunchKernelGGL(k_ln_hw_diag<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, fr, N.node2f,
-                         (const float*)X, (const float*)N.hrs, (const float*)N.hcs, (const float*)N.G, (int)L,
-                         (int)LS, wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, (int)M);
+      hipLaunchKernelGGL(k_ln_hw_diag<AT>, dim3((unsigned)(M / 4)), dim3(256), 0, st, fr, N.node2f, (const float*)X,
+                         (const float*)N.hrs, (const float*)N.hcs, (const float*)N.G, (int)L, (int)LS,
+                         wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, N.hhr, N.hhc);
     else if (sidx == 0)
       hipLaunchKernelGGL(k_ln_concat<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, (const float*)X, d,
                          (const float*)N.R, d, (const float*)N.C, d, (const float*)N.G, (const int*)N.node2f,

@@ -182,24 +182,29 @@ def test_bf16_leaf_attention_matrix_cores_match_vector_alus(cfg, recipe, seed):
     assert e_G <= BF16_BOUND["G"] and e_B <= BF16_BOUND["B"]
 
 
+N_GEMM_VARIANTS = 10  # tile variants the library header lists for "gemm_variant"
+
+
 @pytest.mark.parametrize("cfg,recipe,seed", [(PLAIN, "plain1024", 1000), (DEF, "precision8192", 2000)])
-def test_bf16_wide_gemm_equals_small_tile_gemm(cfg, recipe, seed):
-    """The 128 x 128 double-buffered GEMM runs the same MFMA sequence along K
-    as the 64 x 64 kernel, so the whole BF16 forward is bit-identical."""
+def test_bf16_gemm_tile_variants_are_bit_identical(cfg, recipe, seed):
+    """Every BF16 GEMM tile variant runs the same MFMA sequence along K with
+    the same epilogue, so the whole BF16 forward is bit-identical whichever
+    variant runs."""
     import torch
     w = test_weights(cfg)
     frs = [inputs.make_frame(recipe, seed), inputs.make_frame(recipe, seed + 1)]
     s = Side(cfg, frs, with_net=True)
     wt = torch.tensor(hp.pack_weights(cfg, w), device="cuda")
-    out = {}
-    for small in (1, 0):
-        s.B.debug_set("gemm_small_tiles", small)
+    out = []
+    for v in range(N_GEMM_VARIANTS):
+        s.B.debug_set("gemm_variant", v)
         fac = s.B.new_factors(hp.HP_BF16)
         s.B.infer_factors(wt, s.rho, s.sys, fac, hp.HP_BF16)
         torch.cuda.synchronize()
-        out[small] = (_dbg(s, "xd", (s.B.ntot, cfg.d)), fac.clone())
-    assert np.array_equal(out[0][0], out[1][0])
-    assert torch.equal(out[0][1], out[1][1])
+        out.append((_dbg(s, "xd", (s.B.ntot, cfg.d)), fac.clone()))
+    for v in range(1, N_GEMM_VARIANTS):
+        assert np.array_equal(out[0][0], out[v][0]), v
+        assert torch.equal(out[0][1], out[v][1]), v
 
 
 def test_gemm_autotuner_keeps_results_and_reports_choices():
