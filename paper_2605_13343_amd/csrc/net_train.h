@@ -224,7 +224,7 @@ static hp_status train_grad_t(Batch& b, const float* W, const float* rho, const 
     HP_TRY(layer_fwd<AT>(b, W, sys, l, nullptr));
   }
   // heads (Sec. 4.4) into an FP32 factor set
-  hipLaunchKernelGGL(k_layernorm128<AT>, dim3(gsz(Nd, 4)), dim3(256), 0, st, (const float*)N.H, X.wp("diaglnf.g"),
+  hipLaunchKernelGGL(k_layernorm128<AT>, dim3(gsz(Nd, 16)), dim3(256), 0, st, (const float*)N.H, X.wp("diaglnf.g"),
                      X.wp("diaglnf.b"), (AT*)N.a128, (int)Nd);
   gemm<AT>(b, N.a128, d, N, P.hleaf1, X.wp("hleaf1.b"), nullptr, 0, nullptr, 0, N.b128, d, Nd, 1, T.preh, d);
   gemm<AT>(b, N.b128, d, N, P.hleaf2, X.wp("hleaf2.b"), nullptr, 0, N.Frows, L, nullptr, 0, Nd, 0);
@@ -236,7 +236,7 @@ static hp_status train_grad_t(Batch& b, const float* W, const float* rho, const 
     hipLaunchKernelGGL(k_split_nodeheads<8>, dim3(gsz(Nd)), dim3(256), 0, st, (const float*)N.NH, Nd, T.Ut, T.Vt,
                        T.lam);
   if (use_off) {
-    hipLaunchKernelGGL(k_layernorm128<AT>, dim3(gsz(No, 4)), dim3(256), 0, st, (const float*)N.Xo, X.wp("offlnf.g"),
+    hipLaunchKernelGGL(k_layernorm128<AT>, dim3(gsz(No, 16)), dim3(256), 0, st, (const float*)N.Xo, X.wp("offlnf.g"),
                        X.wp("offlnf.b"), (AT*)N.ao128, (int)No);
     gemm<AT>(b, N.ao128, d, N, P.huv, N.bias_uv, nullptr, 0, N.UV, 2 * LS, nullptr, 0, No, 0);
     if (LS == 16)
@@ -341,9 +341,9 @@ static hp_status train_grad_t(Batch& b, const float* W, const float* rho, const 
     }
     // highway adjoint (Sec. 4.3): r, c, g are means of the streams
     if (c.highways) {
-      hipLaunchKernelGGL(k_chunk_sums, dim3((unsigned)N.nchunks), dim3(128), 0, st, (const SumChunk*)N.chunks,
+      hipLaunchKernelGGL(k_chunk_sums, dim3((unsigned)N.nchunks), dim3(512), 0, st, (const SumChunk*)N.chunks,
                          (const float*)T.dGd, (const float*)T.dGo, N.gpart);
-      hipLaunchKernelGGL(k_frame_mean, dim3(b.nframes), dim3(512), 0, st, (const int*)N.chunk0,
+      hipLaunchKernelGGL(k_frame_mean, dim3(b.nframes), dim3(1024), 0, st, (const int*)N.chunk0,
                          (const float*)N.gpart, (const float*)T.ones, T.dgf);
       if (use_off) {
         hipLaunchKernelGGL(k_pack_ctx, dim3(gsz(No * d)), dim3(256), 0, st, (const float*)T.dao,

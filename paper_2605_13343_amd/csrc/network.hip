@@ -395,22 +395,46 @@ __device__ inline void store8(AT* y, const float (&v)[8]) {
   for (int i = 0; i < 8; ++i) y[i] = to_act<AT>(v[i]);
 }
 
-// One wave per row of C = 128 (eps 1e-5), FP32 in, activation type out; lane
-// l holds columns 2 l and 2 l + 1 (one 8-byte load, one packed store).
+// LayerNorm of rows of C = 128 (eps 1e-5), FP32 in, activation type out.  A
+// wave takes four rows at once (their loads and reductions in flight
+// together); lane l holds columns 2 l and 2 l + 1 of each (one 8-byte load,
+// one packed store).
 template <typename AT>
 __global__ __launch_bounds__(256) void k_layernorm128(const float* X, const float* g, const float* b, AT* Y, int M) {
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (row >= M) return;
-  const float2 x = *(const float2*)(X + (int64_t)row * 128 + 2 * lane);
-  const float mu = wave_sum_f(x.x + x.y) * (1.f / 128.f);
-  const float d0 = x.x - mu, d1 = x.y - mu;
-  const float var = wave_sum_f(d0 * d0 + d1 * d1) * (1.f / 128.f);
-  const float rs = rsqrtf(var + 1e-5f);
-  const float y0 = d0 * rs * g[2 * lane] + b[2 * lane], y1 = d1 * rs * g[2 * lane + 1] + b[2 * lane + 1];
-  if constexpr (sizeof(AT) == 2)
-    *(uint32_t*)(Y + (int64_t)row * 128 + 2 * lane) = pack_bf16x2(y0, y1);
-  else
-    *(float2*)(Y + (int64_t)row * 128 + 2 * lane) = make_float2(y0, y1);
+  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 4, lane = threadIdx.x & 63;
+  if (row0 >= M) return;
+  float2 x[4];
+  float mu[4], var[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    x[r] = row0 + r < M ? *(const float2*)(X + (int64_t)(row0 + r) * 128 + 2 * lane) : make_float2(0.f, 0.f);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) mu[r] = x[r].x + x[r].y;
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) mu[r] += __shfl_xor(mu[r], o, 64);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    mu[r] *= (1.f / 128.f);
+    const float d0 = x[r].x - mu[r], d1 = x[r].y - mu[r];
+    var[r] = d0 * d0 + d1 * d1;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) var[r] += __shfl_xor(var[r], o, 64);
+  }
+  const float g0 = g[2 * lane], g1 = g[2 * lane + 1], b0 = b[2 * lane], b1 = b[2 * lane + 1];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if (row0 + r >= M) break;
+    const float rs = rsqrtf(var[r] * (1.f / 128.f) + 1e-5f);
+    const float y0 = (x[r].x - mu[r]) * rs * g0 + b0, y1 = (x[r].y - mu[r]) * rs * g1 + b1;
+    if constexpr (sizeof(AT) == 2)
+      *(uint32_t*)(Y + (int64_t)(row0 + r) * 128 + 2 * lane) = pack_bf16x2(y0, y1);
+    else
+      *(float2*)(Y + (int64_t)(row0 + r) * 128 + 2 * lane) = make_float2(y0, y1);
+  }
 }
 
 // LayerNorm over the 4d concat [x | a | c | g] (Sec. 4.3: each token joins its
@@ -1177,95 +1201,134 @@ __global__ __launch_bounds__(256) void k_hw_materialize(const FrameDesc* fr, con
   leaf_sides(k, F.J, nr, nc);
   const int64_t gi = (((int64_t)F.k0 + k) * LS + l / p) * 128 + col;
   const float x = Xd[i * 128 + col];
-  R[i * 128 + col] = (x + rs[gi]) / (float)nr;
-  Cc[i * 128 + col] = (x + cs[gi]) / (float)nc;
+  // r = (x + rs) / n_r as a product with the reciprocal, as the diagonal LayerNorm forms it
+  R[i * 128 + col] = (x + rs[gi]) * (1.f / (float)nr);
+  Cc[i * 128 + col] = (x + cs[gi]) * (1.f / (float)nc);
 }
 
 // LN([x | r | c | g]) of the diagonal tokens with r, c formed on the fly from
-// the level sums (one wave per row, as k_ln_concat).  A block's four rows are
-// the p = 4 tokens of one (leaf, sub-strip) group, so the block also writes
-// the group's sums of r and of c (fixed order over the four rows), which the
+// the level sums.  One wave per (leaf, sub-strip) group: its p = 4 rows share
+// the level sums, so the wave loads them once, keeps the four rows in flight
+// together (lane l: segment l / 16 of the concat, 8 features), and also
+// writes the group's sums of r and of c (rows added in order), which the
 // off-diagonal context is built from.
+__device__ inline void wave_sum4(float (&v)[4]) {
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] += __shfl_xor(v[r], o, 64);
+  }
+}
+
 template <typename AT>
 __global__ __launch_bounds__(256) void k_ln_hw_diag(const FrameDesc* fr, const int* node2f, const float* X,
                                                     const float* rs, const float* cs, const float* G, int L, int LS,
-                                                    const float* gam, const float* bet, AT* Y, float* hr, float* hc) {
-  __shared__ float rc[2][4][128];
-  const int w = threadIdx.x >> 6, row = blockIdx.x * 4 + w, lane = threadIdx.x & 63;
-  const int f = node2f[row];
+                                                    const float* gam, const float* bet, AT* Y, float* hr, float* hc,
+                                                    int M) {
+  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 4, lane = threadIdx.x & 63;
+  if (row0 >= M) return;
+  const int f = node2f[row0];
   const FrameDesc F = fr[f];
-  const int c = row - F.n0, k = c / L, l = c % L, p = L / LS;
+  const int c = row0 - F.n0, k = c / L, l = c % L, p = L / LS;
   const int seg = lane >> 4, c0 = (lane & 15) * 8;
-  float v[8];
+  const int64_t grp = ((int64_t)F.k0 + k) * LS + l / p;
+  float v[4][8];
   if (seg == 3) {
-    load8(G + (int64_t)f * 128 + c0, v);
+    load8(G + (int64_t)f * 128 + c0, v[0]);
+#pragma unroll
+    for (int r = 1; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[r][q] = v[0][q];
   } else {
-    load8(X + (int64_t)row * 128 + c0, v);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) load8(X + (int64_t)(row0 + r) * 128 + c0, v[r]);
     if (seg > 0) {
       int nr, nc;
       leaf_sides(k, F.J, nr, nc);
-      const float n = (float)(seg == 1 ? nr : nc);
-      float h[8];
-      load8((seg == 1 ? rs : cs) + (((int64_t)F.k0 + k) * LS + l / p) * 128 + c0, h);
+      const float inv = 1.f / (float)(seg == 1 ? nr : nc);
+      float h[8], o[8];
+      load8((seg == 1 ? rs : cs) + grp * 128 + c0, h);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        v[q] = (v[q] + h[q]) / n;
-        rc[seg - 1][w][c0 + q] = v[q];
-      }
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[r][q] = (v[r][q] + h[q]) * inv;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) o[q] = ((v[0][q] + v[1][q]) + v[2][q]) + v[3][q];
+      float* dst = (seg == 1 ? hr : hc) + grp * 128 + c0;
+      ((float4*)dst)[0] = make_float4(o[0], o[1], o[2], o[3]);
+      ((float4*)dst)[1] = make_float4(o[4], o[5], o[6], o[7]);
     }
   }
-  float sm = 0.f;
+  float mu[4], rsd[4];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) sm += v[q];
-  const float mu = wave_sum_f(sm) * (1.f / 512.f);
-  float qv = 0.f;
+  for (int r = 0; r < 4; ++r) {
+    mu[r] = 0.f;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) qv += (v[q] - mu) * (v[q] - mu);
-  const float rsd = rsqrtf(wave_sum_f(qv) * (1.f / 512.f) + 1e-5f);
+    for (int q = 0; q < 8; ++q) mu[r] += v[r][q];
+  }
+  wave_sum4(mu);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    mu[r] *= (1.f / 512.f);
+    rsd[r] = 0.f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) rsd[r] += (v[r][q] - mu[r]) * (v[r][q] - mu[r]);
+  }
+  wave_sum4(rsd);
   const int gc = seg * 128 + c0;
-  float gm[8], bt[8], o[8];
+  float gm[8], bt[8];
   load8(gam + gc, gm);
   load8(bet + gc, bt);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) o[q] = (v[q] - mu) * rsd * gm[q] + bt[q];
-  store8<AT>(Y + (int64_t)row * 512 + gc, o);
-  __syncthreads();
-  // group sums: thread (side, feature) adds the four rows in order
-  const int side = threadIdx.x >> 7, col = threadIdx.x & 127;
-  const int row0 = blockIdx.x * 4, cg = row0 - F.n0;
-  const int64_t grp = ((int64_t)F.k0 + cg / L) * LS + (cg % L) / p;
-  (side ? hc : hr)[grp * 128 + col] = ((rc[side][0][col] + rc[side][1][col]) + rc[side][2][col]) + rc[side][3][col];
+  for (int r = 0; r < 4; ++r) {
+    const float sd = rsqrtf(rsd[r] * (1.f / 512.f) + 1e-5f);
+    float o[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) o[q] = (v[r][q] - mu[r]) * sd * gm[q] + bt[q];
+    store8<AT>(Y + (int64_t)(row0 + r) * 512 + gc, o);
+  }
 }
 
 // Column sums of 128-wide rows over chunks of at most SUM_CHUNK rows (first
 // stage of the per-frame global token g = mean of all tokens of the frame).
-constexpr int SUM_CHUNK = 32;
+// 512 threads: row group g (4 of them) adds rows g, g + 4, ... of the chunk,
+// then the groups are added in order.
+constexpr int SUM_CHUNK = 64;
 struct SumChunk {
   int frame, kind;  // kind 0: diagonal rows, 1: off-diagonal rows
   int64_t row0;
   int rows;
 };
 
-__global__ __launch_bounds__(128) void k_chunk_sums(const SumChunk* ch, const float* Xd, const float* Xo,
+__global__ __launch_bounds__(512) void k_chunk_sums(const SumChunk* ch, const float* Xd, const float* Xo,
                                                     float* part) {
-  const SumChunk c = ch[blockIdx.x];
-  const float* X = c.kind ? Xo : Xd;
-  float s = 0.f;
-  for (int r = 0; r < c.rows; ++r) s += X[(c.row0 + r) * 128 + threadIdx.x];
-  part[(int64_t)blockIdx.x * 128 + threadIdx.x] = s;
-}
-
-// Per-frame mean from the chunk sums: 4 groups of 128 features, group g adds
-// chunks g, g + 4, ... in order, then the groups are added in order.
-__global__ __launch_bounds__(512) void k_frame_mean(const int* chunk0, const float* part, const float* count,
-                                                    float* G) {
   __shared__ float red[4][128];
-  const int f = blockIdx.x, col = threadIdx.x & 127, g = threadIdx.x >> 7;
+  const SumChunk c = ch[blockIdx.x];
+  const float* X = (c.kind ? Xo : Xd) + c.row0 * 128;
+  const int col = threadIdx.x & 127, g = threadIdx.x >> 7;
   float s = 0.f;
-  for (int c = chunk0[f] + g; c < chunk0[f + 1]; c += 4) s += part[(int64_t)c * 128 + col];
+#pragma unroll 4
+  for (int r = g; r < c.rows; r += 4) s += X[(int64_t)r * 128 + col];
   red[g][col] = s;
   __syncthreads();
-  if (g == 0) G[f * 128 + col] = (red[0][col] + red[1][col] + red[2][col] + red[3][col]) / count[f];
+  if (g == 0) part[(int64_t)blockIdx.x * 128 + col] = ((red[0][col] + red[1][col]) + red[2][col]) + red[3][col];
+}
+
+// Per-frame mean from the chunk sums: 8 groups of 128 features, group g adds
+// chunks g, g + 8, ... in order, then the groups are added in order.
+__global__ __launch_bounds__(1024) void k_frame_mean(const int* chunk0, const float* part, const float* count,
+                                                     float* G) {
+  __shared__ float red[8][128];
+  const int f = blockIdx.x, col = threadIdx.x & 127, g = threadIdx.x >> 7;
+  float s = 0.f;
+  for (int c = chunk0[f] + g; c < chunk0[f + 1]; c += 8) s += part[(int64_t)c * 128 + col];
+  red[g][col] = s;
+  __syncthreads();
+  if (g == 0) {
+    float t = red[0][col];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) t += red[q][col];
+    G[f * 128 + col] = t / count[f];
+  }
 }
 
 // ------------------------------------------------------------------ heads and packing
@@ -1878,7 +1941,7 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
     void* a = sidx ? N.ao128 : N.a128;
     void* q = sidx ? N.qkvo : N.qkv;
     void* o = sidx ? N.bo128 : N.b128;
-    hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, (const float*)X,
+    hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((M + 15) / 16)), dim3(256), 0, st, (const float*)X,
                        wp(p + "ln1.g"), wp(p + "ln1.b"), (AT*)a, (int)M);
     gemm<AT>(b, a, d, N, P.qkv[sidx][l], wp(p + "qkv.b"), nullptr, 0, nullptr, 0, q, 3 * d, M, 0);
     if (sidx == 0) {
@@ -1931,9 +1994,9 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
       HP_HIP(hipMemcpyAsync(N.R, N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
       HP_HIP(hipMemcpyAsync(N.C, N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
     }
-    hipLaunchKernelGGL(k_chunk_sums, dim3((unsigned)N.nchunks), dim3(128), 0, st, (const SumChunk*)N.chunks,
+    hipLaunchKernelGGL(k_chunk_sums, dim3((unsigned)N.nchunks), dim3(512), 0, st, (const SumChunk*)N.chunks,
                        (const float*)N.H, (const float*)N.Xo, N.gpart);
-    hipLaunchKernelGGL(k_frame_mean, dim3(b.nframes), dim3(512), 0, st, (const int*)N.chunk0,
+    hipLaunchKernelGGL(k_frame_mean, dim3(b.nframes), dim3(1024), 0, st, (const int*)N.chunk0,
                        (const float*)N.gpart, (const float*)N.gcount, N.G);
   }
   for (int sidx = 0; sidx < 2; ++sidx) {
@@ -1953,9 +2016,9 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
                          (const int*)N.strip0, (const float*)N.strip_tot, (int)L, (int)LS, N.ctxf);
     }
     if (sidx == 0 && c.highways && use_off)
-      hipLaunchKernelGGL(k_ln_hw_diag<AT>, dim3((unsigned)(M / 4)), dim3(256), 0, st, fr, N.node2f, (const float*)X,
-                         (const float*)N.hrs, (const float*)N.hcs, (const float*)N.G, (int)L, (int)LS,
-                         wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, N.hhr, N.hhc);
+      hipLaunchKernelGGL(k_ln_hw_diag<AT>, dim3((unsigned)((M + 15) / 16)), dim3(256), 0, st, fr, N.node2f,
+                         (const float*)X, (const float*)N.hrs, (const float*)N.hcs, (const float*)N.G, (int)L,
+                         (int)LS, wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, N.hhr, N.hhc, (int)M);
     else if (sidx == 0)
       hipLaunchKernelGGL(k_ln_concat<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, (const float*)X, d,
                          (const float*)N.R, d, (const float*)N.C, d, (const float*)N.G, (const int*)N.node2f,
@@ -1991,7 +2054,7 @@ static hp_status forward(Batch& b, const float* W, const float* rho, const float
   const char* base = (const char*)fac;
   int64_t offs[5], tot;
   factor_offsets(b, sizeof(FT) == 2 ? HP_BF16 : HP_F32, offs, &tot);
-  hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((Nd + 3) / 4)), dim3(256), 0, st, (const float*)N.H,
+  hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((Nd + 15) / 16)), dim3(256), 0, st, (const float*)N.H,
                      wp("diaglnf.g"), wp("diaglnf.b"), (AT*)N.a128, (int)Nd);
   gemm<AT>(b, N.a128, d, N, P.hleaf1, wp("hleaf1.b"), nullptr, 0, nullptr, 0, N.b128, d, Nd, 1);
   gemm<AT>(b, N.b128, d, N, P.hleaf2, wp("hleaf2.b"), nullptr, 0, N.Frows, L, nullptr, 0, Nd, 0);
@@ -2010,7 +2073,7 @@ static hp_status forward(Batch& b, const float* W, const float* rho, const float
                        (const float*)N.NH, Nd, (FT*)(base + offs[2]), (FT*)(base + offs[3]), (float*)(base + offs[4]));
   if (b.mtot > 0) {
     if (use_off) {
-      hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((No + 3) / 4)), dim3(256), 0, st, (const float*)N.Xo,
+      hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((No + 15) / 16)), dim3(256), 0, st, (const float*)N.Xo,
                          wp("offlnf.g"), wp("offlnf.b"), (AT*)N.ao128, (int)No);
       gemm<AT>(b, N.ao128, d, N, P.huv, N.bias_uv, nullptr, 0, N.UV, 2 * LS, nullptr, 0, No, 0);
     } else {
