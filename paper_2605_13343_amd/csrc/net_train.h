@@ -443,7 +443,7 @@ static hp_status train_grad_t(Batch& b, const float* W, const float* rho, const 
   // ---- encoder: GCN layers H += GELU((D^-1 A) H W + b) in reverse, then the MLP
   for (int g = c.gcn - 1; g >= 0; --g) {
     const std::string p = "gcn" + std::to_string(g);
-    hipLaunchKernelGGL(k_gcn_spmm<AT>, dim3((unsigned)((Nd + 1) / 2)), dim3(256), 0, st, fr, N.node2f, sys, b.ntot,
+    hipLaunchKernelGGL(k_gcn_spmm<AT>, dim3((unsigned)((Nd + 7) / 8)), dim3(256), 0, st, fr, N.node2f, sys, b.ntot,
                        (const float*)T.sv.Hg[g], (AT*)N.a128);
     gemm<AT>(b, N.a128, d, N, P.gcn[g], X.wp(p + ".b"), nullptr, 0, nullptr, 0, N.b128, d, Nd, 1, T.preg, d);
     hipLaunchKernelGGL(k_gelu_bwd<AT>, dim3(gsz(Nd * d)), dim3(256), 0, st, (const float*)T.dXd,

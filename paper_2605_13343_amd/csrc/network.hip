@@ -30,6 +30,14 @@ __device__ inline float wave_sum_f(float v) {
   return v;
 }
 
+// Four independent wave sums, their butterflies interleaved.
+__device__ inline void wave_sum4(float (&v)[4]) {
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] += __shfl_xor(v[r], o, 64);
+  }
+}
+
 // ------------------------------------------------------------------ GEMM
 // Y[M, N] = act(X[M, K] W + b) (+ resid), with W given transposed as
 // Wt[N][K] (K contiguous, K % 32 == 0).  64 x 64 block tile, four waves of
@@ -440,43 +448,62 @@ __global__ __launch_bounds__(256) void k_layernorm128(const float* X, const floa
 // LayerNorm over the 4d concat [x | a | c | g] (Sec. 4.3: each token joins its
 // row, column and global highway context before the FFN).  Segment s of row
 // r is read from S_s + r * ld_s (s < 3) or from G + frame * 128; with has_ctx
-// = 0 the three context segments are zero.
+// = 0 the three context segments are zero.  A wave takes four rows at once
+// (lane l: segment l / 16, 8 features of each row).
 template <typename AT>
 __global__ __launch_bounds__(256) void k_ln_concat(const float* S0, int64_t ld0, const float* S1, int64_t ld1,
                                                    const float* S2, int64_t ld2, const float* G, const int* row2f,
                                                    const float* gam, const float* bet, AT* Y, int M, int has_ctx) {
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (row >= M) return;
+  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 4, lane = threadIdx.x & 63;
+  if (row0 >= M) return;
   const int seg = lane >> 4, c0 = (lane & 15) * 8;
-  float v[8];
-  const float* src = nullptr;
-  if (seg == 0) src = S0 + (int64_t)row * ld0;
-  else if (has_ctx) {
-    if (seg == 1) src = S1 + (int64_t)row * ld1;
-    else if (seg == 2) src = S2 + (int64_t)row * ld2;
-    else src = G + (int64_t)row2f[row] * 128;
+  float v[4][8];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = min(row0 + r, M - 1);  // rows past M repeat the last row and are not stored
+    const float* src = nullptr;
+    if (seg == 0) src = S0 + (int64_t)row * ld0;
+    else if (has_ctx) {
+      if (seg == 1) src = S1 + (int64_t)row * ld1;
+      else if (seg == 2) src = S2 + (int64_t)row * ld2;
+      else src = G + (int64_t)row2f[row] * 128;
+    }
+    if (src) {
+      load8(src + c0, v[r]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[r][i] = 0.f;
+    }
   }
-  if (src) {
-    load8(src + c0, v);
-  } else {
+  float mu[4], var[4];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = 0.f;
+  for (int r = 0; r < 4; ++r) {
+    mu[r] = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) mu[r] += v[r][i];
   }
-  float s = 0.f;
+  wave_sum4(mu);
 #pragma unroll
-  for (int i = 0; i < 8; ++i) s += v[i];
-  const float mu = wave_sum_f(s) * (1.f / 512.f);
-  float q = 0.f;
+  for (int r = 0; r < 4; ++r) {
+    mu[r] *= (1.f / 512.f);
+    var[r] = 0.f;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) q += (v[i] - mu) * (v[i] - mu);
-  const float rs = rsqrtf(wave_sum_f(q) * (1.f / 512.f) + 1e-5f);
+    for (int i = 0; i < 8; ++i) var[r] += (v[r][i] - mu[r]) * (v[r][i] - mu[r]);
+  }
+  wave_sum4(var);
   const int gc = seg * 128 + c0;
-  float gm[8], bt[8], o[8];
+  float gm[8], bt[8];
   load8(gam + gc, gm);
   load8(bet + gc, bt);
 #pragma unroll
-  for (int i = 0; i < 8; ++i) o[i] = (v[i] - mu) * rs * gm[i] + bt[i];
-  store8<AT>(Y + (int64_t)row * 512 + gc, o);
+  for (int r = 0; r < 4; ++r) {
+    if (row0 + r >= M) break;
+    const float rs = rsqrtf(var[r] * (1.f / 512.f) + 1e-5f);
+    float o[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) o[i] = (v[r][i] - mu[r]) * rs * gm[i] + bt[i];
+    store8<AT>(Y + (int64_t)(row0 + r) * 512 + gc, o);
+  }
 }
 
 // ------------------------------------------------------------------ features
@@ -575,27 +602,38 @@ __global__ void k_features(const FrameDesc* fr, const int* blk2f, const float* r
 
 // ------------------------------------------------------------------ encoder GCN
 // Y = D^-1 A H: y_i = h_i - sum_j (w_ij / A_ii) h_j over the 6 faces.
-// Two rows per block of 256 threads (one thread per feature).
+// Eight rows per block of 256 threads, 32 threads a row with four features
+// each (16-byte loads of the seven rows involved).
 template <typename AT>
 __global__ __launch_bounds__(256) void k_gcn_spmm(const FrameDesc* fr, const int* node2f, const float* sys,
                                                   int64_t ntot, const float* H, AT* Y) {
-  const int64_t i = (int64_t)blockIdx.x * 2 + (threadIdx.x >> 7);
+  const int64_t i = (int64_t)blockIdx.x * 8 + (threadIdx.x >> 5);
   if (i >= ntot) return;
-  const int col = threadIdx.x & 127;
+  const int col = (threadIdx.x & 31) * 4;
   const FrameDesc F = fr[node2f[i]];
   const unsigned c = (unsigned)(i - F.n0);
   const float *dg = sys, *wx = sys + ntot, *wy = sys + 2 * ntot, *wz = sys + 3 * ntot;
   const float id = 1.f / dg[i];
-  const int64_t xp = F.n0 + mstep_plus(c, F.xm), xn = F.n0 + mstep_minus(c, F.xm);
-  const int64_t yp = F.n0 + mstep_plus(c, F.ym), yn = F.n0 + mstep_minus(c, F.ym);
-  const int64_t zp = F.n0 + mstep_plus(c, F.zm), zn = F.n0 + mstep_minus(c, F.zm);
-  float s = wx[i] * H[xp * 128 + col];
-  s = fmaf(wx[xn], H[xn * 128 + col], s);
-  s = fmaf(wy[i], H[yp * 128 + col], s);
-  s = fmaf(wy[yn], H[yn * 128 + col], s);
-  s = fmaf(wz[i], H[zp * 128 + col], s);
-  s = fmaf(wz[zn], H[zn * 128 + col], s);
-  Y[i * 128 + col] = to_act<AT>(H[i * 128 + col] - s * id);
+  const int64_t nb[6] = {F.n0 + mstep_plus(c, F.xm), F.n0 + mstep_minus(c, F.xm), F.n0 + mstep_plus(c, F.ym),
+                         F.n0 + mstep_minus(c, F.ym), F.n0 + mstep_plus(c, F.zm), F.n0 + mstep_minus(c, F.zm)};
+  const float wv[6] = {wx[i], wx[nb[1]], wy[i], wy[nb[3]], wz[i], wz[nb[5]]};
+  float4 hv[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) hv[q] = *(const float4*)(H + nb[q] * 128 + col);
+  const float4 hi = *(const float4*)(H + i * 128 + col);
+  float y[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    auto comp = [&](const float4& t) { return e == 0 ? t.x : e == 1 ? t.y : e == 2 ? t.z : t.w; };
+    float sum = wv[0] * comp(hv[0]);
+#pragma unroll
+    for (int q = 1; q < 6; ++q) sum = fmaf(wv[q], comp(hv[q]), sum);
+    y[e] = comp(hi) - sum * id;
+  }
+  if constexpr (sizeof(AT) == 2)
+    *(uint2*)(Y + i * 128 + col) = make_uint2(pack_bf16x2(y[0], y[1]), pack_bf16x2(y[2], y[3]));
+  else
+    *(float4*)(Y + i * 128 + col) = make_float4(y[0], y[1], y[2], y[3]);
 }
 
 // ------------------------------------------------------------------ edge-bias MLPs
@@ -619,6 +657,15 @@ __device__ inline void edge_stage(const EdgeW& w, float* sw) {
 // MLP_e(e) from the staged parameters; out[h] for h < H (8 slots).  The
 // hidden units are folded into the output sums one at a time (no hidden
 // array), in the same order as a hidden-then-output evaluation.
+template <bool FAST>
+__device__ inline float edge_gelu(float x) {
+  if constexpr (FAST) return gelu_bf16path(x);
+  else return gelu_f(x);
+}
+
+// FAST: the BF16 path's GELU (the MLP's outputs are attention biases added to
+// logits of BF16 queries and keys); otherwise the library erff.
+template <bool FAST>
 __device__ inline void edge_mlp(const float* sw, int E, int H, const float e[4], float out[8]) {
   const float *w1 = sw, *b1 = sw + 4 * E, *w2 = sw + 5 * E, *b2 = sw + 5 * E + E * H;
 #pragma unroll
@@ -627,7 +674,7 @@ __device__ inline void edge_mlp(const float* sw, int E, int H, const float e[4],
     float s = b1[k];
 #pragma unroll
     for (int q = 0; q < 4; ++q) s = fmaf(e[q], w1[q * E + k], s);
-    const float g = gelu_f(s);
+    const float g = edge_gelu<FAST>(s);
 #pragma unroll
     for (int h = 0; h < 8; ++h)
       if (h < H) out[h] = fmaf(g, w2[k * H + h], out[h]);
@@ -636,6 +683,7 @@ __device__ inline void edge_mlp(const float* sw, int E, int H, const float e[4],
 
 // Within-leaf bias table with A_ij = 0: T0[h][i][j] = MLP_e((pos j - pos i)/4, 0).
 // Every leaf has the same shape, so one table per layer serves all leaves.
+template <bool FAST>
 __global__ void k_edge_table(EdgeW w, int L, unsigned xm, unsigned ym, unsigned zm, float* T0) {
   __shared__ float sw[EDGE_MAX_FLOATS];
   edge_stage(w, sw);
@@ -645,7 +693,7 @@ __global__ void k_edge_table(EdgeW w, int L, unsigned xm, unsigned ym, unsigned 
   float e[4] = {(mcoord(j, xm) - mcoord(i, xm)) * 0.25f, (mcoord(j, ym) - mcoord(i, ym)) * 0.25f,
                 (mcoord(j, zm) - mcoord(i, zm)) * 0.25f, 0.f};
   float o[8];
-  edge_mlp(sw, w.E, w.H, e, o);
+  edge_mlp<FAST>(sw, w.E, w.H, e, o);
   for (int h = 0; h < w.H; ++h) T0[(h * L + i) * L + j] = o[h];
 }
 
@@ -682,34 +730,73 @@ __global__ void k_leaf_stencil(const FrameDesc* fr, const int* node2f, const flo
 
 // Per-layer corrections of the diagonal bias at the stencil entries:
 // corr[i][e][h] = MLP_e(dx_ij/4, Ahat_ij) - MLP_e(dx_ij/4, 0).
-__global__ __launch_bounds__(128) void k_edge_corr(EdgeW w, const uint8_t* nbr, const float* ahat, int64_t ntot,
-                                                   float* corr) {
-  // MLP_e(dx_e, 0) depends on the stencil slot only: 7 evaluations per block
-  __shared__ float base[7][8];
+// Stencil-slot constants of one layer's edge MLP (one block): the first
+// layer's partial sums b1 + dx_e W1[0..2] (cst[e][k], row stride 65) and
+// MLP_e(dx_e, 0) (base[e][h]), for the 7 slots e.
+constexpr int EDGE_CST = 7 * 65 + 7 * 8;
+
+template <bool FAST>
+__global__ __launch_bounds__(256) void k_edge_slots(EdgeW w, float* out) {
   __shared__ float sw[EDGE_MAX_FLOATS];
   edge_stage(w, sw);
+  const int E = w.E, H = w.H;
+  const float *w1 = sw, *b1 = sw + 4 * E;
+  auto slot_dx = [](int e, float (&d)[3]) {
+    d[0] = d[1] = d[2] = 0.f;
+    if (e > 0) d[(e - 1) / 2] = ((e - 1) % 2 == 0) ? 0.25f : -0.25f;
+  };
+  for (int q = threadIdx.x; q < 7 * E; q += blockDim.x) {
+    const int e = q / E, k = q % E;
+    float d[3];
+    slot_dx(e, d);
+    float sv = b1[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sv = fmaf(d[c], w1[c * E + k], sv);
+    out[e * 65 + k] = sv;
+  }
   if (threadIdx.x < 7) {
     const int e = threadIdx.x;
-    float d[3] = {0.f, 0.f, 0.f};
-    if (e > 0) d[(e - 1) / 2] = ((e - 1) % 2 == 0) ? 0.25f : -0.25f;
+    float d[3], o[8];
+    slot_dx(e, d);
     const float e0[4] = {d[0], d[1], d[2], 0.f};
-    edge_mlp(sw, w.E, w.H, e0, base[e]);
+    edge_mlp<FAST>(sw, E, H, e0, o);
+    for (int h = 0; h < 8; ++h) out[7 * 65 + e * 8 + h] = h < H ? o[h] : 0.f;
   }
-  __syncthreads();
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= ntot * 7) return;
-  const int e = (int)(p % 7);
-  float* o = corr + p * w.H;
-  if (nbr[p] == 255) {
-    for (int h = 0; h < w.H; ++h) o[h] = 0.f;
-    return;
+}
+
+// Stencil corrections MLP_e(dx_e, Ahat) - MLP_e(dx_e, 0) of every (node,
+// slot) pair, the same operations as edge_mlp with the first three input
+// terms taken from the slot constants; grid-stride over pairs.
+template <bool FAST>
+__global__ __launch_bounds__(256) void k_edge_corr(EdgeW w, const float* slots, const uint8_t* nbr, const float* ahat,
+                                                   int64_t ntot, float* corr) {
+  __shared__ float cst[EDGE_CST];
+  __shared__ float sw[EDGE_MAX_FLOATS];
+  for (int q = threadIdx.x; q < EDGE_CST; q += blockDim.x) cst[q] = slots[q];
+  edge_stage(w, sw);  // ends with a barrier
+  const int E = w.E, H = w.H;
+  const float *w1 = sw, *w2 = sw + 5 * E, *b2 = sw + 5 * E + E * H;
+  const float* base = cst + 7 * 65;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < ntot * 7;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int e = (int)(p % 7);
+    float* o = corr + p * H;
+    if (nbr[p] == 255) {
+      for (int h = 0; h < H; ++h) o[h] = 0.f;
+      continue;
+    }
+    const float a = ahat[p];
+    float out[8];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) out[h] = h < H ? b2[h] : 0.f;
+    for (int k = 0; k < E; ++k) {
+      const float g = edge_gelu<FAST>(fmaf(a, w1[3 * E + k], cst[e * 65 + k]));
+#pragma unroll
+      for (int h = 0; h < 8; ++h)
+        if (h < H) out[h] = fmaf(g, w2[k * H + h], out[h]);
+    }
+    for (int h = 0; h < H; ++h) o[h] = out[h] - base[e * 8 + h];
   }
-  float d[3] = {0.f, 0.f, 0.f};
-  if (e > 0) d[(e - 1) / 2] = ((e - 1) % 2 == 0) ? 0.25f : -0.25f;
-  const float e1[4] = {d[0], d[1], d[2], ahat[p]};
-  float a[8];
-  edge_mlp(sw, w.E, w.H, e1, a);
-  for (int h = 0; h < w.H; ++h) o[h] = a[h] - base[e][h];
 }
 
 // Off-diagonal pair descriptors (Supplementary "Off-diagonal attention
@@ -792,6 +879,7 @@ __global__ __launch_bounds__(256) void k_off_desc_final(const FrameDesc* fr, con
 }
 
 // Off-diagonal bias per layer: bias[m][h][t][t'] = MLP_e(desc[m][t][t']).
+template <bool FAST>
 __global__ void k_edge_off(EdgeW w, const float* desc, int64_t npairs, int LS, float* bias) {
   __shared__ float sw[EDGE_MAX_FLOATS];
   edge_stage(w, sw);
@@ -801,7 +889,7 @@ __global__ void k_edge_off(EdgeW w, const float* desc, int64_t npairs, int LS, f
   const int tt = (int)(p % (LS * LS));
   float e[4] = {desc[p * 4], desc[p * 4 + 1], desc[p * 4 + 2], desc[p * 4 + 3]};
   float o[8];
-  edge_mlp(sw, w.E, w.H, e, o);
+  edge_mlp<FAST>(sw, w.E, w.H, e, o);
   for (int h = 0; h < w.H; ++h) bias[(m * w.H + h) * LS * LS + tt] = o[h];
 }
 
@@ -1212,12 +1300,6 @@ __global__ __launch_bounds__(256) void k_hw_materialize(const FrameDesc* fr, con
 // together (lane l: segment l / 16 of the concat, 8 features), and also
 // writes the group's sums of r and of c (rows added in order), which the
 // off-diagonal context is built from.
-__device__ inline void wave_sum4(float (&v)[4]) {
-  for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) v[r] += __shfl_xor(v[r], o, 64);
-  }
-}
 
 template <typename AT>
 __global__ __launch_bounds__(256) void k_ln_hw_diag(const FrameDesc* fr, const int* node2f, const float* X,
@@ -1537,6 +1619,7 @@ struct NetBufs {
   void *ctx = nullptr, *ao128 = nullptr, *bo128 = nullptr, *qkvo = nullptr, *uo512 = nullptr, *ho512 = nullptr;
   float *ctxf = nullptr;
   float *hrs = nullptr, *hcs = nullptr, *hhr = nullptr, *hhc = nullptr;  // highway group sums [ktot L_s][128]
+  float* eslots = nullptr;     // edge-MLP stencil-slot constants of the current layer [EDGE_CST]
   int2* strip_tab = nullptr;   // (frame, chunk) of the context tree's lower levels
   int nstrip = 0;
   int* strip0 = nullptr;       // first chunk of each frame [nframes]
@@ -1603,6 +1686,7 @@ hp_status network_alloc(Batch& b) {
     for (int q = 0; q < b.fr[f].K / C; ++q) stab.push_back(make_int2(f, q));
   }
   N->nstrip = (int)stab.size();
+  A(&N->eslots, EDGE_CST * 4);
   A(&N->strip_tab, std::max<size_t>(stab.size(), 1) * sizeof(int2));
   A(&N->strip0, std::max(b.nframes, 1) * 4);
   A(&N->strip_tot, std::max<size_t>(stab.size(), 1) * c.rank * 2 * d * 4);
@@ -1892,7 +1976,7 @@ static hp_status fwd_prologue(Batch& b, const float* W, const float* rho, const 
   gemm<AT>(b, N.a128, d, N, P.enc2, wp("enc2.b"), nullptr, 0, N.H, d, N.b128, d, Nd, 0);
   for (int g = 0; g < c.gcn; ++g) {
     if (sv) HP_HIP(hipMemcpyAsync(sv->Hg[g], N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_gcn_spmm<AT>, dim3((unsigned)((Nd + 1) / 2)), dim3(256), 0, st, fr, N.node2f, sys, b.ntot,
+    hipLaunchKernelGGL(k_gcn_spmm<AT>, dim3((unsigned)((Nd + 7) / 8)), dim3(256), 0, st, fr, N.node2f, sys, b.ntot,
                        (const float*)N.H, (AT*)N.a128);
     gemm<AT>(b, N.a128, d, N, P.gcn[g], wp("gcn" + std::to_string(g) + ".b"), N.H, d, N.H, d, N.b128, d, Nd, 1);
   }
@@ -1945,10 +2029,12 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
                        wp(p + "ln1.g"), wp(p + "ln1.b"), (AT*)a, (int)M);
     gemm<AT>(b, a, d, N, P.qkv[sidx][l], wp(p + "qkv.b"), nullptr, 0, nullptr, 0, q, 3 * d, M, 0);
     if (sidx == 0) {
-      hipLaunchKernelGGL(k_edge_table, dim3((unsigned)((L * L + 63) / 64)), dim3(64), 0, st, ew, (int)L,
+      hipLaunchKernelGGL(k_edge_table<sizeof(AT) == 2>, dim3((unsigned)((L * L + 63) / 64)), dim3(64), 0, st, ew, (int)L,
                          F0.xm & lowmask, F0.ym & lowmask, F0.zm & lowmask, N.T0);
-      hipLaunchKernelGGL(k_edge_corr, dim3((unsigned)((Nd * 7 + 127) / 128)), dim3(128), 0, st, ew,
-                         (const uint8_t*)N.nbr, (const float*)N.ahat, Nd, N.corr);
+      hipLaunchKernelGGL(k_edge_slots<sizeof(AT) == 2>, dim3(1), dim3(256), 0, st, ew, N.eslots);
+      hipLaunchKernelGGL(k_edge_corr<sizeof(AT) == 2>,
+                         dim3((unsigned)std::min<int64_t>((Nd * 7 + 1023) / 1024, 4096)), dim3(256), 0, st, ew,
+                         (const float*)N.eslots, (const uint8_t*)N.nbr, (const float*)N.ahat, Nd, N.corr);
       if (sizeof(AT) == 2 && !b.attn_valu) {
         if (L == 64)
           hipLaunchKernelGGL(k_attention_mfma<64>, dim3((unsigned)b.ktot), dim3(256), 0, st, (const uint16_t*)q,
@@ -1967,7 +2053,7 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
       }
     } else {
       const int64_t npairs = b.mtot * LS * LS;
-      hipLaunchKernelGGL(k_edge_off, dim3((unsigned)((npairs + 127) / 128)), dim3(128), 0, st, ew,
+      hipLaunchKernelGGL(k_edge_off<sizeof(AT) == 2>, dim3((unsigned)((npairs + 127) / 128)), dim3(128), 0, st, ew,
                          (const float*)N.desc, npairs, (int)LS, N.boff);
       if (sizeof(AT) == 2 && LS == 16 && !b.attn_valu)
         hipLaunchKernelGGL(k_attention_tile_mfma, dim3((unsigned)b.mtot), dim3(256), 0, st, (const uint16_t*)q,
@@ -2020,11 +2106,11 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
                          (const float*)X, (const float*)N.hrs, (const float*)N.hcs, (const float*)N.G, (int)L,
                          (int)LS, wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, N.hhr, N.hhc, (int)M);
     else if (sidx == 0)
-      hipLaunchKernelGGL(k_ln_concat<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, (const float*)X, d,
+      hipLaunchKernelGGL(k_ln_concat<AT>, dim3((unsigned)((M + 15) / 16)), dim3(256), 0, st, (const float*)X, d,
                          (const float*)N.R, d, (const float*)N.C, d, (const float*)N.G, (const int*)N.node2f,
                          wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, (int)M, c.highways);
     else
-      hipLaunchKernelGGL(k_ln_concat<AT>, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, st, (const float*)X, d,
+      hipLaunchKernelGGL(k_ln_concat<AT>, dim3((unsigned)((M + 15) / 16)), dim3(256), 0, st, (const float*)X, d,
                          (const float*)N.ctxf, 2 * d, (const float*)(N.ctxf + d), 2 * d, (const float*)N.G,
                          (const int*)N.tok2f, wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, (int)M, c.highways);
     if (ls) HP_HIP(hipMemcpyAsync(sidx ? ls->xmid_o : ls->xmid_d, X, M * d * 4, hipMemcpyDeviceToDevice, st));
