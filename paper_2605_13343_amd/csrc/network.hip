@@ -681,12 +681,49 @@ __device__ inline void edge_mlp(const float* sw, int E, int H, const float e[4],
   }
 }
 
+// Stencil-slot constants of one layer's edge MLP, computed by one block: the
+// first layer's partial sums b1 + dx_e W1[0..2] (cst[e][k], row stride 65)
+// and MLP_e(dx_e, 0) (base[e][h]), for the 7 slots e.
+constexpr int EDGE_CST = 7 * 65 + 7 * 8;
+
+template <bool FAST>
+__device__ inline void edge_slot_consts(const float* sw, int E, int H, float* out) {
+  const float *w1 = sw, *b1 = sw + 4 * E;
+  auto slot_dx = [](int e, float (&d)[3]) {
+    d[0] = d[1] = d[2] = 0.f;
+    if (e > 0) d[(e - 1) / 2] = ((e - 1) % 2 == 0) ? 0.25f : -0.25f;
+  };
+  for (int q = threadIdx.x; q < 7 * E; q += blockDim.x) {
+    const int e = q / E, k = q % E;
+    float d[3];
+    slot_dx(e, d);
+    float sv = b1[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sv = fmaf(d[c], w1[c * E + k], sv);
+    out[e * 65 + k] = sv;
+  }
+  if (threadIdx.x < 7) {
+    const int e = threadIdx.x;
+    float d[3], o[8];
+    slot_dx(e, d);
+    const float e0[4] = {d[0], d[1], d[2], 0.f};
+    edge_mlp<FAST>(sw, E, H, e0, o);
+    for (int h = 0; h < 8; ++h) out[7 * 65 + e * 8 + h] = h < H ? o[h] : 0.f;
+  }
+}
+
 // Within-leaf bias table with A_ij = 0: T0[h][i][j] = MLP_e((pos j - pos i)/4, 0).
 // Every leaf has the same shape, so one table per layer serves all leaves.
+// The block after the table's blocks writes the stencil-slot constants.
 template <bool FAST>
-__global__ void k_edge_table(EdgeW w, int L, unsigned xm, unsigned ym, unsigned zm, float* T0) {
+__global__ __launch_bounds__(256) void k_edge_table(EdgeW w, int L, unsigned xm, unsigned ym, unsigned zm, float* T0,
+                                                    float* slots) {
   __shared__ float sw[EDGE_MAX_FLOATS];
   edge_stage(w, sw);
+  if (blockIdx.x == gridDim.x - 1) {
+    edge_slot_consts<FAST>(sw, w.E, w.H, slots);
+    return;
+  }
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= L * L) return;
   const int i = p / L, j = p % L;
@@ -730,40 +767,6 @@ __global__ void k_leaf_stencil(const FrameDesc* fr, const int* node2f, const flo
 
 // Per-layer corrections of the diagonal bias at the stencil entries:
 // corr[i][e][h] = MLP_e(dx_ij/4, Ahat_ij) - MLP_e(dx_ij/4, 0).
-// Stencil-slot constants of one layer's edge MLP (one block): the first
-// layer's partial sums b1 + dx_e W1[0..2] (cst[e][k], row stride 65) and
-// MLP_e(dx_e, 0) (base[e][h]), for the 7 slots e.
-constexpr int EDGE_CST = 7 * 65 + 7 * 8;
-
-template <bool FAST>
-__global__ __launch_bounds__(256) void k_edge_slots(EdgeW w, float* out) {
-  __shared__ float sw[EDGE_MAX_FLOATS];
-  edge_stage(w, sw);
-  const int E = w.E, H = w.H;
-  const float *w1 = sw, *b1 = sw + 4 * E;
-  auto slot_dx = [](int e, float (&d)[3]) {
-    d[0] = d[1] = d[2] = 0.f;
-    if (e > 0) d[(e - 1) / 2] = ((e - 1) % 2 == 0) ? 0.25f : -0.25f;
-  };
-  for (int q = threadIdx.x; q < 7 * E; q += blockDim.x) {
-    const int e = q / E, k = q % E;
-    float d[3];
-    slot_dx(e, d);
-    float sv = b1[k];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) sv = fmaf(d[c], w1[c * E + k], sv);
-    out[e * 65 + k] = sv;
-  }
-  if (threadIdx.x < 7) {
-    const int e = threadIdx.x;
-    float d[3], o[8];
-    slot_dx(e, d);
-    const float e0[4] = {d[0], d[1], d[2], 0.f};
-    edge_mlp<FAST>(sw, E, H, e0, o);
-    for (int h = 0; h < 8; ++h) out[7 * 65 + e * 8 + h] = h < H ? o[h] : 0.f;
-  }
-}
-
 // Stencil corrections MLP_e(dx_e, Ahat) - MLP_e(dx_e, 0) of every (node,
 // slot) pair, the same operations as edge_mlp with the first three input
 // terms taken from the slot constants; grid-stride over pairs.
@@ -1168,6 +1171,10 @@ __global__ __launch_bounds__(256) void k_attention_tile_mfma(const uint16_t* qkv
   }
 }
 
+// Leaves per chunk of the highway trees (levels below the chunk size are
+// handled in registers).
+constexpr int STRIP_CHUNK = 16;
+
 // Highway buffers of the diagonal tokens (Sec. 4.3): r_i (c_i) is the mean of
 // the diagonal token i and of every off-diagonal token whose row (column)
 // sub-strip contains i.  Leaf k sits at level j in tile K - K/2^j + (k >> (j+1))
@@ -1177,10 +1184,13 @@ __global__ __launch_bounds__(256) void k_attention_tile_mfma(const uint16_t* qkv
 // per group:  rs (cs) = sum over the levels where the leaf is on the row
 // (column) side of token t of that level's tile.  Then r_i = (x_i + rs) / n_r
 // and c_i = (x_i + cs) / n_c, with n_r (n_c) = 1 + the number of row (column)
-// levels of the leaf; and the group sums of r and c, hr = (gx + p rs) / n_r
-// and hc = (gx + p cs) / n_c with gx the sum of the p diagonal tokens, feed
-// the off-diagonal tokens' context.
-// One block per leaf: 4 groups of sub-strips x 128 features.
+// levels of the leaf; the group sums of r and c feed the off-diagonal
+// tokens' context.
+// rs is a root-to-leaf path sum: with u = k >> j the level-j ancestor of
+// leaf k, R_j(u) = R_{j+1}(u >> 1) + [u even] Xo(tile (j, u >> 1), t), R_J =
+// 0, rs = R_0 (cs alike with [u odd]).  Upper levels (2^j >= C = min(16, K)):
+// per (frame, t), R at each aligned chunk of C leaves; lower levels: per
+// (chunk, t), down to the leaves in registers.  Levels are added top-down.
 __device__ inline void leaf_sides(int k, int J, int& nr, int& nc) {
   nr = 1;
   nc = 1;
@@ -1190,23 +1200,48 @@ __device__ inline void leaf_sides(int k, int J, int& nr, int& nc) {
   }
 }
 
-__global__ __launch_bounds__(512) void k_hw_groups(const FrameDesc* fr, const int* leaf2f, const float* Xo, int LS,
-                                                   float* rs, float* cs) {
-  const int64_t kg = blockIdx.x;
-  const FrameDesc F = fr[leaf2f[kg]];
-  const int k = (int)(kg - F.k0), K = F.K, col = threadIdx.x & 127;
-  for (int t = threadIdx.x >> 7; t < LS; t += 4) {
-    float r = 0.f, c = 0.f;
-    for (int j = 0; j < F.J; ++j) {
-      const int m = K - (K >> j) + (k >> (j + 1));
-      const float v = Xo[((int64_t)(F.m0 + m) * LS + t) * 128 + col];
-      if (((k >> j) & 1) == 0) r += v;
-      else c += v;
+__global__ __launch_bounds__(256) void k_hw_levels_hi(const FrameDesc* fr, const int* chunk0, const float* Xo,
+                                                      int LS, float* top) {
+  const int f = blockIdx.x, t = blockIdx.y, side = threadIdx.x >> 7, col = threadIdx.x & 127;
+  const FrameDesc F = fr[f];
+  const int K = F.K, C = min(STRIP_CHUNK, K);
+  int jc = 0;
+  while ((1 << jc) < C) ++jc;  // C = 2^jc
+  for (int q = 0; q < K / C; ++q) {
+    float R = 0.f;
+    for (int j = F.J - 1; j >= jc; --j) {
+      const int u = q >> (j - jc);
+      if ((u & 1) == side) R += Xo[((int64_t)(F.m0 + K - (K >> j) + (u >> 1)) * LS + t) * 128 + col];
     }
-    const int64_t o = (kg * LS + t) * 128 + col;
-    rs[o] = r;
-    cs[o] = c;
+    top[(((int64_t)chunk0[f] + q) * LS + t) * 256 + 128 * side + col] = R;
   }
+}
+
+__global__ __launch_bounds__(256) void k_hw_levels_lo(const FrameDesc* fr, const int2* tab, const float* top,
+                                                      const float* Xo, int LS, float* rs, float* cs) {
+  const int2 e = tab[blockIdx.x];
+  const int t = blockIdx.y, side = threadIdx.x >> 7, col = threadIdx.x & 127;
+  const FrameDesc F = fr[e.x];
+  const int K = F.K, C = min(STRIP_CHUNK, K), leaf0 = e.y * C;
+  float v[STRIP_CHUNK];
+  v[0] = top[(((int64_t)blockIdx.x) * LS + t) * 256 + 128 * side + col];
+  // level j: node i (local, descending so the parent v[i >> 1] is still the level-(j+1) value)
+#pragma unroll
+  for (int j = 3; j >= 0; --j) {
+    if ((C >> j) < 2) continue;  // level j lies above the chunk
+#pragma unroll
+    for (int i = (STRIP_CHUNK >> j) - 1; i >= 0; --i) {
+      if (i >= (C >> j)) continue;
+      const int u = (leaf0 >> j) + i;
+      float x = v[i >> 1];
+      if ((u & 1) == side) x += Xo[((int64_t)(F.m0 + K - (K >> j) + (u >> 1)) * LS + t) * 128 + col];
+      v[i] = x;
+    }
+  }
+  float* out = side ? cs : rs;
+#pragma unroll
+  for (int q = 0; q < STRIP_CHUNK; ++q)
+    if (q < C) out[(((int64_t)F.k0 + leaf0 + q) * LS + t) * 128 + col] = v[q];
 }
 
 // Off-diagonal token context (the mean of r over I_m^t and of c over J_m^t)
@@ -1219,7 +1254,6 @@ __global__ __launch_bounds__(512) void k_hw_groups(const FrameDesc* fr, const in
 // in registers, writes the context of every tile that lies inside the chunk,
 // and the chunk total.  Upper levels (2 S > C): per (frame, t), strip sums
 // of the chunk totals in chunk order.  Each context entry is divided by S p.
-constexpr int STRIP_CHUNK = 16;
 
 // One level of the chunk tree: the context of the level's tiles inside the
 // chunk (v holds the blocks of size S), then the fold to blocks of size 2 S.
@@ -1620,6 +1654,10 @@ struct NetBufs {
   float *ctxf = nullptr;
   float *hrs = nullptr, *hcs = nullptr, *hhr = nullptr, *hhc = nullptr;  // highway group sums [ktot L_s][128]
   float* eslots = nullptr;     // edge-MLP stencil-slot constants of the current layer [EDGE_CST]
+  int2* lvl_tab = nullptr;     // (frame, chunk) of every frame's leaves, for the level sums
+  int nlvl = 0;
+  int* lvl0 = nullptr;         // first chunk of each frame [nframes]
+  float* lvl_top = nullptr;    // level sums above each chunk [nlvl][L_s][2][128]
   int2* strip_tab = nullptr;   // (frame, chunk) of the context tree's lower levels
   int nstrip = 0;
   int* strip0 = nullptr;       // first chunk of each frame [nframes]
@@ -1687,6 +1725,17 @@ hp_status network_alloc(Batch& b) {
   }
   N->nstrip = (int)stab.size();
   A(&N->eslots, EDGE_CST * 4);
+  std::vector<int2> ltab;
+  std::vector<int> lvl0(b.nframes, 0);
+  for (int f = 0; f < b.nframes; ++f) {
+    lvl0[f] = (int)ltab.size();
+    const int C = std::min(STRIP_CHUNK, b.fr[f].K);
+    for (int q = 0; q < b.fr[f].K / C; ++q) ltab.push_back(make_int2(f, q));
+  }
+  N->nlvl = (int)ltab.size();
+  A(&N->lvl_tab, std::max<size_t>(ltab.size(), 1) * sizeof(int2));
+  A(&N->lvl0, std::max(b.nframes, 1) * 4);
+  A(&N->lvl_top, std::max<size_t>(ltab.size(), 1) * c.rank * 2 * d * 4);
   A(&N->strip_tab, std::max<size_t>(stab.size(), 1) * sizeof(int2));
   A(&N->strip0, std::max(b.nframes, 1) * 4);
   A(&N->strip_tot, std::max<size_t>(stab.size(), 1) * c.rank * 2 * d * 4);
@@ -1769,6 +1818,8 @@ hp_status network_alloc(Batch& b) {
   up(N->chunks, ch.data(), ch.size() * sizeof(SumChunk));
   if (!stab.empty()) up(N->strip_tab, stab.data(), stab.size() * sizeof(int2));
   if (b.nframes > 0) up(N->strip0, strip0.data(), strip0.size() * 4);
+  if (!ltab.empty()) up(N->lvl_tab, ltab.data(), ltab.size() * sizeof(int2));
+  if (b.nframes > 0) up(N->lvl0, lvl0.data(), lvl0.size() * 4);
   if (!dch.empty()) up(N->desc_chunks, dch.data(), dch.size() * sizeof(DescChunk));
   up(N->desc_chunk0, dch0.data(), dch0.size() * sizeof(int));
   up(N->gcount, cnt.data(), cnt.size() * 4);
@@ -2029,9 +2080,8 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
                        wp(p + "ln1.g"), wp(p + "ln1.b"), (AT*)a, (int)M);
     gemm<AT>(b, a, d, N, P.qkv[sidx][l], wp(p + "qkv.b"), nullptr, 0, nullptr, 0, q, 3 * d, M, 0);
     if (sidx == 0) {
-      hipLaunchKernelGGL(k_edge_table<sizeof(AT) == 2>, dim3((unsigned)((L * L + 63) / 64)), dim3(64), 0, st, ew, (int)L,
-                         F0.xm & lowmask, F0.ym & lowmask, F0.zm & lowmask, N.T0);
-      hipLaunchKernelGGL(k_edge_slots<sizeof(AT) == 2>, dim3(1), dim3(256), 0, st, ew, N.eslots);
+      hipLaunchKernelGGL(k_edge_table<sizeof(AT) == 2>, dim3((unsigned)((L * L + 255) / 256 + 1)), dim3(256), 0, st,
+                         ew, (int)L, F0.xm & lowmask, F0.ym & lowmask, F0.zm & lowmask, N.T0, N.eslots);
       hipLaunchKernelGGL(k_edge_corr<sizeof(AT) == 2>,
                          dim3((unsigned)std::min<int64_t>((Nd * 7 + 1023) / 1024, 4096)), dim3(256), 0, st, ew,
                          (const float*)N.eslots, (const uint8_t*)N.nbr, (const float*)N.ahat, Nd, N.corr);
@@ -2070,8 +2120,10 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
   // highways (Sec. 4.3)
   if (c.highways) {
     if (use_off) {
-      hipLaunchKernelGGL(k_hw_groups, dim3((unsigned)b.ktot), dim3(512), 0, st, fr, b.d_leaf2f, (const float*)N.Xo,
-                         (int)LS, N.hrs, N.hcs);
+      hipLaunchKernelGGL(k_hw_levels_hi, dim3((unsigned)b.nframes, (unsigned)LS), dim3(256), 0, st, fr,
+                         (const int*)N.lvl0, (const float*)N.Xo, (int)LS, N.lvl_top);
+      hipLaunchKernelGGL(k_hw_levels_lo, dim3((unsigned)N.nlvl, (unsigned)LS), dim3(256), 0, st, fr,
+                         (const int2*)N.lvl_tab, (const float*)N.lvl_top, (const float*)N.Xo, (int)LS, N.hrs, N.hcs);
       if (ls)  // the reverse pass reads r and c
         hipLaunchKernelGGL(k_hw_materialize, dim3((unsigned)((Nd + 1) / 2)), dim3(256), 0, st, fr, N.node2f,
                            (const float*)N.H, (const float*)N.hrs, (const float*)N.hcs, (int)L, (int)LS, Nd, N.R,
