@@ -1010,6 +1010,8 @@ __global__ __launch_bounds__(256) void k_attention_mfma(const uint16_t* qkv, uin
                                                        const float* corr, const uint8_t* nbr) {
   constexpr int DH = 32, H = 4, D = H * DH, NT = T / 32, VP = T + 8;
   __shared__ __attribute__((aligned(16))) uint16_t sVt[H][DH][VP];
+  // stencil corrections of the current query tile as a dense row per query
+  __shared__ __attribute__((aligned(16))) float sC[H][32][T + 4];
   const int h = threadIdx.x >> 6, lane = threadIdx.x & 63, hh = lane >> 5, c32 = lane & 31;
   const int64_t row0 = (int64_t)blockIdx.x * T;
   const uint16_t* base = qkv + row0 * 3 * D + h * DH;
@@ -1050,13 +1052,19 @@ __global__ __launch_bounds__(256) void k_attention_mfma(const uint16_t* qkv, uin
     const int q = 32 * b + c32;
     const int64_t row = row0 + q;
     const float* bt = T0 + ((int64_t)h * T + q) * T;
-    int lj[7];
-    float cv[7];
+    // the query's row of corrections: zero its half, then the half-wave hh
+    // writes neighbours e = 4 hh .. (distinct neighbours have distinct keys)
 #pragma unroll
-    for (int e = 0; e < 7; ++e) {
-      lj[e] = nbr[row * 7 + e];
-      cv[e] = corr[(row * 7 + e) * H + h];
+    for (int z = 0; z < T / 8; ++z) *(float4*)&sC[h][c32][hh * (T / 2) + 4 * z] = make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+#pragma unroll
+    for (int e = 4 * hh; e < 4 * hh + 4; ++e) {
+      if (e < 7) {
+        const int lj = nbr[row * 7 + e];
+        if (lj != 255) sC[h][c32][lj] = corr[(row * 7 + e) * H + h];
+      }
     }
+    __syncthreads();
     float mx = -3.4e38f;
 #pragma unroll
     for (int a = 0; a < NT; ++a)
@@ -1064,12 +1072,11 @@ __global__ __launch_bounds__(256) void k_attention_mfma(const uint16_t* qkv, uin
       for (int i = 0; i < 4; ++i) {
         const int k0 = 32 * a + 8 * i + 4 * hh;
         const float4 bv = *(const float4*)(bt + k0);
-        const float bj[4] = {bv.x, bv.y, bv.z, bv.w};
+        const float4 cw = *(const float4*)&sC[h][c32][k0];
+        const float bj[4] = {bv.x + cw.x, bv.y + cw.y, bv.z + cw.z, bv.w + cw.w};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          float v = fmaf(S[a][4 * i + j], scale, bj[j]);
-#pragma unroll
-          for (int e = 0; e < 7; ++e) v += (lj[e] == k0 + j) ? cv[e] : 0.f;
+          const float v = fmaf(S[a][4 * i + j], scale, bj[j]);
           S[a][4 * i + j] = v;
           mx = fmaxf(mx, v);
         }
@@ -1080,7 +1087,7 @@ __global__ __launch_bounds__(256) void k_attention_mfma(const uint16_t* qkv, uin
     for (int a = 0; a < NT; ++a)
 #pragma unroll
       for (int q2 = 0; q2 < 16; ++q2) {
-        const float p = expf(S[a][q2] - mx);
+        const float p = __expf(S[a][q2] - mx);  // P is rounded to BF16 for the product below
         S[a][q2] = p;
         sum += p;
       }
@@ -1098,21 +1105,18 @@ __global__ __launch_bounds__(256) void k_attention_mfma(const uint16_t* qkv, uin
         *(uint2*)&vv[0] = *(const uint2*)&sVt[h][c32][kb];
         *(uint2*)&vv[4] = *(const uint2*)&sVt[h][c32][kb + 8];
         vb = __builtin_bit_cast(bf16x8_t, *(const uint4*)vv);
-        uint16_t pp[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) pp[e] = f32_to_bf16(S[a][8 * s + e]);
-        pb = __builtin_bit_cast(bf16x8_t, *(const uint4*)pp);
+        const uint4 pw = make_uint4(pack_bf16x2(S[a][8 * s], S[a][8 * s + 1]), pack_bf16x2(S[a][8 * s + 2], S[a][8 * s + 3]),
+                                    pack_bf16x2(S[a][8 * s + 4], S[a][8 * s + 5]),
+                                    pack_bf16x2(S[a][8 * s + 6], S[a][8 * s + 7]));
+        pb = __builtin_bit_cast(bf16x8_t, pw);
         O = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vb, pb, O, 0, 0, 0);
       }
     const float inv = 1.f / sum;
     uint16_t* orow = out + row * D + h * DH;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      uint16_t o4[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) o4[j] = f32_to_bf16(O[4 * i + j] * inv);
-      *(uint2*)(orow + 8 * i + 4 * hh) = *(const uint2*)o4;
-    }
+    for (int i = 0; i < 4; ++i)
+      *(uint2*)(orow + 8 * i + 4 * hh) =
+          make_uint2(pack_bf16x2(O[4 * i] * inv, O[4 * i + 1] * inv), pack_bf16x2(O[4 * i + 2] * inv, O[4 * i + 3] * inv));
   }
 }
 
