@@ -312,7 +312,9 @@ hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, int64_t bytes
  * 128x128x32w8pf2, 7: 256x128x32w8pf2, 8: 64x64x64pf2, 9: 128x128x64w8;
  * other GEMMs on variant 0), -1 lets the autotuner choose (the tests
  * compare the variants); "gemm_small_tiles" (0/1): the same as gemm_variant
- * 0 / -1; "gemm_autotune" (0/1, default 1): time every variant on the first
+ * 0 / -1; "ffn_fused" (0/1, default 0): with BF16 compute outside training,
+ * run each FFN as one fused kernel (hidden activations kept on chip) instead
+ * of two GEMMs (slower at present: one wave per SIMD); "gemm_autotune" (0/1, default 1): time every variant on the first
  * call of each BF16 GEMM shape, writing to a scratch buffer, and keep the
  * fastest (off: the 128 x 128 x 32 kernel).  HP_E_INVALID on an unknown name
  * or a variant out of range. */

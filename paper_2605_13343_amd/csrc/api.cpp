@@ -424,6 +424,10 @@ extern "C" hp_status hp_debug_set(hp_batch b, const char* name, int32_t value) {
     b->attn_valu = value != 0;
     return HP_OK;
   }
+  if (n == "ffn_fused") {
+    b->ffn_fused = value != 0;
+    return HP_OK;
+  }
   if (n == "gemm_small_tiles") {
     b->gemm_variant = value != 0 ? 0 : -1;
     return HP_OK;

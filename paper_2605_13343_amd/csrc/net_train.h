@@ -214,6 +214,14 @@ static hp_status train_grad_t(Batch& b, const float* W, const float* rho, const 
   const bool use_off = c.offdiag && b.mtot > 0;
   const FrameDesc* fr = b.d_fr;
   hipLaunchKernelGGL(k_fill, dim3(gsz(T.nw)), dim3(256), 0, st, grad, T.nw, 0.f);
+  // the forward pass runs the FFNs as the two GEMMs its per-layer
+  // recomputation differentiates (never the fused inference kernel)
+  struct FfnGuard {
+    Batch& b;
+    int saved;
+    ~FfnGuard() { b.ffn_fused = saved; }
+  } ffn_guard{b, b.ffn_fused};
+  b.ffn_fused = 0;
 
   // ---- probes (Sec. 6.3) and the forward pass with saves
   HP_TRY(probes(b, sys, zraw, T.Zs, T.X, sweeps, omega));

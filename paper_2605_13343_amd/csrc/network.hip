@@ -372,6 +372,140 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_bt(GemmArgs
       gemm_epilogue<uint16_t>(a, acc[i][j], m0 + wm + 32 * i + (lane & 31), n0 + wn + 32 * j + 4 * (lane >> 5), vec);
 }
 
+// ------------------------------------------------------------------ fused FFN
+// X += GELU(U W1 + b1) W2 + b2 for d = 128, hidden 4d = 512, BF16 operands and
+// FP32 accumulation, without the hidden activations leaving the chip (the
+// inference path).  Block: 4 waves of 32 rows.  A wave keeps its rows of U as
+// MFMA operands in registers (32 steps of 16 along K = 512); W1 and W2 pass
+// through LDS in chunks of FC = 32 hidden units (double-buffered, the next
+// chunk's global loads issued before the current chunk's MFMAs).  Per chunk:
+// H^T = W1c U^T (lane: one row, hidden 8 i + 4 (lane / 32) + j), then the
+// bias and GELU, rounded to BF16 as the two-GEMM path rounds its hidden
+// output; those values are the B operand of Y^T += W2c H^T as they stand when
+// the 16 hidden units of a step are taken in the order [0-3, 8-11, 4-7,
+// 12-15], so W2's columns are staged in LDS in that order.  The hidden
+// pre-activations are summed along K in four interleaved chains (steps s mod
+// 4, added pairwise at the end) and the second product takes the hidden
+// units of each MFMA step in the permuted order: both differ from the
+// two-GEMM path only in summation order.  Needs M rows of U, X with leading
+// dimensions 512 and 128.
+constexpr int FFN_FC = 32;
+
+__global__ __launch_bounds__(256) void k_ffn_fused(const uint16_t* U, const uint16_t* W1t, const float* b1,
+                                                   const uint16_t* W2t, const float* b2, float* X, int M) {
+  constexpr int K = 512, NH = 512, NO = 128, FC = FFN_FC, NCH = NH / FC, LD1 = K + 8, LD2 = FC + 8;
+  __shared__ __attribute__((aligned(16))) uint16_t sW1[2][FC][LD1];
+  __shared__ __attribute__((aligned(16))) uint16_t sW2[2][NO][LD2];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, hh = lane >> 5, r32 = lane & 31;
+  const int row = blockIdx.x * 128 + wave * 32 + r32;
+  // this lane's row of U: step s holds columns 16 s + 8 hh .. + 7
+  uint4 ua[K / 16];
+#pragma unroll
+  for (int s2 = 0; s2 < K / 16; ++s2)
+    ua[s2] = row < M ? *(const uint4*)(U + (int64_t)row * K + 16 * s2 + 8 * hh) : make_uint4(0, 0, 0, 0);
+  // weight chunk staging: W1c rows go from global memory straight to LDS (one
+  // 1 KB row per wave instruction, lane i -> columns 8 i .. 8 i + 7); W2c
+  // passes through 2 16-byte registers per thread for its column order
+  uint4 p2[2];
+  auto gload = [&](int c, int buf) {
+    const int h0 = c * FC;
+#pragma unroll
+    for (int q = 0; q < FC / 4; ++q) {
+      const int r = wave * (FC / 4) + q;
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(W1t + (int64_t)(h0 + r) * K + 8 * lane),
+                                       (__attribute__((address_space(3))) void*)&sW1[buf][r][0], 16, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = tid + 256 * q, n = idx >> 2, g = idx & 3;
+      p2[q] = *(const uint4*)(W2t + (int64_t)n * NH + h0 + 8 * g);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int idx = tid + 256 * q, n = idx >> 2, g = idx & 3;
+      // hidden units 8g .. 8g+7 of the chunk: within its 16-block, units 0-3
+      // go to positions 0-3, 4-7 to 8-11, 8-11 to 4-7, 12-15 to 12-15
+      const int b16 = (g >> 1) * 16, lo = (g & 1) ? 4 : 0, hi = (g & 1) ? 12 : 8;
+      *(uint2*)&sW2[buf][n][b16 + lo] = make_uint2(p2[q].x, p2[q].y);
+      *(uint2*)&sW2[buf][n][b16 + hi] = make_uint2(p2[q].z, p2[q].w);
+    }
+  };
+  f32x16_t acc[NO / 32];
+#pragma unroll
+  for (int o = 0; o < NO / 32; ++o)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[o][q] = 0.f;
+  gload(0, 0);
+  sstore(0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  for (int c = 0; c < NCH; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < NCH) gload(c + 1, buf ^ 1);
+    // H^T chunk: 32 hidden units x 32 rows, K split over four accumulators
+    // (steps s = 4 q + a into chain a; independent MFMA chains in flight)
+    f32x16_t hc4[4];
+#pragma unroll
+    for (int a4 = 0; a4 < 4; ++a4)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) hc4[a4][q] = 0.f;
+#pragma unroll
+    for (int s2 = 0; s2 < K / 16; ++s2) {
+      const bf16x8_t a = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sW1[buf][r32][16 * s2 + 8 * hh]);
+      hc4[s2 & 3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, __builtin_bit_cast(bf16x8_t, ua[s2]), hc4[s2 & 3], 0, 0, 0);
+    }
+    f32x16_t hacc;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) hacc[q] = (hc4[0][q] + hc4[1][q]) + (hc4[2][q] + hc4[3][q]);
+    // bias, GELU, BF16: step u of the second product takes i = 2u, 2u + 1
+    uint4 pb[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      float g[8];
+#pragma unroll
+      for (int ii = 0; ii < 2; ++ii) {
+        const int i = 2 * u + ii, h = c * FC + 8 * i + 4 * hh;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) g[4 * ii + j] = gelu_bf16path(hacc[4 * i + j] + b1[h + j]);
+      }
+      pb[u] = make_uint4(pack_bf16x2(g[0], g[1]), pack_bf16x2(g[2], g[3]), pack_bf16x2(g[4], g[5]),
+                         pack_bf16x2(g[6], g[7]));
+    }
+#pragma unroll
+    for (int o = 0; o < NO / 32; ++o)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const bf16x8_t a = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sW2[buf][32 * o + r32][16 * u + 8 * hh]);
+        acc[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, __builtin_bit_cast(bf16x8_t, pb[u]), acc[o], 0, 0, 0);
+      }
+    if (c + 1 < NCH) sstore(buf ^ 1);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the direct-to-LDS rows of the next chunk
+    __syncthreads();
+  }
+  GemmArgs ea;
+  ea.X = nullptr;
+  ea.ldx = 0;
+  ea.Wt = nullptr;
+  ea.K = K;
+  ea.bias = b2;
+  ea.resid = X;
+  ea.ldr = NO;
+  ea.Yf = X;
+  ea.ldf = NO;
+  ea.Yb = nullptr;
+  ea.ldb = 0;
+  ea.pre = nullptr;
+  ea.ldp = 0;
+  ea.M = M;
+  ea.N = NO;
+  ea.act = 0;
+  const bool vec = gemm_vec_ok(ea, 2);
+#pragma unroll
+  for (int o = 0; o < NO / 32; ++o) gemm_epilogue<uint16_t>(ea, acc[o], row, 32 * o + 4 * hh, vec);
+}
+
 // ------------------------------------------------------------------ LayerNorm
 // Eight consecutive values of a row: loaded with two 16-byte loads when the
 // address allows, stored as one 16-byte BF16 pack (or two FP32 float4).
@@ -1988,6 +2122,30 @@ static void gemm(Batch& b, const void* X, int64_t ldx, const NetBufs& NB, const 
   }
 }
 
+// The fused FFN (BF16 inference): X += GELU(U W1 + b1) W2 + b2, timed with
+// the GEMMs when GEMM timing is on (work: the two products' flops, or the
+// algorithmic bytes U, W1, W2, biases, X read and written).
+static void ffn_fused(Batch& b, const void* U, const NetBufs& NB, const GemmW& w1, const float* b1, const GemmW& w2,
+                      const float* b2, float* X, int64_t M) {
+  if (M <= 0) return;
+  hipStream_t st = b.stream;
+  const bool timed = (b.prof.kind == PROF_GEMM || b.prof.kind == PROF_GEMM_BYTES) &&
+                     2 * (b.prof.used + 1) <= (int)b.prof.ev.size();
+  if (timed) hipEventRecord(b.prof.ev[2 * b.prof.used], st);
+  hipLaunchKernelGGL(k_ffn_fused, dim3((unsigned)((M + 127) / 128)), dim3(256), 0, st, (const uint16_t*)U,
+                     (const uint16_t*)NB.warena + w1.off, b1, (const uint16_t*)NB.warena + w2.off, b2, X, (int)M);
+  if (timed) {
+    hipEventRecord(b.prof.ev[2 * b.prof.used + 1], st);
+    b.prof.used++;
+    const double m = (double)M;
+    if (b.prof.kind == PROF_GEMM)
+      b.prof.work += 2.0 * m * w1.N * w1.K + 2.0 * m * w2.N * w2.K;
+    else
+      b.prof.work += 2.0 * (m * w1.K + (double)w1.N * w1.K + (double)w2.N * w2.K) + 4.0 * (w1.N + w2.N) +
+                     8.0 * m * w2.N;
+  }
+}
+
 // Training saves of the forward pass (FP32).
 struct TrainSave {
   float* Hg[5];                      // encoder: input of each GCN layer, then the encoder output
@@ -2170,9 +2328,13 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
                          (const float*)N.ctxf, 2 * d, (const float*)(N.ctxf + d), 2 * d, (const float*)N.G,
                          (const int*)N.tok2f, wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, (int)M, c.highways);
     if (ls) HP_HIP(hipMemcpyAsync(sidx ? ls->xmid_o : ls->xmid_d, X, M * d * 4, hipMemcpyDeviceToDevice, st));
-    gemm<AT>(b, u, 4 * d, N, P.f1[sidx][l], wp(p + "f1.b"), nullptr, 0, nullptr, 0, h, 4 * d, M, 1,
-             ls ? (sidx ? ls->pre_o : ls->pre_d) : nullptr, 4 * d);
-    gemm<AT>(b, h, 4 * d, N, P.f2[sidx][l], wp(p + "f2.b"), X, d, X, d, nullptr, 0, M, 0);
+    if (sizeof(AT) == 2 && !ls && b.ffn_fused) {
+      ffn_fused(b, u, N, P.f1[sidx][l], wp(p + "f1.b"), P.f2[sidx][l], wp(p + "f2.b"), X, M);
+    } else {
+      gemm<AT>(b, u, 4 * d, N, P.f1[sidx][l], wp(p + "f1.b"), nullptr, 0, nullptr, 0, h, 4 * d, M, 1,
+               ls ? (sidx ? ls->pre_o : ls->pre_d) : nullptr, 4 * d);
+      gemm<AT>(b, h, 4 * d, N, P.f2[sidx][l], wp(p + "f2.b"), X, d, X, d, nullptr, 0, M, 0);
+    }
   }
   HP_HIP(hipGetLastError());
   return HP_OK;
