@@ -296,14 +296,18 @@ hp_status hp_train_step(hp_batch b, float* d_weights, float* d_grad, float* d_m,
  * into d_dst (device, caller-owned), on the batch's stream.  Names: "feats"
  * [ntot][32] encoder input (compute type), "glob" [nframes][12] FP32 frame
  * summaries, "enc" [ntot][d] FP32 encoder output, "xo0" [mtot L_s][d] FP32
- * pooled off-diagonal tokens, "xd" / "xo" [..][d] FP32 residual streams after
+ * pooled off-diagonal tokens (these two only when the "keep_stages" switch of
+ * hp_debug_set was on during the inference), "xd" / "xo" [..][d] FP32 residual streams after
  * the last layer, "desc" [mtot][L_s][L_s][4] FP32 off-diagonal pair
  * descriptors, "frows" [ntot][L] FP32 leaf-head rows (F), "nodeh" [ntot][36]
  * FP32 node heads (Ut | Vt | lam logit), "uv" [mtot L_s][2 L_s] FP32 (U | V).
  * For tests; HP_E_INVALID on an unknown name or a size beyond the buffer. */
 hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, int64_t bytes);
 
-/* Test switches of one batch.  "attention_valu" (0/1): with BF16 compute, run
+/* Test switches of one batch.  "keep_stages" (0/1, default 0): keep the
+ * encoder output and the pooled off-diagonal tokens of each inference for
+ * hp_debug_copy ("enc", "xo0"; two device copies per inference);
+ * "attention_valu" (0/1): with BF16 compute, run
  * the within-leaf attention on the vector ALUs instead of the matrix cores;
  * "gemm_variant" (-1 or 0..9, default -1): run every BF16 GEMM whose K the
  * variant's K step divides on that tile variant (block tile x K step, "w8":
@@ -321,8 +325,8 @@ hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, int64_t bytes
 hp_status hp_debug_set(hp_batch b, const char* name, int32_t value);
 
 /* The GEMM autotuner's records of this batch, one text line per shape
- * ("gemm N=.. K=.. M=.. tile=<chosen> us=<variant>:<us>,..", the mean time
- * of each timed variant in microseconds), written into buf
+ * ("gemm N=.. K=.. M=.. tile=<chosen> us=<variant>:<us>,..", the fastest of five
+ * timed launches of each variant in microseconds), written into buf
  * (host, len bytes, always NUL-terminated when len > 0; truncated if short).
  * *entries (optional) receives the number of shapes. */
 hp_status hp_autotune_report(hp_batch b, char* buf, int64_t len, int32_t* entries);

@@ -424,6 +424,10 @@ extern "C" hp_status hp_debug_set(hp_batch b, const char* name, int32_t value) {
     b->attn_valu = value != 0;
     return HP_OK;
   }
+  if (n == "keep_stages") {
+    b->keep_stages = value != 0;
+    return HP_OK;
+  }
   if (n == "ffn_fused") {
     b->ffn_fused = value != 0;
     return HP_OK;

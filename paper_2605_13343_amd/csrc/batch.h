@@ -108,6 +108,7 @@ struct Batch {
   int attn_valu = 0;                    // diagnostics: BF16 leaf attention on the vector ALUs
   int gemm_variant = -1;                // diagnostics: BF16 GEMMs forced onto one tile variant (-1: autotuned)
   int ffn_fused = 0;                    // BF16 inference: the FFN as one fused kernel (default: two GEMMs)
+  int keep_stages = 0;                  // diagnostics: keep the encoder output and pooled tokens for hp_debug_copy
   int gemm_autotune = 1;                // time both tile kernels on a shape's first call
   std::map<std::tuple<int, int, int64_t>, GemmPick> gemm_pick;
   void* net_train = nullptr;            // network training workspace (first hp_train_grad)

@@ -406,7 +406,7 @@ __global__ __launch_bounds__(256) void k_edge_bwd(EdgeW w, EdgeBwdSrc src, int64
 }
 
 // ------------------------------------------------------------------ strips, highways, pooling
-// Adjoint of k_strip_means for node rows: dA_i (+)= sum over the tokens whose
+// Adjoint of the strip means (pooling and highway context) for node rows: dA_i (+)= sum over the tokens whose
 // row sub-strip holds i of dout[tok][0:128] * s_tok, and likewise dBsrc_i over
 // column sub-strips with dout[tok][128:256]; s_tok = 1 / (S p) (means).
 __global__ __launch_bounds__(256) void k_strip_means_bwd(const FrameDesc* fr, const int* node2f, const float* dout,

@@ -644,9 +644,10 @@ __global__ __launch_bounds__(256) void k_ln_concat(const float* S0, int64_t ld0,
 // Per-frame summary (one block per frame), the definition used here of
 // the 12 global features: log2(N)/16, log(rho_max/rho_min), mean and std of
 // log rho, heavy fraction, mean/std/min/max of log A_ii, nx/32, ny/32, nz/32.
-__global__ __launch_bounds__(256) void k_frame_stats(const FrameDesc* fr, const float* rho, const float* sys,
+__global__ __launch_bounds__(1024) void k_frame_stats(const FrameDesc* fr, const float* rho, const float* sys,
                                                      int64_t ntot, float* glob) {
-  __shared__ double red[4][8];
+  constexpr int NW = 16;  // waves of the 1024-thread block
+  __shared__ double red[NW][2];
   const FrameDesc F = fr[blockIdx.x];
   const double* dg8 = reinterpret_cast<const double*>(sys + 5 * ntot);
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -655,7 +656,9 @@ __global__ __launch_bounds__(256) void k_frame_stats(const FrameDesc* fr, const 
     __syncthreads();
     if (lane == 0) red[w][0] = v;
     __syncthreads();
-    return red[0][0] + red[1][0] + red[2][0] + red[3][0];
+    double r = red[0][0];
+    for (int i = 1; i < NW; ++i) r += red[i][0];
+    return r;
   };
   auto bmin = [&](double v, bool mx) -> double {
     for (int o = 32; o > 0; o >>= 1) {
@@ -666,11 +669,11 @@ __global__ __launch_bounds__(256) void k_frame_stats(const FrameDesc* fr, const 
     if (lane == 0) red[w][1] = v;
     __syncthreads();
     double r = red[0][1];
-    for (int i = 1; i < 4; ++i) r = mx ? fmax(r, red[i][1]) : fmin(r, red[i][1]);
+    for (int i = 1; i < NW; ++i) r = mx ? fmax(r, red[i][1]) : fmin(r, red[i][1]);
     return r;
   };
   double sr = 0, sa = 0, mnr = 1e300, mxr = -1e300, mna = 1e300, mxa = -1e300;
-  for (int c = t; c < F.n; c += 256) {
+  for (int c = t; c < F.n; c += 1024) {
     double lr = log((double)rho[F.n0 + c]), la = log(dg8[F.n0 + c]);
     sr += lr;
     sa += la;
@@ -685,7 +688,7 @@ __global__ __launch_bounds__(256) void k_frame_stats(const FrameDesc* fr, const 
   const double amin = bmin(mna, false), amax = bmin(mxa, true);
   double vr = 0, va = 0, hv = 0;
   const double mid = 0.5 * (lmin + lmax);
-  for (int c = t; c < F.n; c += 256) {
+  for (int c = t; c < F.n; c += 1024) {
     double lr = log((double)rho[F.n0 + c]), la = log(dg8[F.n0 + c]);
     vr += (lr - mr) * (lr - mr);
     va += (la - ma) * (la - ma);
@@ -1017,17 +1020,18 @@ __global__ __launch_bounds__(256) void k_off_desc_final(const FrameDesc* fr, con
 
 // Off-diagonal bias per layer: bias[m][h][t][t'] = MLP_e(desc[m][t][t']).
 template <bool FAST>
-__global__ void k_edge_off(EdgeW w, const float* desc, int64_t npairs, int LS, float* bias) {
+__global__ __launch_bounds__(256) void k_edge_off(EdgeW w, const float* desc, int64_t npairs, int LS, float* bias) {
   __shared__ float sw[EDGE_MAX_FLOATS];
   edge_stage(w, sw);
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npairs) return;
-  const int64_t m = p / (LS * LS);
-  const int tt = (int)(p % (LS * LS));
-  float e[4] = {desc[p * 4], desc[p * 4 + 1], desc[p * 4 + 2], desc[p * 4 + 3]};
-  float o[8];
-  edge_mlp<FAST>(sw, w.E, w.H, e, o);
-  for (int h = 0; h < w.H; ++h) bias[(m * w.H + h) * LS * LS + tt] = o[h];
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npairs; p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = p / (LS * LS);
+    const int tt = (int)(p % (LS * LS));
+    const float4 dv = *(const float4*)(desc + p * 4);
+    const float e[4] = {dv.x, dv.y, dv.z, dv.w};
+    float o[8];
+    edge_mlp<FAST>(sw, w.E, w.H, e, o);
+    for (int h = 0; h < w.H; ++h) bias[(m * w.H + h) * LS * LS + tt] = o[h];
+  }
 }
 
 // ------------------------------------------------------------------ attention
@@ -1091,43 +1095,6 @@ __global__ __launch_bounds__(64) void k_attention(const AT* qkv, AT* out, const 
   }
 #pragma unroll
   for (int c = 0; c < DH; ++c) out[row * d + h * DH + c] = to_act<AT>(o[c] * inv);
-}
-
-// ------------------------------------------------------------------ strips and highways
-// Strip means for off-diagonal token (m, t): out[tok][0:128] = mean of A over
-// I_m^t (row strip), out[tok][128:256] = mean of Bsrc over J_m^t (column
-// strip).  Used for pooling (A = Bsrc = encoder output) and for the highway
-// context of off-diagonal tokens (A = r, Bsrc = c).  One block per token:
-// 4 row groups x 128 features; group g adds the strip rows g, g + 4, ... in
-// order, then the groups are added in order (big tiles have S p = 256 rows).
-template <typename OT>
-__global__ __launch_bounds__(512) void k_strip_means(const FrameDesc* fr, const int* tile2f, const float* A,
-                                                     const float* Bsrc, int L, int LS, OT* out) {
-  constexpr int NG = 4;
-  __shared__ float red[2][NG][128];
-  const int64_t tok = blockIdx.x;
-  const int mg = (int)(tok / LS), t = (int)(tok % LS);
-  const FrameDesc F = fr[tile2f[mg]];
-  const int m = mg - F.m0, K = F.K;
-  int j = 0;
-  while (m >= K - (K >> (j + 1))) ++j;
-  const int i = m - (K - (K >> j)), S = 1 << j, r0 = 2 * i * S, c0 = r0 + S, p = L / LS;
-  const int col = threadIdx.x & 127, g = threadIdx.x >> 7;
-  float sa = 0.f, sb = 0.f;
-  for (int q = g; q < S * p; q += NG) {
-    const int k = q / p, l = t * p + q % p;
-    sa += A[((int64_t)F.n0 + (int64_t)(r0 + k) * L + l) * 128 + col];
-    sb += Bsrc[((int64_t)F.n0 + (int64_t)(c0 + k) * L + l) * 128 + col];
-  }
-  red[0][g][col] = sa;
-  red[1][g][col] = sb;
-  __syncthreads();
-  if (g < 2) {
-    float v = 0.f;
-    for (int q = 0; q < NG; ++q) v += red[g][q][col];
-    const float inv = 1.f / (float)(S * p);
-    out[tok * 256 + 128 * g + col] = to_act<OT>(v * inv);
-  }
 }
 
 // Within-leaf attention on the matrix cores (BF16 operands, FP32
@@ -1309,6 +1276,7 @@ __global__ __launch_bounds__(256) void k_attention_tile_mfma(const uint16_t* qkv
   }
 }
 
+// ------------------------------------------------------------------ strips and highways
 // Leaves per chunk of the highway trees (levels below the chunk size are
 // handled in registers).
 constexpr int STRIP_CHUNK = 16;
@@ -1395,22 +1363,40 @@ __global__ __launch_bounds__(256) void k_hw_levels_lo(const FrameDesc* fr, const
 
 // One level of the chunk tree: the context of the level's tiles inside the
 // chunk (v holds the blocks of size S), then the fold to blocks of size 2 S.
-template <int S>
+template <int S, typename OT>
 __device__ inline void strip_level(float (&v)[STRIP_CHUNK], int C, int leaf0, int j, const FrameDesc& F, int t,
-                                   int LS, int side, int col, int p, float* out) {
+                                   int LS, int side, int col, int p, OT* out) {
 #pragma unroll
   for (int il = 0; il < STRIP_CHUNK / (2 * S); ++il) {
     if (il < C / (2 * S)) {
       const int m = F.K - (F.K >> j) + leaf0 / (2 * S) + il;
-      out[((int64_t)(F.m0 + m) * LS + t) * 256 + 128 * side + col] = v[2 * il + side] / (float)(S * p);
+      out[((int64_t)(F.m0 + m) * LS + t) * 256 + 128 * side + col] = to_act<OT>(v[2 * il + side] / (float)(S * p));
     }
   }
 #pragma unroll
   for (int q = 0; q < STRIP_CHUNK / (2 * S); ++q) v[q] = v[2 * q] + v[2 * q + 1];
 }
 
+// Sums over the p rows of each (leaf, sub-strip) group of a node stream:
+// out[(leaf, t)][128] (one block per leaf, 4 sub-strip groups x 128
+// features; rows added in order).  With hr = hc = these sums, the strip tree
+// below yields the pooling means of the off-diagonal tokens.
+__global__ __launch_bounds__(512) void k_group_sums(const FrameDesc* fr, const int* leaf2f, const float* X, int L,
+                                                    int LS, float* out) {
+  const int64_t kg = blockIdx.x;
+  const FrameDesc F = fr[leaf2f[kg]];
+  const int p = L / LS, col = threadIdx.x & 127;
+  const float* base = X + ((int64_t)F.n0 + (kg - F.k0) * L) * 128 + col;
+  for (int t = threadIdx.x >> 7; t < LS; t += 4) {
+    float a = 0.f;
+    for (int q = 0; q < p; ++q) a += base[(int64_t)(t * p + q) * 128];
+    out[(kg * LS + t) * 128 + col] = a;
+  }
+}
+
+template <typename OT>
 __global__ __launch_bounds__(256) void k_hw_strips_lo(const FrameDesc* fr, const int2* tab, const float* hr,
-                                                      const float* hc, int L, int LS, float* out, float* tot) {
+                                                      const float* hc, int L, int LS, OT* out, float* tot) {
   const int2 e = tab[blockIdx.x];
   const int t = blockIdx.y, side = threadIdx.x >> 7, col = threadIdx.x & 127, p = L / LS;
   const FrameDesc F = fr[e.x];
@@ -1428,8 +1414,9 @@ __global__ __launch_bounds__(256) void k_hw_strips_lo(const FrameDesc* fr, const
   tot[(((int64_t)blockIdx.x) * LS + t) * 256 + 128 * side + col] = v[0];
 }
 
+template <typename OT>
 __global__ __launch_bounds__(256) void k_hw_strips_hi(const FrameDesc* fr, const int* chunk0, const float* tot,
-                                                      int L, int LS, float* out) {
+                                                      int L, int LS, OT* out) {
   const int f = blockIdx.x, t = blockIdx.y, side = threadIdx.x >> 7, col = threadIdx.x & 127, p = L / LS;
   const FrameDesc F = fr[f];
   const int K = F.K, C = min(STRIP_CHUNK, K);
@@ -1443,7 +1430,7 @@ __global__ __launch_bounds__(256) void k_hw_strips_hi(const FrameDesc* fr, const
       float sum = 0.f;
       for (int q = 0; q < nc; ++q) sum += T[(int64_t)(c0 + q) * LS * 256];
       const int m = K - (K >> j) + i;
-      out[((int64_t)(F.m0 + m) * LS + t) * 256 + 128 * side + col] = sum / (float)(S * p);
+      out[((int64_t)(F.m0 + m) * LS + t) * 256 + 128 * side + col] = to_act<OT>(sum / (float)(S * p));
     }
   }
 }
@@ -1586,20 +1573,47 @@ __global__ __launch_bounds__(1024) void k_frame_mean(const int* chunk0, const fl
 }
 
 // ------------------------------------------------------------------ heads and packing
-// G_k = F_k F_k^T (one block per leaf).  Entry (i, j) and (j, i) run the same
-// FMA sequence, so G_k is exactly symmetric.
+// G_k = F_k F_k^T (one block per leaf).  Thread (bi, bj) forms the 4 x 4
+// block of rows 4 bi.., columns 4 bj.. (8 LDS reads per 16 FMAs); each entry is
+// its own FMA chain over c in order, and entries (i, j) and (j, i) multiply the
+// same pairs, so G_k is exactly symmetric.
 template <typename FT, int L>
 __global__ __launch_bounds__(256) void k_gram(const float* Frows, FT* G) {
-  __shared__ float sF[L][L + 1];
+  constexpr int NB = L / 4, LP = L + 4;
+  __shared__ __attribute__((aligned(16))) float sF[L][LP];
   const int64_t kg = blockIdx.x;
-  for (int idx = threadIdx.x; idx < L * L; idx += 256) sF[idx / L][idx % L] = Frows[kg * L * L + idx];
+  for (int idx = threadIdx.x; idx < L * L / 4; idx += 256) {
+    const int i = (4 * idx) / L, c = (4 * idx) % L;
+    *(float4*)&sF[i][c] = *(const float4*)(Frows + kg * L * L + 4 * idx);
+  }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < L * L; idx += 256) {
-    const int i = idx / L, j = idx % L;
-    float a = 0.f;
-#pragma unroll 8
-    for (int c = 0; c < L; ++c) a = fmaf(sF[i][c], sF[j][c], a);
-    G[kg * L * L + idx] = to_act<FT>(a);
+  if (threadIdx.x >= NB * NB) return;
+  const int bi = threadIdx.x / NB, bj = threadIdx.x % NB;
+  float acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[r][q] = 0.f;
+#pragma unroll 4
+  for (int c = 0; c < L; ++c) {
+    float fi[4], fj[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      fi[r] = sF[4 * bi + r][c];
+      fj[r] = sF[4 * bj + r][c];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[r][q] = fmaf(fi[r], fj[q], acc[r][q]);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    FT* g = G + kg * L * L + (int64_t)(4 * bi + r) * L + 4 * bj;
+    if constexpr (sizeof(FT) == 2)
+      *(uint2*)g = make_uint2(pack_bf16x2(acc[r][0], acc[r][1]), pack_bf16x2(acc[r][2], acc[r][3]));
+    else
+      *(float4*)g = make_float4(acc[r][0], acc[r][1], acc[r][2], acc[r][3]);
   }
 }
 
@@ -2016,7 +2030,7 @@ static void launch_gemm(int kind, const GemmArgs& a, bool bf16, hipStream_t st) 
 
 // GEMM tile autotuner (BF16, N > 64): the first call of a shape (N, K, M) on
 // a batch times every variant whose K step divides K (one warm launch, then
-// 3 timed launches each) with the call's outputs redirected to a scratch
+// the fastest of 5 launches timed one by one) with the call's outputs redirected to a scratch
 // buffer, so tuning never touches the call's own outputs (in-place residual
 // calls included); the call then runs once with the fastest.  All variants
 // compute bit-identical results.  Under stream capture, with tuning off, or if
@@ -2052,9 +2066,9 @@ static int gemm_choice(Batch& b, const GemmArgs& a, hipStream_t st) {
   if (t.Yf) t.Yf = (float*)scratch;
   if (t.Yb) t.Yb = scratch;
   if (t.pre) t.pre = (float*)scratch;
-  hipEvent_t ev[2];
-  hipEventCreate(&ev[0]);
-  hipEventCreate(&ev[1]);
+  constexpr int REPS = 5;
+  hipEvent_t ev[REPS + 1];
+  for (auto& e : ev) hipEventCreate(&e);
   GemmPick g;
   g.pick = 1;
   g.us.assign(kNumGemmVars, -1.f);
@@ -2062,16 +2076,21 @@ static int gemm_choice(Batch& b, const GemmArgs& a, hipStream_t st) {
     if (!gemm_variant_fits(kind, a.K)) continue;
     launch_gemm(kind, t, true, st);
     hipEventRecord(ev[0], st);
-    for (int r = 0; r < 3; ++r) launch_gemm(kind, t, true, st);
-    hipEventRecord(ev[1], st);
-    hipEventSynchronize(ev[1]);
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, ev[0], ev[1]);
-    g.us[kind] = ms * 1e3f / 3.f;
+    for (int r = 0; r < REPS; ++r) {
+      launch_gemm(kind, t, true, st);
+      hipEventRecord(ev[r + 1], st);
+    }
+    hipEventSynchronize(ev[REPS]);
+    float best = 1e30f;
+    for (int r = 0; r < REPS; ++r) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ev[r], ev[r + 1]);
+      best = std::min(best, ms);
+    }
+    g.us[kind] = best * 1e3f;
     if (g.us[kind] < g.us[g.pick] || g.us[g.pick] < 0.f) g.pick = kind;
   }
-  hipEventDestroy(ev[0]);
-  hipEventDestroy(ev[1]);
+  for (auto& e : ev) hipEventDestroy(e);
   hipFree(scratch);
   b.gemm_pick[key] = g;
   return g.pick;
@@ -2182,7 +2201,7 @@ static hp_status fwd_prologue(Batch& b, const float* W, const float* rho, const 
   HP_HIP(hipMemcpyAsync(N.bias_uv, wp("hu.b"), LS * 4, hipMemcpyDeviceToDevice, st));
   HP_HIP(hipMemcpyAsync(N.bias_uv + LS, wp("hv.b"), LS * 4, hipMemcpyDeviceToDevice, st));
   // features and encoder (Sec. 4.1)
-  hipLaunchKernelGGL(k_frame_stats, dim3(b.nframes), dim3(256), 0, st, fr, rho, sys, b.ntot, N.glob);
+  hipLaunchKernelGGL(k_frame_stats, dim3(b.nframes), dim3(1024), 0, st, fr, rho, sys, b.ntot, N.glob);
   hipLaunchKernelGGL(k_features<AT>, dim3(b.nblk), dim3(NODE_BLOCK), 0, st, fr, b.d_blk2f, rho, sys, b.ntot, N.glob,
                      (AT*)N.feats);
   gemm<AT>(b, N.feats, 32, N, P.enc1, wp("enc1.b"), nullptr, 0, nullptr, 0, N.a128, d, Nd, 1);
@@ -2193,14 +2212,21 @@ static hp_status fwd_prologue(Batch& b, const float* W, const float* rho, const 
                        (const float*)N.H, (AT*)N.a128);
     gemm<AT>(b, N.a128, d, N, P.gcn[g], wp("gcn" + std::to_string(g) + ".b"), N.H, d, N.H, d, N.b128, d, Nd, 1);
   }
-  HP_HIP(hipMemcpyAsync(N.Henc, N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
+  if (b.keep_stages) HP_HIP(hipMemcpyAsync(N.Henc, N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
   if (sv) HP_HIP(hipMemcpyAsync(sv->Hg[c.gcn], N.H, Nd * d * 4, hipMemcpyDeviceToDevice, st));
   // off-diagonal tokens: pooled strip means through [W_r; W_c] (Sec. 4.2)
   if (use_off) {
-    hipLaunchKernelGGL(k_strip_means<AT>, dim3((unsigned)No), dim3(512), 0, st, fr, N.tile2f, (const float*)N.H,
-                       (const float*)N.H, (int)L, (int)LS, (AT*)N.ctx);
+    // strip means of the encoder output: group sums, then the dyadic strip tree
+    // (both strips from the same sums; N.hhr is free until the first layer)
+    hipLaunchKernelGGL(k_group_sums, dim3((unsigned)b.ktot), dim3(512), 0, st, fr, b.d_leaf2f, (const float*)N.H,
+                       (int)L, (int)LS, N.hhr);
+    hipLaunchKernelGGL(k_hw_strips_lo<AT>, dim3((unsigned)N.nstrip, (unsigned)LS), dim3(256), 0, st, fr,
+                       (const int2*)N.strip_tab, (const float*)N.hhr, (const float*)N.hhr, (int)L, (int)LS, (AT*)N.ctx,
+                       N.strip_tot);
+    hipLaunchKernelGGL(k_hw_strips_hi<AT>, dim3((unsigned)b.nframes, (unsigned)LS), dim3(256), 0, st, fr,
+                       (const int*)N.strip0, (const float*)N.strip_tot, (int)L, (int)LS, (AT*)N.ctx);
     gemm<AT>(b, N.ctx, 2 * d, N, P.pool, wp("pool.b"), nullptr, 0, N.Xo, d, nullptr, 0, No, 0);
-    HP_HIP(hipMemcpyAsync(N.Xo0, N.Xo, No * d * 4, hipMemcpyDeviceToDevice, st));
+    if (b.keep_stages) HP_HIP(hipMemcpyAsync(N.Xo0, N.Xo, No * d * 4, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_off_desc_part, dim3((unsigned)N.ndesc_chunks), dim3(256), 0, st, fr, N.tile2f,
                        (const DescChunk*)N.desc_chunks, sys, b.ntot, (int)L, (int)LS, N.desc_part);
     hipLaunchKernelGGL(k_off_desc_final, dim3((unsigned)b.mtot), dim3(256), 0, st, fr, N.tile2f,
@@ -2244,8 +2270,7 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
     if (sidx == 0) {
       hipLaunchKernelGGL(k_edge_table<sizeof(AT) == 2>, dim3((unsigned)((L * L + 255) / 256 + 1)), dim3(256), 0, st,
                          ew, (int)L, F0.xm & lowmask, F0.ym & lowmask, F0.zm & lowmask, N.T0, N.eslots);
-      hipLaunchKernelGGL(k_edge_corr<sizeof(AT) == 2>,
-                         dim3((unsigned)std::min<int64_t>((Nd * 7 + 1023) / 1024, 4096)), dim3(256), 0, st, ew,
+      hipLaunchKernelGGL(k_edge_corr<sizeof(AT) == 2>, dim3((unsigned)((Nd * 7 + 255) / 256)), dim3(256), 0, st, ew,
                          (const float*)N.eslots, (const uint8_t*)N.nbr, (const float*)N.ahat, Nd, N.corr);
       if (sizeof(AT) == 2 && !b.attn_valu) {
         if (L == 64)
@@ -2265,7 +2290,7 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
       }
     } else {
       const int64_t npairs = b.mtot * LS * LS;
-      hipLaunchKernelGGL(k_edge_off<sizeof(AT) == 2>, dim3((unsigned)((npairs + 127) / 128)), dim3(128), 0, st, ew,
+      hipLaunchKernelGGL(k_edge_off<sizeof(AT) == 2>, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, ew,
                          (const float*)N.desc, npairs, (int)LS, N.boff);
       if (sizeof(AT) == 2 && LS == 16 && !b.attn_valu)
         hipLaunchKernelGGL(k_attention_tile_mfma, dim3((unsigned)b.mtot), dim3(256), 0, st, (const uint16_t*)q,
@@ -2309,10 +2334,10 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
     if (sidx == 1 && c.highways && N.nstrip > 0) {
       // context of the off-diagonal tokens from the group sums the diagonal
       // LayerNorm wrote (taken before the diagonal FFN)
-      hipLaunchKernelGGL(k_hw_strips_lo, dim3((unsigned)N.nstrip, (unsigned)LS), dim3(256), 0, st, fr,
+      hipLaunchKernelGGL(k_hw_strips_lo<float>, dim3((unsigned)N.nstrip, (unsigned)LS), dim3(256), 0, st, fr,
                          (const int2*)N.strip_tab, (const float*)N.hhr, (const float*)N.hhc, (int)L, (int)LS, N.ctxf,
                          N.strip_tot);
-      hipLaunchKernelGGL(k_hw_strips_hi, dim3((unsigned)b.nframes, (unsigned)LS), dim3(256), 0, st, fr,
+      hipLaunchKernelGGL(k_hw_strips_hi<float>, dim3((unsigned)b.nframes, (unsigned)LS), dim3(256), 0, st, fr,
                          (const int*)N.strip0, (const float*)N.strip_tot, (int)L, (int)LS, N.ctxf);
     }
     if (sidx == 0 && c.highways && use_off)
@@ -2415,6 +2440,9 @@ extern "C" hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, in
   const std::string n = name;
   const int64_t d = b->cfg.d;
   if (n == "feats") src = N.feats, cap = N.Nd * 32 * 4;
+  else if ((n == "enc" || n == "xo0") && !b->keep_stages)
+    return set_error(HP_E_INVALID, "hp_debug_copy: '%s' is kept only with hp_debug_set(\"keep_stages\", 1)",
+                     n.c_str());
   else if (n == "enc") src = N.Henc, cap = N.Nd * d * 4;
   else if (n == "xo0") src = N.Xo0, cap = N.No * d * 4;
   else if (n == "xd") src = N.H, cap = N.Nd * d * 4;

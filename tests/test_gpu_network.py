@@ -38,6 +38,7 @@ def _dbg(side, name, shape):
 def _run(cfg, frames, compute, w):
     import torch
     s = Side(cfg, frames, with_net=True)
+    s.B.debug_set("keep_stages", 1)  # the encoder output and pooled tokens for the stage checks
     wt = torch.tensor(hp.pack_weights(cfg, w), device="cuda")
     fac = s.B.new_factors(compute)
     s.B.infer_factors(wt, s.rho, s.sys, fac, compute)
