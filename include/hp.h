@@ -325,8 +325,8 @@ hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, int64_t bytes
 hp_status hp_debug_set(hp_batch b, const char* name, int32_t value);
 
 /* The GEMM autotuner's records of this batch, one text line per shape
- * ("gemm N=.. K=.. M=.. tile=<chosen> us=<variant>:<us>,..", the fastest of five
- * timed launches of each variant in microseconds), written into buf
+ * ("gemm N=.. K=.. M=.. tile=<chosen> us=<variant>:<us>,..", the fastest of six
+ * timed launches of each variant, in three interleaved rounds, in microseconds), written into buf
  * (host, len bytes, always NUL-terminated when len > 0; truncated if short).
  * *entries (optional) receives the number of shapes. */
 hp_status hp_autotune_report(hp_batch b, char* buf, int64_t len, int32_t* entries);

@@ -41,8 +41,8 @@ struct FrameDesc {
   int nx, ny;       // grid width and depth
 };
 
-constexpr int NODE_BLOCK = 256;   // rows per node block
-constexpr int LEAF_THREADS = 256; // threads per leaf block
+constexpr int NODE_BLOCK = 128;   // rows per node block
+constexpr int LEAF_THREADS = 128; // threads per leaf block
 
 // Per-frame PCG scalars (device), double-buffered by iteration parity.
 struct FrameState {

@@ -2029,8 +2029,9 @@ static void launch_gemm(int kind, const GemmArgs& a, bool bf16, hipStream_t st) 
 }
 
 // GEMM tile autotuner (BF16, N > 64): the first call of a shape (N, K, M) on
-// a batch times every variant whose K step divides K (one warm launch, then
-// the fastest of 5 launches timed one by one) with the call's outputs redirected to a scratch
+// a batch times every variant whose K step divides K (one warm launch each,
+// then three rounds over the variants of two launches timed one by one, the
+// fastest kept) with the call's outputs redirected to a scratch
 // buffer, so tuning never touches the call's own outputs (in-place residual
 // calls included); the call then runs once with the fastest.  All variants
 // compute bit-identical results.  Under stream capture, with tuning off, or if
@@ -2066,30 +2067,34 @@ static int gemm_choice(Batch& b, const GemmArgs& a, hipStream_t st) {
   if (t.Yf) t.Yf = (float*)scratch;
   if (t.Yb) t.Yb = scratch;
   if (t.pre) t.pre = (float*)scratch;
-  constexpr int REPS = 5;
+  // rounds over all variants (so drifting clocks affect every variant alike),
+  // each variant's fastest timed launch kept
+  constexpr int ROUNDS = 3, REPS = 2;
   hipEvent_t ev[REPS + 1];
   for (auto& e : ev) hipEventCreate(&e);
   GemmPick g;
   g.pick = 1;
   g.us.assign(kNumGemmVars, -1.f);
-  for (int kind = 0; kind < kNumGemmVars; ++kind) {
-    if (!gemm_variant_fits(kind, a.K)) continue;
-    launch_gemm(kind, t, true, st);
-    hipEventRecord(ev[0], st);
-    for (int r = 0; r < REPS; ++r) {
-      launch_gemm(kind, t, true, st);
-      hipEventRecord(ev[r + 1], st);
+  for (int kind = 0; kind < kNumGemmVars; ++kind)
+    if (gemm_variant_fits(kind, a.K)) launch_gemm(kind, t, true, st);  // warm
+  for (int round = 0; round < ROUNDS; ++round) {
+    for (int kind = 0; kind < kNumGemmVars; ++kind) {
+      if (!gemm_variant_fits(kind, a.K)) continue;
+      hipEventRecord(ev[0], st);
+      for (int r = 0; r < REPS; ++r) {
+        launch_gemm(kind, t, true, st);
+        hipEventRecord(ev[r + 1], st);
+      }
+      hipEventSynchronize(ev[REPS]);
+      for (int r = 0; r < REPS; ++r) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, ev[r], ev[r + 1]);
+        if (g.us[kind] < 0.f || ms * 1e3f < g.us[kind]) g.us[kind] = ms * 1e3f;
+      }
     }
-    hipEventSynchronize(ev[REPS]);
-    float best = 1e30f;
-    for (int r = 0; r < REPS; ++r) {
-      float ms = 0.f;
-      hipEventElapsedTime(&ms, ev[r], ev[r + 1]);
-      best = std::min(best, ms);
-    }
-    g.us[kind] = best * 1e3f;
-    if (g.us[kind] < g.us[g.pick] || g.us[g.pick] < 0.f) g.pick = kind;
   }
+  for (int kind = 0; kind < kNumGemmVars; ++kind)
+    if (g.us[kind] >= 0.f && (g.us[kind] < g.us[g.pick] || g.us[g.pick] < 0.f)) g.pick = kind;
   for (auto& e : ev) hipEventDestroy(e);
   hipFree(scratch);
   b.gemm_pick[key] = g;
