@@ -1991,7 +1991,7 @@ struct GemmVar {
 static const GemmVar kGemmVars[] = {
     {"64x64x32", 32},       {"128x128x32", 32},      {"64x64x64", 64},          {"128x64x64", 64},
     {"128x128x32w8", 32},   {"256x128x32w8", 32},    {"128x128x32w8pf2", 32},   {"256x128x32w8pf2", 32},
-    {"64x64x64pf2", 64},    {"128x128x64w8", 64},
+    {"64x64x64pf2", 64},    {"128x128x64w8", 64},    {"128x256x32w8", 32},
 };
 constexpr int kNumGemmVars = (int)(sizeof(kGemmVars) / sizeof(kGemmVars[0]));
 int gemm_variant_count() { return kNumGemmVars; }
@@ -2021,6 +2021,7 @@ static void launch_gemm(int kind, const GemmArgs& a, bool bf16, hipStream_t st) 
     case 7: launch_bt<256, 128, 32, 64, 64, 2>(a, st); break;
     case 8: launch_bt<64, 64, 64, 32, 32, 2>(a, st); break;
     case 9: launch_bt<128, 128, 64, 64, 32>(a, st); break;
+    case 10: launch_bt<128, 256, 32, 64, 64>(a, st); break;
     default: {
       const unsigned nb = (unsigned)(((a.M + 63) / 64) * ((a.N + 63) / 64));
       hipLaunchKernelGGL(k_gemm<uint16_t>, dim3(nb), dim3(256), 0, st, a);
