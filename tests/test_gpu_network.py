@@ -261,3 +261,34 @@ def test_gemm_autotuner_keeps_results_and_reports_choices():
     print("\n".join(rep))
     assert out[0][2] == [] and len(rep) >= 4
     assert all("tile=" in ln for ln in rep)
+
+
+def test_small_frames_in_one_batch_match_oracle():
+    """Frames with fewer leaves than one 16-leaf chunk of the highway and
+    pooling trees (K = 8) and with a single leaf and no tiles (K = 1), batched
+    with a K = 16 frame: FP32 factors against the oracle per frame, and the
+    learned-M PCG on the BF16 factors to a true 1e-6 relative residual."""
+    import torch
+    cfg = DEF
+    w = test_weights(cfg)
+    frames = [inputs.make_frame("plain1024", 1000), inputs.make_frame_grid(8, 8, 8, 7),
+              inputs.make_frame_grid(4, 4, 4, 3)]
+    s, fac = _run(cfg, frames, hp.HP_F32, w)
+    got = s.download_factors(fac, hp.HP_F32)
+    for f in range(len(frames)):
+        o = _oracle(cfg, s, f, w)
+        G, B, Ut, Vt, lam = got[f]
+        errs = {"G": relerr(G, hmatrix.gram(o["F"])), "Ut": relerr(Ut, o["Ut"]), "Vt": relerr(Vt, o["Vt"]),
+                "lam": relerr(lam, o["lam"])}
+        if o["U"].shape[0] > 0:
+            errs["B"] = relerr(B, hmatrix.coupling(o["U"], o["V"]))
+        print("frame", f, frames[f].n, {k: f"{v:.1e}" for k, v in errs.items()})
+        for k, v in errs.items():
+            assert v <= 1e-4, (f, k, v)
+    fb = s.B.new_factors(hp.HP_BF16)
+    s.B.infer_factors(torch.tensor(hp.pack_weights(cfg, w), device="cuda"), s.rho, s.sys, fb, hp.HP_BF16)
+    x = torch.zeros(s.B.ntot, dtype=torch.float64, device="cuda")
+    res = s.B.pcg_solve(s.sys, fb, s.b, x, hp.PRECOND_HMAT, fdtype=hp.HP_BF16, tol=1e-6)
+    for f, xf in enumerate(s.split(x)):
+        assert res[f][1] & hp.CONVERGED, (f, res[f])
+        assert np.linalg.norm(s.bo[f] - s.A[f] @ xf) / np.linalg.norm(s.bo[f]) <= 1e-6
