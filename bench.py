@@ -281,8 +281,9 @@ def _traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/hbm_traffic_counters.txt: FETCH_SIZE and WRITE_SIZE runs of
     rocprofv3, scaled by a plain copy of known size), or None when there is
-    none or when the kernel's source file changed since the counters were
-    taken (its SHA-256 is recorded beside the figures)."""
+    none or when one of the kernel's source files changed since the counters
+    were taken (the SHA-256 of their concatenation is recorded beside the
+    figures)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_counters.txt")
     if not os.path.exists(path):
@@ -293,8 +294,14 @@ def _traffic(kernel: str):
         kv = dict(t.split("=", 1) for t in line.strip().split(" | "))
         if kv.get("kernel") != kernel:
             continue
-        src = os.path.join(ROOT, kv["source"])
-        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != kv["source_sha256"]:
+        # the SHA-256 of the listed sources' bytes, concatenated in the order listed
+        h = hashlib.sha256()
+        for rel in kv["source"].split(","):
+            src = os.path.join(ROOT, rel)
+            if not os.path.exists(src):
+                return None
+            h.update(open(src, "rb").read())
+        if h.hexdigest() != kv["source_sha256"]:
             return None
         return float(kv["hbm_bytes_per_launch"])
     return None
