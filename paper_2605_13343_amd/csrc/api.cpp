@@ -33,6 +33,7 @@ Batch::~Batch() {
   if (train_free && train_ws) train_free(train_ws);
   if (net_train_free && net_train) net_train_free(net_train);
   for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+  for (auto& kv : infer_graphs) hipGraphExecDestroy(kv.second);
   for (void* p : allocs) hipFree(p);
   if (h_pin) hipHostFree(h_pin);
   if (cap_stream) hipStreamDestroy(cap_stream);
@@ -422,6 +423,10 @@ extern "C" hp_status hp_debug_set(hp_batch b, const char* name, int32_t value) {
   const std::string n = name;
   if (n == "attention_valu") {
     b->attn_valu = value != 0;
+    return HP_OK;
+  }
+  if (n == "infer_graph") {
+    b->infer_graph = value != 0;
     return HP_OK;
   }
   if (n == "keep_stages") {

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <array>
 #include <map>
+#include <set>
 #include <tuple>
 #include <vector>
 
@@ -114,6 +115,11 @@ struct Batch {
   void* net_train = nullptr;            // network training workspace (first hp_train_grad)
   void (*net_train_free)(void*) = nullptr;
   std::map<std::tuple<int, int, const void*, const void*, const void*, const void*, int>, hipGraphExec_t> graphs;
+  // inference graphs by (compute, weights, rho, sys, factors, switches); the
+  // (compute, switches) pairs that have run eagerly once (GEMM shapes tuned)
+  std::map<std::tuple<int, const void*, const void*, const void*, const void*, int>, hipGraphExec_t> infer_graphs;
+  std::set<std::pair<int, int>> infer_warm;
+  int infer_graph = 0;                  // replay inferences from a captured hipGraph after the first (opt-in)
   std::vector<void*> allocs;
 
   ~Batch();

@@ -292,3 +292,43 @@ def test_small_frames_in_one_batch_match_oracle():
     for f, xf in enumerate(s.split(x)):
         assert res[f][1] & hp.CONVERGED, (f, res[f])
         assert np.linalg.norm(s.bo[f] - s.A[f] @ xf) / np.linalg.norm(s.bo[f]) <= 1e-6
+
+
+def test_inference_graph_replays_match_eager():
+    """After the first call, hp_infer_factors captures the inference once and
+    replays it as a hipGraph.  Each replay reads the buffers' current contents:
+    with the inputs changed in place between replays, and eager work and
+    synchronisations in between, every replay equals the eager inference on
+    the same inputs bit for bit."""
+    import torch
+    cfg = DEF
+    w = test_weights(cfg)
+    frames = [inputs.make_frame("precision8192", 2000), inputs.make_frame("batch_mixed", 4001)]
+    s = Side(cfg, frames, with_net=True)
+    wt = torch.tensor(hp.pack_weights(cfg, w), device="cuda")
+    rho0 = s.rho.clone()
+    rho1 = s.rho * 1.7 + 0.3
+
+    def set_inputs(r):
+        s.rho.copy_(r)
+        s.B.assemble(s.rho, s.sys)
+
+    fac = s.B.new_factors(hp.HP_BF16)
+    s.B.debug_set("infer_graph", 0)
+    ref = []
+    for r in (rho0, rho1):
+        set_inputs(r)
+        s.B.infer_factors(wt, s.rho, s.sys, fac, hp.HP_BF16)
+        torch.cuda.synchronize()
+        ref.append(fac.clone())
+    assert not torch.equal(ref[0], ref[1])
+    s.B.debug_set("infer_graph", 1)
+    for rep in range(5):
+        set_inputs((rho0, rho1)[rep % 2])
+        fac.zero_()
+        s.B.infer_factors(wt, s.rho, s.sys, fac, hp.HP_BF16)
+        torch.cuda.synchronize()
+        assert torch.equal(fac, ref[rep % 2]), rep
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
