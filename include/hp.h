@@ -213,12 +213,12 @@ hp_status hp_weight_info(const hp_model_config* cfg, int32_t index, char* name, 
  * HP_F32 runs everything in FP32 and writes FP32 factors.
  *   d_weights [weight_floats] FP32; d_rho [ntot] FP32 (Morton);
  *   d_sys from hp_assemble; d_factors per hp_batch_info(compute).
- * Asynchronous on the batch stream.  The first call per compute type runs
- * eagerly and tunes the GEMM tiles (it synchronises and allocates); later
- * calls replay an inference captured once per (d_weights, d_rho, d_sys,
- * d_factors) buffer set as a hipGraph (it reads the buffers' contents at each
- * replay; at most 8 such sets are kept).  Results equal the eager path's bit
- * for bit.  The "infer_graph" switch of hp_debug_set (0/1) turns this off. */
+ * Asynchronous on the batch stream.  The first call per compute type tunes
+ * the GEMM tiles (it synchronises and allocates).  With the "infer_graph"
+ * switch of hp_debug_set on (default off), later calls replay an inference
+ * captured once per (d_weights, d_rho, d_sys, d_factors) buffer set as a
+ * hipGraph (it reads the buffers' contents at each replay; at most 8 such
+ * sets are kept), with results equal to the eager path's bit for bit. */
 hp_status hp_infer_factors(hp_batch b, const float* d_weights, const float* d_rho,
                            const float* d_sys, void* d_factors, int32_t compute);
 
@@ -310,7 +310,7 @@ hp_status hp_train_step(hp_batch b, float* d_weights, float* d_grad, float* d_m,
  * For tests; HP_E_INVALID on an unknown name or a size beyond the buffer. */
 hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, int64_t bytes);
 
-/* Test switches of one batch.  "infer_graph" (0/1, default 1): replay
+/* Test switches of one batch.  "infer_graph" (0/1, default 0): replay
  * inferences from a captured hipGraph after the first (see
  * hp_infer_factors); "keep_stages" (0/1, default 0): keep the
  * encoder output and the pooled off-diagonal tokens of each inference for
