@@ -317,12 +317,14 @@ hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, int64_t bytes
  * hp_debug_copy ("enc", "xo0"; two device copies per inference);
  * "attention_valu" (0/1): with BF16 compute, run
  * the within-leaf attention on the vector ALUs instead of the matrix cores;
- * "gemm_variant" (-1 or 0..10, default -1): run every BF16 GEMM whose K the
+ * "gemm_variant" (-1 or 0..13, default -1): run every BF16 GEMM whose K the
  * variant's K step divides on that tile variant (block tile x K step, "w8":
  * 8 waves, "pf2": loads two K steps ahead; 0: 64x64x32, 1: 128x128x32, 2:
  * 64x64x64, 3: 128x64x64, 4: 128x128x32w8, 5: 256x128x32w8, 6:
  * 128x128x32w8pf2, 7: 256x128x32w8pf2, 8: 64x64x64pf2, 9: 128x128x64w8,
- * 10: 128x256x32w8;
+ * 10: 128x256x32w8; "dl", 11-13: K through an LDS ring of 4 or 3 stages
+ * filled straight from global memory: 11: dl128x128x32s4, 12:
+ * dl256x128x32s3, 13: dl128x256x32s3;
  * other GEMMs on variant 0), -1 lets the autotuner choose (the tests
  * compare the variants); "gemm_small_tiles" (0/1): the same as gemm_variant
  * 0 / -1; "ffn_fused" (0/1, default 0): with BF16 compute outside training,

@@ -1987,6 +1987,97 @@ hp_status network_alloc(Batch& b) {
   return s;
 }
 
+// BF16 tile kernel with a deeper K pipeline: K steps of 32 pass through an
+// LDS ring of ST stages filled straight from global memory
+// (global_load_lds_dwordx4: one wave instruction writes 1 KB = 16 rows of 64
+// bytes, lane i -> row i / 4, 16-byte position i % 4), so ST - 1 steps of
+// loads are in flight while a step is multiplied.  Rows are unpadded; the
+// 16-byte chunk c of row r sits at position c ^ ((r / 4) % 4), which keeps
+// the 16-byte operand reads of 16 consecutive rows on distinct banks.  Rows
+// past M (or N) load the last row; they only feed outputs that are not
+// stored.  Same MFMA sequence along K and same epilogue as k_gemm_bt, so the
+// results are bit-identical to it.
+template <int BM, int BN, int WM, int WN, int ST>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmArgs a, int tiles_n) {
+  constexpr int NWN = BN / WN, NW = (BM / WM) * NWN, BK = 32, FM = WM / 32, FN = WN / 32;
+  constexpr int BLK = (BM + BN) / 16, LPW = BLK / NW;  // 1 KB blocks per stage, per wave
+  static_assert(BLK % NW == 0, "stage blocks do not split over the waves");
+  static_assert(ST >= 3, "at least three stages");
+  __shared__ __attribute__((aligned(1024))) uint16_t ring[ST][(BM + BN) * BK];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int nblk = (int)gridDim.x, id = (int)blockIdx.x;
+  const int lin = (nblk % 8 == 0) ? (id % 8) * (nblk / 8) + id / 8 : id;
+  const int m0 = (lin / tiles_n) * BM, n0 = (lin % tiles_n) * BN;
+  const int wm = (wave / NWN) * WM, wn = (wave % NWN) * WN;
+  const uint16_t* X = (const uint16_t*)a.X;
+  const uint16_t* W = (const uint16_t*)a.Wt;
+  // this lane's source row and chunk for each of the wave's blocks (k offset added per step)
+  const uint16_t* src[LPW];
+#pragma unroll
+  for (int q = 0; q < LPW; ++q) {
+    const int blk = wave * LPW + q, crow = 16 * blk + (lane >> 2);  // row of the combined [A | B] stage
+    const int c = (lane & 3) ^ ((crow >> 2) & 3);                   // the chunk that lands at position lane % 4
+    src[q] = crow < BM ? X + (int64_t)min(m0 + crow, a.M - 1) * a.ldx + 8 * c
+                       : W + (int64_t)min(n0 + crow - BM, a.N - 1) * a.K + 8 * c;
+  }
+  auto issue = [&](int slot, int k0) {
+#pragma unroll
+    for (int q = 0; q < LPW; ++q) {
+      const int blk = wave * LPW + q;
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src[q] + k0),
+                                       (__attribute__((address_space(3))) void*)&ring[slot][blk * 512], 16, 0, 0);
+    }
+  };
+  // 16-byte operand of row r (of the A part, or of the B part at row BM + r), k chunk c
+  auto opnd = [&](int slot, int row, int c) {
+    return __builtin_bit_cast(bf16x8_t, *(const uint4*)&ring[slot][row * BK + 8 * (c ^ ((row >> 2) & 3))]);
+  };
+  f32x16_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[i][j][q] = 0.f;
+  const int nk = a.K / BK;
+#pragma unroll
+  for (int s2 = 0; s2 < ST - 1; ++s2)
+    if (s2 < nk) issue(s2, s2 * BK);
+  for (int kt = 0; kt < nk; ++kt) {
+    // step kt has landed once only the later steps' loads are outstanding
+    if (kt + ST - 2 < nk) asm volatile("s_waitcnt vmcnt(%0)" ::"n"((ST - 2) * LPW) : "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // a bare barrier (__syncthreads' fence would wait for every load in
+    // flight): this wave's reads of step kt - 1 are done, its part of step kt
+    // has landed, so after the barrier every part of step kt is in LDS and
+    // step kt - 1's slot may be refilled
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (kt + ST - 1 < nk) issue((kt + ST - 1) % ST, (kt + ST - 1) * BK);
+    const int slot = kt % ST;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      const int c = kk / 8 + (lane >> 5);
+      bf16x8_t av[FM], bv[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) av[i] = opnd(slot, wm + 32 * i + (lane & 31), c);
+#pragma unroll
+      for (int j = 0; j < FN; ++j) bv[j] = opnd(slot, BM + wn + 32 * j + (lane & 31), c);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bv[j], av[i], acc[i][j], 0, 0, 0);
+    }
+  }
+  const bool vec = gemm_vec_ok(a, 2);
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+      gemm_epilogue<uint16_t>(a, acc[i][j], m0 + wm + 32 * i + (lane & 31), n0 + wn + 32 * j + 4 * (lane >> 5), vec);
+}
+
 // BF16 GEMM variants, indexed by the autotuner's "kind": block tile BM x BN,
 // K step BK (K must be a multiple of it), waves.
 struct GemmVar {
@@ -1997,6 +2088,7 @@ static const GemmVar kGemmVars[] = {
     {"64x64x32", 32},       {"128x128x32", 32},      {"64x64x64", 64},          {"128x64x64", 64},
     {"128x128x32w8", 32},   {"256x128x32w8", 32},    {"128x128x32w8pf2", 32},   {"256x128x32w8pf2", 32},
     {"64x64x64pf2", 64},    {"128x128x64w8", 64},    {"128x256x32w8", 32},
+    {"dl128x128x32s4", 32}, {"dl256x128x32s3", 32},  {"dl128x256x32s3", 32},
 };
 constexpr int kNumGemmVars = (int)(sizeof(kGemmVars) / sizeof(kGemmVars[0]));
 int gemm_variant_count() { return kNumGemmVars; }
@@ -2008,6 +2100,13 @@ static void launch_bt(const GemmArgs& a, hipStream_t st) {
   const int tn = (a.N + BN - 1) / BN, tm = (a.M + BM - 1) / BM;
   hipLaunchKernelGGL((k_gemm_bt<BM, BN, BK, WM, WN, PF>), dim3((unsigned)(tm * tn)), dim3((BM / WM) * (BN / WN) * 64),
                      0, st, a, tn);
+}
+
+template <int BM, int BN, int WM, int WN, int ST>
+static void launch_dl(const GemmArgs& a, hipStream_t st) {
+  const int tn = (a.N + BN - 1) / BN, tm = (a.M + BM - 1) / BM;
+  hipLaunchKernelGGL((k_gemm_dl<BM, BN, WM, WN, ST>), dim3((unsigned)(tm * tn)), dim3((BM / WM) * (BN / WN) * 64), 0,
+                     st, a, tn);
 }
 
 static void launch_gemm(int kind, const GemmArgs& a, bool bf16, hipStream_t st) {
@@ -2027,6 +2126,9 @@ static void launch_gemm(int kind, const GemmArgs& a, bool bf16, hipStream_t st) 
     case 8: launch_bt<64, 64, 64, 32, 32, 2>(a, st); break;
     case 9: launch_bt<128, 128, 64, 64, 32>(a, st); break;
     case 10: launch_bt<128, 256, 32, 64, 64>(a, st); break;
+    case 11: launch_dl<128, 128, 64, 32, 4>(a, st); break;
+    case 12: launch_dl<256, 128, 64, 64, 3>(a, st); break;
+    case 13: launch_dl<128, 256, 64, 64, 3>(a, st); break;
     default: {
       const unsigned nb = (unsigned)(((a.M + 63) / 64) * ((a.N + 63) / 64));
       hipLaunchKernelGGL(k_gemm<uint16_t>, dim3(nb), dim3(256), 0, st, a);

@@ -214,7 +214,7 @@ def test_bf16_fused_ffn_matches_two_gemm_ffn(cfg, recipe, seed):
     assert e_G <= BF16_BOUND["G"] and e_B <= BF16_BOUND["B"]
 
 
-N_GEMM_VARIANTS = 11  # tile variants the library header lists for "gemm_variant"
+N_GEMM_VARIANTS = 14  # tile variants the library header lists for "gemm_variant"
 
 
 @pytest.mark.parametrize("cfg,recipe,seed", [(PLAIN, "plain1024", 1000), (DEF, "precision8192", 2000)])
