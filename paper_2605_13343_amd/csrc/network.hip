@@ -59,18 +59,25 @@ struct GemmArgs {
   int M, N, act;
 };
 
-// GELU of the BF16 path: erf by Abramowitz & Stegun, Handbook of
-// Mathematical Functions, formula 7.1.26 (a rational function of t = 1 / (1 +
-// p z) times exp(-z^2), absolute error at most 1.5e-7, far below the BF16
-// rounding of the value that follows); one exp and one reciprocal, no
-// branches.  The FP32 path keeps the library erff.
+// GELU of the BF16 path from the complementary error function of
+// Abramowitz & Stegun, Handbook of Mathematical Functions, formula 7.1.26:
+// erfc(z) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-z^2), t = 1 / (1 +
+// p z), z >= 0, absolute error at most 1.5e-7.  With z = |x| / sqrt(2) and
+// q = erfc(z) / 2, GELU(x) = x (1 + erf(x / sqrt 2)) / 2 = max(x, 0) - |x| q
+// for either sign; the 1/2 is folded into a1..a5 and 1/sqrt 2 into p and the
+// exponent.  14 operations (one reciprocal, one exp2), no branches, and no
+// cancellation in 1 + erf for negative x; far below the BF16 rounding of the
+// value that follows.  The FP32 path keeps the library erff.
 __device__ inline float gelu_bf16path(float x) {
-  const float z = fabsf(x) * 0.7071067811865476f;
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, z, 1.f));
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(ax, 0.23164189758f, 1.f));  // p / sqrt 2
   const float poly =
-      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
-  const float e = 1.f - poly * __expf(-z * z);
-  return 0.5f * x * (1.f + copysignf(e, x));
+      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 0.5307027145f, -0.7265760135f), 0.7107068705f), -0.142248368f),
+               0.127414796f);
+  const float e2 = __builtin_amdgcn_exp2f(x * (x * -0.72134752044f));  // exp(-x^2 / 2) = 2^(-x^2 log2(e) / 2)
+  float relu;  // max(x, 0) as one instruction (fmaxf adds a NaN-canonicalising max)
+  asm("v_max_f32 %0, 0, %1" : "=v"(relu) : "v"(x));
+  return fmaf(-ax, poly * e2, relu);
 }
 
 template <typename AT> __device__ inline float gemm_gelu(float v);
@@ -136,6 +143,9 @@ __device__ inline void gemm_epilogue(const GemmArgs& a, const f32x16_t& acc, int
         rv[4 * q + 2] = t.z;
         rv[4 * q + 3] = t.w;
       }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) rv[e] = 0.f;  // added unconditionally below (cheaper than a select)
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -148,10 +158,8 @@ __device__ inline void gemm_epilogue(const GemmArgs& a, const f32x16_t& acc, int
 #pragma unroll
         for (int c = 0; c < 4; ++c) v[c] = gemm_gelu<AT>(v[c]);
       }
-      if (has_res) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) v[c] += rv[4 * q + c];
-      }
+      for (int c = 0; c < 4; ++c) v[c] += rv[4 * q + c];
       if (has_yf) *(float4*)(yf + c0) = make_float4(v[0], v[1], v[2], v[3]);
       if (has_yb) {
         if constexpr (sizeof(AT) == 2)
