@@ -97,6 +97,31 @@ __device__ inline uint32_t pack_bf16x2(float lo, float hi) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
 }
 
+// Bias of the four column groups cb + 8q .. cb + 8q + 3 (q = 0..3) of a
+// fragment, zero without a bias.
+__device__ inline void gemm_bias16(const GemmArgs& a, int cb, float bv[16]) {
+  if (a.bias) {
+    if (((uintptr_t)a.bias & 15) == 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 t = *(const float4*)(a.bias + cb + 8 * q);
+        bv[4 * q] = t.x;
+        bv[4 * q + 1] = t.y;
+        bv[4 * q + 2] = t.z;
+        bv[4 * q + 3] = t.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bv[4 * q + c] = a.bias[cb + 8 * q + c];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) bv[e] = 0.f;
+  }
+}
+
 template <typename AT>
 __device__ inline void gemm_epilogue(const GemmArgs& a, const f32x16_t& acc, int row, int cb, bool vec) {
   if (row >= a.M) return;
@@ -114,26 +139,7 @@ __device__ inline void gemm_epilogue(const GemmArgs& a, const f32x16_t& acc, int
     // every column of the fragment in range: the bias and residual loads of
     // all four column groups are issued together, then one wait
     float bv[16], rv[16];
-    if (a.bias) {
-      if (((uintptr_t)a.bias & 15) == 0) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float4 t = *(const float4*)(a.bias + cb + 8 * q);
-          bv[4 * q] = t.x;
-          bv[4 * q + 1] = t.y;
-          bv[4 * q + 2] = t.z;
-          bv[4 * q + 3] = t.w;
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) bv[4 * q + c] = a.bias[cb + 8 * q + c];
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) bv[e] = 0.f;
-    }
+    gemm_bias16(a, cb, bv);
     if (has_res) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -2077,6 +2083,106 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmArgs
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bv[j], av[i], acc[i][j], 0, 0, 0);
     }
+  }
+  // A full block tile whose only output is the BF16 one leaves through LDS:
+  // from the fragments a lane holds 8 bytes of each of 4 column groups of one
+  // row, so a direct store sends 32 rows' pieces per instruction; restaged,
+  // 8 lanes write one row's 128 contiguous bytes.  The values are those of
+  // the direct epilogue (bias, activation, a zero residual, BF16 rounding).
+  static_assert(NW * WM * WN <= ST * (BM + BN) * BK, "staging tiles exceed the ring");
+  if (a.Yb && !a.Yf && !a.resid && !a.pre && m0 + BM <= a.M && n0 + BN <= a.N &&
+      (((uintptr_t)a.Yb | (uintptr_t)(2 * a.ldb)) & 15) == 0) {
+    __syncthreads();  // every wave is done with the ring's operands
+    uint16_t* stg = &ring[0][0] + wave * (WM * WN);
+    // element (r, col) of the wave's WM x WN tile; the 16-byte chunks of each
+    // 128-byte LDS line are XOR-swizzled by the line index, so the fragment
+    // writes (32 rows at once) and the row reads both spread over all banks
+    auto at = [&](int r, int col) {
+      const int byte = 2 * (r * WN + col), line = byte >> 7;
+      return ((line << 7) | (((byte >> 4) & 7) ^ (line & 7)) << 4 | (byte & 15)) >> 1;
+    };
+    const bool gelu = a.act == 1;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int cl = 32 * j + 4 * (lane >> 5);
+        float bv[16];
+        gemm_bias16(a, n0 + wn + cl, bv);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float v[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            v[c] = acc[i][j][4 * q + c] + bv[4 * q + c];
+            if (gelu) v[c] = gelu_bf16path(v[c]);
+            v[c] += 0.f;
+          }
+          *(uint2*)&stg[at(32 * i + (lane & 31), cl + 8 * q)] =
+              make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+        }
+      }
+    // the wave reads back only its own tile, and one wave's LDS accesses
+    // complete in order
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    constexpr int LPR = WN / 8, RPI = 64 / LPR;  // lanes per row, rows per store
+    uint16_t* yb = (uint16_t*)a.Yb + (int64_t)(m0 + wm) * a.ldb + n0 + wn;
+#pragma unroll
+    for (int t = 0; t < WM / RPI; ++t) {
+      const int r = t * RPI + lane / LPR, col = 8 * (lane % LPR);
+      *(uint4*)(yb + (int64_t)r * a.ldb + col) = *(const uint4*)&stg[at(r, col)];
+    }
+    return;
+  }
+  // A full block tile whose only output is the BF16 one leaves through LDS:
+  // from the fragments a lane holds 8 bytes of each of 4 column groups of one
+  // row, so a direct store sends 32 rows' pieces per instruction; restaged,
+  // 8 lanes write one row's 128 contiguous bytes.  The values are those of
+  // the direct epilogue (bias, activation, a zero residual, BF16 rounding).
+  static_assert(NW * WM * WN <= ST * (BM + BN) * BK, "staging tiles exceed the ring");
+  if (a.Yb && !a.Yf && !a.resid && !a.pre && m0 + BM <= a.M && n0 + BN <= a.N &&
+      (((uintptr_t)a.Yb | (uintptr_t)(2 * a.ldb)) & 15) == 0) {
+    __syncthreads();  // every wave is done with the ring's operands
+    uint16_t* stg = &ring[0][0] + wave * (WM * WN);
+    // element (r, col) of the wave's WM x WN tile; the 16-byte chunks of each
+    // 128-byte LDS line are XOR-swizzled by the line index, so the fragment
+    // writes (32 rows at once) and the row reads both spread over all banks
+    auto at = [&](int r, int col) {
+      const int byte = 2 * (r * WN + col), line = byte >> 7;
+      return ((line << 7) | (((byte >> 4) & 7) ^ (line & 7)) << 4 | (byte & 15)) >> 1;
+    };
+    const bool gelu = a.act == 1;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int cl = 32 * j + 4 * (lane >> 5);
+        float bv[16];
+        gemm_bias16(a, n0 + wn + cl, bv);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float v[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            v[c] = acc[i][j][4 * q + c] + bv[4 * q + c];
+            if (gelu) v[c] = gelu_bf16path(v[c]);
+            v[c] += 0.f;
+          }
+          *(uint2*)&stg[at(32 * i + (lane & 31), cl + 8 * q)] =
+              make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+        }
+      }
+    // the wave reads back only its own tile, and one wave's LDS accesses
+    // complete in order
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    constexpr int LPR = WN / 8, RPI = 64 / LPR;  // lanes per row, rows per store
+    uint16_t* yb = (uint16_t*)a.Yb + (int64_t)(m0 + wm) * a.ldb + n0 + wn;
+#pragma unroll
+    for (int t = 0; t < WM / RPI; ++t) {
+      const int r = t * RPI + lane / LPR, col = 8 * (lane % LPR);
+      *(uint4*)(yb + (int64_t)r * a.ldb + col) = *(const uint4*)&stg[at(r, col)];
+    }
+    return;
   }
   const bool vec = gemm_vec_ok(a, 2);
 #pragma unroll
