@@ -2184,6 +2184,66 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmArgs
     }
     return;
   }
+  // With an FP32 output or a residual (and no pre-activation copy) a full
+  // tile goes through LDS as FP32 in passes of 32 rows: a lane then reads
+  // and writes 16 contiguous bytes and a row's columns leave together; the
+  // residual is read the same way.  Same values as the direct epilogue.
+  static_assert(NW * 32 * WN * 4 <= ST * (BM + BN) * BK * 2, "FP32 staging tiles exceed the ring");
+  if (!a.pre && (a.Yf || a.resid) && m0 + BM <= a.M && n0 + BN <= a.N && gemm_vec_ok(a, 2)) {
+    __syncthreads();  // every wave is done with the ring's operands
+    float* stg = (float*)&ring[0][0] + wave * (32 * WN);
+    auto at = [&](int r, int col) {
+      const int byte = 4 * (r * WN + col), line = byte >> 7;
+      return ((line << 7) | (((byte >> 4) & 7) ^ (line & 7)) << 4 | (byte & 15)) >> 2;
+    };
+    const bool gelu = a.act == 1;
+    constexpr int LPR = WN / 4, RPI = 64 / LPR;  // lanes per row, rows per access
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int cl = 32 * j + 4 * (lane >> 5);
+        float bv[16];
+        gemm_bias16(a, n0 + wn + cl, bv);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float v[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            v[c] = acc[i][j][4 * q + c] + bv[4 * q + c];
+            if (gelu) v[c] = gelu_bf16path(v[c]);
+          }
+          *(float4*)&stg[at(lane & 31, cl + 8 * q)] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+      }
+      // the wave reads back only its own rows, and one wave's LDS accesses
+      // complete in order (so the next pass may overwrite them after these reads)
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+      for (int t = 0; t < 32 / RPI; ++t) {
+        const int r = t * RPI + lane / LPR, col = 4 * (lane % LPR);
+        const float4 u = *(const float4*)&stg[at(r, col)];
+        const int64_t row = m0 + wm + 32 * i + r;
+        const int gc = n0 + wn + col;
+        float v[4] = {u.x, u.y, u.z, u.w};
+        if (a.resid) {
+          const float4 rr = *(const float4*)(a.resid + row * a.ldr + gc);
+          v[0] += rr.x;
+          v[1] += rr.y;
+          v[2] += rr.z;
+          v[3] += rr.w;
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) v[c] += 0.f;
+        }
+        if (a.Yf) *(float4*)(a.Yf + row * a.ldf + gc) = make_float4(v[0], v[1], v[2], v[3]);
+        if (a.Yb)
+          *(uint2*)((uint16_t*)a.Yb + row * a.ldb + gc) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+      }
+      asm volatile("" ::: "memory");
+    }
+    return;
+  }
   const bool vec = gemm_vec_ok(a, 2);
 #pragma unroll
   for (int i = 0; i < FM; ++i)
