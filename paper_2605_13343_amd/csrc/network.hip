@@ -9,6 +9,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <type_traits>
+
 #include "batch.h"
 
 namespace hp {
@@ -122,8 +124,8 @@ __device__ inline void gemm_bias16(const GemmArgs& a, int cb, float bv[16]) {
   }
 }
 
-template <typename AT>
-__device__ inline void gemm_epilogue(const GemmArgs& a, const f32x16_t& acc, int row, int cb, bool vec) {
+template <typename AT, bool GELU>
+__device__ inline void gemm_epilogue_t(const GemmArgs& a, const f32x16_t& acc, int row, int cb, bool vec) {
   if (row >= a.M) return;
   const int64_t r = row;
   // row bases formed once; the columns below are 32-bit offsets from them
@@ -131,7 +133,7 @@ __device__ inline void gemm_epilogue(const GemmArgs& a, const f32x16_t& acc, int
   const float* res = a.resid ? a.resid + r * a.ldr : nullptr;
   float* yf = a.Yf ? a.Yf + r * a.ldf : nullptr;
   AT* yb = a.Yb ? (AT*)a.Yb + r * a.ldb : nullptr;
-  const bool gelu = a.act == 1;
+  constexpr bool gelu = GELU;
   // presence tests on the (uniform) kernel arguments, not on the row pointers
   const bool has_pre = a.pre != nullptr, has_res = a.resid != nullptr, has_yf = a.Yf != nullptr,
              has_yb = a.Yb != nullptr;
@@ -149,9 +151,6 @@ __device__ inline void gemm_epilogue(const GemmArgs& a, const f32x16_t& acc, int
         rv[4 * q + 2] = t.z;
         rv[4 * q + 3] = t.w;
       }
-    } else {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) rv[e] = 0.f;  // added unconditionally below (cheaper than a select)
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -164,8 +163,10 @@ __device__ inline void gemm_epilogue(const GemmArgs& a, const f32x16_t& acc, int
 #pragma unroll
         for (int c = 0; c < 4; ++c) v[c] = gemm_gelu<AT>(v[c]);
       }
+      if (has_res) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) v[c] += rv[4 * q + c];
+        for (int c = 0; c < 4; ++c) v[c] += rv[4 * q + c];
+      }
       if (has_yf) *(float4*)(yf + c0) = make_float4(v[0], v[1], v[2], v[3]);
       if (has_yb) {
         if constexpr (sizeof(AT) == 2)
@@ -190,6 +191,14 @@ __device__ inline void gemm_epilogue(const GemmArgs& a, const f32x16_t& acc, int
       if (has_yb) yb[col] = to_act<AT>(x);
     }
   }
+}
+
+// The activation is a template parameter so that the per-element code has no
+// branches; the launch-wide choice is taken once here.
+template <typename AT>
+__device__ inline void gemm_epilogue(const GemmArgs& a, const f32x16_t& acc, int row, int cb, bool vec) {
+  if (a.act == 1) gemm_epilogue_t<AT, true>(a, acc, row, cb, vec);
+  else gemm_epilogue_t<AT, false>(a, acc, row, cb, vec);
 }
 
 // Whether every output and the residual admit the four-wide accesses of the
@@ -2011,8 +2020,11 @@ hp_status network_alloc(Batch& b) {
 // past M (or N) load the last row; they only feed outputs that are not
 // stored.  Same MFMA sequence along K and same epilogue as k_gemm_bt, so the
 // results are bit-identical to it.
+// Two blocks per CU (their rings fit the LDS together) need at most 128 VGPRs
+// per lane: four waves per SIMD.
 template <int BM, int BN, int WM, int WN, int ST>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmArgs a, int tiles_n) {
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) __attribute__((amdgpu_waves_per_eu(4)))
+void k_gemm_dl(GemmArgs a, int tiles_n) {
   constexpr int NWN = BN / WN, NW = (BM / WM) * NWN, BK = 32, FM = WM / 32, FN = WN / 32;
   constexpr int BLK = (BM + BN) / 16, LPW = BLK / NW;  // 1 KB blocks per stage, per wave
   static_assert(BLK % NW == 0, "stage blocks do not split over the waves");
@@ -2088,7 +2100,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmArgs
   // from the fragments a lane holds 8 bytes of each of 4 column groups of one
   // row, so a direct store sends 32 rows' pieces per instruction; restaged,
   // 8 lanes write one row's 128 contiguous bytes.  The values are those of
-  // the direct epilogue (bias, activation, a zero residual, BF16 rounding).
+  // the direct epilogue (bias, activation, BF16 rounding).
   static_assert(NW * WM * WN <= ST * (BM + BN) * BK, "staging tiles exceed the ring");
   if (a.Yb && !a.Yf && !a.resid && !a.pre && m0 + BM <= a.M && n0 + BN <= a.N &&
       (((uintptr_t)a.Yb | (uintptr_t)(2 * a.ldb)) & 15) == 0) {
@@ -2101,27 +2113,31 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmArgs
       const int byte = 2 * (r * WN + col), line = byte >> 7;
       return ((line << 7) | (((byte >> 4) & 7) ^ (line & 7)) << 4 | (byte & 15)) >> 1;
     };
-    const bool gelu = a.act == 1;
+    // the activation as a compile-time choice: branch-free per-element code
+    auto fill = [&](auto gelu_tag) {
+      constexpr bool GELU = decltype(gelu_tag)::value;
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        const int cl = 32 * j + 4 * (lane >> 5);
-        float bv[16];
-        gemm_bias16(a, n0 + wn + cl, bv);
+        for (int j = 0; j < FN; ++j) {
+          const int cl = 32 * j + 4 * (lane >> 5);
+          float bv[16];
+          gemm_bias16(a, n0 + wn + cl, bv);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          float v[4];
+          for (int q = 0; q < 4; ++q) {
+            float v[4];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            v[c] = acc[i][j][4 * q + c] + bv[4 * q + c];
-            if (gelu) v[c] = gelu_bf16path(v[c]);
-            v[c] += 0.f;
+            for (int c = 0; c < 4; ++c) {
+              v[c] = acc[i][j][4 * q + c] + bv[4 * q + c];
+              if constexpr (GELU) v[c] = gelu_bf16path(v[c]);
+            }
+            *(uint2*)&stg[at(32 * i + (lane & 31), cl + 8 * q)] =
+                make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
           }
-          *(uint2*)&stg[at(32 * i + (lane & 31), cl + 8 * q)] =
-              make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
         }
-      }
+    };
+    if (a.act == 1) fill(std::true_type{});
+    else fill(std::false_type{});
     // the wave reads back only its own tile, and one wave's LDS accesses
     // complete in order
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -2138,7 +2154,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmArgs
   // from the fragments a lane holds 8 bytes of each of 4 column groups of one
   // row, so a direct store sends 32 rows' pieces per instruction; restaged,
   // 8 lanes write one row's 128 contiguous bytes.  The values are those of
-  // the direct epilogue (bias, activation, a zero residual, BF16 rounding).
+  // the direct epilogue (bias, activation, BF16 rounding).
   static_assert(NW * WM * WN <= ST * (BM + BN) * BK, "staging tiles exceed the ring");
   if (a.Yb && !a.Yf && !a.resid && !a.pre && m0 + BM <= a.M && n0 + BN <= a.N &&
       (((uintptr_t)a.Yb | (uintptr_t)(2 * a.ldb)) & 15) == 0) {
@@ -2151,27 +2167,31 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmArgs
       const int byte = 2 * (r * WN + col), line = byte >> 7;
       return ((line << 7) | (((byte >> 4) & 7) ^ (line & 7)) << 4 | (byte & 15)) >> 1;
     };
-    const bool gelu = a.act == 1;
+    // the activation as a compile-time choice: branch-free per-element code
+    auto fill = [&](auto gelu_tag) {
+      constexpr bool GELU = decltype(gelu_tag)::value;
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        const int cl = 32 * j + 4 * (lane >> 5);
-        float bv[16];
-        gemm_bias16(a, n0 + wn + cl, bv);
+        for (int j = 0; j < FN; ++j) {
+          const int cl = 32 * j + 4 * (lane >> 5);
+          float bv[16];
+          gemm_bias16(a, n0 + wn + cl, bv);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          float v[4];
+          for (int q = 0; q < 4; ++q) {
+            float v[4];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            v[c] = acc[i][j][4 * q + c] + bv[4 * q + c];
-            if (gelu) v[c] = gelu_bf16path(v[c]);
-            v[c] += 0.f;
+            for (int c = 0; c < 4; ++c) {
+              v[c] = acc[i][j][4 * q + c] + bv[4 * q + c];
+              if constexpr (GELU) v[c] = gelu_bf16path(v[c]);
+            }
+            *(uint2*)&stg[at(32 * i + (lane & 31), cl + 8 * q)] =
+                make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
           }
-          *(uint2*)&stg[at(32 * i + (lane & 31), cl + 8 * q)] =
-              make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
         }
-      }
+    };
+    if (a.act == 1) fill(std::true_type{});
+    else fill(std::false_type{});
     // the wave reads back only its own tile, and one wave's LDS accesses
     // complete in order
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -2196,10 +2216,9 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmArgs
       const int byte = 4 * (r * WN + col), line = byte >> 7;
       return ((line << 7) | (((byte >> 4) & 7) ^ (line & 7)) << 4 | (byte & 15)) >> 2;
     };
-    const bool gelu = a.act == 1;
     constexpr int LPR = WN / 4, RPI = 64 / LPR;  // lanes per row, rows per access
-#pragma unroll
-    for (int i = 0; i < FM; ++i) {
+    auto fill = [&](int i, auto gelu_tag) {
+      constexpr bool GELU = decltype(gelu_tag)::value;
 #pragma unroll
       for (int j = 0; j < FN; ++j) {
         const int cl = 32 * j + 4 * (lane >> 5);
@@ -2211,11 +2230,16 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmArgs
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             v[c] = acc[i][j][4 * q + c] + bv[4 * q + c];
-            if (gelu) v[c] = gelu_bf16path(v[c]);
+            if constexpr (GELU) v[c] = gelu_bf16path(v[c]);
           }
           *(float4*)&stg[at(lane & 31, cl + 8 * q)] = make_float4(v[0], v[1], v[2], v[3]);
         }
       }
+    };
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      if (a.act == 1) fill(i, std::true_type{});
+      else fill(i, std::false_type{});
       // the wave reads back only its own rows, and one wave's LDS accesses
       // complete in order (so the next pass may overwrite them after these reads)
       asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -2232,9 +2256,6 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_dl(GemmArgs
           v[1] += rr.y;
           v[2] += rr.z;
           v[3] += rr.w;
-        } else {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) v[c] += 0.f;
         }
         if (a.Yf) *(float4*)(a.Yf + row * a.ldf + gc) = make_float4(v[0], v[1], v[2], v[3]);
         if (a.Yb)
