@@ -118,6 +118,31 @@ __host__ __device__ inline uint16_t f32_to_bf16(float f) {  // round to nearest 
   return (uint16_t)(c.u >> 16);
 }
 
+// Cross-lane sums on the VALU's data-parallel-primitive (DPP) lane paths
+// instead of LDS permutes.  row16_sum: the sum over each aligned group of 16
+// lanes, with the same bits in every lane of the group (partners by quad
+// permutations, then the half-row and row mirrors).  wave_total: the sum over
+// all 64 lanes (row broadcasts fold the four rows into lane 63), returned as
+// a wave-uniform value.  Every lane of the wave must be active.
+template <int CTRL>
+__device__ inline float dpp_move(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ inline float row16_sum(float v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
+  return v;
+}
+__device__ inline float wave_total(float v) {
+  v = row16_sum(v);
+  // row_bcast:15 into rows 1 and 3, then row_bcast:31 into rows 2 and 3
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xC, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
 template <typename T> __device__ inline float ldf(const T* p, int64_t i);
 template <> __device__ inline float ldf<float>(const float* p, int64_t i) { return p[i]; }
 template <> __device__ inline float ldf<uint16_t>(const uint16_t* p, int64_t i) { return bf16_to_f32(p[i]); }

@@ -27,17 +27,12 @@ template <typename AT> __device__ inline AT to_act(float v);
 template <> __device__ inline float to_act<float>(float v) { return v; }
 template <> __device__ inline uint16_t to_act<uint16_t>(float v) { return f32_to_bf16(v); }
 
-__device__ inline float wave_sum_f(float v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+__device__ inline float wave_sum_f(float v) { return wave_total(v); }
 
-// Four independent wave sums, their butterflies interleaved.
+// Four independent wave sums.
 __device__ inline void wave_sum4(float (&v)[4]) {
-  for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) v[r] += __shfl_xor(v[r], o, 64);
-  }
+  for (int r = 0; r < 4; ++r) v[r] = wave_total(v[r]);
 }
 
 // ------------------------------------------------------------------ GEMM
@@ -566,45 +561,35 @@ __device__ inline void store8(AT* y, const float (&v)[8]) {
 }
 
 // LayerNorm of rows of C = 128 (eps 1e-5), FP32 in, activation type out.  A
-// wave takes four rows at once (their loads and reductions in flight
-// together); lane l holds columns 2 l and 2 l + 1 of each (one 8-byte load,
-// one packed store).
+// wave takes four rows, one per 16-lane DPP row: lane l holds columns
+// 8 (l % 16) .. + 7 of row l / 16 (two 16-byte loads, one 16-byte BF16
+// store), and the row statistics are 16-lane DPP sums.
 template <typename AT>
 __global__ __launch_bounds__(256) void k_layernorm128(const float* X, const float* g, const float* b, AT* Y, int M) {
-  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 4, lane = threadIdx.x & 63;
-  if (row0 >= M) return;
-  float2 x[4];
-  float mu[4], var[4];
+  const int lane = threadIdx.x & 63, row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 4;
+  if (row0 >= M) return;  // wave-uniform: the reductions below need every lane
+  const int row = row0 + (lane >> 4), c0 = 8 * (lane & 15);
+  const bool live = row < M;
+  float x[8];
+  if (live) load8(X + (int64_t)row * 128 + c0, x);
+  else {
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
-    x[r] = row0 + r < M ? *(const float2*)(X + (int64_t)(row0 + r) * 128 + 2 * lane) : make_float2(0.f, 0.f);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) mu[r] = x[r].x + x[r].y;
-  for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) mu[r] += __shfl_xor(mu[r], o, 64);
+    for (int q = 0; q < 8; ++q) x[q] = 0.f;
   }
+  float mu = 0.f;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    mu[r] *= (1.f / 128.f);
-    const float d0 = x[r].x - mu[r], d1 = x[r].y - mu[r];
-    var[r] = d0 * d0 + d1 * d1;
-  }
-  for (int o = 32; o > 0; o >>= 1) {
+  for (int q = 0; q < 8; ++q) mu += x[q];
+  mu = row16_sum(mu) * (1.f / 128.f);
+  float var = 0.f;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) var[r] += __shfl_xor(var[r], o, 64);
-  }
-  const float g0 = g[2 * lane], g1 = g[2 * lane + 1], b0 = b[2 * lane], b1 = b[2 * lane + 1];
+  for (int q = 0; q < 8; ++q) var += (x[q] - mu) * (x[q] - mu);
+  const float rs = rsqrtf(row16_sum(var) * (1.f / 128.f) + 1e-5f);
+  float gm[8], bt[8], y[8];
+  load8(g + c0, gm);
+  load8(b + c0, bt);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    if (row0 + r >= M) break;
-    const float rs = rsqrtf(var[r] * (1.f / 128.f) + 1e-5f);
-    const float y0 = (x[r].x - mu[r]) * rs * g0 + b0, y1 = (x[r].y - mu[r]) * rs * g1 + b1;
-    if constexpr (sizeof(AT) == 2)
-      *(uint32_t*)(Y + (int64_t)(row0 + r) * 128 + 2 * lane) = pack_bf16x2(y0, y1);
-    else
-      *(float2*)(Y + (int64_t)(row0 + r) * 128 + 2 * lane) = make_float2(y0, y1);
-  }
+  for (int q = 0; q < 8; ++q) y[q] = (x[q] - mu) * rs * gm[q] + bt[q];
+  if (live) store8<AT>(Y + (int64_t)row * 128 + c0, y);
 }
 
 // LayerNorm over the 4d concat [x | a | c | g] (Sec. 4.3: each token joins its
