@@ -128,19 +128,45 @@ template <int CTRL>
 __device__ inline float dpp_move(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
 }
-__device__ inline float row16_sum(float v) {
-  v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
-  v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
-  v += dpp_move<0x141>(v);  // row_half_mirror
-  v += dpp_move<0x140>(v);  // row_mirror
+// sum over each aligned group of W lanes (W = 1, 2, 4, 8 or 16)
+template <int W>
+__device__ inline float group_sum(float v) {
+  static_assert(W == 1 || W == 2 || W == 4 || W == 8 || W == 16, "DPP groups are 1 to 16 lanes");
+  if constexpr (W >= 2) v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  if constexpr (W >= 4) v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  if constexpr (W >= 8) v += dpp_move<0x141>(v);  // row_half_mirror
+  if constexpr (W >= 16) v += dpp_move<0x140>(v); // row_mirror
   return v;
 }
+__device__ inline float row16_sum(float v) { return group_sum<16>(v); }
 __device__ inline float wave_total(float v) {
   v = row16_sum(v);
   // row_bcast:15 into rows 1 and 3, then row_bcast:31 into rows 2 and 3
   v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false));
   v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xC, 0xF, false));
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+// The same for FP64 (each move takes the two 32-bit halves); rows outside
+// ROWS receive zero in the broadcast steps.
+template <int CTRL, int ROWS = 0xF>
+__device__ inline double dpp_move_d(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, ROWS, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROWS, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ inline double wave_total_d(double v) {
+  v += dpp_move_d<0xB1>(v);
+  v += dpp_move_d<0x4E>(v);
+  v += dpp_move_d<0x141>(v);
+  v += dpp_move_d<0x140>(v);
+  v += dpp_move_d<0x142, 0xA>(v);
+  v += dpp_move_d<0x143, 0xC>(v);
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), 63);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
 template <typename T> __device__ inline float ldf(const T* p, int64_t i);

@@ -29,10 +29,7 @@ namespace hp {
 
 // ------------------------------------------------------------------ helpers
 
-__device__ inline double warp_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+__device__ inline double warp_sum(double v) { return wave_total_d(v); }
 
 // Fixed-order block sum of one double per thread (blockDim multiple of 64).
 __device__ inline double block_sum(double v, double* red) {
@@ -216,8 +213,7 @@ struct LeafPre {
       float a = 0.f;
 #pragma unroll
       for (int c = 0; c < CPT; ++c) a = fmaf(g[c], rs[c0 + c], a);
-#pragma unroll
-      for (int o = TPR / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+      a = group_sum<TPR>(a);
       if (t % TPR == 0) y[row0 + row] = fmaf(gate, rs[row], a);
     }
     const int s = t % LS, grp = t / LS;
@@ -293,8 +289,7 @@ struct ProlongPre {
         a = fmaf(v[s], tcs[s0 + s], a);
       }
     }
-#pragma unroll
-    for (int o = TPR / 2; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    a = group_sum<TPR>(a);
     return yrow + a;
   }
 };
