@@ -1129,17 +1129,21 @@ __global__ __launch_bounds__(256) void k_attention_mfma(const uint16_t* qkv, uin
   const int h = threadIdx.x >> 6, lane = threadIdx.x & 63, hh = lane >> 5, c32 = lane & 31;
   const int64_t row0 = (int64_t)blockIdx.x * T;
   const uint16_t* base = qkv + row0 * 3 * D + h * DH;
-  // V^T into LDS: lane -> key rows, 16 B chunks
-  for (int idx = lane; idx < T * 4; idx += 64) {
-    const int key = idx >> 2, c0 = (idx & 3) * 8;
-    const uint4 v = *(const uint4*)(base + (int64_t)key * 3 * D + 2 * D + c0);
-    const uint16_t* pv = (const uint16_t*)&v;
+  // Each LDS region (sVt[h], sC[h]) is written and read by the wave of head
+  // h only, and one wave's LDS accesses complete in order: the waves never
+  // wait for each other, a wait for the wave's own LDS operations and a
+  // compiler fence stand in for block barriers.
+  auto wave_lds_fence = [] { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); };
+  // the block's global operands are requested together: V rows (key ->
+  // 16-byte chunks) and the K operands of both key tiles and both 16-wide
+  // steps, which stay in registers
+  constexpr int NV = T * 4 / 64;
+  uint4 vch[NV];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) sVt[h][c0 + e][key] = pv[e];
+  for (int u = 0; u < NV; ++u) {
+    const int idx = lane + 64 * u, key = idx >> 2, c0 = (idx & 3) * 8;
+    vch[u] = *(const uint4*)(base + (int64_t)key * 3 * D + 2 * D + c0);
   }
-  __syncthreads();
-  // K operands of both key tiles and both 16-wide steps stay in registers;
-  // the query tiles are processed one at a time (fewer live accumulators)
   bf16x8_t kop[2][NT];
 #pragma unroll
   for (int s = 0; s < 2; ++s)
@@ -1147,9 +1151,45 @@ __global__ __launch_bounds__(256) void k_attention_mfma(const uint16_t* qkv, uin
     for (int t = 0; t < NT; ++t)
       kop[s][t] = __builtin_bit_cast(bf16x8_t,
                                      *(const uint4*)(base + (int64_t)(32 * t + c32) * 3 * D + D + 16 * s + 8 * hh));
+  // V^T into LDS
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    const int idx = lane + 64 * u, key = idx >> 2, c0 = (idx & 3) * 8;
+    const uint16_t* pv = (const uint16_t*)&vch[u];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sVt[h][c0 + e][key] = pv[e];
+  }
+  wave_lds_fence();
   const float scale = 0.17677669529663687f;  // 1/sqrt(32)
 #pragma unroll 1
   for (int b = 0; b < NT; ++b) {
+    const int q = 32 * b + c32;
+    const int64_t row = row0 + q;
+    // this query tile's global operands together: Q, the query's stencil
+    // entries held by this half (slots e = 4 hh .. 4 hh + 3 of 7) and its
+    // row of the bias table
+    bf16x8_t qop[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+      qop[s] = __builtin_bit_cast(bf16x8_t, *(const uint4*)(base + (int64_t)(32 * b + c32) * 3 * D + 16 * s + 8 * hh));
+    int lj[4];
+    float cv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = 4 * hh + u;
+      lj[u] = 255;
+      cv[u] = 0.f;
+      if (e < 7) {
+        lj[u] = nbr[row * 7 + e];
+        cv[u] = corr[(row * 7 + e) * H + h];
+      }
+    }
+    const float* bt = T0 + ((int64_t)h * T + q) * T;
+    float4 bvv[NT][4];
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bvv[a][i] = *(const float4*)(bt + 32 * a + 8 * i + 4 * hh);
     // S^T tiles of this query tile: S[a] = K[32a..][:] Q[32b..][:]^T
     f32x16_t S[NT];
 #pragma unroll
@@ -1157,35 +1197,25 @@ __global__ __launch_bounds__(256) void k_attention_mfma(const uint16_t* qkv, uin
 #pragma unroll
       for (int q2 = 0; q2 < 16; ++q2) S[a][q2] = 0.f;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const bf16x8_t qop =
-          __builtin_bit_cast(bf16x8_t, *(const uint4*)(base + (int64_t)(32 * b + c32) * 3 * D + 16 * s + 8 * hh));
+    for (int s = 0; s < 2; ++s)
 #pragma unroll
-      for (int a = 0; a < NT; ++a) S[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kop[s][a], qop, S[a], 0, 0, 0);
-    }
-    const int q = 32 * b + c32;
-    const int64_t row = row0 + q;
-    const float* bt = T0 + ((int64_t)h * T + q) * T;
+      for (int a = 0; a < NT; ++a) S[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kop[s][a], qop[s], S[a], 0, 0, 0);
     // the query's row of corrections: zero its half, then the half-wave hh
-    // writes neighbours e = 4 hh .. (distinct neighbours have distinct keys)
+    // writes its neighbours (distinct neighbours have distinct keys)
 #pragma unroll
     for (int z = 0; z < T / 8; ++z) *(float4*)&sC[h][c32][hh * (T / 2) + 4 * z] = make_float4(0.f, 0.f, 0.f, 0.f);
-    __syncthreads();
+    wave_lds_fence();
 #pragma unroll
-    for (int e = 4 * hh; e < 4 * hh + 4; ++e) {
-      if (e < 7) {
-        const int lj = nbr[row * 7 + e];
-        if (lj != 255) sC[h][c32][lj] = corr[(row * 7 + e) * H + h];
-      }
-    }
-    __syncthreads();
+    for (int u = 0; u < 4; ++u)
+      if (lj[u] != 255) sC[h][c32][lj[u]] = cv[u];
+    wave_lds_fence();
     float mx = -3.4e38f;
 #pragma unroll
     for (int a = 0; a < NT; ++a)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int k0 = 32 * a + 8 * i + 4 * hh;
-        const float4 bv = *(const float4*)(bt + k0);
+        const float4 bv = bvv[a][i];
         const float4 cw = *(const float4*)&sC[h][c32][k0];
         const float bj[4] = {bv.x + cw.x, bv.y + cw.y, bv.z + cw.z, bv.w + cw.w};
 #pragma unroll
