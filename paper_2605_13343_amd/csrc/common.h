@@ -118,6 +118,15 @@ __host__ __device__ inline uint16_t f32_to_bf16(float f) {  // round to nearest 
   return (uint16_t)(c.u >> 16);
 }
 
+// Block index remapped so that each of the 8 XCDs (the dispatcher deals the
+// blocks of a launch out to them round-robin) runs one contiguous range of
+// the logical blocks: the neighbouring rows a stencil reads then sit in the
+// same L2.  A bijection of [0, n) for any n.
+__device__ inline int xcd_block(int id, int n) {
+  const int q = n >> 3, r = n & 7, x = id & 7, k = id >> 3;
+  return x * q + min(x, r) + k;
+}
+
 // Cross-lane sums on the VALU's data-parallel-primitive (DPP) lane paths
 // instead of LDS permutes.  row16_sum: the sum over each aligned group of 16
 // lanes, with the same bits in every lane of the group (partners by quad

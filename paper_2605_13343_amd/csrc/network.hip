@@ -757,7 +757,7 @@ __global__ void k_features(const FrameDesc* fr, const int* blk2f, const float* r
 template <typename AT>
 __global__ __launch_bounds__(256) void k_gcn_spmm(const FrameDesc* fr, const int* node2f, const float* sys,
                                                   int64_t ntot, const float* H, AT* Y) {
-  const int64_t i = (int64_t)blockIdx.x * 8 + (threadIdx.x >> 5);
+  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 8 + (threadIdx.x >> 5);
   if (i >= ntot) return;
   const int col = (threadIdx.x & 31) * 4;
   const FrameDesc F = fr[node2f[i]];

@@ -483,18 +483,19 @@ template <bool SIMPLE>
 __global__ __launch_bounds__(NODE_BLOCK) void k_spmv_p(const FrameDesc* fr, const int* blk2f, PcgBufs B_, int rd,
                                                        int wr, const float* pold, float* pnew) {
   __shared__ double red[NODE_BLOCK / 64];
-  const int f = blk2f[blockIdx.x];
+  const int bid = xcd_block(blockIdx.x, gridDim.x);  // stencil neighbours in one L2
+  const int f = blk2f[bid];
   const FrameDesc F = fr[f];
   FrameState S = load_state(B_.st + 2 * f + rd);
   FrameState* out = B_.st + 2 * f + wr;
-  const bool lead = blockIdx.x == F.b0 && threadIdx.x == 0;
+  const bool lead = bid == F.b0 && threadIdx.x == 0;
   if (S.done) {
     if (lead) store_state(out, S);
     return;
   }
   const SolveParams prm = *B_.prm;
   // stencil operands (independent of beta) before the reductions
-  const int c = (blockIdx.x - F.b0) * NODE_BLOCK + threadIdx.x;
+  const int c = (bid - F.b0) * NODE_BLOCK + threadIdx.x;
   const bool own = c < F.n;
   float zv[7], pv[7], cf[7];
   if (own) {
@@ -558,7 +559,7 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_spmv_p(const FrameDesc* fr, cons
     pq = (double)P[0] * (double)qi;
   }
   double bs = block_sum(pq, red);
-  if (threadIdx.x == 0) B_.part_pq[blockIdx.x] = bs;
+  if (threadIdx.x == 0) B_.part_pq[bid] = bs;
   if (lead) store_state(out, S);
 }
 
