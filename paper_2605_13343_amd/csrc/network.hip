@@ -957,10 +957,14 @@ __global__ __launch_bounds__(256) void k_edge_corr(EdgeW w, const float* slots, 
 //   (centroid(J_m^t') - centroid(I_m^t)) / 4,  mean of Ahat over I_m^t x J_m^t'.
 // The strip pairs of a tile are split into chunks of at most DESC_CHUNK
 // leaves a side (a big tile's serial loop would otherwise dominate): one
-// block per chunk, thread (t, t'), FP64 partial sums
-// [chunk][t][t'][cI x, y, z | cJ x, y, z | sum Ahat]; a second kernel adds
-// a tile's chunks in order.
+// block per chunk, FP64 partial sums [chunk][t][t'][cI x, y, z | cJ x, y, z |
+// sum Ahat]; a second kernel adds a tile's chunks in order.  Within a block,
+// one thread per row-strip node first finds its stencil entries that land
+// in the column strip (the group t' of each and its Ahat, once per entry);
+// thread (t, t') then adds those of group t whose target is in group t', in
+// the order node, axis, direction.
 constexpr int DESC_CHUNK = 4;
+constexpr int DESC_MAX_LEAF = 64;  // leaf sizes 32 and 64
 struct DescChunk {
   int tile;   // global tile index
   int k0, k1; // leaf range [k0, k1) inside the strips
@@ -968,33 +972,51 @@ struct DescChunk {
 
 __global__ __launch_bounds__(256) void k_off_desc_part(const FrameDesc* fr, const int* tile2f, const DescChunk* ch,
                                                        const float* sys, int64_t ntot, int L, int LS, double* part) {
+  __shared__ double sval[DESC_CHUNK * DESC_MAX_LEAF][6];
+  __shared__ int8_t sgrp[DESC_CHUNK * DESC_MAX_LEAF][6];
   const DescChunk c = ch[blockIdx.x];
   const FrameDesc F = fr[tile2f[c.tile]];
   const int m = c.tile - F.m0, K = F.K;
   int j = 0;
   while (m >= K - (K >> (j + 1))) ++j;
   const int i = m - (K - (K >> j)), S = 1 << j, r0 = 2 * i * S, c0 = r0 + S, p = L / LS;
-  const int t = threadIdx.x / LS, t2 = threadIdx.x % LS;
-  if (t >= LS) return;
   const double* d8 = reinterpret_cast<const double*>(sys + 5 * ntot);
   const double* w8[3] = {d8 + ntot, d8 + 2 * ntot, d8 + 3 * ntot};
   const unsigned masks[3] = {F.xm, F.ym, F.zm};
+  const int nn = (c.k1 - c.k0) * L;  // row-strip nodes of the chunk (at most DESC_CHUNK * DESC_MAX_LEAF)
+  for (int n = threadIdx.x; n < nn; n += blockDim.x) {
+    const unsigned ci = (unsigned)((r0 + c.k0) * L + n);
+    for (int a = 0; a < 3; ++a) {
+      for (int sgn = 0; sgn < 2; ++sgn) {
+        const int e = 2 * a + sgn;
+        int8_t g = -1;
+        double v = 0.0;
+        const bool edge = sgn == 0 ? (ci & masks[a]) == masks[a] : (ci & masks[a]) == 0;
+        if (!edge) {
+          const unsigned cj = sgn == 0 ? mstep_plus(ci, masks[a]) : mstep_minus(ci, masks[a]);
+          const int kj = cj / L;
+          if (kj >= c0 && kj < c0 + S) {
+            const double w = sgn == 0 ? w8[a][F.n0 + ci] : w8[a][F.n0 + cj];
+            g = (int8_t)((cj % L) / p);
+            v = -w / sqrt(d8[F.n0 + ci] * d8[F.n0 + cj]);
+          }
+        }
+        sgrp[n][e] = g;
+        sval[n][e] = v;
+      }
+    }
+  }
+  __syncthreads();
+  const int t = threadIdx.x / LS, t2 = threadIdx.x % LS;
+  if (t >= LS) return;
   double cI[3] = {0, 0, 0}, cJ[3] = {0, 0, 0}, acc = 0.0;
   for (int k = c.k0; k < c.k1; ++k) {
     for (int l = t * p; l < (t + 1) * p; ++l) {
       const unsigned ci = (unsigned)((r0 + k) * L + l);
       for (int a = 0; a < 3; ++a) cI[a] += mcoord(ci, masks[a]);
-      for (int a = 0; a < 3; ++a) {
-        for (int sgn = 0; sgn < 2; ++sgn) {
-          const bool edge = sgn == 0 ? (ci & masks[a]) == masks[a] : (ci & masks[a]) == 0;
-          if (edge) continue;
-          const unsigned cj = sgn == 0 ? mstep_plus(ci, masks[a]) : mstep_minus(ci, masks[a]);
-          const int kj = cj / L, lj = cj % L;
-          if (kj < c0 || kj >= c0 + S || lj / p != t2) continue;
-          const double w = sgn == 0 ? w8[a][F.n0 + ci] : w8[a][F.n0 + cj];
-          acc += -w / sqrt(d8[F.n0 + ci] * d8[F.n0 + cj]);
-        }
-      }
+      const int n = (k - c.k0) * L + l;
+      for (int e = 0; e < 6; ++e)
+        if (sgrp[n][e] == t2) acc += sval[n][e];
     }
     for (int l = t2 * p; l < (t2 + 1) * p; ++l) {
       const unsigned cj = (unsigned)((c0 + k) * L + l);
