@@ -152,7 +152,7 @@ def main() -> int:
     gemm_tf = gemm_flops / (gemm_ms * 1e-3) / 1e12
     gemm_gbs = gemm_bytes / (gemm_ms_b * 1e-3) / 1e9
     hbm_bound = gemm_bytes / (PEAK_HBM_GBS * 1e9) >= gemm_flops / (PEAK_BF16_TFLOPS * 1e12)
-    gemm_kernel = "k_gemm_bt<..> / k_gemm<bf16> (MFMA 32x32x16, FP32 accumulation)"
+    gemm_kernel = "k_gemm_dl<..> / k_gemm_bt<..> / k_gemm<bf16> (MFMA 32x32x16, FP32 accumulation)"
     gemm_common = {"traffic": None, "kernel": gemm_kernel, "launches": n_gemm,
                    "avg_launch_us": round(gemm_ms * 1e3 / max(n_gemm, 1), 2), "ms_per_inference": round(gemm_ms, 4),
                    "flops_per_inference": gemm_flops, "bytes_per_inference": gemm_bytes,
