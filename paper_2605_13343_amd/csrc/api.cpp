@@ -28,6 +28,7 @@ void factor_offsets(const Batch& b, int dtype, int64_t offs[5], int64_t* total) 
 }
 
 Batch::~Batch() {
+  if (side) hipStreamSynchronize(side);
   for (hipEvent_t e : prof.ev) hipEventDestroy(e);
   if (net_free && net.ws) net_free(net.ws);
   if (train_free && train_ws) train_free(train_ws);
@@ -37,6 +38,10 @@ Batch::~Batch() {
   for (void* p : allocs) hipFree(p);
   if (h_pin) hipHostFree(h_pin);
   if (cap_stream) hipStreamDestroy(cap_stream);
+  for (hipEvent_t e : side_ev) hipEventDestroy(e);
+  if (side_start) hipEventDestroy(side_start);
+  if (side_done) hipEventDestroy(side_done);
+  if (side) hipStreamDestroy(side);
 }
 
 hp_status Batch::alloc(void** p, size_t bytes) {

@@ -85,6 +85,12 @@ struct Batch {
   int nblk = 0, kmax = 0, nmax = 0;
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
+  // inference side stream: the per-layer edge-bias tables (they depend on the
+  // system and the weights only) run there beside the encoder; side_ev[l]
+  // marks layer l's tables
+  hipStream_t side = nullptr;
+  hipEvent_t side_start = nullptr, side_done = nullptr;
+  std::vector<hipEvent_t> side_ev;
   FrameDesc* d_fr = nullptr;
   int* d_blk2f = nullptr;
   int* d_leaf2f = nullptr;

@@ -1882,6 +1882,11 @@ struct NetBufs {
   float *Frows = nullptr, *NH = nullptr, *UV = nullptr;
   float *T0 = nullptr, *corr = nullptr, *ahat = nullptr, *desc = nullptr, *boff = nullptr;
   uint8_t* nbr = nullptr;
+  // the inference's per-layer copies of T0, eslots, corr and boff (computed
+  // ahead of the layers); pre: layer_fwd reads them, pre_side: they come
+  // from the side stream (layer l waits for side_ev[l])
+  float *T0l = nullptr, *eslotsl = nullptr, *corrl = nullptr, *boffl = nullptr;
+  int pre = 0, pre_side = 0;
   float *gpart = nullptr, *G = nullptr, *gcount = nullptr, *glob = nullptr, *bias_node = nullptr, *bias_uv = nullptr;
   void* warena = nullptr;
   ConvDesc* d_conv = nullptr;
@@ -1970,6 +1975,13 @@ hp_status network_alloc(Batch& b) {
   A(&N->nbr, Nd * 7);
   A(&N->desc, std::max<int64_t>(b.mtot, 1) * c.rank * c.rank * 4 * 4);
   A(&N->boff, std::max<int64_t>(b.mtot, 1) * c.heads * c.rank * c.rank * 4);
+  {
+    const size_t nl = (size_t)std::max(c.layers, 1);
+    A(&N->T0l, nl * c.heads * c.leaf * c.leaf * 4);
+    A(&N->eslotsl, nl * EDGE_CST * 4);
+    A(&N->corrl, nl * Nd * 7 * c.heads * 4);
+    A(&N->boffl, nl * std::max<int64_t>(b.mtot, 1) * c.heads * c.rank * c.rank * 4);
+  }
   A(&N->G, b.nframes * d * 4);
   A(&N->gcount, b.nframes * 4);
   A(&N->glob, b.nframes * 12 * 4);
@@ -2403,6 +2415,8 @@ static int gemm_choice(Batch& b, const GemmArgs& a, hipStream_t st) {
     (void)hipGetLastError();
     return fallback();
   }
+  // the inference's side stream would share the GPU with the timed launches
+  if (b.side) hipStreamSynchronize(b.side);
   GemmArgs t = a;
   if (t.Yf) t.Yf = (float*)scratch;
   if (t.Yb) t.Yb = scratch;
@@ -2521,6 +2535,62 @@ struct LayerSave {
   float *pre_d, *pre_o;              // FFN hidden pre-activations [M][4d]
 };
 
+// Stencil slots (neighbour index and Ahat) of every node and the
+// off-diagonal pair descriptors: functions of the system alone.
+static void stencil_desc(Batch& b, const float* sys, hipStream_t st) {
+  NetBufs& N = *nb_of(b);
+  const hp_model_config& c = b.cfg;
+  const int64_t Nd = N.Nd, L = c.leaf, LS = c.rank;
+  const FrameDesc* fr = b.d_fr;
+  if (c.offdiag && b.mtot > 0) {
+    hipLaunchKernelGGL(k_off_desc_part, dim3((unsigned)N.ndesc_chunks), dim3(256), 0, st, fr, N.tile2f,
+                       (const DescChunk*)N.desc_chunks, sys, b.ntot, (int)L, (int)LS, N.desc_part);
+    hipLaunchKernelGGL(k_off_desc_final, dim3((unsigned)b.mtot), dim3(256), 0, st, fr, N.tile2f,
+                       (const int*)N.desc_chunk0, (const double*)N.desc_part, (int)L, (int)LS, N.desc);
+  }
+  hipLaunchKernelGGL(k_leaf_stencil, dim3((unsigned)((Nd + 255) / 256)), dim3(256), 0, st, fr, N.node2f, sys, b.ntot,
+                     (int)L, N.nbr, N.ahat);
+}
+
+// Where layer l's edge-bias tables live: the shared buffers, or the
+// inference's per-layer copies.
+struct EdgeTabs {
+  float *T0, *eslots, *corr, *boff;
+};
+static EdgeTabs edge_tabs(const Batch& b, const NetBufs& N, int l) {
+  if (!N.pre) return {N.T0, N.eslots, N.corr, N.boff};
+  const hp_model_config& c = b.cfg;
+  return {N.T0l + (size_t)l * c.heads * c.leaf * c.leaf, N.eslotsl + (size_t)l * EDGE_CST,
+          N.corrl + (size_t)l * N.Nd * 7 * c.heads,
+          N.boffl + (size_t)l * std::max<int64_t>(b.mtot, 1) * c.heads * c.rank * c.rank};
+}
+
+// Layer l's edge-bias tables of one stack (sidx 0: the within-leaf table T0,
+// the slot constants and the stencil corrections; 1: the off-diagonal pair
+// biases), from the edge MLP's FP32 weights.
+template <typename AT>
+static void edge_tables(Batch& b, const float* W, int l, int sidx, const EdgeTabs& t, hipStream_t st) {
+  NetBufs& N = *nb_of(b);
+  const NetPlan& P = N.plan;
+  const hp_model_config& c = b.cfg;
+  const int64_t Nd = N.Nd, L = c.leaf, LS = c.rank, H = c.heads;
+  const std::string p = std::string(sidx ? "off" : "diag") + std::to_string(l) + ".";
+  auto wp = [&](const std::string& n) { return W + woff(P, n); };
+  EdgeW ew{wp(p + "e1.w"), wp(p + "e1.b"), wp(p + "e2.w"), wp(p + "e2.b"), c.edge_hidden, (int)H};
+  if (sidx == 0) {
+    const unsigned lowmask = (unsigned)(L - 1);
+    const FrameDesc& F0 = b.fr[0];
+    hipLaunchKernelGGL(k_edge_table<sizeof(AT) == 2>, dim3((unsigned)((L * L + 255) / 256 + 1)), dim3(256), 0, st, ew,
+                       (int)L, F0.xm & lowmask, F0.ym & lowmask, F0.zm & lowmask, t.T0, t.eslots);
+    hipLaunchKernelGGL(k_edge_corr<sizeof(AT) == 2>, dim3((unsigned)((Nd * 7 + 255) / 256)), dim3(256), 0, st, ew,
+                       (const float*)t.eslots, (const uint8_t*)N.nbr, (const float*)N.ahat, Nd, t.corr);
+  } else {
+    const int64_t npairs = b.mtot * LS * LS;
+    hipLaunchKernelGGL(k_edge_off<sizeof(AT) == 2>, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, ew,
+                       (const float*)N.desc, npairs, (int)LS, t.boff);
+  }
+}
+
 // Features, encoder, pooled off-diagonal tokens, descriptors and stencils.
 // With sv, the encoder's intermediate H values are saved for training.
 template <typename AT>
@@ -2572,13 +2642,8 @@ static hp_status fwd_prologue(Batch& b, const float* W, const float* rho, const 
                        (const int*)N.strip0, (const float*)N.strip_tot, (int)L, (int)LS, (AT*)N.ctx);
     gemm<AT>(b, N.ctx, 2 * d, N, P.pool, wp("pool.b"), nullptr, 0, N.Xo, d, nullptr, 0, No, 0);
     if (b.keep_stages) HP_HIP(hipMemcpyAsync(N.Xo0, N.Xo, No * d * 4, hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_off_desc_part, dim3((unsigned)N.ndesc_chunks), dim3(256), 0, st, fr, N.tile2f,
-                       (const DescChunk*)N.desc_chunks, sys, b.ntot, (int)L, (int)LS, N.desc_part);
-    hipLaunchKernelGGL(k_off_desc_final, dim3((unsigned)b.mtot), dim3(256), 0, st, fr, N.tile2f,
-                       (const int*)N.desc_chunk0, (const double*)N.desc_part, (int)L, (int)LS, N.desc);
   }
-  hipLaunchKernelGGL(k_leaf_stencil, dim3((unsigned)((Nd + 255) / 256)), dim3(256), 0, st, fr, N.node2f, sys, b.ntot,
-                     (int)L, N.nbr, N.ahat);
+  if (!N.pre) stencil_desc(b, sys, st);  // else computed ahead with the per-layer tables
   HP_HIP(hipGetLastError());
   return HP_OK;
 }
@@ -2598,12 +2663,10 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
   const FrameDesc* fr = b.d_fr;
   auto wp = [&](const std::string& n) { return W + woff(P, n); };
   (void)fr; (void)use_off; (void)H; (void)No; (void)L; (void)LS;
-  const unsigned lowmask = (unsigned)(L - 1);
-  const FrameDesc& F0 = b.fr[0];
+  const EdgeTabs tabs = edge_tabs(b, N, l);
   for (int sidx = 0; sidx < 2; ++sidx) {
     if (sidx == 1 && !use_off) continue;
     const std::string p = std::string(sidx ? "off" : "diag") + std::to_string(l) + ".";
-    EdgeW ew{wp(p + "e1.w"), wp(p + "e1.b"), wp(p + "e2.w"), wp(p + "e2.b"), c.edge_hidden, (int)H};
     float* X = sidx ? N.Xo : N.H;
     const int64_t M = sidx ? No : Nd;
     void* a = sidx ? N.ao128 : N.a128;
@@ -2612,40 +2675,35 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
     hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((M + 15) / 16)), dim3(256), 0, st, (const float*)X,
                        wp(p + "ln1.g"), wp(p + "ln1.b"), (AT*)a, (int)M);
     gemm<AT>(b, a, d, N, P.qkv[sidx][l], wp(p + "qkv.b"), nullptr, 0, nullptr, 0, q, 3 * d, M, 0);
+    if (!N.pre) edge_tables<AT>(b, W, l, sidx, tabs, st);
+    else if (N.pre_side && sidx == 0) HP_HIP(hipStreamWaitEvent(st, b.side_ev[l], 0));
     if (sidx == 0) {
-      hipLaunchKernelGGL(k_edge_table<sizeof(AT) == 2>, dim3((unsigned)((L * L + 255) / 256 + 1)), dim3(256), 0, st,
-                         ew, (int)L, F0.xm & lowmask, F0.ym & lowmask, F0.zm & lowmask, N.T0, N.eslots);
-      hipLaunchKernelGGL(k_edge_corr<sizeof(AT) == 2>, dim3((unsigned)((Nd * 7 + 255) / 256)), dim3(256), 0, st, ew,
-                         (const float*)N.eslots, (const uint8_t*)N.nbr, (const float*)N.ahat, Nd, N.corr);
       if (sizeof(AT) == 2 && !b.attn_valu) {
         if (L == 64)
           hipLaunchKernelGGL(k_attention_mfma<64>, dim3((unsigned)b.ktot), dim3(256), 0, st, (const uint16_t*)q,
-                             (uint16_t*)o, (const float*)N.T0, (const float*)N.corr, (const uint8_t*)N.nbr);
+                             (uint16_t*)o, (const float*)tabs.T0, (const float*)tabs.corr, (const uint8_t*)N.nbr);
         else
           hipLaunchKernelGGL(k_attention_mfma<32>, dim3((unsigned)b.ktot), dim3(256), 0, st, (const uint16_t*)q,
-                             (uint16_t*)o, (const float*)N.T0, (const float*)N.corr, (const uint8_t*)N.nbr);
+                             (uint16_t*)o, (const float*)tabs.T0, (const float*)tabs.corr, (const uint8_t*)N.nbr);
       } else if (L == 64) {
         hipLaunchKernelGGL((k_attention<AT, 64, true>), dim3((unsigned)b.ktot, (unsigned)H), dim3(64), 0, st,
-                           (const AT*)q, (AT*)o, (const float*)N.T0, (const float*)N.corr, (const uint8_t*)N.nbr,
-                           (int)H);
+                           (const AT*)q, (AT*)o, (const float*)tabs.T0, (const float*)tabs.corr,
+                           (const uint8_t*)N.nbr, (int)H);
       } else {
         hipLaunchKernelGGL((k_attention<AT, 32, true>), dim3((unsigned)b.ktot, (unsigned)H), dim3(64), 0, st,
-                           (const AT*)q, (AT*)o, (const float*)N.T0, (const float*)N.corr, (const uint8_t*)N.nbr,
-                           (int)H);
+                           (const AT*)q, (AT*)o, (const float*)tabs.T0, (const float*)tabs.corr,
+                           (const uint8_t*)N.nbr, (int)H);
       }
     } else {
-      const int64_t npairs = b.mtot * LS * LS;
-      hipLaunchKernelGGL(k_edge_off<sizeof(AT) == 2>, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, ew,
-                         (const float*)N.desc, npairs, (int)LS, N.boff);
       if (sizeof(AT) == 2 && LS == 16 && !b.attn_valu)
         hipLaunchKernelGGL(k_attention_tile_mfma, dim3((unsigned)b.mtot), dim3(256), 0, st, (const uint16_t*)q,
-                           (uint16_t*)o, (const float*)N.boff);
+                           (uint16_t*)o, (const float*)tabs.boff);
       else if (LS == 16)
         hipLaunchKernelGGL((k_attention<AT, 16, false>), dim3((unsigned)b.mtot, (unsigned)H), dim3(64), 0, st,
-                           (const AT*)q, (AT*)o, (const float*)N.boff, nullptr, nullptr, (int)H);
+                           (const AT*)q, (AT*)o, (const float*)tabs.boff, nullptr, nullptr, (int)H);
       else
         hipLaunchKernelGGL((k_attention<AT, 8, false>), dim3((unsigned)b.mtot, (unsigned)H), dim3(64), 0, st,
-                           (const AT*)q, (AT*)o, (const float*)N.boff, nullptr, nullptr, (int)H);
+                           (const AT*)q, (AT*)o, (const float*)tabs.boff, nullptr, nullptr, (int)H);
     }
     gemm<AT>(b, o, d, N, P.o[sidx][l], wp(p + "o.b"), X, d, X, d, nullptr, 0, M, 0);
   }
@@ -2710,11 +2768,58 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
   return HP_OK;
 }
 
+// The stencil slots, descriptors and every layer's edge-bias tables depend
+// on the system and the weights only.  They are computed first, into
+// per-layer buffers: on the side stream, beside the encoder and the early
+// layers (layer l waits for its tables' event), or in order on the batch
+// stream while a graph is being captured or kernels are being timed.
+template <typename AT>
+static hp_status tables_ahead(Batch& b, const float* W, const float* sys) {
+  NetBufs& N = *nb_of(b);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HP_HIP(hipStreamIsCapturing(b.stream, &cs));
+  N.pre = 1;
+  N.pre_side = cs == hipStreamCaptureStatusNone && b.prof.kind == PROF_NONE;
+  hipStream_t st = b.stream;
+  if (N.pre_side) {
+    if (!b.side) HP_HIP(hipStreamCreateWithFlags(&b.side, hipStreamNonBlocking));
+    if (!b.side_start) HP_HIP(hipEventCreateWithFlags(&b.side_start, hipEventDisableTiming));
+    if (!b.side_done) HP_HIP(hipEventCreateWithFlags(&b.side_done, hipEventDisableTiming));
+    while ((int)b.side_ev.size() < b.cfg.layers) {
+      hipEvent_t e;
+      HP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      b.side_ev.push_back(e);
+    }
+    // after everything enqueued so far (an earlier inference's readers of
+    // these buffers included)
+    HP_HIP(hipEventRecord(b.side_start, b.stream));
+    HP_HIP(hipStreamWaitEvent(b.side, b.side_start, 0));
+    st = b.side;
+  }
+  stencil_desc(b, sys, st);
+  const bool use_off = b.cfg.offdiag && b.mtot > 0;
+  for (int l = 0; l < b.cfg.layers; ++l) {
+    const EdgeTabs t = edge_tabs(b, N, l);
+    edge_tables<AT>(b, W, l, 0, t, st);
+    if (use_off) edge_tables<AT>(b, W, l, 1, t, st);
+    if (N.pre_side) HP_HIP(hipEventRecord(b.side_ev[l], st));
+  }
+  if (N.pre_side) HP_HIP(hipEventRecord(b.side_done, st));
+  HP_HIP(hipGetLastError());
+  return HP_OK;
+}
+
 template <typename AT, typename FT>
 static hp_status forward(Batch& b, const float* W, const float* rho, const float* sys, void* fac) {
+  struct PreReset {
+    NetBufs& N;
+    ~PreReset() { N.pre = N.pre_side = 0; }
+  } pre_reset{*nb_of(b)};
+  HP_TRY(tables_ahead<AT>(b, W, sys));
   HP_TRY(fwd_prologue<AT>(b, W, rho, sys, nullptr));
   for (int l = 0; l < b.cfg.layers; ++l) HP_TRY(layer_fwd<AT>(b, W, sys, l, nullptr));
   NetBufs& N = *nb_of(b);
+  if (N.pre_side) HP_HIP(hipStreamWaitEvent(b.stream, b.side_done, 0));  // every side launch joined
   const NetPlan& P = N.plan;
   const hp_model_config& c = b.cfg;
   hipStream_t st = b.stream;
