@@ -29,6 +29,7 @@ void factor_offsets(const Batch& b, int dtype, int64_t offs[5], int64_t* total) 
 
 Batch::~Batch() {
   if (side) hipStreamSynchronize(side);
+  if (offs) hipStreamSynchronize(offs);
   for (hipEvent_t e : prof.ev) hipEventDestroy(e);
   if (net_free && net.ws) net_free(net.ws);
   if (train_free && train_ws) train_free(train_ws);
@@ -42,6 +43,8 @@ Batch::~Batch() {
   if (side_start) hipEventDestroy(side_start);
   if (side_done) hipEventDestroy(side_done);
   if (side) hipStreamDestroy(side);
+  for (hipEvent_t e : off_ev) hipEventDestroy(e);
+  if (offs) hipStreamDestroy(offs);
 }
 
 hp_status Batch::alloc(void** p, size_t bytes) {

@@ -91,6 +91,11 @@ struct Batch {
   hipStream_t side = nullptr;
   hipEvent_t side_start = nullptr, side_done = nullptr;
   std::vector<hipEvent_t> side_ev;
+  // the off-diagonal stack's stream: its attention and FFN sublayers run
+  // beside the diagonal ones, joined where the highways couple the stacks
+  // (off_ev: [0] prologue done, [1] off stack done, then two per layer)
+  hipStream_t offs = nullptr;
+  std::vector<hipEvent_t> off_ev;
   FrameDesc* d_fr = nullptr;
   int* d_blk2f = nullptr;
   int* d_leaf2f = nullptr;

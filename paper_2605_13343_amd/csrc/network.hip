@@ -1887,6 +1887,7 @@ struct NetBufs {
   // from the side stream (layer l waits for side_ev[l])
   float *T0l = nullptr, *eslotsl = nullptr, *corrl = nullptr, *boffl = nullptr;
   int pre = 0, pre_side = 0;
+  int par = 0;  // the off-diagonal stack runs on the batch's off stream
   float *gpart = nullptr, *G = nullptr, *gcount = nullptr, *glob = nullptr, *bias_node = nullptr, *bias_uv = nullptr;
   void* warena = nullptr;
   ConvDesc* d_conv = nullptr;
@@ -2415,8 +2416,8 @@ static int gemm_choice(Batch& b, const GemmArgs& a, hipStream_t st) {
     (void)hipGetLastError();
     return fallback();
   }
-  // the inference's side stream would share the GPU with the timed launches
-  if (b.side) hipStreamSynchronize(b.side);
+  // the inference's other streams would share the GPU with the timed launches
+  hipDeviceSynchronize();
   GemmArgs t = a;
   if (t.Yf) t.Yf = (float*)scratch;
   if (t.Yb) t.Yb = scratch;
@@ -2656,7 +2657,19 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
   NetBufs& N = *nb_of(b);
   const NetPlan& P = N.plan;
   const hp_model_config& c = b.cfg;
-  hipStream_t st = b.stream;
+  // with N.par the off-diagonal sublayers go to the off stream (b.stream is
+  // pointed there around them, so the GEMM helper launches there too)
+  hipStream_t const main_st = b.stream;
+  hipStream_t st = main_st;
+  struct StreamRestore {
+    Batch& b;
+    hipStream_t s;
+    ~StreamRestore() { b.stream = s; }
+  } restore{b, main_st};
+  auto stack_stream = [&](int sidx) {
+    b.stream = (N.par && sidx == 1) ? b.offs : main_st;
+    return b.stream;
+  };
   const int64_t Nd = N.Nd, d = c.d, L = c.leaf, LS = c.rank, H = c.heads;
   const int64_t No = b.mtot * LS;
   const bool use_off = c.offdiag && b.mtot > 0;
@@ -2666,6 +2679,7 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
   const EdgeTabs tabs = edge_tabs(b, N, l);
   for (int sidx = 0; sidx < 2; ++sidx) {
     if (sidx == 1 && !use_off) continue;
+    st = stack_stream(sidx);
     const std::string p = std::string(sidx ? "off" : "diag") + std::to_string(l) + ".";
     float* X = sidx ? N.Xo : N.H;
     const int64_t M = sidx ? No : Nd;
@@ -2676,7 +2690,7 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
                        wp(p + "ln1.g"), wp(p + "ln1.b"), (AT*)a, (int)M);
     gemm<AT>(b, a, d, N, P.qkv[sidx][l], wp(p + "qkv.b"), nullptr, 0, nullptr, 0, q, 3 * d, M, 0);
     if (!N.pre) edge_tables<AT>(b, W, l, sidx, tabs, st);
-    else if (N.pre_side && sidx == 0) HP_HIP(hipStreamWaitEvent(st, b.side_ev[l], 0));
+    else if (N.pre_side && (sidx == 0 || N.par)) HP_HIP(hipStreamWaitEvent(st, b.side_ev[l], 0));
     if (sidx == 0) {
       if (sizeof(AT) == 2 && !b.attn_valu) {
         if (L == 64)
@@ -2706,7 +2720,11 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
                            (const AT*)q, (AT*)o, (const float*)tabs.boff, nullptr, nullptr, (int)H);
     }
     gemm<AT>(b, o, d, N, P.o[sidx][l], wp(p + "o.b"), X, d, X, d, nullptr, 0, M, 0);
+    if (N.par && sidx == 1) HP_HIP(hipEventRecord(b.off_ev[2 + 2 * l], st));
   }
+  st = stack_stream(0);
+  // the highways read both stacks' attention outputs
+  if (N.par) HP_HIP(hipStreamWaitEvent(st, b.off_ev[2 + 2 * l], 0));
   // highways (Sec. 4.3)
   if (c.highways) {
     if (use_off) {
@@ -2729,6 +2747,10 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
   }
   for (int sidx = 0; sidx < 2; ++sidx) {
     if (sidx == 1 && !use_off) continue;
+    st = stack_stream(sidx);
+    // the off-diagonal FFN's context comes from the group sums of the
+    // diagonal LayerNorm (and its frame means from the highway step)
+    if (N.par && sidx == 1) HP_HIP(hipStreamWaitEvent(st, b.off_ev[3 + 2 * l], 0));
     const std::string p = std::string(sidx ? "off" : "diag") + std::to_string(l) + ".";
     float* X = sidx ? N.Xo : N.H;
     const int64_t M = sidx ? No : Nd;
@@ -2755,6 +2777,7 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
       hipLaunchKernelGGL(k_ln_concat<AT>, dim3((unsigned)((M + 15) / 16)), dim3(256), 0, st, (const float*)X, d,
                          (const float*)N.ctxf, 2 * d, (const float*)(N.ctxf + d), 2 * d, (const float*)N.G,
                          (const int*)N.tok2f, wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, (int)M, c.highways);
+    if (N.par && sidx == 0) HP_HIP(hipEventRecord(b.off_ev[3 + 2 * l], st));
     if (ls) HP_HIP(hipMemcpyAsync(sidx ? ls->xmid_o : ls->xmid_d, X, M * d * 4, hipMemcpyDeviceToDevice, st));
     if (sizeof(AT) == 2 && !ls && b.ffn_fused) {
       ffn_fused(b, u, N, P.f1[sidx][l], wp(p + "f1.b"), P.f2[sidx][l], wp(p + "f2.b"), X, M);
@@ -2796,8 +2819,17 @@ static hp_status tables_ahead(Batch& b, const float* W, const float* sys) {
     HP_HIP(hipStreamWaitEvent(b.side, b.side_start, 0));
     st = b.side;
   }
-  stencil_desc(b, sys, st);
   const bool use_off = b.cfg.offdiag && b.mtot > 0;
+  N.par = N.pre_side && use_off;
+  if (N.par) {
+    if (!b.offs) HP_HIP(hipStreamCreateWithFlags(&b.offs, hipStreamNonBlocking));
+    while ((int)b.off_ev.size() < 2 + 2 * b.cfg.layers) {
+      hipEvent_t e;
+      HP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      b.off_ev.push_back(e);
+    }
+  }
+  stencil_desc(b, sys, st);
   for (int l = 0; l < b.cfg.layers; ++l) {
     const EdgeTabs t = edge_tabs(b, N, l);
     edge_tables<AT>(b, W, l, 0, t, st);
@@ -2813,12 +2845,20 @@ template <typename AT, typename FT>
 static hp_status forward(Batch& b, const float* W, const float* rho, const float* sys, void* fac) {
   struct PreReset {
     NetBufs& N;
-    ~PreReset() { N.pre = N.pre_side = 0; }
+    ~PreReset() { N.pre = N.pre_side = N.par = 0; }
   } pre_reset{*nb_of(b)};
   HP_TRY(tables_ahead<AT>(b, W, sys));
   HP_TRY(fwd_prologue<AT>(b, W, rho, sys, nullptr));
-  for (int l = 0; l < b.cfg.layers; ++l) HP_TRY(layer_fwd<AT>(b, W, sys, l, nullptr));
   NetBufs& N = *nb_of(b);
+  if (N.par) {  // the off stack starts from the pooled tokens
+    HP_HIP(hipEventRecord(b.off_ev[0], b.stream));
+    HP_HIP(hipStreamWaitEvent(b.offs, b.off_ev[0], 0));
+  }
+  for (int l = 0; l < b.cfg.layers; ++l) HP_TRY(layer_fwd<AT>(b, W, sys, l, nullptr));
+  if (N.par) {  // the heads read the off stack's last output
+    HP_HIP(hipEventRecord(b.off_ev[1], b.offs));
+    HP_HIP(hipStreamWaitEvent(b.stream, b.off_ev[1], 0));
+  }
   if (N.pre_side) HP_HIP(hipStreamWaitEvent(b.stream, b.side_done, 0));  // every side launch joined
   const NetPlan& P = N.plan;
   const hp_model_config& c = b.cfg;
