@@ -318,9 +318,23 @@ struct TilePre {
     const int64_t lr = (int64_t)F.k0 + 2 * i * S, lc = lr + S;
     a = 0.f;
     c = 0.f;
-    for (int k = ch; k < S; k += NCH) {
-      a += uh[(lr + k) * LS + s];
-      c += vh[(lc + k) * LS + s];
+    // the chunk's loads are issued U at a time before their (in-order) sums:
+    // a load-add chain would expose one memory latency per leaf
+    constexpr int U = 8;
+    for (int k0 = ch; k0 < S; k0 += U * NCH) {
+      float ua[U], va[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int k = k0 + q * NCH;
+        ua[q] = k < S ? uh[(lr + k) * LS + s] : 0.f;
+        va[q] = k < S ? vh[(lc + k) * LS + s] : 0.f;
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q)
+        if (k0 + q * NCH < S) {
+          a += ua[q];
+          c += va[q];
+        }
     }
     mg = (int64_t)F.m0 + m;
     const FT* Bm = B + mg * LS * LS;
@@ -371,10 +385,29 @@ __device__ inline void gather_leaf(const FrameDesc& F, int64_t kg, int s, const 
                                    float& Tr, float& Tc) {
   const int k = (int)(kg - F.k0), K = F.K;
   float a = 0.f, c = 0.f;
-  for (int j = 0; j < F.J; ++j) {
-    const int64_t m = (int64_t)F.m0 + K - (K >> j) + (k >> (j + 1));
-    if (((k >> j) & 1) == 0) a += tr[m * LS + s];
-    else c += tc[m * LS + s];
+  constexpr int JMAX = 16;  // every level's load in flight at once (up to 2^16 leaves)
+  if (F.J <= JMAX) {
+    float tv[JMAX];
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j) {
+      tv[j] = 0.f;
+      if (j < F.J) {
+        const int64_t m = (int64_t)F.m0 + K - (K >> j) + (k >> (j + 1));
+        tv[j] = ((k >> j) & 1) == 0 ? tr[m * LS + s] : tc[m * LS + s];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j)
+      if (j < F.J) {
+        if (((k >> j) & 1) == 0) a += tv[j];
+        else c += tv[j];
+      }
+  } else {
+    for (int j = 0; j < F.J; ++j) {
+      const int64_t m = (int64_t)F.m0 + K - (K >> j) + (k >> (j + 1));
+      if (((k >> j) & 1) == 0) a += tr[m * LS + s];
+      else c += tc[m * LS + s];
+    }
   }
   Tr = a;
   Tc = c;
