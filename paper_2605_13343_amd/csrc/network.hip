@@ -2536,6 +2536,23 @@ struct LayerSave {
   float *pre_d, *pre_o;              // FFN hidden pre-activations [M][4d]
 };
 
+// The heads' biases gathered for their GEMMs: [hut | hvt | hlam] and
+// [hu | hv] (one launch instead of five small copies).
+__global__ __launch_bounds__(64) void k_head_biases(const float* hut, const float* hvt, const float* hlam,
+                                                    const float* hu, const float* hv, int LS, float* bias_node,
+                                                    float* bias_uv) {
+  const int t = threadIdx.x;
+  if (t < LS) {
+    bias_node[t] = hut[t];
+    bias_uv[t] = hu[t];
+  } else if (t < 2 * LS) {
+    bias_node[t] = hvt[t - LS];
+    bias_uv[t] = hv[t - LS];
+  } else if (t == 2 * LS) {
+    bias_node[t] = hlam[0];
+  }
+}
+
 // Stencil slots (neighbour index and Ahat) of every node and the
 // off-diagonal pair descriptors: functions of the system alone.
 static void stencil_desc(Batch& b, const float* sys, hipStream_t st) {
@@ -2611,11 +2628,8 @@ static hp_status fwd_prologue(Batch& b, const float* W, const float* rho, const 
   const int ntiles = sv ? (int)P.tiles.size() : P.ntiles_fwd;
   hipLaunchKernelGGL(k_convert<AT>, dim3((unsigned)ntiles), dim3(256), 0, st, N.d_conv, (const int4*)N.d_tiles, W,
                      (AT*)N.warena);
-  HP_HIP(hipMemcpyAsync(N.bias_node, wp("hut.b"), LS * 4, hipMemcpyDeviceToDevice, st));
-  HP_HIP(hipMemcpyAsync(N.bias_node + LS, wp("hvt.b"), LS * 4, hipMemcpyDeviceToDevice, st));
-  HP_HIP(hipMemcpyAsync(N.bias_node + 2 * LS, wp("hlam.b"), 4, hipMemcpyDeviceToDevice, st));
-  HP_HIP(hipMemcpyAsync(N.bias_uv, wp("hu.b"), LS * 4, hipMemcpyDeviceToDevice, st));
-  HP_HIP(hipMemcpyAsync(N.bias_uv + LS, wp("hv.b"), LS * 4, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(k_head_biases, dim3(1), dim3(64), 0, st, wp("hut.b"), wp("hvt.b"), wp("hlam.b"), wp("hu.b"),
+                     wp("hv.b"), (int)LS, N.bias_node, N.bias_uv);
   // features and encoder (Sec. 4.1)
   hipLaunchKernelGGL(k_frame_stats, dim3(b.nframes), dim3(1024), 0, st, fr, rho, sys, b.ntot, N.glob);
   hipLaunchKernelGGL(k_features<AT>, dim3(b.nblk), dim3(NODE_BLOCK), 0, st, fr, b.d_blk2f, rho, sys, b.ntot, N.glob,
