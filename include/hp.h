@@ -213,8 +213,12 @@ hp_status hp_weight_info(const hp_model_config* cfg, int32_t index, char* name, 
  * HP_F32 runs everything in FP32 and writes FP32 factors.
  *   d_weights [weight_floats] FP32; d_rho [ntot] FP32 (Morton);
  *   d_sys from hp_assemble; d_factors per hp_batch_info(compute).
- * Asynchronous on the batch stream.  The first call per compute type tunes
- * the GEMM tiles (it synchronises and allocates).  With the "infer_graph"
+ * Asynchronous on the batch stream.  Internally an eager call also uses two
+ * streams of the batch's own (the edge-bias tables, the off-diagonal stack),
+ * forked from and joined back into the batch stream, so later work on the
+ * batch stream is ordered after the whole inference; they stay unused under
+ * graph capture and live kernel timing.  The first call per compute type
+ * tunes the GEMM tiles (it synchronises the device and allocates).  With the "infer_graph"
  * switch of hp_debug_set on (default off), later calls replay an inference
  * captured once per (d_weights, d_rho, d_sys, d_factors) buffer set as a
  * hipGraph (it reads the buffers' contents at each replay; at most 8 such
