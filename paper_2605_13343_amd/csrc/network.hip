@@ -815,11 +815,15 @@ __device__ inline float edge_gelu(float x) {
 
 // FAST: the BF16 path's GELU (the MLP's outputs are attention biases added to
 // logits of BF16 queries and keys); otherwise the library erff.
-template <bool FAST>
-__device__ inline void edge_mlp(const float* sw, int E, int H, const float e[4], float out[8]) {
+// HK, EK > 0 fix H and E at compile time (the per-head loop then has exactly
+// H multiply-adds); 0 takes them from the arguments.
+template <bool FAST, int HK = 0, int EK = 0>
+__device__ inline void edge_mlp(const float* sw, int E_, int H_, const float e[4], float out[8]) {
+  const int E = EK ? EK : E_, H = HK ? HK : H_;
   const float *w1 = sw, *b1 = sw + 4 * E, *w2 = sw + 5 * E, *b2 = sw + 5 * E + E * H;
 #pragma unroll
   for (int h = 0; h < 8; ++h) out[h] = h < H ? b2[h] : 0.f;
+#pragma unroll(EK ? 4 : 1)
   for (int k = 0; k < E; ++k) {
     float s = b1[k];
 #pragma unroll
@@ -920,14 +924,14 @@ __global__ void k_leaf_stencil(const FrameDesc* fr, const int* node2f, const flo
 // Stencil corrections MLP_e(dx_e, Ahat) - MLP_e(dx_e, 0) of every (node,
 // slot) pair, the same operations as edge_mlp with the first three input
 // terms taken from the slot constants; grid-stride over pairs.
-template <bool FAST>
+template <bool FAST, int HK = 0, int EK = 0>
 __global__ __launch_bounds__(256) void k_edge_corr(EdgeW w, const float* slots, const uint8_t* nbr, const float* ahat,
                                                    int64_t ntot, float* corr) {
   __shared__ float cst[EDGE_CST];
   __shared__ float sw[EDGE_MAX_FLOATS];
   for (int q = threadIdx.x; q < EDGE_CST; q += blockDim.x) cst[q] = slots[q];
   edge_stage(w, sw);  // ends with a barrier
-  const int E = w.E, H = w.H;
+  const int E = EK ? EK : w.E, H = HK ? HK : w.H;
   const float *w1 = sw, *w2 = sw + 5 * E, *b2 = sw + 5 * E + E * H;
   const float* base = cst + 7 * 65;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < ntot * 7;
@@ -942,13 +946,16 @@ __global__ __launch_bounds__(256) void k_edge_corr(EdgeW w, const float* slots, 
     float out[8];
 #pragma unroll
     for (int h = 0; h < 8; ++h) out[h] = h < H ? b2[h] : 0.f;
+#pragma unroll(EK ? 4 : 1)
     for (int k = 0; k < E; ++k) {
       const float g = edge_gelu<FAST>(fmaf(a, w1[3 * E + k], cst[e * 65 + k]));
 #pragma unroll
       for (int h = 0; h < 8; ++h)
         if (h < H) out[h] = fmaf(g, w2[k * H + h], out[h]);
     }
-    for (int h = 0; h < H; ++h) o[h] = out[h] - base[e * 8 + h];
+#pragma unroll
+    for (int h = 0; h < 8; ++h)
+      if (h < H) o[h] = out[h] - base[e * 8 + h];
   }
 }
 
@@ -1054,18 +1061,21 @@ __global__ __launch_bounds__(256) void k_off_desc_final(const FrameDesc* fr, con
 }
 
 // Off-diagonal bias per layer: bias[m][h][t][t'] = MLP_e(desc[m][t][t']).
-template <bool FAST>
+template <bool FAST, int HK = 0, int EK = 0>
 __global__ __launch_bounds__(256) void k_edge_off(EdgeW w, const float* desc, int64_t npairs, int LS, float* bias) {
   __shared__ float sw[EDGE_MAX_FLOATS];
   edge_stage(w, sw);
+  const int H = HK ? HK : w.H;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npairs; p += (int64_t)gridDim.x * blockDim.x) {
     const int64_t m = p / (LS * LS);
     const int tt = (int)(p % (LS * LS));
     const float4 dv = *(const float4*)(desc + p * 4);
     const float e[4] = {dv.x, dv.y, dv.z, dv.w};
     float o[8];
-    edge_mlp<FAST>(sw, w.E, w.H, e, o);
-    for (int h = 0; h < w.H; ++h) bias[(m * w.H + h) * LS * LS + tt] = o[h];
+    edge_mlp<FAST, HK, EK>(sw, w.E, w.H, e, o);
+#pragma unroll
+    for (int h = 0; h < 8; ++h)
+      if (h < H) bias[(m * H + h) * LS * LS + tt] = o[h];
   }
 }
 
@@ -2600,12 +2610,20 @@ static void edge_tables(Batch& b, const float* W, int l, int sidx, const EdgeTab
     const FrameDesc& F0 = b.fr[0];
     hipLaunchKernelGGL(k_edge_table<sizeof(AT) == 2>, dim3((unsigned)((L * L + 255) / 256 + 1)), dim3(256), 0, st, ew,
                        (int)L, F0.xm & lowmask, F0.ym & lowmask, F0.zm & lowmask, t.T0, t.eslots);
-    hipLaunchKernelGGL(k_edge_corr<sizeof(AT) == 2>, dim3((unsigned)((Nd * 7 + 255) / 256)), dim3(256), 0, st, ew,
-                       (const float*)t.eslots, (const uint8_t*)N.nbr, (const float*)N.ahat, Nd, t.corr);
+    if (H == 4 && c.edge_hidden == 32)  // the paper's widths: compile-time loops
+      hipLaunchKernelGGL((k_edge_corr<sizeof(AT) == 2, 4, 32>), dim3((unsigned)((Nd * 7 + 255) / 256)), dim3(256), 0,
+                         st, ew, (const float*)t.eslots, (const uint8_t*)N.nbr, (const float*)N.ahat, Nd, t.corr);
+    else
+      hipLaunchKernelGGL(k_edge_corr<sizeof(AT) == 2>, dim3((unsigned)((Nd * 7 + 255) / 256)), dim3(256), 0, st, ew,
+                         (const float*)t.eslots, (const uint8_t*)N.nbr, (const float*)N.ahat, Nd, t.corr);
   } else {
     const int64_t npairs = b.mtot * LS * LS;
-    hipLaunchKernelGGL(k_edge_off<sizeof(AT) == 2>, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, ew,
-                       (const float*)N.desc, npairs, (int)LS, t.boff);
+    if (H == 4 && c.edge_hidden == 32)
+      hipLaunchKernelGGL((k_edge_off<sizeof(AT) == 2, 4, 32>), dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0,
+                         st, ew, (const float*)N.desc, npairs, (int)LS, t.boff);
+    else
+      hipLaunchKernelGGL(k_edge_off<sizeof(AT) == 2>, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, ew,
+                         (const float*)N.desc, npairs, (int)LS, t.boff);
   }
 }
 
