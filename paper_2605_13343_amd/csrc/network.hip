@@ -659,55 +659,97 @@ __global__ __launch_bounds__(256) void k_ln_concat(const float* S0, int64_t ld0,
 // log rho, heavy fraction, mean/std/min/max of log A_ii, nx/32, ny/32, nz/32.
 __global__ __launch_bounds__(1024) void k_frame_stats(const FrameDesc* fr, const float* rho, const float* sys,
                                                      int64_t ntot, float* glob) {
-  constexpr int NW = 16;  // waves of the 1024-thread block
-  __shared__ double red[NW][2];
+  constexpr int NW = 16;   // waves of the 1024-thread block
+  constexpr int CAP = 16;  // nodes per thread whose logs stay in registers (frames up to 16384 nodes)
+  __shared__ double red[NW][6];
   const FrameDesc F = fr[blockIdx.x];
   const double* dg8 = reinterpret_cast<const double*>(sys + 5 * ntot);
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  auto bsum = [&](double v) -> double {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    __syncthreads();
-    if (lane == 0) red[w][0] = v;
-    __syncthreads();
-    double r = red[0][0];
-    for (int i = 1; i < NW; ++i) r += red[i][0];
-    return r;
-  };
-  auto bmin = [&](double v, bool mx) -> double {
-    for (int o = 32; o > 0; o >>= 1) {
-      double u = __shfl_xor(v, o, 64);
-      v = mx ? fmax(v, u) : fmin(v, u);
+  // K wave reductions at once (sum, or min / max by op), then the waves'
+  // results in wave order: one pair of barriers per batch of statistics
+  auto reduce = [&](double (&v)[6], const int (&op)[6], int K) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      if (i >= K) break;
+      double x = v[i];
+      auto comb = [&](double a, double b) { return op[i] == 0 ? a + b : op[i] < 0 ? fmin(a, b) : fmax(a, b); };
+      x = comb(x, dpp_move_d<0xB1>(x));
+      x = comb(x, dpp_move_d<0x4E>(x));
+      x = comb(x, dpp_move_d<0x141>(x));
+      x = comb(x, dpp_move_d<0x140>(x));
+      // row broadcasts: the rows outside the mask keep their own value
+      {
+        const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+        const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)u, (int)(unsigned)u, 0x142, 0xA, 0xF, false);
+        const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(u >> 32), (int)(unsigned)(u >> 32), 0x142, 0xA, 0xF, false);
+        const double y = __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+        x = (lane >> 4) & 1 ? comb(x, y) : x;
+      }
+      {
+        const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+        const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)u, (int)(unsigned)u, 0x143, 0xC, 0xF, false);
+        const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(u >> 32), (int)(unsigned)(u >> 32), 0x143, 0xC, 0xF, false);
+        const double y = __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+        x = (lane >> 5) & 1 ? comb(x, y) : x;
+      }
+      v[i] = x;  // lane 63 holds the wave's result
     }
     __syncthreads();
-    if (lane == 0) red[w][1] = v;
+    if (lane == 63)
+      for (int i = 0; i < K; ++i) red[w][i] = v[i];
     __syncthreads();
-    double r = red[0][1];
-    for (int i = 1; i < NW; ++i) r = mx ? fmax(r, red[i][1]) : fmin(r, red[i][1]);
-    return r;
+    for (int i = 0; i < K; ++i) {
+      double r = red[0][i];
+      for (int q = 1; q < NW; ++q) r = op[i] == 0 ? r + red[q][i] : op[i] < 0 ? fmin(r, red[q][i]) : fmax(r, red[q][i]);
+      v[i] = r;
+    }
   };
-  double sr = 0, sa = 0, mnr = 1e300, mxr = -1e300, mna = 1e300, mxa = -1e300;
-  for (int c = t; c < F.n; c += 1024) {
-    double lr = log((double)rho[F.n0 + c]), la = log(dg8[F.n0 + c]);
-    sr += lr;
-    sa += la;
-    mnr = fmin(mnr, lr);
-    mxr = fmax(mxr, lr);
-    mna = fmin(mna, la);
-    mxa = fmax(mxa, la);
+  double lrv[CAP], lav[CAP];
+  const bool cached = F.n <= 1024 * CAP;
+  double a1[6] = {0, 0, 1e300, -1e300, 1e300, -1e300};
+#pragma unroll
+  for (int u = 0; u < CAP; ++u) {
+    const int c = t + 1024 * u;
+    if (c < F.n) {
+      lrv[u] = log((double)rho[F.n0 + c]);
+      lav[u] = log(dg8[F.n0 + c]);
+      a1[0] += lrv[u];
+      a1[1] += lav[u];
+      a1[2] = fmin(a1[2], lrv[u]);
+      a1[3] = fmax(a1[3], lrv[u]);
+      a1[4] = fmin(a1[4], lav[u]);
+      a1[5] = fmax(a1[5], lav[u]);
+    }
   }
+  for (int c = t + 1024 * CAP; c < F.n; c += 1024) {  // frames beyond the register cache
+    const double lr = log((double)rho[F.n0 + c]), la = log(dg8[F.n0 + c]);
+    a1[0] += lr;
+    a1[1] += la;
+    a1[2] = fmin(a1[2], lr);
+    a1[3] = fmax(a1[3], lr);
+    a1[4] = fmin(a1[4], la);
+    a1[5] = fmax(a1[5], la);
+  }
+  reduce(a1, {0, 0, -1, 1, -1, 1}, 6);
   const double n = F.n;
-  const double mr = bsum(sr) / n, ma = bsum(sa) / n;
-  const double lmin = bmin(mnr, false), lmax = bmin(mxr, true);
-  const double amin = bmin(mna, false), amax = bmin(mxa, true);
-  double vr = 0, va = 0, hv = 0;
+  const double mr = a1[0] / n, ma = a1[1] / n;
+  const double lmin = a1[2], lmax = a1[3], amin = a1[4], amax = a1[5];
   const double mid = 0.5 * (lmin + lmax);
-  for (int c = t; c < F.n; c += 1024) {
-    double lr = log((double)rho[F.n0 + c]), la = log(dg8[F.n0 + c]);
-    vr += (lr - mr) * (lr - mr);
-    va += (la - ma) * (la - ma);
-    hv += lr > mid ? 1.0 : 0.0;
+  double a2[6] = {0, 0, 0, 0, 0, 0};
+  auto second = [&](double lr, double la) {
+    a2[0] += (lr - mr) * (lr - mr);
+    a2[1] += (la - ma) * (la - ma);
+    a2[2] += lr > mid ? 1.0 : 0.0;
+  };
+  if (cached) {
+#pragma unroll
+    for (int u = 0; u < CAP; ++u)
+      if (t + 1024 * u < F.n) second(lrv[u], lav[u]);
+  } else {
+    for (int c = t; c < F.n; c += 1024) second(log((double)rho[F.n0 + c]), log(dg8[F.n0 + c]));
   }
-  const double sdr = sqrt(bsum(vr) / n), sda = sqrt(bsum(va) / n), heavy = lmax > lmin ? bsum(hv) / n : 0.0;
+  reduce(a2, {0, 0, 0, 0, 0, 0}, 3);
+  const double sdr = sqrt(a2[0] / n), sda = sqrt(a2[1] / n), heavy = lmax > lmin ? a2[2] / n : 0.0;
   if (t == 0) {
     float* g = glob + blockIdx.x * 12;
     g[0] = (float)(log2(n) / 16.0);
