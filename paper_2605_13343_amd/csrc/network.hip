@@ -1734,6 +1734,40 @@ __global__ __launch_bounds__(256) void k_gram(const float* Frows, FT* G) {
   }
 }
 
+// G_k = F_k F_k^T for L = 64 on the matrix cores (FP32 MFMA 32x32x2, FP32
+// accumulation; one block per leaf, wave (I, J) forms the 32 x 32 block
+// (I, J) along c in steps of 2).  Entries (i, j) and (j, i) multiply the same
+// pairs in the same order, so G_k stays exactly symmetric, and each wave
+// writes its block transposed (block (J, I)): a lane then holds four
+// consecutive columns of one row.
+typedef float f32x16v_t __attribute__((ext_vector_type(16)));
+template <typename FT>
+__global__ __launch_bounds__(256) void k_gram_mfma(const float* Frows, FT* G) {
+  constexpr int L = 64, LP = L + 1;  // odd pitch: a column read touches 32 banks
+  __shared__ float sF[L][LP];
+  const int64_t kg = blockIdx.x;
+  const float* src = Frows + kg * L * L;
+  for (int idx = threadIdx.x; idx < L * L; idx += 256) sF[idx / L][idx % L] = src[idx];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int I = wave >> 1, J = wave & 1, r = lane & 31, h = lane >> 5;
+  f32x16v_t acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+#pragma unroll 8
+  for (int k = 0; k < L; k += 2)
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(sF[32 * I + r][k + h], sF[32 * J + r][k + h], acc, 0, 0, 0);
+  // acc[4 i + j] = G[32 I + 8 i + 4 h + j][32 J + r] = G[32 J + r][32 I + 8 i + 4 h + j]
+  FT* g = G + kg * L * L + (int64_t)(32 * J + r) * L + 32 * I + 4 * h;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if constexpr (sizeof(FT) == 2)
+      *(uint2*)(g + 8 * i) = make_uint2(pack_bf16x2(acc[4 * i], acc[4 * i + 1]), pack_bf16x2(acc[4 * i + 2], acc[4 * i + 3]));
+    else
+      *(float4*)(g + 8 * i) = make_float4(acc[4 * i], acc[4 * i + 1], acc[4 * i + 2], acc[4 * i + 3]);
+  }
+}
+
 // B_m = U_m V_m^T (one block per tile); UV rows = [U row | V row].
 template <typename FT, int LS>
 __global__ void k_uvt(const float* UV, FT* B) {
@@ -2952,7 +2986,7 @@ static hp_status forward(Batch& b, const float* W, const float* rho, const float
   gemm<AT>(b, N.a128, d, N, P.hleaf1, wp("hleaf1.b"), nullptr, 0, nullptr, 0, N.b128, d, Nd, 1);
   gemm<AT>(b, N.b128, d, N, P.hleaf2, wp("hleaf2.b"), nullptr, 0, N.Frows, L, nullptr, 0, Nd, 0);
   if (L == 64)
-    hipLaunchKernelGGL((k_gram<FT, 64>), dim3((unsigned)b.ktot), dim3(256), 0, st, (const float*)N.Frows,
+    hipLaunchKernelGGL((k_gram_mfma<FT>), dim3((unsigned)b.ktot), dim3(256), 0, st, (const float*)N.Frows,
                        (FT*)(base + offs[0]));
   else
     hipLaunchKernelGGL((k_gram<FT, 32>), dim3((unsigned)b.ktot), dim3(256), 0, st, (const float*)N.Frows,
