@@ -274,13 +274,26 @@ static hp_status run_pass(Batch* b, PcgLaunch& P, const hp_solve_opts& o, const 
   int* h_nact = (int*)(b->h_pin + 64);
   SolveParams* h_prm = (SolveParams*)(b->h_pin + 128);
   FrameState* h_st = (FrameState*)(b->h_pin + 256);
-  HP_HIP(hipStreamSynchronize(b->stream));
-  for (int f = 0; f < b->nframes; ++f) h_st[2 * f] = h_st[2 * f + 1] = init[f];
-  *h_nact = nact;
-  *h_prm = SolveParams{o.tol, o.max_iter, o.recompute_every, o.stagnation, 0};
-  HP_HIP(hipMemcpyAsync(b->st, h_st, sizeof(FrameState) * 2 * b->nframes, hipMemcpyHostToDevice, b->stream));
-  HP_HIP(hipMemcpyAsync(b->n_active, h_nact, sizeof(int), hipMemcpyHostToDevice, b->stream));
-  HP_HIP(hipMemcpyAsync(b->prm, h_prm, sizeof(SolveParams), hipMemcpyHostToDevice, b->stream));
+  const SolveParams prm{o.tol, o.max_iter, o.recompute_every, o.stagnation, 0};
+  // every frame active from the standard state: written on the device, so
+  // the host does not wait for the work already on the stream (the inference)
+  bool standard = nact == b->nframes;
+  for (int f = 0; f < b->nframes && standard; ++f)
+    standard = init[f].active == 1 && init[f].done == 0 && init[f].rho == 1.0 && init[f].it == 0 &&
+               init[f].flags == 0 && init[f].force_rc == 0 && init[f].fresh == 0 && init[f].alpha == 0.0 &&
+               init[f].beta == 0.0 && init[f].rr == 0.0 && init[f].target == 0.0 && init[f].bnorm == 0.0 &&
+               init[f].rwin == 0.0;
+  if (standard) {
+    HP_TRY(pcg_init_states(b->st, b->nframes, b->n_active, b->prm, prm, b->stream));
+  } else {
+    HP_HIP(hipStreamSynchronize(b->stream));  // the pinned staging may still feed an earlier copy
+    for (int f = 0; f < b->nframes; ++f) h_st[2 * f] = h_st[2 * f + 1] = init[f];
+    *h_nact = nact;
+    *h_prm = prm;
+    HP_HIP(hipMemcpyAsync(b->st, h_st, sizeof(FrameState) * 2 * b->nframes, hipMemcpyHostToDevice, b->stream));
+    HP_HIP(hipMemcpyAsync(b->n_active, h_nact, sizeof(int), hipMemcpyHostToDevice, b->stream));
+    HP_HIP(hipMemcpyAsync(b->prm, h_prm, sizeof(SolveParams), hipMemcpyHostToDevice, b->stream));
+  }
   HP_TRY(pcg_setup(P));
   const int chunk = std::max(2, o.chunk + (o.chunk & 1));
   hipGraphExec_t exec = nullptr;
@@ -309,9 +322,14 @@ static hp_status run_pass(Batch* b, PcgLaunch& P, const hp_solve_opts& o, const 
   }
   const int64_t max_chunks = (int64_t)o.max_iter / chunk + 2;
   for (int64_t c = 0; c < max_chunks; ++c) {
-    HP_HIP(hipMemcpyAsync(h_active, b->n_active, sizeof(int), hipMemcpyDeviceToHost, b->stream));
-    HP_HIP(hipStreamSynchronize(b->stream));
-    if (*h_active <= 0) break;
+    // the first chunk goes straight after the setup (a frame the setup
+    // stopped is skipped by every kernel); later ones after a look at the
+    // active count
+    if (c > 0) {
+      HP_HIP(hipMemcpyAsync(h_active, b->n_active, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+      HP_HIP(hipStreamSynchronize(b->stream));
+      if (*h_active <= 0) break;
+    }
     if (exec) HP_HIP(hipGraphLaunch(exec, b->stream));
     else HP_TRY(pcg_iterations(P, chunk));
   }

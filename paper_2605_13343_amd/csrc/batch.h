@@ -146,6 +146,11 @@ hp_status launch_spmv(const LaunchGeom& g, const float* sys, const float* p, flo
 hp_status launch_apply(const LaunchGeom& g, int L, int LS, int fdtype, const float* sys, const void* fac,
                        const int64_t* offs, const float* r, float* y, float* uh, float* vh, float* Tr, float* Tc);
 hp_status pcg_setup(const PcgLaunch& P);
+// Every frame of the batch active from the standard initial state, the
+// active count and the solve parameters, written by a kernel on stream s
+// (no host copy, so no wait for earlier work on the stream).
+hp_status pcg_init_states(FrameState* st, int nframes, int* n_active, SolveParams* prm, const SolveParams& p,
+                          hipStream_t s);
 hp_status pcg_iterations(const PcgLaunch& P, int count);
 hp_status pcg_finalize(const PcgLaunch& P);
 

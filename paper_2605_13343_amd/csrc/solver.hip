@@ -997,6 +997,34 @@ static void hmat_iter(const PcgLaunch& P, int par) {
   hipLaunchKernelGGL((k_prolong<L, LS, FT>), dim3(g.ktot), dim3(LEAF_THREADS), 0, g.stream, g.fr, g.leaf2f, P.B, fac);
 }
 
+__global__ void k_pcg_init(FrameState* st, int nframes, int* n_active, SolveParams* prm, SolveParams p) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f < nframes) {
+    FrameState s;
+    s.rho = 1.0;
+    s.alpha = s.beta = s.rr = s.target = s.bnorm = s.rwin = 0.0;
+    s.it = s.flags = s.done = s.force_rc = s.fresh = 0;
+    s.active = 1;
+    store_state(st + 2 * f, s);
+    store_state(st + 2 * f + 1, s);
+  }
+  if (f == 0) {
+    *n_active = nframes;
+    prm->tol = p.tol;
+    prm->max_iter = p.max_iter;
+    prm->recompute_every = p.recompute_every;
+    prm->stagnation = p.stagnation;
+    prm->pad = 0;
+  }
+}
+
+hp_status pcg_init_states(FrameState* st, int nframes, int* n_active, SolveParams* prm, const SolveParams& p,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_init, dim3((unsigned)((nframes + 63) / 64)), dim3(64), 0, s, st, nframes, n_active, prm, p);
+  HP_HIP(hipGetLastError());
+  return HP_OK;
+}
+
 hp_status pcg_setup(const PcgLaunch& P) {
   const LaunchGeom& g = P.g;
   if (P.mode == HP_PRECOND_HMAT) {
