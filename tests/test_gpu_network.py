@@ -294,6 +294,37 @@ def test_small_frames_in_one_batch_match_oracle():
         assert np.linalg.norm(s.bo[f] - s.A[f] @ xf) / np.linalg.norm(s.bo[f]) <= 1e-6
 
 
+def test_back_to_back_eager_inferences_match_synchronised_ones():
+    """An eager inference forks two streams of the batch (edge-bias tables,
+    off-diagonal stack) off the batch stream and joins them back before it
+    returns.  Calls issued back to back with the inputs changed in between
+    and no host synchronisation give, bit for bit, the results of calls
+    that are each synchronised."""
+    import torch
+    cfg = DEF
+    w = test_weights(cfg)
+    frames = [inputs.make_frame("precision8192", 2001), inputs.make_frame("batch_mixed", 4003)]
+    s = Side(cfg, frames, with_net=True)
+    wt = torch.tensor(hp.pack_weights(cfg, w), device="cuda")
+    rhos = [s.rho.clone(), s.rho * 1.7 + 0.3, s.rho * 0.6 + 0.05]
+
+    def run(r):
+        s.rho.copy_(r)
+        s.B.assemble(s.rho, s.sys)
+        s.B.infer_factors(wt, s.rho, s.sys, fac, hp.HP_BF16)
+        return fac.clone()
+
+    fac = s.B.new_factors(hp.HP_BF16)
+    ref = []
+    for r in rhos:
+        ref.append(run(r))
+        torch.cuda.synchronize()
+    outs = [run(rhos[k % 3]) for k in range(6)]  # no synchronisation in between
+    torch.cuda.synchronize()
+    for k, o in enumerate(outs):
+        assert torch.equal(o, ref[k % 3]), k
+
+
 def test_inference_graph_replays_match_eager():
     """After the first call, hp_infer_factors captures the inference once and
     replays it as a hipGraph.  Each replay reads the buffers' current contents:
