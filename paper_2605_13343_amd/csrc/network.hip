@@ -1448,6 +1448,21 @@ __global__ __launch_bounds__(256) void k_hw_levels_lo(const FrameDesc* fr, const
   const int K = F.K, C = min(STRIP_CHUNK, K), leaf0 = e.y * C;
   float v[STRIP_CHUNK];
   v[0] = top[(((int64_t)blockIdx.x) * LS + t) * 256 + 128 * side + col];
+  // every level's token is loaded first (branch-free, so the loads issue
+  // together: a load behind a branch was waited for before the next one),
+  // then added where the leaf is on this side.  Entries past the chunk's
+  // levels load a valid row of the frame's tiles and are not used.
+  float xo[2 * STRIP_CHUNK - 2];  // level j at offset (16 >> j) - 2
+  if (F.MH > 0) {
+    const int mlast = F.m0 + F.MH - 1;
+#pragma unroll
+    for (int j = 3; j >= 0; --j)
+#pragma unroll
+      for (int i = 0; i < (STRIP_CHUNK >> j); ++i) {
+        const int u = (leaf0 >> j) + i, m = min(F.m0 + K - (K >> j) + (u >> 1), mlast);
+        xo[(STRIP_CHUNK >> j) - 2 + i] = Xo[((int64_t)m * LS + t) * 128 + col];
+      }
+  }
   // level j: node i (local, descending so the parent v[i >> 1] is still the level-(j+1) value)
 #pragma unroll
   for (int j = 3; j >= 0; --j) {
@@ -1456,9 +1471,8 @@ __global__ __launch_bounds__(256) void k_hw_levels_lo(const FrameDesc* fr, const
     for (int i = (STRIP_CHUNK >> j) - 1; i >= 0; --i) {
       if (i >= (C >> j)) continue;
       const int u = (leaf0 >> j) + i;
-      float x = v[i >> 1];
-      if ((u & 1) == side) x += Xo[((int64_t)(F.m0 + K - (K >> j) + (u >> 1)) * LS + t) * 128 + col];
-      v[i] = x;
+      const float x = v[i >> 1];
+      v[i] = (u & 1) == side ? x + xo[(STRIP_CHUNK >> j) - 2 + i] : x;
     }
   }
   float* out = side ? cs : rs;
