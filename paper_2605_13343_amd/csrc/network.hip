@@ -1796,11 +1796,24 @@ __global__ void k_uvt(const float* UV, FT* B) {
 }
 
 // Node heads [Ut | Vt | lam-logit] -> factor sections; lam = softplus.
+// The row (36 floats, 16-byte aligned) is read whole before any store: with
+// loads and stores interleaved, each load waited for the store before it.
 template <typename FT, int LS>
-__global__ void k_pack_nodes(const float* NH, int64_t ntot, FT* Ut, FT* Vt, float* lam) {
+__global__ void k_pack_nodes(const float* __restrict__ NH, int64_t ntot, FT* __restrict__ Ut, FT* __restrict__ Vt,
+                             float* __restrict__ lam) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ntot) return;
-  const float* r = NH + i * 36;
+  constexpr int NQ = (2 * LS + 1 + 3) / 4;  // float4s covering [Ut | Vt | lam-logit] (<= 9 of the 36)
+  float r[4 * NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const float4 t = *(const float4*)(NH + i * 36 + 4 * q);
+    r[4 * q] = t.x;
+    r[4 * q + 1] = t.y;
+    r[4 * q + 2] = t.z;
+    r[4 * q + 3] = t.w;
+  }
+#pragma unroll
   for (int s = 0; s < LS; ++s) {
     Ut[i * LS + s] = to_act<FT>(r[s]);
     Vt[i * LS + s] = to_act<FT>(r[LS + s]);
