@@ -296,29 +296,49 @@ static hp_status run_pass(Batch* b, PcgLaunch& P, const hp_solve_opts& o, const 
   }
   HP_TRY(pcg_setup(P));
   const int chunk = std::max(2, o.chunk + (o.chunk & 1));
-  hipGraphExec_t exec = nullptr;
-  if (o.use_graph) {
+  // The first chunk runs as many iterations as the batch's previous solve
+  // with this preconditioner needed (even, at least one chunk): for a batch
+  // solved again and again, one active-count readback instead of several.
+  // Frames stop at their own iteration either way; only trailing no-op
+  // iterations of stopped frames differ.
+  int first = chunk;
+  {
+    const int prev = b->last_iters[P.mode];
+    if (prev > chunk) first = (int)std::min<int64_t>(prev + (prev & 1), (int64_t)o.max_iter + 2);
+    first = std::max(first + (first & 1), 2);
+  }
+  // one captured graph per chunk length
+  auto graph_for = [&](int n, hipGraphExec_t* out) -> hp_status {
     auto key = std::make_tuple(P.mode, P.fdtype, (const void*)P.B.sys, P.fbase, (const void*)P.B.b,
-                               (const void*)P.B.x0, chunk);
+                               (const void*)P.B.x0, n);
     auto it = b->graphs.find(key);
     if (it != b->graphs.end()) {
-      exec = it->second;
-    } else {
-      if (!b->cap_stream) HP_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
-      PcgLaunch C = P;
-      C.g.stream = b->cap_stream;
-      C.prof = nullptr;
-      hipGraph_t graph;
-      HP_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-      hp_status s = pcg_iterations(C, chunk);
-      hipError_t e = hipStreamEndCapture(b->cap_stream, &graph);
-      if (s != HP_OK) return s;
-      if (e != hipSuccess) return set_error(HP_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      hipGraphDestroy(graph);
-      if (e != hipSuccess) return set_error(HP_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-      b->graphs[key] = exec;
+      *out = it->second;
+      return HP_OK;
     }
+    if (!b->cap_stream) HP_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    PcgLaunch C = P;
+    C.g.stream = b->cap_stream;
+    C.prof = nullptr;
+    hipGraph_t graph;
+    HP_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    hp_status s = pcg_iterations(C, n);
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &graph);
+    if (s != HP_OK) return s;
+    if (e != hipSuccess) return set_error(HP_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return set_error(HP_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    b->graphs[key] = exec;
+    *out = exec;
+    return HP_OK;
+  };
+  hipGraphExec_t exec = nullptr, exec_first = nullptr;
+  if (o.use_graph) {
+    HP_TRY(graph_for(chunk, &exec));
+    exec_first = exec;
+    if (first != chunk) HP_TRY(graph_for(first, &exec_first));
   }
   const int64_t max_chunks = (int64_t)o.max_iter / chunk + 2;
   for (int64_t c = 0; c < max_chunks; ++c) {
@@ -330,8 +350,8 @@ static hp_status run_pass(Batch* b, PcgLaunch& P, const hp_solve_opts& o, const 
       HP_HIP(hipStreamSynchronize(b->stream));
       if (*h_active <= 0) break;
     }
-    if (exec) HP_HIP(hipGraphLaunch(exec, b->stream));
-    else HP_TRY(pcg_iterations(P, chunk));
+    if (exec) HP_HIP(hipGraphLaunch(c == 0 ? exec_first : exec, b->stream));
+    else HP_TRY(pcg_iterations(P, c == 0 ? first : chunk));
   }
   HP_TRY(pcg_finalize(P));
   return HP_OK;
@@ -401,6 +421,11 @@ extern "C" hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_
   HP_TRY(run_pass(b, P, o, init, b->nframes));
   std::vector<FrameState> out;
   HP_TRY(read_states(b, out));
+  {
+    int mx = 0;
+    for (int f = 0; f < b->nframes; ++f) mx = std::max(mx, out[f].it);
+    b->last_iters[o.precond] = mx;
+  }
   bool any_fail = false;
   for (int f = 0; f < b->nframes; ++f) {
     res[f].iters = out[f].it;

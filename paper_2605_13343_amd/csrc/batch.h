@@ -131,6 +131,7 @@ struct Batch {
   std::map<std::tuple<int, const void*, const void*, const void*, const void*, int>, hipGraphExec_t> infer_graphs;
   std::set<std::pair<int, int>> infer_warm;
   int infer_graph = 0;                  // replay inferences from a captured hipGraph after the first (opt-in)
+  int last_iters[3] = {0, 0, 0};        // iterations the last solve needed, per preconditioner (first chunk length)
   std::vector<void*> allocs;
 
   ~Batch();

@@ -169,6 +169,15 @@ def test_batched_equals_single_and_deterministic(torch_cuda):
     assert r1 == r2 and bool((x1 == x2).all())
     x3, r3 = _solve(s, hp.PRECOND_HMAT, fac, hp.HP_BF16, use_graph=False)
     assert r1 == r3 and bool((x1 == x3).all())
+    # a tighter solve first: the next solve's first chunk (sized from the
+    # previous solve's iterations) then runs past every frame's stop
+    _, rt = _solve(s, hp.PRECOND_HMAT, fac, hp.HP_BF16, tol=1e-9)
+    print("iterations", [r[0] for r in r1], [r[0] for r in rt])
+    assert max(r[0] for r in rt) > max(r[0] for r in r1) + 2
+    for use_graph in (True, False):
+        x4, r4 = _solve(s, hp.PRECOND_HMAT, fac, hp.HP_BF16, use_graph=use_graph)
+        assert r1 == r4 and bool((x1 == x4).all())
+        _solve(s, hp.PRECOND_HMAT, fac, hp.HP_BF16, tol=1e-9)
     for f in range(len(frames)):
         s1 = Side(DEF, [frames[f]])
         fac1, _ = s1.upload_factors([facs[f]], hp.HP_BF16)
