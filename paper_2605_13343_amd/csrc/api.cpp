@@ -297,15 +297,16 @@ static hp_status run_pass(Batch* b, PcgLaunch& P, const hp_solve_opts& o, const 
   HP_TRY(pcg_setup(P));
   const int chunk = std::max(2, o.chunk + (o.chunk & 1));
   // The first chunk runs as many iterations as the batch's previous solve
-  // with this preconditioner needed (even, at least one chunk): for a batch
-  // solved again and again, one active-count readback instead of several.
-  // Frames stop at their own iteration either way; only trailing no-op
-  // iterations of stopped frames differ.
+  // with this preconditioner needed, rounded up to a multiple of 4 (even, as
+  // every chunk) and kept between one chunk and 256 iterations (so at most
+  // 64 more graph lengths are ever captured): for a batch solved again and
+  // again, one active-count readback instead of several.  Frames stop at
+  // their own iteration either way; only trailing no-op iterations of
+  // stopped frames differ.
   int first = chunk;
   {
-    const int prev = b->last_iters[P.mode];
-    if (prev > chunk) first = (int)std::min<int64_t>(prev + (prev & 1), (int64_t)o.max_iter + 2);
-    first = std::max(first + (first & 1), 2);
+    const int64_t prev = std::min<int64_t>(b->last_iters[P.mode], 256);
+    if (prev > chunk) first = (int)((prev + 3) / 4 * 4);
   }
   // one captured graph per chunk length
   auto graph_for = [&](int n, hipGraphExec_t* out) -> hp_status {
