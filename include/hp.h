@@ -167,7 +167,9 @@ typedef struct {
   int32_t recompute_every;  /* r = b - A x in FP64 every this many iterations (0 = never) */
   int32_t fallback;         /* 1: NOT_SPD/STAGNATED/MAXITER frames restart with Jacobi-PCG from x */
   int32_t use_graph;        /* 1: replay a captured hipGraph per chunk of iterations */
-  int32_t chunk;            /* iterations per host check (even, >= 2) */
+  int32_t chunk;            /* iterations per host check (even, >= 2); the first check comes
+                               after as many iterations as the batch's previous solve with
+                               the same precond needed (multiple of 4, at most 256), if more */
   int32_t stagnation;       /* 1: STAGNATED when ||r_k|| > 0.5 ||r_{k-100}|| at k % 100 == 0 */
 } hp_solve_opts;
 
