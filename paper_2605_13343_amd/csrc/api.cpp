@@ -269,7 +269,8 @@ extern "C" hp_status hp_apply(hp_batch b, const float* d_sys, const void* d_fact
 // The pinned staging area is rewritten only after the stream has drained
 // (every pass ends with a synchronisation), so the async uploads never race.
 static hp_status run_pass(Batch* b, PcgLaunch& P, const hp_solve_opts& o, const std::vector<FrameState>& init,
-                          int nact) {
+                          int nact, std::vector<FrameState>& out) {
+  out.clear();
   int* h_active = (int*)b->h_pin;
   int* h_nact = (int*)(b->h_pin + 64);
   SolveParams* h_prm = (SolveParams*)(b->h_pin + 128);
@@ -346,7 +347,19 @@ static hp_status run_pass(Batch* b, PcgLaunch& P, const hp_solve_opts& o, const 
     // the first chunk goes straight after the setup (a frame the setup
     // stopped is skipped by every kernel); later ones after a look at the
     // active count
-    if (c > 0) {
+    if (c == 1 && first > chunk) {
+      // a warm first chunk has most likely stopped every frame: the stopped
+      // frames' x, the active count and the states come back in one wait
+      HP_TRY(pcg_finalize(P, true));
+      HP_HIP(hipMemcpyAsync(h_active, b->n_active, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+      HP_HIP(hipMemcpyAsync(h_st, b->st, sizeof(FrameState) * 2 * b->nframes, hipMemcpyDeviceToHost, b->stream));
+      HP_HIP(hipStreamSynchronize(b->stream));
+      if (*h_active <= 0) {
+        out.resize(b->nframes);
+        for (int f = 0; f < b->nframes; ++f) out[f] = h_st[2 * f];
+        return HP_OK;
+      }
+    } else if (c > 0) {
       HP_HIP(hipMemcpyAsync(h_active, b->n_active, sizeof(int), hipMemcpyDeviceToHost, b->stream));
       HP_HIP(hipStreamSynchronize(b->stream));
       if (*h_active <= 0) break;
@@ -419,9 +432,9 @@ extern "C" hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_
     s.rho = 1.0;
     s.active = 1;
   }
-  HP_TRY(run_pass(b, P, o, init, b->nframes));
   std::vector<FrameState> out;
-  HP_TRY(read_states(b, out));
+  HP_TRY(run_pass(b, P, o, init, b->nframes, out));
+  if (out.empty()) HP_TRY(read_states(b, out));
   {
     int mx = 0;
     for (int f = 0; f < b->nframes; ++f) mx = std::max(mx, out[f].it);
@@ -450,9 +463,9 @@ extern "C" hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_
     o2.stagnation = 0;
     PcgLaunch P2 = P;
     P2.mode = HP_PRECOND_JACOBI;
-    HP_TRY(run_pass(b, P2, o2, init2, nact));
     std::vector<FrameState> out2;
-    HP_TRY(read_states(b, out2));
+    HP_TRY(run_pass(b, P2, o2, init2, nact, out2));
+    if (out2.empty()) HP_TRY(read_states(b, out2));
     any_fail = false;
     for (int f = 0; f < b->nframes; ++f) {
       if (!init2[f].active) continue;

@@ -153,7 +153,7 @@ hp_status pcg_setup(const PcgLaunch& P);
 hp_status pcg_init_states(FrameState* st, int nframes, int* n_active, SolveParams* prm, const SolveParams& p,
                           hipStream_t s);
 hp_status pcg_iterations(const PcgLaunch& P, int count);
-hp_status pcg_finalize(const PcgLaunch& P);
+hp_status pcg_finalize(const PcgLaunch& P, bool stopped_only = false);
 
 // network.hip
 hp_status network_alloc(Batch& b);

@@ -885,12 +885,14 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_update_simple(const FrameDesc* f
 }
 
 // After a pass: a frame that did an odd number of updates holds x in x1.
+// With stopped_only, frames still iterating are left alone (x0 is the other
+// half of their iterate pair).
 __global__ void k_finalize_x(const FrameDesc* fr, const int* blk2f, const FrameState* st, const double* x1,
-                             double* x0) {
+                             double* x0, int stopped_only) {
   const int f = blk2f[blockIdx.x];
   const FrameDesc F = fr[f];
   const FrameState S = load_state(st + 2 * f);
-  if (!S.active || (S.it & 1) == 0) return;
+  if (!S.active || (S.it & 1) == 0 || (stopped_only && !S.done)) return;
   int c = (blockIdx.x - F.b0) * NODE_BLOCK + threadIdx.x;
   if (c < F.n) x0[F.n0 + c] = x1[F.n0 + c];
 }
@@ -1082,10 +1084,10 @@ hp_status pcg_iterations(const PcgLaunch& P, int count) {
   return HP_OK;
 }
 
-hp_status pcg_finalize(const PcgLaunch& P) {
+hp_status pcg_finalize(const PcgLaunch& P, bool stopped_only) {
   const LaunchGeom& g = P.g;
   hipLaunchKernelGGL(k_finalize_x, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f,
-                     (const FrameState*)P.B.st, (const double*)P.B.x1, P.B.x0);
+                     (const FrameState*)P.B.st, (const double*)P.B.x1, P.B.x0, (int)stopped_only);
   HP_HIP(hipGetLastError());
   return HP_OK;
 }
