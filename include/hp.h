@@ -153,9 +153,13 @@ hp_status hp_spmv(hp_batch b, const float* d_sys, const float* d_p, float* d_q);
  * Sec. 5 (restriction u = Ut^T r, v = Vt^T r; strip sums; t^c = B^T s^r,
  * t^r = B s^c; prolongation Ut sum t^r + Vt sum t^c).
  *
- * hp_apply: y = M r for every frame.  d_r, d_y: [ntot] FP32 (ncols must be 1
- * here; multi-column products are internal to training).  fdtype HP_F32 or
- * HP_BF16 selects how d_factors is read; accumulation is FP32. */
+ * hp_apply: y = M r for every frame and each of ncols >= 1 right-hand
+ * sides.  d_r, d_y: [ncols][ntot] FP32, column-major (column c is
+ * d_r[c ntot .. (c+1) ntot)); the two ranges must not overlap.  The columns
+ * run one after another through the single-column kernels, so every column
+ * equals a one-column call bit for bit.  fdtype HP_F32 or HP_BF16 selects how
+ * d_factors is read; accumulation is FP32.  Asynchronous on the batch
+ * stream; errors (HP_E_INVALID) before anything is enqueued. */
 hp_status hp_apply(hp_batch b, const float* d_sys, const void* d_factors, int32_t fdtype,
                    const float* d_r, float* d_y, int32_t ncols);
 
@@ -169,7 +173,8 @@ typedef struct {
   int32_t use_graph;        /* 1: replay a captured hipGraph per chunk of iterations */
   int32_t chunk;            /* iterations per host check (even, >= 2); the first check comes
                                after as many iterations as the batch's previous solve with
-                               the same precond needed (multiple of 4, at most 256), if more */
+                               the same precond needed (multiple of 4, at most 256 and at
+                               most max_iter rounded up to even), if more */
   int32_t stagnation;       /* 1: STAGNATED when ||r_k|| > 0.5 ||r_{k-100}|| at k % 100 == 0 */
 } hp_solve_opts;
 

@@ -3,11 +3,15 @@ PyTorch CPU float64; autograd provides the reference gradients).
 
 TEST INFRASTRUCTURE ONLY -- see oracle/__init__.py.
 
-Parity unpinned against the paper: the paper prints no weights and no
-activations.  The forward is pinned by internal invariants in the tests
-(softmax rows, LayerNorm moments, leaf locality with highways and the
-off-diagonal stack switched off, batch-order equivariance, parameter count
-against the paper's "~2.6 M") and by finite differences for its gradient.
+The paper prints no weights and no activations, so no end-to-end forward
+value of the paper can be compared.  The pieces are pinned instead: hand-
+worked cases of the attention sublayer (head split of the QKV columns, the
+1/sqrt(d_h) scale, pair-bias and output-map orientation), of the edge MLP
+and exact-erf GELU, of all 20 encoder input columns on a 4 x 2 x 2 grid and
+of the edge-descriptor sign; invariants (softmax rows, LayerNorm moments,
+leaf locality with highways and the off-diagonal stack switched off,
+highway buffers by definition, descriptors by brute force); the parameter
+count against the paper's "~2.6 M"; finite differences for the gradient.
 
 Structure (Sec. 4 and Supplementary "Network Architecture Details"):
   encoder   h = W2 GELU(W1 f + b1) + b2, then n_gcn times

@@ -171,7 +171,6 @@ extern "C" hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes
   A((void**)&b->part_pq, np);
   A((void**)&b->part_rr, np);
   A((void**)&b->part_rz, np);
-  A((void**)&b->ticket, sizeof(unsigned) * 4 * nframes);
   A((void**)&b->n_active, sizeof(int));
   A((void**)&b->st, sizeof(FrameState) * 2 * nframes);
   A((void**)&b->prm, sizeof(SolveParams));
@@ -191,8 +190,6 @@ extern "C" hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes
   cp(b->d_blk2f, blk2f.data(), sizeof(int) * nb0);
   cp(b->d_leaf2f, leaf2f.data(), sizeof(int) * k0);
   cp(b->d_cblk, cblk.data(), sizeof(int2) * cblk.size());
-  if (s == HP_OK && hipMemset(b->ticket, 0, sizeof(unsigned) * 4 * nframes) != hipSuccess)
-    s = set_error(HP_E_HIP, "hp_batch_create: memset failed");
   if (s == HP_OK) s = network_alloc(*b);
   if (s != HP_OK) {
     delete b;
@@ -252,16 +249,29 @@ extern "C" hp_status hp_spmv(hp_batch b, const float* d_sys, const float* d_p, f
   return launch_spmv(b->geom(), d_sys, d_p, d_q);
 }
 
+// Shared checks of the apply entry points; fills offs for fdtype.
+static hp_status apply_args(hp_batch b, const float* d_sys, const void* d_factors, int32_t fdtype, const float* d_r,
+                            float* d_y, int32_t ncols, const char* who, int64_t offs[5]) {
+  if (!b || !d_sys || !d_factors || !d_r || !d_y) return set_error(HP_E_INVALID, "%s: NULL argument", who);
+  if (ncols < 1) return set_error(HP_E_INVALID, "%s: ncols must be >= 1", who);
+  if (fdtype != HP_F32 && fdtype != HP_BF16) return set_error(HP_E_INVALID, "%s: bad fdtype", who);
+  const uintptr_t r0 = (uintptr_t)d_r, y0 = (uintptr_t)d_y, len = (uintptr_t)(4 * b->ntot * (int64_t)ncols);
+  if (r0 < y0 + len && y0 < r0 + len) return set_error(HP_E_INVALID, "%s: r and y must not overlap", who);
+  int64_t tot;
+  factor_offsets(*b, fdtype, offs, &tot);
+  return HP_OK;
+}
+
 extern "C" hp_status hp_apply(hp_batch b, const float* d_sys, const void* d_factors, int32_t fdtype,
                               const float* d_r, float* d_y, int32_t ncols) {
-  if (!b || !d_sys || !d_factors || !d_r || !d_y) return set_error(HP_E_INVALID, "hp_apply: NULL argument");
-  if (ncols != 1) return set_error(HP_E_INVALID, "hp_apply: ncols must be 1");
-  if (fdtype != HP_F32 && fdtype != HP_BF16) return set_error(HP_E_INVALID, "hp_apply: bad fdtype");
-  if (d_r == d_y) return set_error(HP_E_INVALID, "hp_apply: r and y must not alias");
-  int64_t offs[5], tot;
-  factor_offsets(*b, fdtype, offs, &tot);
-  return launch_apply(b->geom(), b->cfg.leaf, b->cfg.rank, fdtype, d_sys, d_factors, offs, d_r, d_y, b->uh, b->vh,
-                      b->Tr, b->Tc);
+  int64_t offs[5];
+  HP_TRY(apply_args(b, d_sys, d_factors, fdtype, d_r, d_y, ncols, "hp_apply", offs));
+  // column c is r[c ntot .. (c+1) ntot); the columns share the batch's
+  // coarse workspace and run one after another on the batch stream
+  for (int32_t c = 0; c < ncols; ++c)
+    HP_TRY(launch_apply(b->geom(), b->cfg.leaf, b->cfg.rank, fdtype, d_sys, d_factors, offs, d_r + c * b->ntot,
+                        d_y + c * b->ntot, b->uh, b->vh, b->Tr, b->Tc));
+  return HP_OK;
 }
 
 // ------------------------------------------------------------------ PCG driver
@@ -304,10 +314,23 @@ static hp_status run_pass(Batch* b, PcgLaunch& P, const hp_solve_opts& o, const 
   // again, one active-count readback instead of several.  Frames stop at
   // their own iteration either way; only trailing no-op iterations of
   // stopped frames differ.
+  // It never exceeds max_iter (rounded up to even): every frame has stopped
+  // by then, so further iterations would only be no-ops.
   int first = chunk;
   {
     const int64_t prev = std::min<int64_t>(b->last_iters[P.mode], 256);
-    if (prev > chunk) first = (int)((prev + 3) / 4 * 4);
+    const int64_t cap = std::max<int64_t>(2, (int64_t)o.max_iter + (o.max_iter & 1));
+    if (prev > chunk) first = (int)std::min<int64_t>((prev + 3) / 4 * 4, cap);
+  }
+  // Graphs are keyed by the caller's buffers: a caller that cycles through
+  // many buffer sets would grow the cache without bound, so it is emptied
+  // once it holds kMaxPcgGraphs executables (every earlier pass has ended
+  // with a synchronisation, so none of them is still running).
+  constexpr size_t kMaxPcgGraphs = 48;
+  if (o.use_graph && b->graphs.size() >= kMaxPcgGraphs) {
+    HP_HIP(hipStreamSynchronize(b->stream));
+    for (auto& kv : b->graphs) hipGraphExecDestroy(kv.second);
+    b->graphs.clear();
   }
   // one captured graph per chunk length
   auto graph_for = [&](int n, hipGraphExec_t* out) -> hp_status {
@@ -422,7 +445,6 @@ extern "C" hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_
   B.part_pq = b->part_pq;
   B.part_rr = b->part_rr;
   B.part_rz = b->part_rz;
-  B.ticket = b->ticket;
   B.n_active = b->n_active;
   B.st = b->st;
   B.prm = b->prm;

@@ -33,7 +33,6 @@ struct PcgBufs {
   float *r, *z, *q;
   float *uh, *vh, *Tr, *Tc;
   double *part_pq, *part_rr, *part_rz;
-  unsigned* ticket;
   int* n_active;
   FrameState* st;
   const SolveParams* prm;
@@ -106,7 +105,6 @@ struct Batch {
   float *p0 = nullptr, *p1 = nullptr, *r = nullptr, *z = nullptr, *q = nullptr;
   float *uh = nullptr, *vh = nullptr, *Tr = nullptr, *Tc = nullptr;
   double *part_pq = nullptr, *part_rr = nullptr, *part_rz = nullptr;
-  unsigned* ticket = nullptr;
   int* n_active = nullptr;
   // pinned host staging: [0] active count read back, [1] active count upload,
   // then SolveParams, then nframes FrameState

@@ -2313,60 +2313,6 @@ void k_gemm_dl(GemmArgs a, int tiles_n) {
     }
     return;
   }
-  // A full block tile whose only output is the BF16 one leaves through LDS:
-  // from the fragments a lane holds 8 bytes of each of 4 column groups of one
-  // row, so a direct store sends 32 rows' pieces per instruction; restaged,
-  // 8 lanes write one row's 128 contiguous bytes.  The values are those of
-  // the direct epilogue (bias, activation, BF16 rounding).
-  static_assert(NW * WM * WN <= ST * (BM + BN) * BK, "staging tiles exceed the ring");
-  if (a.Yb && !a.Yf && !a.resid && !a.pre && m0 + BM <= a.M && n0 + BN <= a.N &&
-      (((uintptr_t)a.Yb | (uintptr_t)(2 * a.ldb)) & 15) == 0) {
-    __syncthreads();  // every wave is done with the ring's operands
-    uint16_t* stg = &ring[0][0] + wave * (WM * WN);
-    // element (r, col) of the wave's WM x WN tile; the 16-byte chunks of each
-    // 128-byte LDS line are XOR-swizzled by the line index, so the fragment
-    // writes (32 rows at once) and the row reads both spread over all banks
-    auto at = [&](int r, int col) {
-      const int byte = 2 * (r * WN + col), line = byte >> 7;
-      return ((line << 7) | (((byte >> 4) & 7) ^ (line & 7)) << 4 | (byte & 15)) >> 1;
-    };
-    // the activation as a compile-time choice: branch-free per-element code
-    auto fill = [&](auto gelu_tag) {
-      constexpr bool GELU = decltype(gelu_tag)::value;
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          const int cl = 32 * j + 4 * (lane >> 5);
-          float bv[16];
-          gemm_bias16(a, n0 + wn + cl, bv);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            float v[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              v[c] = acc[i][j][4 * q + c] + bv[4 * q + c];
-              if constexpr (GELU) v[c] = gelu_bf16path(v[c]);
-            }
-            *(uint2*)&stg[at(32 * i + (lane & 31), cl + 8 * q)] =
-                make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
-          }
-        }
-    };
-    if (a.act == 1) fill(std::true_type{});
-    else fill(std::false_type{});
-    // the wave reads back only its own tile, and one wave's LDS accesses
-    // complete in order
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    constexpr int LPR = WN / 8, RPI = 64 / LPR;  // lanes per row, rows per store
-    uint16_t* yb = (uint16_t*)a.Yb + (int64_t)(m0 + wm) * a.ldb + n0 + wn;
-#pragma unroll
-    for (int t = 0; t < WM / RPI; ++t) {
-      const int r = t * RPI + lane / LPR, col = 8 * (lane % LPR);
-      *(uint4*)(yb + (int64_t)r * a.ldb + col) = *(const uint4*)&stg[at(r, col)];
-    }
-    return;
-  }
   // With an FP32 output or a residual (and no pre-activation copy) a full
   // tile goes through LDS as FP32 in passes of 32 rows: a lane then reads
   // and writes 16 contiguous bytes and a row's columns leave together; the

@@ -422,8 +422,9 @@ hp_status probes(Batch& b, const float* sys, const float* zraw, float* z, float*
   const unsigned grid = (unsigned)((b.ntot + 15) / 16);
   const float* src = zraw;
   for (int s = 0; s < sweeps; ++s) {
-    float* dst = (s % 2 == 0) ? T.dY : z;   // ping-pong through dY, last sweep lands in z
-    if (s == sweeps - 1) dst = z;
+    // ping-pong between z and dY, chosen by the parity of the sweeps left so
+    // that the last sweep lands in z and no sweep reads its own output
+    float* dst = ((sweeps - 1 - s) % 2 == 0) ? z : T.dY;
     hipLaunchKernelGGL(k_probe_step, dim3(grid), dim3(256), 0, st, b.d_fr, (const int*)T.node2f, sys, b.ntot, src,
                        dst, omega);
     src = dst;

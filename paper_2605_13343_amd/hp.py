@@ -252,8 +252,9 @@ class Batch:
     def spmv(self, sys, p, q):
         _check(lib().hp_spmv(self.h, _ptr(sys), _ptr(p), _ptr(q)))
 
-    def apply(self, sys, fac, dtype: int, r, y):
-        _check(lib().hp_apply(self.h, _ptr(sys), _ptr(fac), dtype, _ptr(r), _ptr(y), 1))
+    def apply(self, sys, fac, dtype: int, r, y, ncols: int = 1):
+        """y = M r; r, y hold ncols columns of ntot values each (column-major)."""
+        _check(lib().hp_apply(self.h, _ptr(sys), _ptr(fac), dtype, _ptr(r), _ptr(y), int(ncols)))
 
     def pcg_solve(self, sys, fac, b, x, precond: int, fdtype: int = HP_F32, tol: float = 1e-6,
                   max_iter: int = 10000, recompute_every: int = 25, fallback: bool = True,
