@@ -17,8 +17,9 @@ Sec. 5 solve loop) with this build's run-time policy:
       beta = rho' / rho;  p = z + beta p
   iterations = number of SpMVs in the loop.
 
-The stagnation window and the Jacobi fallback are this build's additions:
-the paper enforces no SPD property on M and has no fallback.
+The stagnation window and the Jacobi fallback (on any of NOT_SPD, STAGNATED,
+MAXITER) are this build's additions: the paper enforces no SPD property on M
+and has no fallback.
 """
 from __future__ import annotations
 
@@ -98,11 +99,14 @@ def jacobi(A) -> Callable:
 
 
 def solve_with_fallback(A, b, M: Callable, tol: float = 1e-6, max_iter: int = 10000,
-                        recompute_every: int = 25):
-    """Learned-M PCG; on NOT_SPD or STAGNATED, Jacobi-PCG warm-started from the
-    current x to the same target tol * ||b||.  Iterations add up."""
-    x, k, flags, hist = pcg(A, b, M, tol, max_iter, recompute_every)
-    if flags & (NOT_SPD | STAGNATED):
+                        recompute_every: int = 25, stagnation: bool = True):
+    """Learned-M PCG; a frame that did not converge (NOT_SPD, STAGNATED or
+    MAXITER: positivity lost, less than a 2x drop of ||r|| over 100
+    iterations, or the iteration cap) restarts as Jacobi-PCG warm-started from
+    the current x, to the same target tol * ||b||, with the same cap and no
+    stagnation check.  Iterations add up; the flags of both passes are kept."""
+    x, k, flags, hist = pcg(A, b, M, tol, max_iter, recompute_every, stagnation=stagnation)
+    if not flags & CONVERGED:
         bn = float(np.sqrt(b @ b))
         x, k2, f2, h2 = pcg(A, b, jacobi(A), tol, max_iter, recompute_every, x0=x,
                             stagnation=False, bnorm=bn)

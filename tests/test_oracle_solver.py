@@ -139,3 +139,28 @@ def test_pcg_flags():
     x, it, fl, _ = pcg.solve_with_fallback(A, b, lambda r: -r, tol=1e-6)
     assert fl & pcg.FELL_BACK and fl & pcg.CONVERGED and fl & pcg.NOT_SPD
     assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= 1e-6
+
+
+def _weak_diagonal_M(n, spread=4.0, seed=7):
+    """An SPD preconditioner that preconditions badly: a diagonal with
+    entries spread over 2 * spread decades."""
+    d = 10.0 ** np.random.default_rng(seed).uniform(-spread, spread, n)
+    return lambda r: d * r
+
+
+def test_fallback_on_stagnation_and_iteration_cap():
+    A, b = _c1_system()
+    M = _weak_diagonal_M(A.shape[0])
+    # less than a 2x drop over the first 100 iterations: STAGNATED at 100
+    _, k, fl, h = pcg.pcg(A, b, M, tol=1e-6)
+    assert fl == pcg.STAGNATED and k == 100 and h[100] > 0.5 * h[0]
+    x, it, fl, _ = pcg.solve_with_fallback(A, b, M, tol=1e-6)
+    assert fl == pcg.STAGNATED | pcg.FELL_BACK | pcg.CONVERGED and it > 100
+    assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= 1e-6
+    # the warm start counts: Jacobi from x needs fewer iterations than from 0
+    _, kj, _, _ = pcg.pcg(A, b, pcg.jacobi(A), tol=1e-6)
+    assert it - 100 <= kj
+    # the cap: MAXITER hands over as well, to a Jacobi pass with the same cap
+    x, it, fl, _ = pcg.solve_with_fallback(A, b, M, tol=1e-6, max_iter=120, stagnation=False)
+    assert fl == pcg.MAXITER | pcg.FELL_BACK | pcg.CONVERGED and 120 < it <= 240
+    assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= 1e-6
