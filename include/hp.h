@@ -163,6 +163,34 @@ hp_status hp_spmv(hp_batch b, const float* d_sys, const float* d_p, float* d_q);
 hp_status hp_apply(hp_batch b, const float* d_sys, const void* d_factors, int32_t fdtype,
                    const float* d_r, float* d_y, int32_t ncols);
 
+/* ------------------------------------------------------------------ without allocation */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): y = M r as
+ * hp_apply computes it, for ONE frame and without an hp_batch.
+ *   nx, ny, nz   the frame's grid (the admissible grids of hp_batch_create);
+ *   leaf, rank   (64, 16) or (32, 8);
+ *   d_sys        the frame's hp_assemble output (13 N floats);
+ *   d_factors    the one-frame packing [G K L^2][B M_H L_s^2][Ut N L_s]
+ *                [Vt N L_s] in fdtype, then [lam N] FP32, each section
+ *                256-byte aligned (the offsets hp_batch_info reports for a
+ *                one-frame batch);
+ *   d_r, d_y     [ncols][N] FP32, column-major, not overlapping;
+ *   hip_stream   a stream of the current device (NULL: its default stream).
+ * Results equal hp_apply on a one-frame batch bit for bit (same kernels).
+ * Workspace: one fixed 4.5 MiB device array inside the library per device,
+ * held until the process ends, which limits N to 2^20 (HP_E_SHAPE beyond).
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine); its first call on a device looks up that device's array.
+ * Every call on a device uses the same array and rewrites it completely
+ * before reading it: calls that overlap in time on one device (two streams,
+ * or two host threads) race and give wrong results; serialise them.
+ * Asynchronous on hip_stream; argument errors are returned before anything
+ * is enqueued. */
+hp_status hp_apply_static(int32_t nx, int32_t ny, int32_t nz, int32_t leaf, int32_t rank, const float* d_sys,
+                          const void* d_factors, int32_t fdtype, const float* d_r, float* d_y, int32_t ncols,
+                          void* hip_stream);
+
 typedef struct {
   int32_t precond;          /* HP_PRECOND_* */
   int32_t fdtype;           /* factor dtype for HP_PRECOND_HMAT */

@@ -10,21 +10,25 @@ namespace hp {
 
 static int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
 
-void factor_offsets(const Batch& b, int dtype, int64_t offs[5], int64_t* total) {
+void factor_offsets_n(int64_t ktot, int64_t mtot, int64_t ntot, int L, int LS, int dtype, int64_t offs[5],
+                      int64_t* total) {
   const int64_t es = dtype == HP_BF16 ? 2 : 4;
-  const int L = b.cfg.leaf, LS = b.cfg.rank;
   int64_t o = 0;
   offs[0] = o;
-  o = align256(o + b.ktot * L * L * es);
+  o = align256(o + ktot * L * L * es);
   offs[1] = o;
-  o = align256(o + std::max<int64_t>(b.mtot, 1) * LS * LS * es);
+  o = align256(o + std::max<int64_t>(mtot, 1) * LS * LS * es);
   offs[2] = o;
-  o = align256(o + b.ntot * LS * es);
+  o = align256(o + ntot * LS * es);
   offs[3] = o;
-  o = align256(o + b.ntot * LS * es);
+  o = align256(o + ntot * LS * es);
   offs[4] = o;
-  o = align256(o + b.ntot * 4);
+  o = align256(o + ntot * 4);
   *total = o;
+}
+
+void factor_offsets(const Batch& b, int dtype, int64_t offs[5], int64_t* total) {
+  factor_offsets_n(b.ktot, b.mtot, b.ntot, b.cfg.leaf, b.cfg.rank, dtype, offs, total);
 }
 
 Batch::~Batch() {

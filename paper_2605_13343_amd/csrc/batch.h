@@ -138,6 +138,9 @@ struct Batch {
 };
 
 void factor_offsets(const Batch& b, int dtype, int64_t offs[5], int64_t* total);
+// The same section offsets for explicit sizes (ktot leaves, mtot tiles, ntot nodes).
+void factor_offsets_n(int64_t ktot, int64_t mtot, int64_t ntot, int L, int LS, int dtype, int64_t offs[5],
+                      int64_t* total);
 
 // solver.hip
 hp_status launch_assemble(const LaunchGeom& g, const float* rho, float* sys);

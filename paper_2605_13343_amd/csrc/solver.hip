@@ -23,6 +23,8 @@
 #include <float.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "batch.h"
 
 namespace hp {
@@ -942,6 +944,134 @@ hp_status launch_apply(const LaunchGeom& g, int L, int LS, int fdtype, const flo
   }
   return set_error(HP_E_SHAPE, "apply: unsupported (L, L_s) = (%d, %d); supported (64, 16), (32, 8)", L, LS);
 }
+
+// ------------------------------------------------------------------ one-frame apply without allocation
+//
+// hp_apply_static runs the apply kernels above on one frame without a batch.
+// Its workspace (the one-frame table, leaf -> frame map and coarse-block list
+// the kernels index, and the coarse vectors u, v, t^r, t^c) lives in
+// `scratch`, a fixed array of this translation unit's device code.  In host
+// code the array's name is only a stand-in: its device address is obtained
+// once per device with hipGetSymbolAddress and every launch passes that
+// address.  Every call on a device shares that device's array.
+
+constexpr size_t kScratchBytes = 4718592;  // 4.5 MiB: N up to 2^20 at (L, L_s) = (32, 8) or (64, 16)
+constexpr int64_t kStaticMaxN = int64_t(1) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static int64_t round256(int64_t v) { return (v + 255) & ~(int64_t)255; }
+
+// Byte layout of the workspace of one frame with K leaves, rank LS.
+struct StaticLayout {
+  int64_t leaf2f, cblk, uh, vh, tr, tc, end;
+  StaticLayout(int64_t K, int64_t LS) {
+    const int64_t ncb = std::max<int64_t>(K - 1, 1);
+    leaf2f = round256((int64_t)sizeof(FrameDesc));
+    cblk = leaf2f + round256(4 * K);
+    uh = cblk + round256(8 * ncb);
+    vh = uh + round256(4 * K * LS);
+    tr = vh + round256(4 * K * LS);
+    tc = tr + round256(4 * K * LS);
+    end = tc + round256(4 * K * LS);
+  }
+};
+
+// The frame table of a one-frame batch: frame 0 at row 0, every leaf in
+// frame 0, one coarse block per tile (a placeholder when there is none).
+__global__ void k_single_frame_tables(FrameDesc F, FrameDesc* fr, int* leaf2f, int2* cblk) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) fr[0] = F;
+  if (i < F.K) leaf2f[i] = 0;
+  if (i < max(F.MH, 1)) cblk[i] = F.MH > 0 ? make_int2(0, i) : make_int2(0, -1);
+}
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[256];  // device address of `scratch`, per device ordinal
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on each device, with that device current).
+static hp_status scratch_address(char** out) {
+  int dev = -1;
+  HP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 256) return set_error(HP_E_HIP, "hp_apply_static: device ordinal %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error(HP_E_HIP, "hp_apply_static: hipGetSymbolAddress(scratch) on device %d failed: %s", dev,
+                       hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+  }
+  *out = (char*)g_scratch_dev[dev];
+  return HP_OK;
+}
+
+}  // namespace hp
+
+extern "C" hp_status hp_apply_static(int32_t nx, int32_t ny, int32_t nz, int32_t leaf, int32_t rank,
+                                     const float* d_sys, const void* d_factors, int32_t fdtype, const float* d_r,
+                                     float* d_y, int32_t ncols, void* hip_stream) {
+  using namespace hp;
+  if (!d_sys || !d_factors || !d_r || !d_y) return set_error(HP_E_INVALID, "hp_apply_static: NULL argument");
+  if (ncols < 1) return set_error(HP_E_INVALID, "hp_apply_static: ncols must be >= 1");
+  if (fdtype != HP_F32 && fdtype != HP_BF16) return set_error(HP_E_INVALID, "hp_apply_static: bad fdtype");
+  if (!((leaf == 64 && rank == 16) || (leaf == 32 && rank == 8)))
+    return set_error(HP_E_SHAPE, "hp_apply_static: supported (leaf, rank): (64, 16), (32, 8)");
+  if (nx <= 0 || ny <= 0 || nz <= 0 || !admissible_grid(nx, ny, nz, nullptr))
+    return set_error(HP_E_SHAPE, "hp_apply_static: grid %d x %d x %d is not admissible", nx, ny, nz);
+  const int64_t n = (int64_t)nx * ny * nz;
+  if (n > kStaticMaxN)
+    return set_error(HP_E_SHAPE, "hp_apply_static: N = %lld exceeds the static workspace's maximum %lld",
+                     (long long)n, (long long)kStaticMaxN);
+  hp_partition_info pi;
+  HP_TRY(hp_build_partition((int32_t)n, leaf, rank, &pi, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr));
+  const StaticLayout lay(pi.K, rank);
+  if (lay.end > (int64_t)kScratchBytes)
+    return set_error(HP_E_SHAPE, "hp_apply_static: workspace of %lld bytes exceeds the static %zu",
+                     (long long)lay.end, kScratchBytes);
+  const uintptr_t r0 = (uintptr_t)d_r, y0 = (uintptr_t)d_y, len = (uintptr_t)(4 * n * (int64_t)ncols);
+  if (r0 < y0 + len && y0 < r0 + len) return set_error(HP_E_INVALID, "hp_apply_static: r and y must not overlap");
+  char* ws = nullptr;
+  HP_TRY(scratch_address(&ws));
+
+  FrameDesc F{};
+  F.n = (int)n;
+  F.K = pi.K;
+  F.MH = pi.MH;
+  F.J = pi.J;
+  F.nz = nz;
+  F.nx = nx;
+  F.ny = ny;
+  morton_masks(nx, ny, nz, &F.xm, &F.ym, &F.zm);
+  F.nb = (int)((n + NODE_BLOCK - 1) / NODE_BLOCK);
+  LaunchGeom g{};
+  g.fr = (const FrameDesc*)ws;
+  g.blk2f = nullptr;  // the apply kernels index leaves and tiles only
+  g.leaf2f = (const int*)(ws + lay.leaf2f);
+  g.cblk = (const int2*)(ws + lay.cblk);
+  g.nframes = 1;
+  g.nblk = F.nb;
+  g.ncblk = std::max(pi.MH, 1);
+  g.ktot = pi.K;
+  g.ntot = n;
+  g.kmax = pi.K;
+  g.stream = (hipStream_t)hip_stream;
+  hipLaunchKernelGGL(k_single_frame_tables, dim3((pi.K + 255) / 256), dim3(256), 0, g.stream, F, (FrameDesc*)ws,
+                     (int*)(ws + lay.leaf2f), (int2*)(ws + lay.cblk));
+  HP_HIP(hipGetLastError());
+  int64_t offs[5], tot;
+  factor_offsets_n(pi.K, pi.MH, n, leaf, rank, fdtype, offs, &tot);
+  float* uh = (float*)(ws + lay.uh);
+  float* vh = (float*)(ws + lay.vh);
+  float* tr = (float*)(ws + lay.tr);
+  float* tc = (float*)(ws + lay.tc);
+  for (int32_t c = 0; c < ncols; ++c)
+    HP_TRY(launch_apply(g, leaf, rank, fdtype, d_sys, d_factors, offs, d_r + c * n, d_y + c * n, uh, vh, tr, tc));
+  return HP_OK;
+}
+
+namespace hp {
 
 
 

@@ -74,6 +74,8 @@ EXPORTS = {
     "hp_assemble": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
     "hp_spmv": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
     "hp_apply": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32], C.c_int32),
+    "hp_apply_static": ([C.c_int32] * 5 + [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                            C.c_void_p], C.c_int32),
     "hp_pcg_solve": ([C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p,
                       C.POINTER(SolveResult)], C.c_int32),
     "hp_weight_count": ([C.POINTER(ModelConfigC), C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int32),
@@ -178,6 +180,18 @@ def pack_weights(cfg, weights: Dict[str, np.ndarray]) -> np.ndarray:
 
 
 # ------------------------------------------------------------------ batches (GPU)
+
+def apply_static(dims, leaf: int, rank: int, sys, fac, dtype: int, r, y, ncols: int = 1, stream=None):
+    """y = M r for one frame with the library's fixed workspace (no batch, no
+    allocation); r, y hold ncols columns of N values each."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    nx, ny, nz = (int(v) for v in dims)
+    _check(lib().hp_apply_static(nx, ny, nz, int(leaf), int(rank), _ptr(sys), _ptr(fac), int(dtype), _ptr(r),
+                                 _ptr(y), int(ncols), C.c_void_p(stream.cuda_stream)))
+
+
 
 def _ptr(t) -> Optional[int]:
     return None if t is None else t.data_ptr()
