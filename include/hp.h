@@ -114,8 +114,11 @@ typedef struct {
 
 /* Create a batch of nframes frames with dims[3f..3f+2] = (nx, ny, nz) (host).
  * All frames share cfg (one leaf size L and rank L_s).  hip_stream is the
- * caller's hipStream_t (borrowed; NULL = default stream).  Allocates every
- * workspace the batch's calls need; later calls allocate nothing. */
+ * caller's hipStream_t (borrowed; NULL = default stream).  Allocates the
+ * workspaces of the solver calls (assembly, SpMV, apply, PCG; about 130 bytes
+ * per node).  The network's workspace (about 12 KB per node) is allocated by
+ * the first hp_infer_factors, hp_train_grad or hp_adamw_step call on the batch
+ * and kept; later calls allocate nothing. */
 hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes, const int32_t* dims,
                           void* hip_stream, hp_batch* out);
 hp_status hp_batch_destroy(hp_batch b);
@@ -230,6 +233,17 @@ typedef struct {
 hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_factors,
                        const hp_solve_opts* opts, const float* d_b, double* d_x,
                        hp_solve_result* res);
+
+/* Per-frame latency of the last hp_pcg_solve from device-clock stamps: the
+ * lead thread of each frame stamps the clock when the frame stops (its last
+ * stop, fallback included), and the library stamps the start of every
+ * hp_infer_factors and hp_pcg_solve call.  h_stop_ms [nframes] (host)
+ * receives each frame's stop time in ms after the last inference's start
+ * when that inference began before the solve (a step of inference plus
+ * solve), else after the solve's start; h_solve_start_ms (host, optional)
+ * the solve's start on the same scale.  Synchronises the batch stream.
+ * HP_E_STATE if no solve has run on the batch. */
+hp_status hp_frame_times(hp_batch b, double* h_stop_ms, double* h_solve_start_ms);
 
 /* ------------------------------------------------------------------ network */
 

@@ -91,6 +91,7 @@ extern "C" hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes
   if (!cfg || !dims || !out || nframes <= 0) return set_error(HP_E_INVALID, "hp_batch_create: bad arguments");
   std::string why;
   if (!supported_cfg(*cfg, &why)) return set_error(HP_E_SHAPE, "hp_batch_create: %s", why.c_str());
+  HP_TRY(network_supported(*cfg));
   auto* b = new hp_batch_s();
   b->cfg = *cfg;
   b->nframes = nframes;
@@ -176,6 +177,7 @@ extern "C" hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes
   A((void**)&b->part_rr, np);
   A((void**)&b->part_rz, np);
   A((void**)&b->n_active, sizeof(int));
+  A((void**)&b->d_ticks, sizeof(int64_t) * (nframes + 2));
   A((void**)&b->st, sizeof(FrameState) * 2 * nframes);
   A((void**)&b->prm, sizeof(SolveParams));
   if (s != HP_OK) {
@@ -194,7 +196,8 @@ extern "C" hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes
   cp(b->d_blk2f, blk2f.data(), sizeof(int) * nb0);
   cp(b->d_leaf2f, leaf2f.data(), sizeof(int) * k0);
   cp(b->d_cblk, cblk.data(), sizeof(int2) * cblk.size());
-  if (s == HP_OK) s = network_alloc(*b);
+  if (s == HP_OK && hipMemset(b->d_ticks, 0, sizeof(int64_t) * (nframes + 2)) != hipSuccess)
+    s = set_error(HP_E_HIP, "hp_batch_create: memset failed");
   if (s != HP_OK) {
     delete b;
     return s;
@@ -452,6 +455,8 @@ extern "C" hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_
   B.n_active = b->n_active;
   B.st = b->st;
   B.prm = b->prm;
+  B.ticks = b->d_ticks;
+  HP_TRY(launch_tick(b->d_ticks + 1, b->stream));
   std::vector<FrameState> init(b->nframes);
   for (auto& s : init) {
     memset(&s, 0, sizeof s);
@@ -506,6 +511,25 @@ extern "C" hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_
       if (res[f].flags & HP_NOT_SPD) return set_error(HP_E_NOT_SPD, "hp_pcg_solve: frame %d lost positivity", f);
     return set_error(HP_E_NOCONV, "hp_pcg_solve: tolerance not reached");
   }
+  return HP_OK;
+}
+
+extern "C" hp_status hp_frame_times(hp_batch b, double* h_stop_ms, double* h_solve_start_ms) {
+  if (!b || !h_stop_ms) return set_error(HP_E_INVALID, "hp_frame_times: NULL argument");
+  std::vector<int64_t> t(b->nframes + 2);
+  HP_HIP(hipMemcpyAsync(t.data(), b->d_ticks, sizeof(int64_t) * t.size(), hipMemcpyDeviceToHost, b->stream));
+  HP_HIP(hipStreamSynchronize(b->stream));
+  if (t[1] == 0) return set_error(HP_E_STATE, "hp_frame_times: no solve has run on this batch");
+  int dev = 0, khz = 0;
+  HP_HIP(hipGetDevice(&dev));
+  HP_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (khz <= 0) return set_error(HP_E_HIP, "hp_frame_times: device clock rate unknown");
+  // the reference is the last inference's start if it began before the last
+  // solve (an inference-plus-solve step), else the solve's start
+  const int64_t ref = (t[0] != 0 && t[0] <= t[1]) ? t[0] : t[1];
+  const double ms_per_tick = 1.0 / (double)khz;
+  for (int f = 0; f < b->nframes; ++f) h_stop_ms[f] = (double)(t[2 + f] - ref) * ms_per_tick;
+  if (h_solve_start_ms) *h_solve_start_ms = (double)(t[1] - ref) * ms_per_tick;
   return HP_OK;
 }
 

@@ -36,6 +36,7 @@ struct PcgBufs {
   int* n_active;
   FrameState* st;
   const SolveParams* prm;
+  int64_t* ticks;    // device clock: [0] inference start, [1] solve start, [2 + f] frame f's stop
 };
 
 // Live kernel timing: every launch of one kernel family is bracketed by HIP
@@ -106,6 +107,7 @@ struct Batch {
   float *uh = nullptr, *vh = nullptr, *Tr = nullptr, *Tc = nullptr;
   double *part_pq = nullptr, *part_rr = nullptr, *part_rz = nullptr;
   int* n_active = nullptr;
+  int64_t* d_ticks = nullptr;  // [nframes + 2] device clock stamps (PcgBufs::ticks)
   // pinned host staging: [0] active count read back, [1] active count upload,
   // then SolveParams, then nframes FrameState
   char* h_pin = nullptr;
@@ -155,8 +157,12 @@ hp_status pcg_init_states(FrameState* st, int nframes, int* n_active, SolveParam
                           hipStream_t s);
 hp_status pcg_iterations(const PcgLaunch& P, int count);
 hp_status pcg_finalize(const PcgLaunch& P, bool stopped_only = false);
+// One device-clock stamp (wall_clock64) into *p, on stream s.
+hp_status launch_tick(int64_t* p, hipStream_t s);
 
 // network.hip
+hp_status network_supported(const hp_model_config& c);
+// The network workspace, allocated on the first call that needs it (no-op after).
 hp_status network_alloc(Batch& b);
 
 // train.hip

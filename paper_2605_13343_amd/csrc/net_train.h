@@ -37,6 +37,7 @@ hp_status network_train_alloc(Batch& b) {
   const hp_model_config& c = b.cfg;
   if (c.edge_hidden > 32 || c.heads > 8)
     return set_error(HP_E_SHAPE, "training: supported edge_hidden <= 32 and heads <= 8");
+  HP_TRY(network_alloc(b));
   HP_TRY(train_ws_alloc(b));
   auto* T = new NetTrainBufs();
   b.net_train = T;

@@ -2016,15 +2016,36 @@ struct NetBufs {
 
 static NetBufs* nb_of(Batch& b) { return reinterpret_cast<NetBufs*>(b.net.ws); }
 
-hp_status network_alloc(Batch& b) {
-  auto* N = new NetBufs();
-  b.net.ws = N;
-  b.net_free = [](void* p) { delete reinterpret_cast<NetBufs*>(p); };
-  const hp_model_config& c = b.cfg;
+hp_status network_supported(const hp_model_config& c) {
   if (c.d != 128 || c.edge_hidden > 64 || c.heads * 32 != c.d || c.node_feats + c.glob_feats > 32 ||
       c.gcn > 4 || c.layers > 16)
     return set_error(HP_E_SHAPE, "network: supported d = 128, heads = 4 (head dim 32), edge_hidden <= 64, "
                                  "gcn <= 4, layers <= 16, node_feats + glob_feats <= 32");
+  return HP_OK;
+}
+
+static hp_status network_alloc_impl(Batch& b);
+
+// The network workspace (about 12 KB per node) is allocated by the first
+// call that runs the network, so a batch used only for solves and applies
+// holds the solver's workspace alone.  A failed allocation leaves no
+// half-built workspace behind (its buffers are released with the batch).
+hp_status network_alloc(Batch& b) {
+  if (b.net.ws) return HP_OK;
+  HP_TRY(network_supported(b.cfg));
+  const hp_status s = network_alloc_impl(b);
+  if (s != HP_OK && b.net.ws) {
+    b.net_free(b.net.ws);
+    b.net.ws = nullptr;
+  }
+  return s;
+}
+
+static hp_status network_alloc_impl(Batch& b) {
+  auto* N = new NetBufs();
+  b.net.ws = N;
+  b.net_free = [](void* p) { delete reinterpret_cast<NetBufs*>(p); };
+  const hp_model_config& c = b.cfg;
   N->plan = make_plan(c);
   const int64_t Nd = b.ntot, No = std::max<int64_t>(b.mtot, 1) * c.rank, d = c.d;
   N->Nd = Nd;
@@ -2928,6 +2949,7 @@ static hp_status forward(Batch& b, const float* W, const float* rho, const float
     NetBufs& N;
     ~PreReset() { N.pre = N.pre_side = N.par = 0; }
   } pre_reset{*nb_of(b)};
+  HP_TRY(launch_tick(b.d_ticks, b.stream));  // start of the step, for per-frame latencies
   HP_TRY(tables_ahead<AT>(b, W, sys));
   HP_TRY(fwd_prologue<AT>(b, W, rho, sys, nullptr));
   NetBufs& N = *nb_of(b);
@@ -3010,6 +3032,7 @@ extern "C" hp_status hp_infer_factors(hp_batch b, const float* d_weights, const 
   if (compute != HP_BF16 && compute != HP_F32)
     return set_error(HP_E_INVALID, "hp_infer_factors: compute must be HP_F32 or HP_BF16");
   Batch& B = *b;
+  HP_TRY(network_alloc(B));
   auto run = [&]() -> hp_status {
     if (compute == HP_BF16) return forward<uint16_t, uint16_t>(B, d_weights, d_rho, d_sys, d_factors);
     return forward<float, float>(B, d_weights, d_rho, d_sys, d_factors);
@@ -3056,6 +3079,7 @@ extern "C" hp_status hp_infer_factors(hp_batch b, const float* d_weights, const 
 
 extern "C" hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, int64_t bytes) {
   if (!b || !name || !d_dst || bytes < 0) return set_error(HP_E_INVALID, "hp_debug_copy: bad arguments");
+  if (!b->net.ws) return set_error(HP_E_STATE, "hp_debug_copy: no inference has run on this batch");
   NetBufs& N = *nb_of(*b);
   const void* src = nullptr;
   int64_t cap = 0;

@@ -33,6 +33,21 @@ namespace hp {
 
 __device__ inline double warp_sum(double v) { return wave_total_d(v); }
 
+// A frame stops (run by its lead thread once): one fewer active frame, and
+// the device clock at the stop for per-frame latencies.
+__device__ inline void frame_stopped(const PcgBufs& B_, int f) {
+  atomicSub(B_.n_active, 1);
+  B_.ticks[2 + f] = (int64_t)wall_clock64();
+}
+
+__global__ void k_tick(int64_t* p) { *p = (int64_t)wall_clock64(); }
+
+hp_status launch_tick(int64_t* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, s, p);
+  HP_HIP(hipGetLastError());
+  return HP_OK;
+}
+
 // Fixed-order block sum of one double per thread (blockDim multiple of 64).
 __device__ inline double block_sum(double v, double* red) {
   v = warp_sum(v);
@@ -131,10 +146,11 @@ __global__ void k_assemble(const FrameDesc* fr, const int* blk2f, const float* r
   s8[3 * ntot + i] = wpz;
 }
 
-__global__ void k_spmv(const FrameDesc* fr, const int* blk2f, const float* sys, int64_t ntot,
-                       const float* p, float* q) {
-  const FrameDesc F = fr[blk2f[blockIdx.x]];
-  int c = (blockIdx.x - F.b0) * NODE_BLOCK + threadIdx.x;
+__global__ __launch_bounds__(NODE_BLOCK) void k_spmv(const FrameDesc* fr, const int* blk2f, const float* sys,
+                                                      int64_t ntot, const float* p, float* q) {
+  const int bid = xcd_block(blockIdx.x, gridDim.x);  // stencil neighbours in one L2
+  const FrameDesc F = fr[blk2f[bid]];
+  int c = (bid - F.b0) * NODE_BLOCK + threadIdx.x;
   if (c >= F.n) return;
   SysPtr s(sys, ntot);
   q[F.n0 + c] = stencil_f32(s, F, c, [&](int64_t j) { return p[j]; });
@@ -561,7 +577,7 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_spmv_p(const FrameDesc* fr, cons
       if (lead) {
         S.done = 1;
         store_state(out, S);
-        atomicSub(B_.n_active, 1);
+        frame_stopped(B_, f);
       }
       return;
     }
@@ -573,7 +589,7 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_spmv_p(const FrameDesc* fr, cons
       S.flags |= HP_NOT_SPD;
       S.done = 1;
       store_state(out, S);
-      atomicSub(B_.n_active, 1);
+      frame_stopped(B_, f);
     }
     return;
   }
@@ -697,7 +713,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_frame_setup(const FrameDesc* f
   if (threadIdx.x == 0) {
     if (stop) {
       S.done = 1;
-      atomicSub(B_.n_active, 1);
+      frame_stopped(B_, f);
     }
     store_state(sp, S);
   }
@@ -746,7 +762,7 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_coarse_check(const FrameDesc* 
   if (stop) S.done = 1;
   if (lead) {
     store_state(B_.st + 2 * f, S);
-    if (stop) atomicSub(B_.n_active, 1);
+    if (stop) frame_stopped(B_, f);
   }
   if (stop || cb.y < 0) return;
   pre.finish(B_.Tr, B_.Tc);

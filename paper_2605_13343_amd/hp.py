@@ -76,6 +76,7 @@ EXPORTS = {
     "hp_apply": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32], C.c_int32),
     "hp_apply_static": ([C.c_int32] * 5 + [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                             C.c_void_p], C.c_int32),
+    "hp_frame_times": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_double)], C.c_int32),
     "hp_pcg_solve": ([C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p,
                       C.POINTER(SolveResult)], C.c_int32),
     "hp_weight_count": ([C.POINTER(ModelConfigC), C.POINTER(C.c_int32), C.POINTER(C.c_int64)], C.c_int32),
@@ -192,7 +193,6 @@ def apply_static(dims, leaf: int, rank: int, sys, fac, dtype: int, r, y, ncols: 
                                  _ptr(y), int(ncols), C.c_void_p(stream.cuda_stream)))
 
 
-
 def _ptr(t) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
@@ -282,6 +282,14 @@ class Batch:
         if not (st in (5, 6) and not raise_on_fail):
             _check(st)
         return [(r.iters, r.flags, r.relres) for r in res]
+
+    def frame_times(self):
+        """(per-frame stop times in ms after the step's start, solve start in ms)
+        of the last solve, from device-clock stamps."""
+        out = np.zeros(len(self.dims), dtype=np.float64)
+        t0 = C.c_double()
+        _check(lib().hp_frame_times(self.h, out.ctypes.data, C.byref(t0)))
+        return out, t0.value
 
     def debug_set(self, name: str, value: int):
         _check(lib().hp_debug_set(self.h, name.encode(), int(value)))

@@ -113,6 +113,75 @@ def test_forward_bf16_close_to_oracle(cfg, recipe, seed):
         assert v <= BF16_BOUND[k], (k, v)
 
 
+def _levels(K):
+    """Tile ranges of each partition level (finest first): level j holds
+    K / 2^(j+1) tiles."""
+    out, m = [], 0
+    j = 0
+    while (K >> (j + 1)) > 0:
+        n = K >> (j + 1)
+        out.append((j, m, m + n))
+        m += n
+        j += 1
+    return out
+
+
+# Bounds for the benchmarked configuration (trained weights, BF16, N = 8,192).
+# Each GEMM rounds its inputs to BF16 (relative 2^-9 ~ 2e-3); the residual
+# streams stay FP32, so rounding errors add up over the 2 + 2 x 4 sublayers of
+# the diagonal stack rather than compound: ~10 roundings of ~2e-3 with random
+# signs give ~1e-2 on the streams, and the heads' outputs inherit it
+# (measured 2e-3 to 4.4e-3).  B_m = U_m V_m^T sums L_s products whose terms
+# partly cancel, so its error is measured, per partition level (a defect on
+# one level cannot hide behind another level's larger values), against the
+# magnitude of what it sums, max (|U_m| |V_m|^T), the scale of a rounded dot
+# product's error.  Measured per level, finest first: 5.3e-3, 4.7e-3, 5.0e-3,
+# 9.9e-3, 1.8e-2, 1.2e-2, 3.3e-2.  The error grows with the level because a
+# level-j token pools means over 4 * 2^j rows: the mean is much smaller than
+# its terms, whose BF16-rounded parts do not average out.  A level built from
+# the wrong strips or a transposed coupling would read O(1).
+TRAINED_BF16_BOUND = {"xd": 1.5e-2, "G": 1.5e-2, "B": 5e-2, "Ut": 1.5e-2, "Vt": 1.5e-2, "lam": 1e-2,
+                      "Mr": 1e-2}
+
+
+def test_trained_bf16_inference_matches_oracle_at_benchmark_frame():
+    """The benchmarked configuration tensor by tensor: trained weights, BF16
+    inference on the first frame of the precision workload, every factor of M
+    against the float64 oracle forward with the same weights, and the action
+    M r of the two factor sets on a random vector."""
+    import os
+    import torch
+    cfg = DEF
+    path = os.path.join(os.path.dirname(hp.__file__), "weights", "trained_L64.npz")
+    z = np.load(path, allow_pickle=False)
+    w = {k: z[k] for k in z.files}
+    fr = inputs.make_frame("precision8192", 2000)
+    s, fac = _run(cfg, [fr], hp.HP_BF16, w)
+    tr = {}
+    o = _oracle(cfg, s, 0, w, trace=tr)
+    n, d = fr.n, cfg.d
+    G, B, Ut, Vt, lam = s.download_factors(fac, hp.HP_BF16)[0]
+    Go, Bo = hmatrix.gram(o["F"]), hmatrix.coupling(o["U"], o["V"])
+    errs = {"xd": relerr(_dbg(s, "xd", (n, d)), tr[f"ffn{cfg.layers - 1}"][0].detach().numpy()),
+            "G": relerr(G, Go), "Ut": relerr(Ut, o["Ut"]), "Vt": relerr(Vt, o["Vt"]), "lam": relerr(lam, o["lam"])}
+    K = n // cfg.leaf
+    absprod = np.abs(o["U"]) @ np.abs(o["V"]).transpose(0, 2, 1)
+    lev = {j: float(np.abs(B[a:b] - Bo[a:b]).max() / absprod[a:b].max()) for j, a, b in _levels(K)}
+    errs["B"] = max(lev.values())
+    errs_rel = {j: relerr(B[a:b], Bo[a:b]) for j, a, b in _levels(K)}
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(n)
+    dA = s.A[0].diagonal()
+    Mr = hmatrix.apply(s.parts[0], G, B, Ut, Vt, lam, dA, r)
+    Mro = hmatrix.apply(s.parts[0], Go, Bo, o["Ut"], o["Vt"], o["lam"], dA, r)
+    errs["Mr"] = float(np.linalg.norm(Mr - Mro) / np.linalg.norm(Mro))
+    print("trained bf16 vs fp64 oracle", {k: f"{v:.2e}" for k, v in errs.items()},
+          "B per level (vs max |U||V|^T)", {j: f"{v:.1e}" for j, v in lev.items()},
+          "(vs max |B|)", {j: f"{v:.1e}" for j, v in errs_rel.items()})
+    for k, v in errs.items():
+        assert v <= TRAINED_BF16_BOUND[k], (k, v)
+
+
 def test_bf16_factors_precondition_like_fp32():
     """What the BF16 path must preserve is the preconditioner: PCG with BF16
     factors takes (almost) the iterations of PCG with FP32 factors."""

@@ -157,6 +157,11 @@ def test_pcg_hmat_matches_oracle(torch_cuda, dtype):
         print(f"hmat dtype {dtype} frame {f} N={s.frames[f].n} gpu {it} oracle {ko} true {true:.3e}")
         assert iters_close(it, ko), (f, it, ko)
         assert true <= 1e-6, (f, true)
+        # the solution itself against the oracle's float64 PCG with the same
+        # held factors: both follow the same Krylov path to the same stop
+        xe = np.linalg.norm(xf - xo) / np.linalg.norm(xo)
+        print(f"    x vs oracle PCG {xe:.2e}")
+        assert xe <= 1e-5, (f, xe)
 
 
 def test_batched_equals_single_and_deterministic(torch_cuda):
@@ -201,3 +206,103 @@ def test_fallback_on_indefinite_preconditioner(torch_cuda):
     with pytest.raises(hp.HPError) as e:
         _solve(s, hp.PRECOND_HMAT, fac, hp.HP_F32, fallback=False)
     assert e.value.status == 5
+
+
+def _weak_factors(part, seed):
+    """An SPD preconditioner too weak to cut iterations: M = diag(lam / A_ii)
+    with lam spread log-uniformly over 8 decades (G, B, Ut, Vt zero), so
+    cond(M A) is ~1e8 times cond(D^-1 A).  On these frames the oracle's
+    ||r_100|| / ||r_0|| is ~0.73, far from the 0.5 stagnation threshold."""
+    rng = np.random.default_rng(seed)
+    K, L, Ls, n, MH = part["K"], part["L"], part["Ls"], part["n"], part["MH"]
+    lam = 10.0 ** (-8.0 * rng.random(n))
+    return (np.zeros((K, L, L)), np.zeros((MH, Ls, Ls)), np.zeros((n, Ls)), np.zeros((n, Ls)), lam)
+
+
+@pytest.mark.parametrize("case", ["stagnated", "maxiter"])
+def test_fallback_when_m_fails_to_cut_iterations(torch_cuda, case):
+    """A positive definite M that does not cut iterations: PCG stops on the
+    stagnation window (less than a 2x drop of ||r|| over 100 iterations) or,
+    with that check off, on the iteration cap (200: the Jacobi restarts need
+    70 and 141 more); the frame restarts as Jacobi-PCG from its current x and
+    reaches the tolerance.  Flags and iteration counts
+    follow the oracle's solve_with_fallback; a frame with a good M in the same
+    batch is untouched."""
+    frames = [inputs.make_frame("plain1024", 1000), inputs.make_frame("plain1024", 1001),
+              inputs.make_frame("precision8192", 2000)]
+    s = Side(DEF, frames)
+    facs = [_weak_factors(s.parts[0], 1000), rand_factors(s.parts[1], 51, b_scale=2e-4, shift=1.0),
+            _weak_factors(s.parts[2], 2000)]
+    fac, held = s.upload_factors(facs, hp.HP_F32)
+    kw = dict(tol=1e-6, stagnation=True, max_iter=10000) if case == "stagnated" else \
+        dict(tol=1e-6, stagnation=False, max_iter=200)
+    x, res = _solve(s, hp.PRECOND_HMAT, fac, hp.HP_F32, **kw)
+    for f, xf in enumerate(s.split(x)):
+        A, b = s.A[f], s.bo[f]
+        G, Bm, Ut, Vt, lam = held[f]
+        Mf = lambda v: hmatrix.apply(s.parts[f], G, Bm, Ut, Vt, lam, A.diagonal(), v)
+        xo, ko, flo, _ = opcg.solve_with_fallback(A, b, Mf, tol=1e-6, max_iter=kw["max_iter"],
+                                                  stagnation=kw["stagnation"])
+        it, fl, _ = res[f]
+        true = np.linalg.norm(b - A @ xf) / np.linalg.norm(b)
+        print(f"{case} frame {f} N={s.frames[f].n}: gpu {it} flags {fl}, oracle {ko} flags {flo}, "
+              f"true relres {true:.2e}")
+        assert fl == flo, (f, fl, flo)
+        assert true <= 1e-6, (f, true)
+        if f == 1:
+            # a usable M converges (~180 iterations, below the 200 cap)
+            assert fl == hp.CONVERGED
+            assert iters_close(it, ko), (f, it, ko)
+        else:
+            stop = hp.STAGNATED if case == "stagnated" else hp.MAXITER
+            assert fl == hp.CONVERGED | stop | hp.FELL_BACK
+            # the first pass stops at the same window or cap on both sides
+            first = 100 if case == "stagnated" else kw["max_iter"]
+            assert iters_close(it - first, ko - first), (f, it, ko)
+
+
+def test_warm_first_chunk_that_stops_some_frames(torch_cuda):
+    """A solve whose first chunk (sized from the batch's previous solve)
+    stops some frames but not others: the stopped frames' x is copied out
+    mid-solve and later chunks carry on with the rest.  Results equal a cold
+    solve on a fresh batch bit for bit, with and without graphs."""
+    frames = [inputs.make_frame("plain1024", 1000), inputs.make_frame("precision8192", 2003),
+              inputs.make_frame("batch_mixed", 4007)]
+    facs = None
+    outs = {}
+    for use_graph in (True, False):
+        cold = Side(DEF, frames)
+        if facs is None:
+            facs = [rand_factors(p, 60 + i, b_scale=2e-4, shift=1.0) for i, p in enumerate(cold.parts)]
+        fac_c, _ = cold.upload_factors(facs, hp.HP_BF16)
+        xc, rc = _solve(cold, hp.PRECOND_HMAT, fac_c, hp.HP_BF16, tol=1e-9, use_graph=use_graph)
+        warm = Side(DEF, frames)
+        fac_w, _ = warm.upload_factors(facs, hp.HP_BF16)
+        _, r7 = _solve(warm, hp.PRECOND_HMAT, fac_w, hp.HP_BF16, tol=1e-7, use_graph=use_graph)
+        xw, rw = _solve(warm, hp.PRECOND_HMAT, fac_w, hp.HP_BF16, tol=1e-9, use_graph=use_graph)
+        first = min((max(r[0] for r in r7) + 3) // 4 * 4, 256)  # the library's first-chunk rule
+        its = [r[0] for r in rc]
+        print(f"graph {use_graph}: first chunk {first}, cold 1e-9 iterations {its}")
+        # the case this test is for: the first chunk stops some frames, not all
+        assert min(its) <= first < max(its), (first, its)
+        assert rw == rc
+        assert bool((xw == xc).all())
+        outs[use_graph] = (rc, xc.cpu())
+    assert outs[True][0] == outs[False][0] and bool((outs[True][1] == outs[False][1]).all())
+
+
+def test_frame_stop_times_follow_iterations(torch_cuda):
+    """Device-clock stop stamps: in a batched solve every frame advances one
+    iteration per kernel sequence, so a frame that needs more iterations stops
+    later; all stops come after the solve's start."""
+    s = Side(DEF, _mixed_frames(8))
+    _, res = _solve(s, hp.PRECOND_JACOBI, tol=1e-6)
+    stop, t0 = s.B.frame_times()
+    its = [r[0] for r in res]
+    print("iterations", its, "stop ms", np.round(stop, 3).tolist(), "solve start", t0)
+    assert t0 == 0.0  # no inference ran before this solve: the solve's start is the reference
+    assert (stop > 0).all()
+    for f in range(len(its)):
+        for g in range(len(its)):
+            if its[f] < its[g]:
+                assert stop[f] <= stop[g], (f, g, its[f], its[g], stop[f], stop[g])
