@@ -380,9 +380,10 @@ hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, int64_t bytes
  * dl256x128x32s3, 13: dl128x256x32s3;
  * other GEMMs on variant 0), -1 lets the autotuner choose (the tests
  * compare the variants); "gemm_small_tiles" (0/1): the same as gemm_variant
- * 0 / -1; "ffn_fused" (0/1, default 0): with BF16 compute outside training,
- * run each FFN as one fused kernel (hidden activations kept on chip) instead
- * of two GEMMs (slower at present: one wave per SIMD); "gemm_autotune" (0/1, default 1): time every variant on the first
+ * 0 / -1; "ffn_fused" (0/1, default 1): with BF16 compute outside training,
+ * run each FFN as one fused kernel (hidden activations kept on chip; the
+ * same MFMA sequence, GELU and rounding per element, so the results equal
+ * the two-GEMM FFN bit for bit) instead of two GEMMs; "gemm_autotune" (0/1, default 1): time every variant on the first
  * call of each BF16 GEMM shape, writing to a scratch buffer, and keep the
  * fastest (off: the 128 x 128 x 32 kernel).  HP_E_INVALID on an unknown name
  * or a variant out of range. */

@@ -393,135 +393,184 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void k_gemm_bt(GemmArgs
 // ------------------------------------------------------------------ fused FFN
 // X += GELU(U W1 + b1) W2 + b2 for d = 128, hidden 4d = 512, BF16 operands and
 // FP32 accumulation, without the hidden activations leaving the chip (the
-// inference path).  Block: 4 waves of 32 rows.  A wave keeps its rows of U as
-// MFMA operands in registers (32 steps of 16 along K = 512); W1 and W2 pass
-// through LDS in chunks of FC = 32 hidden units (double-buffered, the next
-// chunk's global loads issued before the current chunk's MFMAs).  Per chunk:
-// H^T = W1c U^T (lane: one row, hidden 8 i + 4 (lane / 32) + j), then the
-// bias and GELU, rounded to BF16 as the two-GEMM path rounds its hidden
-// output; those values are the B operand of Y^T += W2c H^T as they stand when
-// the 16 hidden units of a step are taken in the order [0-3, 8-11, 4-7,
-// 12-15], so W2's columns are staged in LDS in that order.  The hidden
-// pre-activations are summed along K in four interleaved chains (steps s mod
-// 4, added pairwise at the end) and the second product takes the hidden
-// units of each MFMA step in the permuted order: both differ from the
-// two-GEMM path only in summation order.  Needs M rows of U, X with leading
-// dimensions 512 and 128.
-constexpr int FFN_FC = 32;
+// inference path).  Block: 128 rows, 4 waves; a wave owns 32 rows and all
+// 128 outputs of them.  The hidden units run in 4 chunks of 128:
+//   1. H^T chunk (128 hidden x the wave's 32 rows: four 32 x 32 fragments) =
+//      W1c U^T along K = 512 in steps of 32; the block's U rows and W1c rows
+//      pass through a 3-stage LDS ring filled straight from global memory,
+//      which runs on across chunks (the next chunk's first steps load while
+//      a chunk ends);
+//   2. bias, GELU and BF16 rounding in registers;
+//   3. Y^T += W2c H^T, with W2c (128 outputs x 128 hidden) staged in LDS
+//      while step 1 runs.
+// Every output element sees the MFMA sequence of the two-GEMM path (k steps
+// of 16 in increasing order, one accumulator chain, W as the first operand),
+// the same bias, GELU and rounding, and the same epilogue ((acc + b2) + X),
+// so the results equal it bit for bit.  After step 1 a lane holds hidden
+// units 8 q + 4 (lane / 32) + 0..3 (q = 0..3) of each fragment for its row;
+// step 3 takes units 8 (lane / 32) + 0..7 of each 16-unit k step, so each
+// lane swaps two of its four groups with the lane 32 away.
+// The biases are read with wave-uniform (scalar) loads, so reading them
+// never waits for the ring's vector loads in flight.  LDS: 80 KB (two blocks
+// per CU); at most 256 registers per lane (two waves per SIMD).  Rows past M
+// load row M - 1 and are not stored.
+constexpr int FFN_BM = 128, FFN_HC = 128, FFN_ST = 3;
+constexpr int FFN_RING = FFN_ST * 256 * 32;  // BF16 elements: per stage 128 U rows + 128 W1 rows, 32 k each
+constexpr int FFN_W2 = 128 * 128;            // BF16 elements: 128 outputs x 128 hidden of one chunk
 
-__global__ __launch_bounds__(256) void k_ffn_fused(const uint16_t* U, const uint16_t* W1t, const float* b1,
-                                                   const uint16_t* W2t, const float* b2, float* X, int M) {
-  constexpr int K = 512, NH = 512, NO = 128, FC = FFN_FC, NCH = NH / FC, LD1 = K + 8, LD2 = FC + 8;
-  __shared__ __attribute__((aligned(16))) uint16_t sW1[2][FC][LD1];
-  __shared__ __attribute__((aligned(16))) uint16_t sW2[2][NO][LD2];
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void k_ffn_fused(const uint16_t* __restrict__ U, const uint16_t* __restrict__ W1t, const float* __restrict__ b1,
+                 const uint16_t* __restrict__ W2t, const float* __restrict__ b2, float* X, int M) {
+  constexpr int K = 512, NO = 128, BK = 32, NCH = 512 / FFN_HC, KT = K / BK, NT = NCH * KT, LPW = 4;
+  __shared__ __attribute__((aligned(1024))) uint16_t lds[FFN_RING + FFN_W2];
+  uint16_t* const ring = lds;            // [stage][256 rows][32 k], 16-byte chunk c of row r at c ^ ((r / 4) % 4)
+  uint16_t* const w2s = lds + FFN_RING;  // [128 outputs][128 hidden], 16-byte chunk c of row r at c ^ (r % 16)
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, hh = lane >> 5, r32 = lane & 31;
-  const int row = blockIdx.x * 128 + wave * 32 + r32;
-  // this lane's row of U: step s holds columns 16 s + 8 hh .. + 7
-  uint4 ua[K / 16];
+  const int m0 = blockIdx.x * FFN_BM;
+  // ring sources: stage rows 0..127 are U rows m0.., rows 128..255 the chunk's
+  // W1 rows; one wave instruction fills one 1 KB block (16 rows of 64 bytes,
+  // lane i -> row i / 4, position i % 4); waves 0-1 fill the U part, 2-3 the W1 part
+  const uint16_t* src[LPW];
+  bool w1part[LPW];
 #pragma unroll
-  for (int s2 = 0; s2 < K / 16; ++s2)
-    ua[s2] = row < M ? *(const uint4*)(U + (int64_t)row * K + 16 * s2 + 8 * hh) : make_uint4(0, 0, 0, 0);
-  // weight chunk staging: W1c rows go from global memory straight to LDS (one
-  // 1 KB row per wave instruction, lane i -> columns 8 i .. 8 i + 7); W2c
-  // passes through 2 16-byte registers per thread for its column order
-  uint4 p2[2];
-  auto gload = [&](int c, int buf) {
-    const int h0 = c * FC;
-#pragma unroll
-    for (int q = 0; q < FC / 4; ++q) {
-      const int r = wave * (FC / 4) + q;
-      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(W1t + (int64_t)(h0 + r) * K + 8 * lane),
-                                       (__attribute__((address_space(3))) void*)&sW1[buf][r][0], 16, 0, 0);
-    }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int idx = tid + 256 * q, n = idx >> 2, g = idx & 3;
-      p2[q] = *(const uint4*)(W2t + (int64_t)n * NH + h0 + 8 * g);
-    }
-  };
-  auto sstore = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int idx = tid + 256 * q, n = idx >> 2, g = idx & 3;
-      // hidden units 8g .. 8g+7 of the chunk: within its 16-block, units 0-3
-      // go to positions 0-3, 4-7 to 8-11, 8-11 to 4-7, 12-15 to 12-15
-      const int b16 = (g >> 1) * 16, lo = (g & 1) ? 4 : 0, hi = (g & 1) ? 12 : 8;
-      *(uint2*)&sW2[buf][n][b16 + lo] = make_uint2(p2[q].x, p2[q].y);
-      *(uint2*)&sW2[buf][n][b16 + hi] = make_uint2(p2[q].z, p2[q].w);
-    }
-  };
-  f32x16_t acc[NO / 32];
-#pragma unroll
-  for (int o = 0; o < NO / 32; ++o)
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc[o][q] = 0.f;
-  gload(0, 0);
-  sstore(0);
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
-  for (int c = 0; c < NCH; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < NCH) gload(c + 1, buf ^ 1);
-    // H^T chunk: 32 hidden units x 32 rows, K split over four accumulators
-    // (steps s = 4 q + a into chain a; independent MFMA chains in flight)
-    f32x16_t hc4[4];
-#pragma unroll
-    for (int a4 = 0; a4 < 4; ++a4)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) hc4[a4][q] = 0.f;
-#pragma unroll
-    for (int s2 = 0; s2 < K / 16; ++s2) {
-      const bf16x8_t a = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sW1[buf][r32][16 * s2 + 8 * hh]);
-      hc4[s2 & 3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, __builtin_bit_cast(bf16x8_t, ua[s2]), hc4[s2 & 3], 0, 0, 0);
-    }
-    f32x16_t hacc;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) hacc[q] = (hc4[0][q] + hc4[1][q]) + (hc4[2][q] + hc4[3][q]);
-    // bias, GELU, BF16: step u of the second product takes i = 2u, 2u + 1
-    uint4 pb[2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      float g[8];
-#pragma unroll
-      for (int ii = 0; ii < 2; ++ii) {
-        const int i = 2 * u + ii, h = c * FC + 8 * i + 4 * hh;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) g[4 * ii + j] = gelu_bf16path(hacc[4 * i + j] + b1[h + j]);
-      }
-      pb[u] = make_uint4(pack_bf16x2(g[0], g[1]), pack_bf16x2(g[2], g[3]), pack_bf16x2(g[4], g[5]),
-                         pack_bf16x2(g[6], g[7]));
-    }
-#pragma unroll
-    for (int o = 0; o < NO / 32; ++o)
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const bf16x8_t a = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sW2[buf][32 * o + r32][16 * u + 8 * hh]);
-        acc[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, __builtin_bit_cast(bf16x8_t, pb[u]), acc[o], 0, 0, 0);
-      }
-    if (c + 1 < NCH) sstore(buf ^ 1);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the direct-to-LDS rows of the next chunk
-    __syncthreads();
+  for (int q = 0; q < LPW; ++q) {
+    const int blk = wave * LPW + q, crow = 16 * blk + (lane >> 2);
+    const int c = (lane & 3) ^ ((crow >> 2) & 3);
+    w1part[q] = crow >= FFN_BM;
+    src[q] = crow < FFN_BM ? U + (int64_t)min(m0 + crow, M - 1) * K + 8 * c : W1t + (int64_t)(crow - FFN_BM) * K + 8 * c;
   }
-  GemmArgs ea;
-  ea.X = nullptr;
-  ea.ldx = 0;
-  ea.Wt = nullptr;
-  ea.K = K;
-  ea.bias = b2;
-  ea.resid = X;
-  ea.ldr = NO;
-  ea.Yf = X;
-  ea.ldf = NO;
-  ea.Yb = nullptr;
-  ea.ldb = 0;
-  ea.pre = nullptr;
-  ea.ldp = 0;
-  ea.M = M;
-  ea.N = NO;
-  ea.act = 0;
-  const bool vec = gemm_vec_ok(ea, 2);
+  auto issue = [&](int t) {
+    const int slot = t % FFN_ST, ch = t / KT, k0 = (t % KT) * BK;
 #pragma unroll
-  for (int o = 0; o < NO / 32; ++o) gemm_epilogue<uint16_t>(ea, acc[o], row, 32 * o + 4 * hh, vec);
+    for (int q = 0; q < LPW; ++q) {
+      const int blk = wave * LPW + q;
+      const uint16_t* p = src[q] + k0 + (w1part[q] ? (int64_t)ch * FFN_HC * K : 0);
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)p,
+                                       (__attribute__((address_space(3))) void*)&ring[slot * 8192 + blk * 512], 16, 0,
+                                       0);
+    }
+  };
+  // W2 columns of chunk ch: 32 instructions of 4 rows x 256 bytes, 8 per wave
+  auto issue_w2 = [&](int ch) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int j = wave * 8 + q, r = 4 * j + (lane >> 4), pos = lane & 15, c = pos ^ (r & 15);
+      __builtin_amdgcn_global_load_lds(
+          (const __attribute__((address_space(1))) void*)(W2t + (int64_t)r * 512 + ch * FFN_HC + 8 * c),
+          (__attribute__((address_space(3))) void*)&w2s[j * 512], 16, 0, 0);
+    }
+  };
+  // the eight biases of columns cb .. cb + 7 (cb wave-uniform), the lane's four of them
+  auto bias4 = [&](const float* b, int cb) {
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      v[e] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, b[cb + e])));
+    return hh ? make_float4(v[4], v[5], v[6], v[7]) : make_float4(v[0], v[1], v[2], v[3]);
+  };
+  auto opnd = [&](int slot, int row, int c) {
+    return __builtin_bit_cast(bf16x8_t, *(const uint4*)&ring[slot * 8192 + row * 32 + 8 * (c ^ ((row >> 2) & 3))]);
+  };
+  f32x16_t acc1[4], acc2[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc1[f][q] = acc2[f][q] = 0.f;
+#pragma unroll
+  for (int t = 0; t < FFN_ST - 1; ++t) issue(t);
+  for (int t = 0; t < NT; ++t) {
+    // step t has landed once only the later steps' loads are outstanding
+    // (waiting for more, such as a W2 chunk issued between them, is safe; the
+    // last steps wait for everything)
+    if (t + FFN_ST - 2 < NT) asm volatile("s_waitcnt vmcnt(%0)" ::"n"((FFN_ST - 2) * LPW) : "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();  // every wave is past step t - 1 (and a chunk's W2 reads)
+    asm volatile("" ::: "memory");
+    const int kt = t % KT, ch = t / KT;
+    if (kt == 0) issue_w2(ch);
+    if (t + FFN_ST - 1 < NT) issue(t + FFN_ST - 1);
+    const int slot = t % FFN_ST;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      const int c = kk / 8 + hh;
+      const bf16x8_t ub = opnd(slot, 32 * wave + r32, c);
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+        acc1[f] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(opnd(slot, FFN_BM + 32 * f + r32, c), ub, acc1[f], 0, 0, 0);
+    }
+    if (kt != KT - 1) continue;
+    // the chunk's hidden values: bias, GELU, BF16 (as the first GEMM's
+    // epilogue), regrouped into the k order of the second product
+    uint4 hop[8];  // B operand of k step 2 f + e of this chunk
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      uint32_t d[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 bb = bias4(b1, ch * FFN_HC + 32 * f + 8 * q);
+        const float v0 = gelu_bf16path(acc1[f][4 * q] + bb.x), v1 = gelu_bf16path(acc1[f][4 * q + 1] + bb.y);
+        const float v2 = gelu_bf16path(acc1[f][4 * q + 2] + bb.z), v3 = gelu_bf16path(acc1[f][4 * q + 3] + bb.w);
+        d[2 * q] = pack_bf16x2(v0, v1);
+        d[2 * q + 1] = pack_bf16x2(v2, v3);
+      }
+      // lane half 0 keeps units 0-3 and 16-19 and needs 4-7, 20-23 from half 1;
+      // half 1 keeps 12-15 and 28-31 and needs 8-11, 24-27 from half 0
+      uint32_t x[4];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        x[2 * e] = (uint32_t)__shfl_xor((int)(hh ? d[4 * e] : d[4 * e + 2]), 32);
+        x[2 * e + 1] = (uint32_t)__shfl_xor((int)(hh ? d[4 * e + 1] : d[4 * e + 3]), 32);
+      }
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+        hop[2 * f + e] = hh ? make_uint4(x[2 * e], x[2 * e + 1], d[4 * e + 2], d[4 * e + 3])
+                            : make_uint4(d[4 * e], d[4 * e + 1], x[2 * e], x[2 * e + 1]);
+      for (int q = 0; q < 16; ++q) acc1[f][q] = 0.f;
+    }
+    // second product over the chunk's 8 k steps (W2 landed and was published by
+    // the barriers of the chunk's later steps)
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+      for (int o = 0; o < 4; ++o) {
+        const int r = 32 * o + r32, pos = (2 * s2 + hh) ^ (r & 15);
+        const bf16x8_t wa = __builtin_bit_cast(bf16x8_t, *(const uint4*)&w2s[r * 128 + 8 * pos]);
+        acc2[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa, __builtin_bit_cast(bf16x8_t, hop[s2]), acc2[o], 0, 0, 0);
+      }
+  }
+  // epilogue through LDS as FP32, 32 rows x 128 outputs per wave: (acc + b2) + X
+  __syncthreads();  // every wave is done with the ring and the W2 chunk
+  float* stg = (float*)lds + wave * (32 * NO);
+  auto at = [&](int r, int col) {
+    const int byte = 4 * (r * NO + col), line = byte >> 7;
+    return ((line << 7) | (((byte >> 4) & 7) ^ (line & 7)) << 4 | (byte & 15)) >> 2;
+  };
+#pragma unroll
+  for (int o = 0; o < 4; ++o) {
+    const int cl = 32 * o + 4 * hh;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 bb = bias4(b2, 32 * o + 8 * q);
+      *(float4*)&stg[at(r32, cl + 8 * q)] = make_float4(acc2[o][4 * q] + bb.x, acc2[o][4 * q + 1] + bb.y,
+                                                         acc2[o][4 * q + 2] + bb.z, acc2[o][4 * q + 3] + bb.w);
+    }
+  }
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the wave reads back only its own rows
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int r = 2 * t + (lane >> 5), col = 4 * (lane & 31);
+    const int64_t row = (int64_t)m0 + 32 * wave + r;
+    const float4 u = *(const float4*)&stg[at(r, col)];
+    if (row < M) {
+      float4 x = *(const float4*)(X + row * NO + col);
+      x.x = u.x + x.x;
+      x.y = u.y + x.y;
+      x.z = u.z + x.z;
+      x.w = u.w + x.w;
+      *(float4*)(X + row * NO + col) = x;
+    }
+  }
 }
 
 __global__ void k_zero_f32(float* p, int64_t n) {
@@ -2584,9 +2633,14 @@ static void gemm(Batch& b, const void* X, int64_t ldx, const NetBufs& NB, const 
 // The fused FFN (BF16 inference): X += GELU(U W1 + b1) W2 + b2, timed with
 // the GEMMs when GEMM timing is on (work: the two products' flops, or the
 // algorithmic bytes U, W1, W2, biases, X read and written).
-static void ffn_fused(Batch& b, const void* U, const NetBufs& NB, const GemmW& w1, const float* b1, const GemmW& w2,
+// Launches the fused FFN where its layout assumptions hold (d = 128, hidden
+// 512, 16-byte aligned biases); returns false to leave the FFN to the two GEMMs.
+static bool ffn_fused(Batch& b, const void* U, const NetBufs& NB, const GemmW& w1, const float* b1, const GemmW& w2,
                       const float* b2, float* X, int64_t M) {
-  if (M <= 0) return;
+  if (w1.N != 512 || w1.K != 512 || w2.N != 128 || w2.K != 512 || ((uintptr_t)b1 & 15) || ((uintptr_t)b2 & 15) ||
+      ((uintptr_t)X & 15) || ((uintptr_t)U & 15))
+    return false;
+  if (M <= 0) return true;
   hipStream_t st = b.stream;
   const bool timed = (b.prof.kind == PROF_GEMM || b.prof.kind == PROF_GEMM_BYTES) &&
                      2 * (b.prof.used + 1) <= (int)b.prof.ev.size();
@@ -2603,6 +2657,7 @@ static void ffn_fused(Batch& b, const void* U, const NetBufs& NB, const GemmW& w
       b.prof.work += 2.0 * (m * w1.K + (double)w1.N * w1.K + (double)w2.N * w2.K) + 4.0 * (w1.N + w2.N) +
                      8.0 * m * w2.N;
   }
+  return true;
 }
 
 // Training saves of the forward pass (FP32).
@@ -2881,8 +2936,8 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
                          (const int*)N.tok2f, wp(p + "ln2.g"), wp(p + "ln2.b"), (AT*)u, (int)M, c.highways);
     if (N.par && sidx == 0) HP_HIP(hipEventRecord(b.off_ev[3 + 2 * l], st));
     if (ls) HP_HIP(hipMemcpyAsync(sidx ? ls->xmid_o : ls->xmid_d, X, M * d * 4, hipMemcpyDeviceToDevice, st));
-    if (sizeof(AT) == 2 && !ls && b.ffn_fused) {
-      ffn_fused(b, u, N, P.f1[sidx][l], wp(p + "f1.b"), P.f2[sidx][l], wp(p + "f2.b"), X, M);
+    if (sizeof(AT) == 2 && !ls && b.ffn_fused &&
+        ffn_fused(b, u, N, P.f1[sidx][l], wp(p + "f1.b"), P.f2[sidx][l], wp(p + "f2.b"), X, M)) {
     } else {
       gemm<AT>(b, u, 4 * d, N, P.f1[sidx][l], wp(p + "f1.b"), nullptr, 0, nullptr, 0, h, 4 * d, M, 1,
                ls ? (sidx ? ls->pre_o : ls->pre_d) : nullptr, 4 * d);

@@ -254,16 +254,16 @@ def test_bf16_leaf_attention_matrix_cores_match_vector_alus(cfg, recipe, seed):
 
 @pytest.mark.parametrize("cfg,recipe,seed", [(PLAIN, "plain1024", 1000), (DEF, "precision8192", 2000)])
 def test_bf16_fused_ffn_matches_two_gemm_ffn(cfg, recipe, seed):
-    """The fused FFN kernel (hidden activations kept on chip, the same BF16
-    rounding of the hidden units, their order inside each MFMA step of the
-    second product permuted) against the two-GEMM FFN: the residual streams
-    after the last layer agree far inside the BF16 bounds, and the factors
-    within them.  The off-diagonal stream (31 x 8 and 127 x 16 rows) ends in a
-    partial 128-row block."""
+    """The fused FFN kernel (hidden activations kept on chip) runs each
+    output element's MFMA sequence, bias, GELU and BF16 rounding exactly as
+    the two-GEMM FFN does, so the whole BF16 forward is bit-identical either
+    way: residual streams and every factor.  The off-diagonal stream (31 x 8
+    and 127 x 16 rows) ends in a partial 128-row block."""
     import torch
     w = test_weights(cfg)
     fr = inputs.make_frame(recipe, seed)
     s = Side(cfg, [fr], with_net=True)
+    s.B.debug_set("keep_stages", 0)
     wt = torch.tensor(hp.pack_weights(cfg, w), device="cuda")
     out = {}
     for fused in (0, 1):
@@ -272,15 +272,11 @@ def test_bf16_fused_ffn_matches_two_gemm_ffn(cfg, recipe, seed):
         s.B.infer_factors(wt, s.rho, s.sys, fac, hp.HP_BF16)
         torch.cuda.synchronize()
         no = s.parts[0]["MH"] * cfg.rank
-        out[fused] = (_dbg(s, "xd", (fr.n, cfg.d)), s.download_factors(fac, hp.HP_BF16)[0],
-                      _dbg(s, "xo", (no, cfg.d)))
-    e_xd = relerr(out[1][0], out[0][0])
-    e_xo = relerr(out[1][2], out[0][2])
-    e_G = relerr(out[1][1][0], out[0][1][0])
-    e_B = relerr(out[1][1][1], out[0][1][1])
-    print(f"fused vs two-GEMM FFN: xd {e_xd:.2e}  xo {e_xo:.2e}  G {e_G:.2e}  B {e_B:.2e}")
-    assert e_xd <= 1e-2 and e_xo <= 1e-2
-    assert e_G <= BF16_BOUND["G"] and e_B <= BF16_BOUND["B"]
+        out[fused] = (_dbg(s, "xd", (fr.n, cfg.d)), _dbg(s, "xo", (no, cfg.d)), fac.clone())
+    print("fused vs two-GEMM FFN: max |dxd|", float(np.abs(out[1][0] - out[0][0]).max()),
+          "max |dxo|", float(np.abs(out[1][1] - out[0][1]).max()))
+    assert np.array_equal(out[1][0], out[0][0]) and np.array_equal(out[1][1], out[0][1])
+    assert torch.equal(out[1][2], out[0][2])
 
 
 N_GEMM_VARIANTS = 14  # tile variants the library header lists for "gemm_variant"
