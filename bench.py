@@ -4,7 +4,9 @@ method vs FP32 plain method vs Jacobi-PCG) on one MI355X.
 A step is one pass of the whole hot path over one batch of synthetic frames:
 network inference (features, encoder, both attention stacks with highways,
 heads, packed factors) and PCG with the learned H-matrix preconditioner until
-every frame reaches ||r|| <= 1e-6 ||b|| on a true residual.  Inputs (density,
+every frame reaches ||r|| <= 1e-6 ||b|| on a true residual, replayed as one
+captured hipGraph (inference, PCG setup and first chunk of iterations; a frame
+still iterating continues in chunk graphs).  Inputs (density,
 right-hand side, assembled operator, weights) are resident in HBM before the
 timed region; assembly is timed separately, as the paper leaves it out.
 
@@ -89,10 +91,20 @@ class Inputs:
 
 
 def _method_step(I, wt, fac, compute):
+    """Eager form: inference, then the PCG solve (its iterations replayed from
+    captured chunk graphs)."""
     from paper_2605_13343_amd import hp
     I.B.infer_factors(wt, I.rho, I.sys, fac, compute)
     I.x.zero_()
     return I.B.pcg_solve(I.sys, fac, I.b, I.x, hp.PRECOND_HMAT, fdtype=compute, tol=TOL, use_graph=True)
+
+
+def _graph_step(I, wt, fac, compute):
+    """One captured graph: inference, PCG setup and the first chunk of
+    iterations (hp_solve_step); the same results as _method_step bit for bit.
+    Needs one _method_step (or inference) of the compute type on the batch first."""
+    I.x.zero_()
+    return I.B.solve_step(wt, I.rho, I.sys, fac, I.b, I.x, compute, tol=TOL)
 
 
 def _timed(stream, fn, steps):
@@ -165,8 +177,10 @@ def main() -> int:
     torch.cuda.synchronize()
     assemble_ms = (time.perf_counter() - t0) / 5 * 1e3
 
-    step = lambda k: _method_step(I, wt, fac, hp.HP_BF16)
-    for _ in range(args.warmup):
+    eager = lambda k: _method_step(I, wt, fac, hp.HP_BF16)
+    step = lambda k: _graph_step(I, wt, fac, hp.HP_BF16)
+    eager(0)  # tunes the GEMM tiles; the graph is captured on the first step
+    for _ in range(max(args.warmup, 1)):
         step(0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -188,25 +202,44 @@ def main() -> int:
     # ---------------------------------------------------------------- rooflines
     roofline = _rooflines(B, I, wt, fac, max(iters))
 
+    # ---------------------------------------------------------------- the eager form of the step
+    # the inference launched kernel by kernel on three streams, then the solve
+    # (the same results bit for bit)
+    eres, _, eager_ms = _timed(stream, eager, args.steps)
+
     # ---------------------------------------------------------------- fresh frames every step
     # the same step on a new set of frames each time (inputs uploaded and
     # assembled beforehand): no step solves frames a previous solve has seen
+    # (each step copies its frames' density, right-hand side and assembled
+    # system into the buffers the captured step reads: inside the timed region)
     fresh_sets = [Inputs(cfg, [inputs.make_frame("precision8192", 2100 + 20 * s + f) for f in range(len(frames))],
                          stream, batch=B) for s in range(args.steps)]
     torch.cuda.synchronize()
     fres_all = []
 
     def fresh_step(k):
-        r = _method_step(fresh_sets[k], wt, fac, hp.HP_BF16)
+        F = fresh_sets[k]
+        I.rho.copy_(F.rho)
+        I.b.copy_(F.b)
+        I.sys.copy_(F.sys)
+        r = _graph_step(I, wt, fac, hp.HP_BF16)
         fres_all.extend(r)
         return r
 
     _, _, fresh_ms = _timed(stream, fresh_step, args.steps)
     del fresh_sets
 
+    # the headline frames back in place for the legs below
+    I2 = Inputs(cfg, frames, stream, batch=B)
+    I.rho.copy_(I2.rho)
+    I.b.copy_(I2.b)
+    I.sys.copy_(I2.sys)
+    del I2
+
     # ---------------------------------------------------------------- FP32 method, batched
     fac32 = B.new_factors(hp.HP_F32)
-    step32 = lambda k: _method_step(I, wt, fac32, hp.HP_F32)
+    step32 = lambda k: _graph_step(I, wt, fac32, hp.HP_F32)
+    _method_step(I, wt, fac32, hp.HP_F32)
     step32(0)
     res32, _, ms32 = _timed(stream, step32, 3)
     x_fp32b = I.x_frames()
@@ -225,7 +258,8 @@ def main() -> int:
     for f in range(len(frames)):
         I1 = Inputs(cfg, [frames[f]], stream)
         f1 = I1.B.new_factors(hp.HP_F32)
-        s1 = lambda k: _method_step(I1, wt, f1, hp.HP_F32)
+        s1 = lambda k: _graph_step(I1, wt, f1, hp.HP_F32)
+        _method_step(I1, wt, f1, hp.HP_F32)
         s1(0)
         pres, _, pms = _timed(stream, s1, 3)
         plain.append((pms, pres[0][0]))
@@ -244,6 +278,10 @@ def main() -> int:
         "bf16_converged": int(sum(1 for fl in flags if fl & hp.CONVERGED)),
         "bf16_fell_back": int(sum(1 for fl in flags if fl & hp.FELL_BACK)),
         "bf16_max_true_relres": float(max(relres)),
+        "bf16_step": "one captured hipGraph per step: inference (three streams forked and joined inside the "
+                     "graph), PCG setup and the first chunk of iterations (hp_solve_step)",
+        "bf16_eager_ms_per_frame": round(eager_ms / len(frames), 4),
+        "bf16_eager_same_results": bool([r[:2] for r in eres] == [r[:2] for r in res]),
         "bf16_fresh_frames_ms_per_frame": round(fresh_ms / len(frames), 4),
         "bf16_fresh_frames": {**_iter_stats(fres_all), "frames": len(fres_all),
                               "seeds": f"2100..{2100 + 20 * args.steps - 1}",
@@ -372,7 +410,8 @@ def _largest_leg(cfg, wt, stream):
     frames = [inputs.make_frame("largest16384", 5000 + f) for f in range(20)]
     I = Inputs(cfg, frames, stream)
     fac = I.B.new_factors(hp.HP_BF16)
-    st = lambda k: _method_step(I, wt, fac, hp.HP_BF16)
+    st = lambda k: _graph_step(I, wt, fac, hp.HP_BF16)
+    _method_step(I, wt, fac, hp.HP_BF16)
     st(0)
     st(0)
     res, _, ms = _timed(stream, st, 3)
@@ -402,7 +441,8 @@ def _batching_leg(cfg, wt, stream):
     frames = [inputs.make_frame("batch_mixed", 4000 + f) for f in range(64)]
     I = Inputs(cfg, frames, stream)
     fac = I.B.new_factors(hp.HP_BF16)
-    st = lambda k: _method_step(I, wt, fac, hp.HP_BF16)
+    st = lambda k: _graph_step(I, wt, fac, hp.HP_BF16)
+    _method_step(I, wt, fac, hp.HP_BF16)
     st(0)
     st(0)
     res, per, ms = _timed(stream, st, 3)

@@ -234,6 +234,23 @@ hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_factors,
                        const hp_solve_opts* opts, const float* d_b, double* d_x,
                        hp_solve_result* res);
 
+/* One step of the method (paper Sec. 5 "Single-graph capture"): network
+ * inference into d_factors (as hp_infer_factors with compute), then PCG with
+ * the learned preconditioner (as hp_pcg_solve; opts->precond must be
+ * HP_PRECOND_HMAT and opts->fdtype equal compute).  With opts->use_graph and
+ * an earlier eager hp_infer_factors of this compute type on the batch (which
+ * tuned its GEMM tiles), the whole inference, the PCG setup and the first
+ * chunk of iterations (as many as the batch's previous solve needed, see
+ * hp_solve_opts.chunk) are one captured hipGraph, kept per (buffers, first
+ * chunk length, tol, max_iter, recompute_every, stagnation; at most 8) and
+ * replayed; a frame still iterating after it continues in chunk graphs, and
+ * the fallback runs as in hp_pcg_solve.  Otherwise the two calls run one
+ * after the other.  Results equal hp_infer_factors followed by hp_pcg_solve
+ * bit for bit.  Synchronises the stream (host results). */
+hp_status hp_solve_step(hp_batch b, const float* d_weights, const float* d_rho, const float* d_sys,
+                        void* d_factors, int32_t compute, const hp_solve_opts* opts, const float* d_b, double* d_x,
+                        hp_solve_result* res);
+
 /* Per-frame latency of the last hp_pcg_solve from device-clock stamps: the
  * lead thread of each frame stamps the clock when the frame stops (its last
  * stop, fallback included), and the library stamps the start of every

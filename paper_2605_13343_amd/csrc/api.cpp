@@ -40,6 +40,7 @@ Batch::~Batch() {
   if (net_train_free && net_train) net_train_free(net_train);
   for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
   for (auto& kv : infer_graphs) hipGraphExecDestroy(kv.second);
+  for (auto& kv : step_graphs) hipGraphExecDestroy(kv.second);
   for (void* p : allocs) hipFree(p);
   if (h_pin) hipHostFree(h_pin);
   if (cap_stream) hipStreamDestroy(cap_stream);
@@ -283,10 +284,31 @@ extern "C" hp_status hp_apply(hp_batch b, const float* d_sys, const void* d_fact
 
 // ------------------------------------------------------------------ PCG driver
 
+// Iterations per host check, and the first chunk's length: as many iterations
+// as the batch's previous solve with this preconditioner needed, rounded up to
+// a multiple of 4 (even, as every chunk) and kept between one chunk and 256
+// iterations (so at most 64 more graph lengths are ever captured): for a
+// batch solved again and again, one active-count readback instead of
+// several.  Frames stop at their own iteration either way; only trailing
+// no-op iterations of stopped frames differ.  It never exceeds max_iter
+// (rounded up to even): every frame has stopped by then, so further
+// iterations would only be no-ops.
+static int chunk_len(const hp_solve_opts& o) { return std::max(2, o.chunk + (o.chunk & 1)); }
+static int first_chunk_len(const Batch* b, int mode, const hp_solve_opts& o) {
+  const int chunk = chunk_len(o);
+  int first = chunk;
+  const int64_t prev = std::min<int64_t>(b->last_iters[mode], 256);
+  const int64_t cap = std::max<int64_t>(2, (int64_t)o.max_iter + (o.max_iter & 1));
+  if (prev > chunk) first = (int)std::min<int64_t>((prev + 3) / 4 * 4, cap);
+  return first;
+}
+
 // The pinned staging area is rewritten only after the stream has drained
 // (every pass ends with a synchronisation), so the async uploads never race.
+// With begun, the pass's setup and first chunk are already enqueued (as part
+// of a captured step graph, every frame active from the standard state).
 static hp_status run_pass(Batch* b, PcgLaunch& P, const hp_solve_opts& o, const std::vector<FrameState>& init,
-                          int nact, std::vector<FrameState>& out) {
+                          int nact, std::vector<FrameState>& out, bool begun = false) {
   out.clear();
   int* h_active = (int*)b->h_pin;
   int* h_nact = (int*)(b->h_pin + 64);
@@ -301,7 +323,9 @@ static hp_status run_pass(Batch* b, PcgLaunch& P, const hp_solve_opts& o, const 
                init[f].flags == 0 && init[f].force_rc == 0 && init[f].fresh == 0 && init[f].alpha == 0.0 &&
                init[f].beta == 0.0 && init[f].rr == 0.0 && init[f].target == 0.0 && init[f].bnorm == 0.0 &&
                init[f].rwin == 0.0;
-  if (standard) {
+  if (begun) {
+    if (!standard) return set_error(HP_E_STATE, "pcg: a begun pass must start from the standard state");
+  } else if (standard) {
     HP_TRY(pcg_init_states(b->st, b->nframes, b->n_active, b->prm, prm, b->stream));
   } else {
     HP_HIP(hipStreamSynchronize(b->stream));  // the pinned staging may still feed an earlier copy
@@ -312,23 +336,9 @@ static hp_status run_pass(Batch* b, PcgLaunch& P, const hp_solve_opts& o, const 
     HP_HIP(hipMemcpyAsync(b->n_active, h_nact, sizeof(int), hipMemcpyHostToDevice, b->stream));
     HP_HIP(hipMemcpyAsync(b->prm, h_prm, sizeof(SolveParams), hipMemcpyHostToDevice, b->stream));
   }
-  HP_TRY(pcg_setup(P));
-  const int chunk = std::max(2, o.chunk + (o.chunk & 1));
-  // The first chunk runs as many iterations as the batch's previous solve
-  // with this preconditioner needed, rounded up to a multiple of 4 (even, as
-  // every chunk) and kept between one chunk and 256 iterations (so at most
-  // 64 more graph lengths are ever captured): for a batch solved again and
-  // again, one active-count readback instead of several.  Frames stop at
-  // their own iteration either way; only trailing no-op iterations of
-  // stopped frames differ.
-  // It never exceeds max_iter (rounded up to even): every frame has stopped
-  // by then, so further iterations would only be no-ops.
-  int first = chunk;
-  {
-    const int64_t prev = std::min<int64_t>(b->last_iters[P.mode], 256);
-    const int64_t cap = std::max<int64_t>(2, (int64_t)o.max_iter + (o.max_iter & 1));
-    if (prev > chunk) first = (int)std::min<int64_t>((prev + 3) / 4 * 4, cap);
-  }
+  if (!begun) HP_TRY(pcg_setup(P));
+  const int chunk = chunk_len(o);
+  const int first = first_chunk_len(b, P.mode, o);
   // Graphs are keyed by the caller's buffers: a caller that cycles through
   // many buffer sets would grow the cache without bound, so it is emptied
   // once it holds kMaxPcgGraphs executables (every earlier pass has ended
@@ -370,7 +380,7 @@ static hp_status run_pass(Batch* b, PcgLaunch& P, const hp_solve_opts& o, const 
   if (o.use_graph) {
     HP_TRY(graph_for(chunk, &exec));
     exec_first = exec;
-    if (first != chunk) HP_TRY(graph_for(first, &exec_first));
+    if (first != chunk && !begun) HP_TRY(graph_for(first, &exec_first));
   }
   const int64_t max_chunks = (int64_t)o.max_iter / chunk + 2;
   for (int64_t c = 0; c < max_chunks; ++c) {
@@ -394,6 +404,7 @@ static hp_status run_pass(Batch* b, PcgLaunch& P, const hp_solve_opts& o, const 
       HP_HIP(hipStreamSynchronize(b->stream));
       if (*h_active <= 0) break;
     }
+    if (c == 0 && begun) continue;  // the first chunk is in the step graph
     if (exec) HP_HIP(hipGraphLaunch(c == 0 ? exec_first : exec, b->stream));
     else HP_TRY(pcg_iterations(P, c == 0 ? first : chunk));
   }
@@ -411,19 +422,25 @@ static hp_status read_states(Batch* b, std::vector<FrameState>& out) {
   return HP_OK;
 }
 
-extern "C" hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_factors, const hp_solve_opts* opts,
-                                  const float* d_b, double* d_x, hp_solve_result* res) {
-  if (!b || !d_sys || !opts || !d_b || !d_x || !res) return set_error(HP_E_INVALID, "hp_pcg_solve: NULL argument");
-  const hp_solve_opts o = *opts;
-  if (o.precond < 0 || o.precond > 2) return set_error(HP_E_INVALID, "hp_pcg_solve: bad precond");
-  if (o.precond == HP_PRECOND_HMAT && !d_factors)
-    return set_error(HP_E_INVALID, "hp_pcg_solve: factors required for HMAT");
+static hp_status check_solve(hp_batch b, const float* d_sys, const void* d_factors, const hp_solve_opts* opts,
+                             const float* d_b, const double* d_x, const hp_solve_result* res, const char* who) {
+  if (!b || !d_sys || !opts || !d_b || !d_x || !res) return set_error(HP_E_INVALID, "%s: NULL argument", who);
+  const hp_solve_opts& o = *opts;
+  if (o.precond < 0 || o.precond > 2) return set_error(HP_E_INVALID, "%s: bad precond", who);
+  if (o.precond == HP_PRECOND_HMAT && !d_factors) return set_error(HP_E_INVALID, "%s: factors required for HMAT", who);
   if (o.precond == HP_PRECOND_HMAT && o.fdtype != HP_F32 && o.fdtype != HP_BF16)
-    return set_error(HP_E_INVALID, "hp_pcg_solve: bad fdtype");
+    return set_error(HP_E_INVALID, "%s: bad fdtype", who);
   if (!(o.tol >= 0) || o.max_iter < 0 || o.recompute_every < 0)
-    return set_error(HP_E_INVALID, "hp_pcg_solve: bad tolerance or limits");
-  if ((const void*)d_b == (const void*)d_x) return set_error(HP_E_INVALID, "hp_pcg_solve: b and x must not alias");
-  int64_t offs[5], tot;
+    return set_error(HP_E_INVALID, "%s: bad tolerance or limits", who);
+  if ((const void*)d_b == (const void*)d_x) return set_error(HP_E_INVALID, "%s: b and x must not alias", who);
+  return HP_OK;
+}
+
+// The launch description of a solve on the batch's stream (offs: factor
+// section offsets, kept alive by the caller).
+static PcgLaunch make_launch(Batch* b, const float* d_sys, const void* d_factors, const hp_solve_opts& o,
+                             const float* d_b, double* d_x, int64_t offs[5]) {
+  int64_t tot;
   factor_offsets(*b, o.precond == HP_PRECOND_HMAT ? o.fdtype : HP_F32, offs, &tot);
   PcgLaunch P;
   P.g = b->geom();
@@ -456,15 +473,27 @@ extern "C" hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_
   B.st = b->st;
   B.prm = b->prm;
   B.ticks = b->d_ticks;
-  HP_TRY(launch_tick(b->d_ticks + 1, b->stream));
-  std::vector<FrameState> init(b->nframes);
+  return P;
+}
+
+// Every frame active from the standard initial state.
+static std::vector<FrameState> standard_states(int nframes) {
+  std::vector<FrameState> init(nframes);
   for (auto& s : init) {
     memset(&s, 0, sizeof s);
     s.rho = 1.0;
     s.active = 1;
   }
+  return init;
+}
+
+// A solve after its checks: the first pass (begun: its setup and first chunk
+// already enqueued), the per-frame results, and the Jacobi-PCG restart of
+// every frame that did not converge.
+static hp_status solve_body(Batch* b, const hp_solve_opts& o, PcgLaunch& P, hp_solve_result* res, bool begun) {
+  std::vector<FrameState> init = standard_states(b->nframes);
   std::vector<FrameState> out;
-  HP_TRY(run_pass(b, P, o, init, b->nframes, out));
+  HP_TRY(run_pass(b, P, o, init, b->nframes, out, begun));
   if (out.empty()) HP_TRY(read_states(b, out));
   {
     int mx = 0;
@@ -512,6 +541,84 @@ extern "C" hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_
     return set_error(HP_E_NOCONV, "hp_pcg_solve: tolerance not reached");
   }
   return HP_OK;
+}
+
+extern "C" hp_status hp_pcg_solve(hp_batch b, const float* d_sys, const void* d_factors, const hp_solve_opts* opts,
+                                  const float* d_b, double* d_x, hp_solve_result* res) {
+  HP_TRY(check_solve(b, d_sys, d_factors, opts, d_b, d_x, res, "hp_pcg_solve"));
+  const hp_solve_opts o = *opts;
+  int64_t offs[5];
+  PcgLaunch P = make_launch(b, d_sys, d_factors, o, d_b, d_x, offs);
+  HP_TRY(launch_tick(b->d_ticks + 1, b->stream));
+  return solve_body(b, o, P, res, false);
+}
+
+// One step of the method: inference, then PCG with the learned preconditioner.
+// With use_graph (and the inference's GEMM tiles already tuned by an earlier
+// eager inference of this compute type), the inference, the PCG setup and the
+// first chunk of iterations are one captured hipGraph, kept per buffer set and
+// first-chunk length; the rest of the solve (further chunks when a frame is
+// still iterating, the fallback) follows as in hp_pcg_solve.
+extern "C" hp_status hp_solve_step(hp_batch b, const float* d_weights, const float* d_rho, const float* d_sys,
+                                   void* d_factors, int32_t compute, const hp_solve_opts* opts, const float* d_b,
+                                   double* d_x, hp_solve_result* res) {
+  HP_TRY(check_solve(b, d_sys, d_factors, opts, d_b, d_x, res, "hp_solve_step"));
+  if (!d_weights || !d_rho) return set_error(HP_E_INVALID, "hp_solve_step: NULL argument");
+  if (opts->precond != HP_PRECOND_HMAT || opts->fdtype != compute)
+    return set_error(HP_E_INVALID, "hp_solve_step: precond must be HMAT with fdtype equal to the compute type");
+  const hp_solve_opts o = *opts;
+  const bool graph = o.use_graph && b->prof.kind == PROF_NONE && infer_ready_for_capture(*b, compute);
+  int64_t offs[5];
+  PcgLaunch P = make_launch(b, d_sys, d_factors, o, d_b, d_x, offs);
+  if (!graph) {
+    HP_TRY(hp_infer_factors(b, d_weights, d_rho, d_sys, d_factors, compute));
+    HP_TRY(launch_tick(b->d_ticks + 1, b->stream));
+    return solve_body(b, o, P, res, false);
+  }
+  const int first = first_chunk_len(b, HP_PRECOND_HMAT, o);
+  const auto key = std::make_tuple((int)compute, (const void*)d_weights, (const void*)d_rho, (const void*)d_sys,
+                                   (const void*)d_factors, (const void*)d_b, (const void*)d_x, first, o.tol, o.max_iter,
+                                   o.recompute_every, o.stagnation);
+  auto it = b->step_graphs.find(key);
+  hipGraphExec_t exec = nullptr;
+  if (it != b->step_graphs.end()) {
+    exec = it->second;
+  } else {
+    if (b->step_graphs.size() >= 8) {  // callers cycling through buffers: keep the cache small
+      HP_HIP(hipStreamSynchronize(b->stream));
+      for (auto& kv : b->step_graphs) hipGraphExecDestroy(kv.second);
+      b->step_graphs.clear();
+    }
+    if (!b->cap_stream) HP_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    const SolveParams prm{o.tol, o.max_iter, o.recompute_every, o.stagnation, 0};
+    std::swap(b->stream, b->cap_stream);  // every launch below goes to the capturing stream
+    PcgLaunch C = P;
+    C.g.stream = b->stream;
+    C.prof = nullptr;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    hp_status s = e == hipSuccess ? HP_OK : set_error(HP_E_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    b->capture_forks = 1;
+    if (s == HP_OK) s = hp_infer_factors(b, d_weights, d_rho, d_sys, d_factors, compute);
+    b->capture_forks = 0;
+    if (s == HP_OK) s = launch_tick(b->d_ticks + 1, b->stream);
+    if (s == HP_OK) s = pcg_init_states(b->st, b->nframes, b->n_active, b->prm, prm, b->stream);
+    if (s == HP_OK) s = pcg_setup(C);
+    if (s == HP_OK) s = pcg_iterations(C, first);
+    if (e == hipSuccess) e = hipStreamEndCapture(b->stream, &g);
+    std::swap(b->stream, b->cap_stream);
+    if (s != HP_OK) {
+      if (g) hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return set_error(HP_E_HIP, "step capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return set_error(HP_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    b->step_graphs[key] = exec;
+  }
+  HP_HIP(hipGraphLaunch(exec, b->stream));
+  return solve_body(b, o, P, res, true);
 }
 
 extern "C" hp_status hp_frame_times(hp_batch b, double* h_stop_ms, double* h_solve_start_ms) {

@@ -131,7 +131,15 @@ struct Batch {
   std::map<std::tuple<int, const void*, const void*, const void*, const void*, int>, hipGraphExec_t> infer_graphs;
   std::set<std::pair<int, int>> infer_warm;
   int infer_graph = 0;                  // replay inferences from a captured hipGraph after the first (opt-in)
+  int capture_forks = 0;                // set while a solve step is captured: the inference keeps its side streams
   int last_iters[3] = {0, 0, 0};        // iterations the last solve needed, per preconditioner (first chunk length)
+  // captured solve steps (inference + PCG setup + first chunk) by (compute,
+  // weights, rho, sys, factors, b, x, first chunk, tol, max_iter,
+  // recompute_every, stagnation)
+  std::map<std::tuple<int, const void*, const void*, const void*, const void*, const void*, const void*, int, double,
+                      int, int, int>,
+           hipGraphExec_t>
+      step_graphs;
   std::vector<void*> allocs;
 
   ~Batch();
@@ -162,6 +170,10 @@ hp_status launch_tick(int64_t* p, hipStream_t s);
 
 // network.hip
 hp_status network_supported(const hp_model_config& c);
+// The switches that select an inference's kernels, and whether an inference
+// of this compute type may be captured (workspace allocated, GEMM tiles tuned).
+int infer_signature(const Batch& B);
+bool infer_ready_for_capture(const Batch& B, int compute);
 // The network workspace, allocated on the first call that needs it (no-op after).
 hp_status network_alloc(Batch& b);
 

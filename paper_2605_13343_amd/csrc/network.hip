@@ -2959,7 +2959,14 @@ static hp_status tables_ahead(Batch& b, const float* W, const float* sys) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HP_HIP(hipStreamIsCapturing(b.stream, &cs));
   N.pre = 1;
-  N.pre_side = cs == hipStreamCaptureStatusNone && b.prof.kind == PROF_NONE;
+  // under a solve-step capture the side streams fork from and join back into
+  // the capturing stream through events, so the graph keeps the overlap; they
+  // exist from the eager inference that preceded the capture
+  const bool fork_in_capture = b.capture_forks && b.side && b.side_start && b.side_done &&
+                               (int)b.side_ev.size() >= b.cfg.layers &&
+                               (!(b.cfg.offdiag && b.mtot > 0) ||
+                                (b.offs && (int)b.off_ev.size() >= 2 + 2 * b.cfg.layers));
+  N.pre_side = (cs == hipStreamCaptureStatusNone || fork_in_capture) && b.prof.kind == PROF_NONE;
   hipStream_t st = b.stream;
   if (N.pre_side) {
     if (!b.side) HP_HIP(hipStreamCreateWithFlags(&b.side, hipStreamNonBlocking));
@@ -3068,6 +3075,15 @@ static hp_status forward(Batch& b, const float* W, const float* rho, const float
   return HP_OK;
 }
 
+int infer_signature(const Batch& B) {
+  return B.keep_stages | (B.ffn_fused << 1) | (B.attn_valu << 2) | (B.gemm_autotune << 3) |
+         ((B.gemm_variant + 1) << 4);
+}
+
+bool infer_ready_for_capture(const Batch& B, int compute) {
+  return B.net.ws && B.infer_warm.count(std::make_pair(compute, infer_signature(B))) > 0;
+}
+
 }  // namespace hp
 
 using namespace hp;
@@ -3092,10 +3108,12 @@ extern "C" hp_status hp_infer_factors(hp_batch b, const float* d_weights, const 
     if (compute == HP_BF16) return forward<uint16_t, uint16_t>(B, d_weights, d_rho, d_sys, d_factors);
     return forward<float, float>(B, d_weights, d_rho, d_sys, d_factors);
   };
-  const int sig = B.keep_stages | (B.ffn_fused << 1) | (B.attn_valu << 2) | (B.gemm_autotune << 3) |
-                  ((B.gemm_variant + 1) << 4);
+  const int sig = infer_signature(B);
   const auto warm = std::make_pair((int)compute, sig);
-  if (!B.infer_graph || B.prof.kind != PROF_NONE || !B.infer_warm.count(warm)) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HP_HIP(hipStreamIsCapturing(B.stream, &cs));
+  // inside a caller's capture (a captured solve step) the launches join it
+  if (!B.infer_graph || B.prof.kind != PROF_NONE || !B.infer_warm.count(warm) || cs != hipStreamCaptureStatusNone) {
     HP_TRY(run());
     B.infer_warm.insert(warm);
     return HP_OK;

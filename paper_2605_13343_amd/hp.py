@@ -76,6 +76,8 @@ EXPORTS = {
     "hp_apply": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32], C.c_int32),
     "hp_apply_static": ([C.c_int32] * 5 + [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                             C.c_void_p], C.c_int32),
+    "hp_solve_step": ([C.c_void_p] * 5 + [C.c_int32, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p,
+                                            C.POINTER(SolveResult)], C.c_int32),
     "hp_frame_times": ([C.c_void_p, C.c_void_p, C.POINTER(C.c_double)], C.c_int32),
     "hp_pcg_solve": ([C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p,
                       C.POINTER(SolveResult)], C.c_int32),
@@ -281,6 +283,18 @@ class Batch:
         st = lib().hp_pcg_solve(self.h, _ptr(sys), _ptr(fac), C.byref(o), _ptr(b), _ptr(x), res)
         if not (st in (5, 6) and not raise_on_fail):
             _check(st)
+        return [(r.iters, r.flags, r.relres) for r in res]
+
+    def solve_step(self, weights, rho, sys, fac, b, x, compute: int, tol: float = 1e-6, max_iter: int = 10000,
+                   recompute_every: int = 25, fallback: bool = True, use_graph: bool = True, chunk: int = 16,
+                   stagnation: bool = True):
+        """Inference then PCG with the learned preconditioner (one captured
+        graph when use_graph and the inference was run eagerly before)."""
+        o = SolveOpts(PRECOND_HMAT, compute, tol, max_iter, recompute_every, int(fallback), int(use_graph), chunk,
+                      int(stagnation))
+        res = (SolveResult * len(self.dims))()
+        _check(lib().hp_solve_step(self.h, _ptr(weights), _ptr(rho), _ptr(sys), _ptr(fac), int(compute), C.byref(o),
+                                   _ptr(b), _ptr(x), res))
         return [(r.iters, r.flags, r.relres) for r in res]
 
     def frame_times(self):

@@ -306,3 +306,45 @@ def test_frame_stop_times_follow_iterations(torch_cuda):
         for g in range(len(its)):
             if its[f] < its[g]:
                 assert stop[f] <= stop[g], (f, g, its[f], its[g], stop[f], stop[g])
+
+
+def test_solve_step_graph_equals_separate_calls(torch_cuda):
+    """hp_solve_step captures the inference, the PCG setup and the first chunk
+    of iterations as one graph.  Its results equal hp_infer_factors followed by
+    hp_pcg_solve bit for bit: on the capture, on a replay, and on a replay after
+    the right-hand side and densities changed in place (the graph reads the
+    buffers at each replay)."""
+    import os
+    torch = torch_cuda
+    path = os.path.join(os.path.dirname(hp.__file__), "weights", "trained_L64.npz")
+    z = np.load(path, allow_pickle=False)
+    wt = torch.tensor(hp.pack_weights(DEF, {k: z[k] for k in z.files}), device="cuda")
+    frames = _mixed_frames(6)
+    s = Side(DEF, frames)
+    fac = s.B.new_factors(hp.HP_BF16)
+
+    def separate():
+        s.B.infer_factors(wt, s.rho, s.sys, fac, hp.HP_BF16)
+        x = torch.zeros(s.B.ntot, dtype=torch.float64, device="cuda")
+        res = s.B.pcg_solve(s.sys, fac, s.b, x, hp.PRECOND_HMAT, fdtype=hp.HP_BF16, tol=1e-6)
+        return x, res, fac.clone()
+
+    def step():
+        x = torch.zeros(s.B.ntot, dtype=torch.float64, device="cuda")
+        res = s.B.solve_step(wt, s.rho, s.sys, fac, s.b, x, hp.HP_BF16, tol=1e-6)
+        return x, res, fac.clone()
+
+    x0, r0, f0 = separate()  # eager: tunes the GEMM tiles, sets the first-chunk length
+    for k in range(2):       # capture, then replay
+        x1, r1, f1 = step()
+        assert r1 == r0 and torch.equal(x1, x0) and torch.equal(f1, f0), k
+    # new inputs in the same buffers
+    g = torch.Generator(device="cpu").manual_seed(9)
+    s.b.copy_((torch.rand(s.B.ntot, generator=g) * 2 - 1).to("cuda"))
+    s.rho.mul_(torch.where(torch.rand(s.B.ntot, generator=g) < 0.1, 10.0, 1.0).to("cuda"))
+    s.B.assemble(s.rho, s.sys)
+    x2, r2, f2 = step()
+    x3, r3, f3 = separate()
+    print("iterations", [r[0] for r in r0], "after the change", [r[0] for r in r3])
+    assert r2 == r3 and torch.equal(x2, x3) and torch.equal(f2, f3)
+    assert all(r[1] & hp.CONVERGED for r in r3)
