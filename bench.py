@@ -372,6 +372,28 @@ def _rooflines(B, I, wt, fac, max_iters):
     else:
         gemm_roof = {"bound": "mfma", "achieved": round(gemm_tf, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(gemm_tf / PEAK_BF16_TFLOPS, 4), **gemm_common}
+    # the fused FFN kernels alone (part of the family above)
+    B.profile_enable("ffn")
+    B.infer_factors(wt, I.rho, I.sys, fac, hp.HP_BF16)
+    n_ffn, ffn_ms, ffn_flops = B.profile_read()
+    B.profile_enable("ffn_bytes")
+    B.infer_factors(wt, I.rho, I.sys, fac, hp.HP_BF16)
+    _, ffn_ms_b, ffn_bytes = B.profile_read()
+    B.profile_enable("none")
+    ffn_roof = None
+    if n_ffn > 0:
+        ffn_tf = ffn_flops / (ffn_ms * 1e-3) / 1e12
+        ffn_gbs = ffn_bytes / (ffn_ms_b * 1e-3) / 1e9
+        ffn_hbm = ffn_bytes / (PEAK_HBM_GBS * 1e9) >= ffn_flops / (PEAK_BF16_TFLOPS * 1e12)
+        ffn_common = {"traffic": None, "kernel": "k_ffn_fused (FFN1 + GELU + FFN2 + residual, MFMA 32x32x16)",
+                      "launches": n_ffn, "avg_launch_us": round(ffn_ms * 1e3 / n_ffn, 2),
+                      "ms_per_inference": round(ffn_ms, 4), "flops_per_inference": ffn_flops,
+                      "bytes_per_inference": ffn_bytes, "tflops": round(ffn_tf, 2),
+                      "mfma_frac": round(ffn_tf / PEAK_BF16_TFLOPS, 4), "hbm_frac": round(ffn_gbs / PEAK_HBM_GBS, 4)}
+        ffn_roof = ({"bound": "hbm", "achieved": round(ffn_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(ffn_gbs / PEAK_HBM_GBS, 4), **ffn_common} if ffn_hbm else
+                    {"bound": "mfma", "achieved": round(ffn_tf, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(ffn_tf / PEAK_BF16_TFLOPS, 4), **ffn_common})
     pcg_roofs = _pcg_rooflines(B, I, fac)
     # the dominant kernel of a step: GEMM time per inference against the
     # update kernel's time over the step's iterations
@@ -380,6 +402,9 @@ def _rooflines(B, I, wt, fac, max_iters):
         r["traffic"] = _traffic(r["kernel"])
     roofline = dict(gemm_roof) if gemm_ms >= upd_ms_step else dict(pcg_roofs["update"])
     roofline["others"] = {"gemm": gemm_roof, "pcg_update": pcg_roofs["update"], "pcg_spmv": pcg_roofs["spmv"]}
+    if ffn_roof:
+        ffn_roof["traffic"] = _traffic(ffn_roof["kernel"])
+        roofline["others"]["ffn_fused"] = ffn_roof
     roofline["others"] = {k: v for k, v in roofline["others"].items() if v["kernel"] != roofline["kernel"]}
     return roofline
 

@@ -387,6 +387,12 @@ hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, int64_t bytes
  * hp_debug_copy ("enc", "xo0"; two device copies per inference);
  * "attention_valu" (0/1): with BF16 compute, run
  * the within-leaf attention on the vector ALUs instead of the matrix cores;
+ * "sai_loss" (0/1, default 0): train with the SAI-style loss of the paper's
+ * loss ablation (Sec. 6.1 Prop. 1(3)) instead of the cosine-Hutchinson loss:
+ * per system || A Y / ||A|| - Z ||_F^2 with Y = M Z (the apply then takes Z,
+ * and the X argument of hp_loss_fwd / hp_loss_bwd is unused) and ||A|| the
+ * largest absolute row sum of A; hp_loss_fwd, hp_loss_bwd, hp_train_grad and
+ * hp_train_step follow the switch;
  * "gemm_variant" (-1 or 0..13, default -1): run every BF16 GEMM whose K the
  * variant's K step divides on that tile variant (block tile x K step, "w8":
  * 8 waves, "pf2": loads two K steps ahead; 0: 64x64x32, 1: 128x128x32, 2:
@@ -418,7 +424,10 @@ hp_status hp_autotune_report(hp_batch b, char* buf, int64_t len, int32_t* entrie
  * bracketed by HIP events (at most 4096 launches are recorded): "gemm" (the
  * network's GEMMs; work = 2 M N K flops per launch), "gemm_bytes" (the same
  * launches; work = their algorithmic HBM bytes: X, W, the bias and every
- * output and residual operand once), "update" (the PCG
+ * output and residual operand once; the fused FFN kernels are part of this
+ * family), "ffn" / "ffn_bytes" (the fused FFN kernels alone: flops
+ * 2 M (512 * 512 + 512 * 128), or U, the weights, the biases and X read and
+ * written once), "update" (the PCG
  * x/r/leaf-stage kernel of the learned preconditioner; work = its algorithmic
  * HBM bytes with every frame active: 44 B per node plus G, Ut, Vt per leaf)
  * and "spmv" (the PCG SpMV kernel; 32 B per node).  PCG launches are timed

@@ -45,30 +45,57 @@ def sai_loss(A, Z, Y):
     return float(np.linalg.norm((A @ Y) / nA - Z) ** 2)
 
 
-def system_loss(cfg, weights: Dict, fs: network.FrameSys, Z: np.ndarray):
-    """Loss of one system: X = A Z is a fixed input (no gradient through A),
-    Y = M X with M built from the network's factors."""
+def sai_scale(A) -> float:
+    """||A|| of the trainable SAI loss: the largest absolute row sum
+    max_i sum_j |A_ij| (the infinity norm, an upper bound of the spectral
+    norm that is exact to compute in one pass; the loss pins M A to a fixed
+    absolute scale either way)."""
+    return float(np.max(np.asarray(abs(A).sum(axis=1)).ravel()))
+
+
+def sai_train_loss(A, Z, Y):
+    """The SAI-style loss of Prop. 1(3) as trained in the loss ablation:
+    || A Y / ||A||_inf - Z ||_F^2 with Y = M Z (torch tensor or numpy)."""
+    s = sai_scale(A)
+    if isinstance(Y, torch.Tensor):
+        A = A.tocsr()
+        Asp = torch.sparse_csr_tensor(torch.as_tensor(A.indptr, dtype=torch.int64),
+                                      torch.as_tensor(A.indices, dtype=torch.int64),
+                                      torch.as_tensor(A.data, dtype=F64), size=A.shape)
+        R = (Asp @ Y) / s - torch.as_tensor(np.asarray(Z, np.float64), dtype=F64)
+        return (R * R).sum()
+    R = (A @ np.asarray(Y, np.float64)) / s - np.asarray(Z, np.float64)
+    return float((R * R).sum())
+
+
+def system_loss(cfg, weights: Dict, fs: network.FrameSys, Z: np.ndarray, kind: str = "cos"):
+    """Loss of one system.  Cosine (Sec. 6.1): X = A Z is a fixed input (no
+    gradient through A), Y = M X with M built from the network's factors,
+    1 - cos(Z, Y).  SAI (the loss ablation, Prop. 1(3)): Y = M Z and
+    || A Y / ||A|| - Z ||_F^2."""
     f = network.forward(cfg, weights, fs)
     G = hmatrix.gram(f["F"])
     B = hmatrix.coupling(f["U"], f["V"])
-    X = torch.as_tensor(fs.A @ np.asarray(Z, np.float64), dtype=F64)
+    Zt = np.asarray(Z, np.float64)
+    X = torch.as_tensor(Zt if kind == "sai" else fs.A @ Zt, dtype=F64)
     Y = hmatrix.apply(fs.part, G, B, f["Ut"], f["Vt"], f["lam"], torch.as_tensor(fs.diagA, dtype=F64), X)
-    return cos_loss(Z, Y)
+    return sai_train_loss(fs.A, Zt, Y) if kind == "sai" else cos_loss(Z, Y)
 
 
-def batch_loss(cfg, weights: Dict, systems: Sequence[network.FrameSys], probes: Sequence[np.ndarray]):
-    """Batch objective: mean over systems of each system's single-angle loss."""
+def batch_loss(cfg, weights: Dict, systems: Sequence[network.FrameSys], probes: Sequence[np.ndarray],
+               kind: str = "cos"):
+    """Batch objective: mean over systems of each system's loss."""
     tot = 0.0
     for fs, Z in zip(systems, probes):
-        tot = tot + system_loss(cfg, weights, fs, Z)
+        tot = tot + system_loss(cfg, weights, fs, Z, kind)
     return tot / len(systems)
 
 
-def loss_and_grad(cfg, weights_np: Dict[str, np.ndarray], systems, probes):
+def loss_and_grad(cfg, weights_np: Dict[str, np.ndarray], systems, probes, kind: str = "cos"):
     """Loss and gradient w.r.t. every weight (float64, reverse mode)."""
     w = {k: torch.tensor(np.asarray(v, np.float64), dtype=F64, requires_grad=True)
          for k, v in weights_np.items()}
-    L = batch_loss(cfg, w, systems, probes)
+    L = batch_loss(cfg, w, systems, probes, kind)
     L.backward()
     return float(L.detach()), {k: v.grad.detach().numpy().copy() if v.grad is not None else np.zeros(v.shape)
                       for k, v in w.items()}

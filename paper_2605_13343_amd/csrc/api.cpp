@@ -670,6 +670,10 @@ extern "C" hp_status hp_debug_set(hp_batch b, const char* name, int32_t value) {
     b->gemm_variant = value;
     return HP_OK;
   }
+  if (n == "sai_loss") {
+    b->loss_kind = value != 0;
+    return HP_OK;
+  }
   if (n == "gemm_autotune") {
     b->gemm_autotune = value != 0;
     return HP_OK;
@@ -709,6 +713,8 @@ extern "C" hp_status hp_profile_enable(hp_batch b, const char* kernel) {
              : k == "gemm_bytes" ? PROF_GEMM_BYTES
              : k == "update"     ? PROF_UPDATE
              : k == "spmv"       ? PROF_SPMV
+             : k == "ffn"        ? PROF_FFN
+             : k == "ffn_bytes"  ? PROF_FFN_BYTES
              : k == "none"       ? PROF_NONE
                                  : -1;
   if (kind < 0) return set_error(HP_E_INVALID, "hp_profile_enable: unknown kernel family '%s'", kernel);

@@ -41,7 +41,8 @@ struct PcgBufs {
 
 // Live kernel timing: every launch of one kernel family is bracketed by HIP
 // events on the batch stream (eager launches only, never inside a capture).
-enum { PROF_NONE = 0, PROF_GEMM = 1, PROF_UPDATE = 2, PROF_SPMV = 3, PROF_GEMM_BYTES = 4 };
+enum { PROF_NONE = 0, PROF_GEMM = 1, PROF_UPDATE = 2, PROF_SPMV = 3, PROF_GEMM_BYTES = 4, PROF_FFN = 5,
+       PROF_FFN_BYTES = 6 };
 struct Prof {
   int kind = PROF_NONE;
   std::vector<hipEvent_t> ev;  // 2 per launch
@@ -132,6 +133,7 @@ struct Batch {
   std::set<std::pair<int, int>> infer_warm;
   int infer_graph = 0;                  // replay inferences from a captured hipGraph after the first (opt-in)
   int capture_forks = 0;                // set while a solve step is captured: the inference keeps its side streams
+  int loss_kind = 0;                    // training objective: 0 cosine-Hutchinson, 1 SAI-style (the loss ablation)
   int last_iters[3] = {0, 0, 0};        // iterations the last solve needed, per preconditioner (first chunk length)
   // captured solve steps (inference + PCG setup + first chunk) by (compute,
   // weights, rho, sys, factors, b, x, first chunk, tol, max_iter,

@@ -2642,7 +2642,8 @@ static bool ffn_fused(Batch& b, const void* U, const NetBufs& NB, const GemmW& w
     return false;
   if (M <= 0) return true;
   hipStream_t st = b.stream;
-  const bool timed = (b.prof.kind == PROF_GEMM || b.prof.kind == PROF_GEMM_BYTES) &&
+  const int pk = b.prof.kind;
+  const bool timed = (pk == PROF_GEMM || pk == PROF_GEMM_BYTES || pk == PROF_FFN || pk == PROF_FFN_BYTES) &&
                      2 * (b.prof.used + 1) <= (int)b.prof.ev.size();
   if (timed) hipEventRecord(b.prof.ev[2 * b.prof.used], st);
   hipLaunchKernelGGL(k_ffn_fused, dim3((unsigned)((M + 127) / 128)), dim3(256), 0, st, (const uint16_t*)U,
@@ -2651,7 +2652,7 @@ static bool ffn_fused(Batch& b, const void* U, const NetBufs& NB, const GemmW& w
     hipEventRecord(b.prof.ev[2 * b.prof.used + 1], st);
     b.prof.used++;
     const double m = (double)M;
-    if (b.prof.kind == PROF_GEMM)
+    if (pk == PROF_GEMM || pk == PROF_FFN)
       b.prof.work += 2.0 * m * w1.N * w1.K + 2.0 * m * w2.N * w2.K;
     else
       b.prof.work += 2.0 * (m * w1.K + (double)w1.N * w1.K + (double)w2.N * w2.K) + 4.0 * (w1.N + w2.N) +

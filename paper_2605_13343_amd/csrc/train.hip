@@ -231,6 +231,74 @@ __global__ void k_loss_dy(const int* node2f, const double* coef, const float* Z,
   dY[e] = (float)(coef[2 * f] * (double)Z[e] + coef[2 * f + 1] * (double)Y[e]);
 }
 
+// ------------------------------------------------------------------ SAI-style loss (the loss ablation)
+// L_f = || A Y / s_f - Z ||_F^2 with Y = M Z (Prop. 1(3)); s_f = ||A_f||
+// read as the largest absolute row sum, from the FP64 coefficients, one
+// block per frame.
+__global__ __launch_bounds__(256) void k_sai_scale(const FrameDesc* fr, const float* sys, int64_t ntot, double* s) {
+  __shared__ double red[4];
+  const FrameDesc F = fr[blockIdx.x];
+  const double* d64 = (const double*)(sys + 5 * ntot);
+  const double *dg = d64, *wx = d64 + ntot, *wy = d64 + 2 * ntot, *wz = d64 + 3 * ntot;
+  double m = 0.0;
+  for (int c = threadIdx.x; c < F.n; c += blockDim.x) {
+    const int64_t i = F.n0 + c;
+    const unsigned cu = (unsigned)c;
+    const int64_t xn = F.n0 + mstep_minus(cu, F.xm), yn = F.n0 + mstep_minus(cu, F.ym),
+                  zn = F.n0 + mstep_minus(cu, F.zm);
+    m = fmax(m, dg[i] + wx[i] + wx[xn] + wy[i] + wy[yn] + wz[i] + wz[zn]);
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
+    s[blockIdx.x] = r;
+  }
+}
+
+// Partials per node block of sum (W / s - Z)^2 with W = A Y (FP64).
+__global__ __launch_bounds__(256) void k_sai_partials(const FrameDesc* fr, const int* blk2f, const float* Z,
+                                                      const float* W, const double* s, double* part) {
+  __shared__ double red[4];
+  const int f = blk2f[blockIdx.x];
+  const FrameDesc F = fr[f];
+  const int c = (blockIdx.x - F.b0) * NODE_BLOCK + threadIdx.x;
+  const double inv = 1.0 / s[f];
+  double acc = 0;
+  if (c < F.n) {
+    const int64_t i = F.n0 + c;
+    for (int q = 0; q < KZ; ++q) {
+      const double r = (double)W[i * KZ + q] * inv - (double)Z[i * KZ + q];
+      acc += r * r;
+    }
+  }
+  acc = bsum_d(acc, red);
+  if (threadIdx.x == 0) part[3 * blockIdx.x] = acc;
+}
+
+// Per frame: the loss and the coefficients of dW = c1 (W c2 - Z) for the
+// objective scale * sum_f L_f: c1 = 2 scale / s_f, c2 = 1 / s_f.
+__global__ void k_sai_frame(const FrameDesc* fr, const double* part, const double* s, double scale, double* lossf,
+                            double* coef) {
+  const FrameDesc F = fr[blockIdx.x];
+  if (threadIdx.x != 0) return;
+  double l = 0;
+  for (int b = 0; b < F.nb; ++b) l += part[3 * (F.b0 + b)];
+  lossf[blockIdx.x] = l;
+  coef[2 * blockIdx.x] = 2.0 * scale / s[blockIdx.x];
+  coef[2 * blockIdx.x + 1] = 1.0 / s[blockIdx.x];
+}
+
+// dW = c1 (W c2 - Z), in place of W; dY = A dW follows (A symmetric).
+__global__ void k_sai_dw(const int* node2f, const double* coef, const float* Z, float* W, int64_t ntot) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ntot * KZ) return;
+  const int f = node2f[e / KZ];
+  W[e] = (float)(coef[2 * f] * ((double)W[e] * coef[2 * f + 1] - (double)Z[e]));
+}
+
 // ------------------------------------------------------------------ reverse pass to the factors
 // Per leaf: dG = dY_k X_k^T, dF_k = (dG + dG^T) F_k, dlam_i = sum_q dY X / A_ii,
 // dUt_k = dY_k TR_k^T + X_k TR2_k^T, dVt_k = dY_k TC_k^T + X_k TC2_k^T.
@@ -316,6 +384,8 @@ __global__ __launch_bounds__(256) void k_grad_tile(const float* U, const float* 
 struct TrainWS {
   int kz = 0;
   float *G = nullptr, *B = nullptr, *Y = nullptr, *dY = nullptr;
+  float* W = nullptr;          // SAI loss: A Y, then its adjoint dW
+  double* sai_s = nullptr;     // SAI loss: ||A|| per frame
   float *uh = nullptr, *vh = nullptr, *gu = nullptr, *gv = nullptr;
   float *SR = nullptr, *SC = nullptr, *SR2 = nullptr, *SC2 = nullptr;
   float *TR = nullptr, *TC = nullptr, *TR2 = nullptr, *TC2 = nullptr, *tmp = nullptr, *scratch = nullptr;
@@ -340,6 +410,8 @@ hp_status train_ws_alloc(Batch& b) {
   A(&T->B, mt * LS * LS * 4);
   A(&T->Y, nt * KZ * 4);
   A(&T->dY, nt * KZ * 4);
+  A(&T->W, nt * KZ * 4);
+  A(&T->sai_s, std::max(b.nframes, 1) * 8);
   for (float** p : {&T->uh, &T->vh, &T->gu, &T->gv, &T->TR, &T->TC, &T->TR2, &T->TC2}) A(p, kt * LS * KZ * 4);
   for (float** p : {&T->SR, &T->SC, &T->SR2, &T->SC2}) A(p, mt * LS * KZ * 4);
   A(&T->tmp, 2 * mt * LS * KZ * 4);
@@ -373,10 +445,20 @@ static hp_status loss_fwd_t(Batch& b, const float* sys, const hp_factor_set& f, 
                      (const float*)T.vh, (const float*)T.B, T.SR, T.SC, T.TR, T.TC, T.tmp);
   hipLaunchKernelGGL((k_m_prolong<L, LS>), dim3((unsigned)b.ktot), dim3(256), 0, st, b.d_fr, b.d_leaf2f,
                      (const float*)f.Ut, (const float*)f.Vt, (const float*)T.TR, (const float*)T.TC, T.Y);
-  hipLaunchKernelGGL(k_loss_partials, dim3(b.nblk), dim3(NODE_BLOCK), 0, st, b.d_fr, b.d_blk2f, Z,
-                     (const float*)T.Y, T.part);
-  hipLaunchKernelGGL(k_loss_frame, dim3(b.nframes), dim3(64), 0, st, b.d_fr, (const double*)T.part, scale,
-                     T.lossf, T.coef);
+  if (b.loss_kind == 1) {  // SAI: W = A Y, || W / s - Z ||^2
+    hipLaunchKernelGGL(k_probe_step, dim3((unsigned)((nt + 15) / 16)), dim3(256), 0, st, b.d_fr,
+                       (const int*)T.node2f, sys, nt, (const float*)T.Y, T.W, -1.f);
+    hipLaunchKernelGGL(k_sai_scale, dim3(b.nframes), dim3(256), 0, st, b.d_fr, sys, nt, T.sai_s);
+    hipLaunchKernelGGL(k_sai_partials, dim3(b.nblk), dim3(NODE_BLOCK), 0, st, b.d_fr, b.d_blk2f, Z,
+                       (const float*)T.W, (const double*)T.sai_s, T.part);
+    hipLaunchKernelGGL(k_sai_frame, dim3(b.nframes), dim3(64), 0, st, b.d_fr, (const double*)T.part,
+                       (const double*)T.sai_s, scale, T.lossf, T.coef);
+  } else {
+    hipLaunchKernelGGL(k_loss_partials, dim3(b.nblk), dim3(NODE_BLOCK), 0, st, b.d_fr, b.d_blk2f, Z,
+                       (const float*)T.Y, T.part);
+    hipLaunchKernelGGL(k_loss_frame, dim3(b.nframes), dim3(64), 0, st, b.d_fr, (const double*)T.part, scale,
+                       T.lossf, T.coef);
+  }
   HP_HIP(hipGetLastError());
   return HP_OK;
 }
@@ -387,8 +469,15 @@ static hp_status loss_bwd_t(Batch& b, const float* sys, const hp_factor_set& f, 
   TrainWS& T = *tws(b);
   hipStream_t st = b.stream;
   const int64_t nt = b.ntot;
-  hipLaunchKernelGGL(k_loss_dy, dim3((unsigned)((nt * KZ + 255) / 256)), dim3(256), 0, st, (const int*)T.node2f,
-                     (const double*)T.coef, Z, (const float*)T.Y, nt, T.dY);
+  if (b.loss_kind == 1) {  // SAI: dW = c1 (W c2 - Z), dY = A dW
+    hipLaunchKernelGGL(k_sai_dw, dim3((unsigned)((nt * KZ + 255) / 256)), dim3(256), 0, st, (const int*)T.node2f,
+                       (const double*)T.coef, Z, T.W, nt);
+    hipLaunchKernelGGL(k_probe_step, dim3((unsigned)((nt + 15) / 16)), dim3(256), 0, st, b.d_fr,
+                       (const int*)T.node2f, sys, nt, (const float*)T.W, T.dY, -1.f);
+  } else {
+    hipLaunchKernelGGL(k_loss_dy, dim3((unsigned)((nt * KZ + 255) / 256)), dim3(256), 0, st,
+                       (const int*)T.node2f, (const double*)T.coef, Z, (const float*)T.Y, nt, T.dY);
+  }
   hipLaunchKernelGGL((k_m_leaf<L, LS>), dim3((unsigned)b.ktot), dim3(256), 0, st, b.d_fr, b.d_leaf2f, sys, nt,
                      (const float*)T.G, (const float*)f.Ut, (const float*)f.Vt, (const float*)f.lam,
                      (const float*)T.dY, T.Y /* unused */, T.gu, T.gv, 0);
@@ -405,15 +494,18 @@ static hp_status loss_bwd_t(Batch& b, const float* sys, const hp_factor_set& f, 
   return HP_OK;
 }
 
+// With the SAI loss the apply's input is Z itself (Y = M Z), not X = A Z.
 hp_status loss_fwd(Batch& b, const float* sys, const hp_factor_set& f, const float* X, const float* Z, double scale) {
-  if (b.cfg.leaf == 64) return loss_fwd_t<64, 16>(b, sys, f, X, Z, scale);
-  return loss_fwd_t<32, 8>(b, sys, f, X, Z, scale);
+  const float* Xa = b.loss_kind == 1 ? Z : X;
+  if (b.cfg.leaf == 64) return loss_fwd_t<64, 16>(b, sys, f, Xa, Z, scale);
+  return loss_fwd_t<32, 8>(b, sys, f, Xa, Z, scale);
 }
 
 hp_status loss_bwd(Batch& b, const float* sys, const hp_factor_set& f, const float* X, const float* Z,
                    const hp_factor_set& g) {
-  if (b.cfg.leaf == 64) return loss_bwd_t<64, 16>(b, sys, f, X, Z, g);
-  return loss_bwd_t<32, 8>(b, sys, f, X, Z, g);
+  const float* Xa = b.loss_kind == 1 ? Z : X;
+  if (b.cfg.leaf == 64) return loss_bwd_t<64, 16>(b, sys, f, Xa, Z, g);
+  return loss_bwd_t<32, 8>(b, sys, f, Xa, Z, g);
 }
 
 hp_status probes(Batch& b, const float* sys, const float* zraw, float* z, float* x, int sweeps, float omega) {

@@ -99,10 +99,12 @@ SEED_BASE = {"train4096": 3_000_000, "precision8192": 5_000_000, "largest16384":
 def train(cfg=inputs.MODEL_DEFAULT, steps: int = 2000, mix=(("train4096", 32),), lr: float = 2e-4,
           compute: int = hp.HP_BF16, init_seed: int = 7, log_every: int = 20, val_every: int = 200,
           val: Optional[Dict[str, List[int]]] = None, init: Optional[Dict[str, np.ndarray]] = None,
-          plateau: bool = True, warmup: int = 0, log=print) -> Dict:
+          plateau: bool = True, warmup: int = 0, first_batch: int = 0, loss: str = "cos", log=print) -> Dict:
     """Train for `steps` steps; step s draws a fresh batch of mix[s % len(mix)]
     = (recipe, systems per batch) with seeds SEED_BASE[recipe] + batch * k + i
-    (k counts that recipe's batches)."""
+    (k counts that recipe's batches, from first_batch: a run that continues an
+    earlier one starts past the batches it drew).  loss: "cos" (the
+    cosine-Hutchinson loss) or "sai" (the SAI-style loss of the ablation)."""
     import torch
     trainers = []
     for recipe, batch in mix:
@@ -110,8 +112,11 @@ def train(cfg=inputs.MODEL_DEFAULT, steps: int = 2000, mix=(("train4096", 32),),
         if len(rc.grids) != 1:
             raise ValueError("training batches use one grid shape per recipe")
         B = hp.Batch(cfg, [rc.grids[0]] * batch)
+        if loss == "sai":
+            B.debug_set("sai_loss", 1)
         trainers.append({"recipe": recipe, "rc": rc, "batch": batch, "B": B, "sys": B.new_sys(),
-                         "perm": hp.morton_order(*rc.grids[0]), "n": int(np.prod(rc.grids[0])), "count": 0})
+                         "perm": hp.morton_order(*rc.grids[0]), "n": int(np.prod(rc.grids[0])),
+                         "count": first_batch})
     w0 = init if init is not None else inputs.init_weights(cfg, init_seed)
     flat = torch.tensor(hp.pack_weights(cfg, w0), device="cuda")
     grad, m, v = torch.zeros_like(flat), torch.zeros_like(flat), torch.zeros_like(flat)
@@ -180,6 +185,10 @@ def main(argv=None) -> int:
     ap.add_argument("--val", default="train4096:3900",
                     help="comma-separated recipe:first_seed validation sets of 20 frames each")
     ap.add_argument("--init", default=None, help="start from these weights (npz)")
+    ap.add_argument("--loss", default="cos", choices=("cos", "sai"),
+                    help="cos: the cosine-Hutchinson loss; sai: the SAI-style loss of the loss ablation")
+    ap.add_argument("--first-batch", type=int, default=0,
+                    help="index of each recipe's first training batch (past those an earlier run drew)")
     ap.add_argument("--out", default=None, help="write the trained weights here (npz)")
     ap.add_argument("--history", default=None, help="write the loss/validation history here (json)")
     a = ap.parse_args(argv)
@@ -193,6 +202,7 @@ def main(argv=None) -> int:
     log_every = a.log_every if a.log_every > 0 else 20 * len(mix)
     r = train(cfg, steps=a.steps, mix=mix, lr=a.lr, compute=hp.HP_F32 if a.fp32 else hp.HP_BF16,
               plateau=not a.no_plateau, val_every=a.val_every, val=val, init=init, warmup=a.warmup,
+              first_batch=a.first_batch, loss=a.loss,
               log_every=log_every,
               log=lambda s: print(s, flush=True))
     if a.out:

@@ -131,24 +131,46 @@ def _levels(K):
 # streams stay FP32, so rounding errors add up over the 2 + 2 x 4 sublayers of
 # the diagonal stack rather than compound: ~10 roundings of ~2e-3 with random
 # signs give ~1e-2 on the streams, and the heads' outputs inherit it
-# (measured 2e-3 to 4.4e-3).  B_m = U_m V_m^T sums L_s products whose terms
-# partly cancel, so its error is measured, per partition level (a defect on
-# one level cannot hide behind another level's larger values), against the
-# magnitude of what it sums, max (|U_m| |V_m|^T), the scale of a rounded dot
-# product's error.  Measured per level, finest first: 5.3e-3, 4.7e-3, 5.0e-3,
-# 9.9e-3, 1.8e-2, 1.2e-2, 3.3e-2.  The error grows with the level because a
-# level-j token pools means over 4 * 2^j rows: the mean is much smaller than
-# its terms, whose BF16-rounded parts do not average out.  A level built from
-# the wrong strips or a transposed coupling would read O(1).
-TRAINED_BF16_BOUND = {"xd": 1.5e-2, "G": 1.5e-2, "B": 5e-2, "Ut": 1.5e-2, "Vt": 1.5e-2, "lam": 1e-2,
-                      "Mr": 1e-2}
+# (measured 2e-3 to 5.8e-3).
+TRAINED_BF16_BOUND = {"xd": 1.5e-2, "G": 1.5e-2, "Ut": 1.5e-2, "Vt": 1.5e-2, "lam": 1e-2, "Mr": 1e-2}
 
 
-def test_trained_bf16_inference_matches_oracle_at_benchmark_frame():
+def _bf16_gemm_forward(cfg, s, f, w, monkeypatch):
+    """The float64 oracle forward with the inputs of every dense layer rounded
+    to BF16 (round to nearest even) and everything else exact: the error that
+    the BF16 GEMM operands alone explain."""
+    import torch
+    rb = lambda a: a.to(torch.bfloat16).to(torch.float64)
+    with monkeypatch.context() as m:
+        m.setattr(network, "_lin", lambda x, ww, name: rb(x) @ rb(ww[name + ".w"]) + ww[name + ".b"])
+        return _oracle(cfg, s, f, w)
+
+
+def _b_level_errors(K, B, Bo, U, V):
+    """Max |B - Bo| per partition level over max (|U_m| |V_m|^T) of that level,
+    the scale of a rounded dot product's error: a level is judged on its own,
+    so a defect on one level cannot hide behind another level's larger
+    values."""
+    absprod = np.abs(U) @ np.abs(V).transpose(0, 2, 1)
+    return {j: float(np.abs(B[a:b] - Bo[a:b]).max() / absprod[a:b].max()) for j, a, b in _levels(K)}
+
+
+def test_trained_bf16_inference_matches_oracle_at_benchmark_frame(monkeypatch):
     """The benchmarked configuration tensor by tensor: trained weights, BF16
     inference on the first frame of the precision workload, every factor of M
     against the float64 oracle forward with the same weights, and the action
-    M r of the two factor sets on a random vector."""
+    M r of the two factor sets on a random vector.
+
+    B_m = U_m V_m^T sums L_s products whose terms partly cancel, and its
+    coarse levels come from tokens pooled over 4 * 2^j rows whose means are
+    much smaller than their terms; how much BF16 operands cost there depends
+    on the weights (0.033 at the top level for one training run, 0.059 for
+    the same run continued).  So B's bound per level is twice the error of the
+    oracle forward with BF16-rounded dense-layer operands at that level (plus
+    2e-3 for the roundings that emulation leaves out: attention products,
+    normalisation statistics, the order of sums).  Measured, GPU against that
+    emulation, finest level first: 3.1e-3/2.3e-3 ... 5.9e-2/6.0e-2.  A level
+    built from the wrong strips or a transposed coupling reads O(1)."""
     import os
     import torch
     cfg = DEF
@@ -165,10 +187,9 @@ def test_trained_bf16_inference_matches_oracle_at_benchmark_frame():
     errs = {"xd": relerr(_dbg(s, "xd", (n, d)), tr[f"ffn{cfg.layers - 1}"][0].detach().numpy()),
             "G": relerr(G, Go), "Ut": relerr(Ut, o["Ut"]), "Vt": relerr(Vt, o["Vt"]), "lam": relerr(lam, o["lam"])}
     K = n // cfg.leaf
-    absprod = np.abs(o["U"]) @ np.abs(o["V"]).transpose(0, 2, 1)
-    lev = {j: float(np.abs(B[a:b] - Bo[a:b]).max() / absprod[a:b].max()) for j, a, b in _levels(K)}
-    errs["B"] = max(lev.values())
-    errs_rel = {j: relerr(B[a:b], Bo[a:b]) for j, a, b in _levels(K)}
+    lev = _b_level_errors(K, B, Bo, o["U"], o["V"])
+    e = _bf16_gemm_forward(cfg, s, 0, w, monkeypatch)
+    lev_emul = _b_level_errors(K, hmatrix.coupling(e["U"], e["V"]), Bo, o["U"], o["V"])
     rng = np.random.default_rng(5)
     r = rng.standard_normal(n)
     dA = s.A[0].diagonal()
@@ -176,10 +197,12 @@ def test_trained_bf16_inference_matches_oracle_at_benchmark_frame():
     Mro = hmatrix.apply(s.parts[0], Go, Bo, o["Ut"], o["Vt"], o["lam"], dA, r)
     errs["Mr"] = float(np.linalg.norm(Mr - Mro) / np.linalg.norm(Mro))
     print("trained bf16 vs fp64 oracle", {k: f"{v:.2e}" for k, v in errs.items()},
-          "B per level (vs max |U||V|^T)", {j: f"{v:.1e}" for j, v in lev.items()},
-          "(vs max |B|)", {j: f"{v:.1e}" for j, v in errs_rel.items()})
+          "B per level (vs max |U||V|^T), GPU / BF16-operand oracle",
+          {j: f"{v:.1e}/{lev_emul[j]:.1e}" for j, v in lev.items()})
     for k, v in errs.items():
         assert v <= TRAINED_BF16_BOUND[k], (k, v)
+    for j, v in lev.items():
+        assert v <= 2 * lev_emul[j] + 2e-3, ("B level", j, v, lev_emul[j])
 
 
 def test_bf16_factors_precondition_like_fp32():

@@ -4,6 +4,8 @@ the float64 autograd oracle (itself pinned by finite differences), and the
 AdamW step against the oracle optimiser."""
 import math
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -54,7 +56,12 @@ def _oracle(cfg, s, w, zraw):
 
 @pytest.mark.parametrize("cfg,recipes", [(PLAIN, [("plain1024", 1000), ("plain1024", 1001)]),
                                          (DEF, [("train4096", 3000000)]),
-                                         (DEF, [("batch_mixed", 4001), ("train4096", 3000001)])])
+                                         (DEF, [("batch_mixed", 4001), ("train4096", 3000001)]),
+                                         # the ablation variants' reverse passes
+                                         (dataclasses.replace(DEF, layers=2, highways=False),
+                                          [("train4096", 3000002)]),
+                                         (dataclasses.replace(DEF, layers=1, offdiag=False),
+                                          [("train4096", 3000003)])])
 def test_weight_gradient_fp32_matches_oracle(cfg, recipes):
     import torch
     s, w, flat, zraw, zr = _setup(cfg, recipes)
@@ -179,3 +186,31 @@ def test_weight_gradient_matches_central_differences():
         print(f"direction {trial}: CD(h) {d1:.6e}  CD(h/2) {d2:.6e}  extrapolated {fd:.6e}  gradient {an:.6e}")
         # FP32 forward noise (~1e-7 of the loss) over h, plus O(h^4) truncation
         assert abs(fd - an) <= 1e-4 * np.linalg.norm(g) + 2e-3 * abs(an)
+
+
+@pytest.mark.parametrize("cfg,recipes", [(PLAIN, [("plain1024", 1000), ("plain1024", 1001)]),
+                                         (DEF, [("train4096", 3000000)])])
+def test_sai_loss_gradient_fp32_matches_oracle(cfg, recipes):
+    """The SAI-style loss of the loss ablation (|| A M Z / ||A|| - Z ||_F^2,
+    Prop. 1(3)): the FP32 loss and weight gradient of hp_train_grad with the
+    "sai_loss" switch against the float64 oracle's."""
+    import torch
+    s, w, flat, zraw, zr = _setup(cfg, recipes)
+    s.B.debug_set("sai_loss", 1)
+    grad = torch.zeros_like(flat)
+    L = s.B.train_grad(flat, s.rho, s.sys, zr, grad, hp.HP_F32)
+    probes = [oloss.smooth_probes(fs.A, z) for fs, z in zip(s.fs, zraw)]
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        Lo, go = oloss.loss_and_grad(cfg, w, s.fs, probes, kind="sai")
+    gg = _unflatten(cfg, grad)
+    tot = math.sqrt(sum(float((v ** 2).sum()) for v in go.values()))
+    diff = math.sqrt(sum(float(((gg[k] - go[k]) ** 2).sum()) for k in go))
+    print(f"sai loss gpu {L:.8f} oracle {Lo:.8f}  |g| {tot:.3e}  rel {diff / tot:.2e}")
+    assert abs(L - Lo) <= 2e-5 * max(1.0, abs(Lo))
+    assert diff <= 2e-4 * tot
+    # the cosine objective on the same batch differs (the switch takes effect)
+    s.B.debug_set("sai_loss", 0)
+    Lc = s.B.train_grad(flat, s.rho, s.sys, zr, grad, hp.HP_F32)
+    assert abs(Lc - L) > 1e-3 * abs(L)

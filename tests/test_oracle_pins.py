@@ -194,3 +194,39 @@ def test_edge_descriptor_sign_hand_pair():
     a1 = -0.4 / math.sqrt(1.6 * 3.4)
     a2 = -1.0 / math.sqrt(3.4 * 4.0)
     assert abs(fs.desc_off[0, 0, 0, 3] - (a1 + a2) / 16) < 1e-15
+
+
+def test_sai_ablation_loss_pins():
+    """The SAI-style loss of the loss ablation (Prop. 1(3)), || A M Z / ||A|| - Z ||_F^2
+    with ||A|| read as the largest absolute row sum: that scale equals the
+    brute-force row sums and bounds the spectral norm; M = ||A|| A^-1 gives
+    exactly zero; the loss is not invariant under M -> alpha M, and its minimum
+    over scalings sits at the closed form beta* = <Z, W> / ||W||^2 (W = A M Z / ||A||)."""
+    import warnings
+    from oracle import grid, loss
+    from paper_2605_13343_amd import inputs
+    fr = inputs.make_frame_grid(4, 4, 4, 3)
+    A = grid.assemble(fr.nx, fr.ny, fr.nz, fr.rho)
+    Ad = A.toarray()
+    s = loss.sai_scale(A)
+    assert s == max(sum(abs(Ad[i, j]) for j in range(fr.n)) for i in range(fr.n))
+    assert s >= np.linalg.norm(Ad, 2) - 1e-12
+    rng = np.random.default_rng(4)
+    Z = np.where(rng.random((fr.n, 3)) < 0.5, -1.0, 1.0)
+    Minv = s * np.linalg.inv(Ad)
+    assert loss.sai_train_loss(A, Z, Minv @ Z) <= 1e-20 * (Z * Z).sum()
+    M = np.diag(1.0 / np.diag(Ad))  # Jacobi as a stand-in M
+    L1 = loss.sai_train_loss(A, Z, M @ Z)
+    assert abs(loss.sai_train_loss(A, Z, 2.0 * M @ Z) - L1) > 1e-3 * L1
+    W = (A @ (M @ Z)) / s
+    beta = float((Z * W).sum() / (W * W).sum())
+    Lb = loss.sai_train_loss(A, Z, beta * M @ Z)
+    for db in (-1e-3, 1e-3, -0.1, 0.1):
+        assert Lb <= loss.sai_train_loss(A, Z, (beta + db) * M @ Z)
+    assert abs(Lb - (Z * Z).sum() * (1.0 - (Z * W).sum() ** 2 / ((Z * Z).sum() * (W * W).sum()))) <= 1e-9 * L1
+    # the torch form (autograd in the oracle's gradient) equals the numpy form
+    import torch
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        Lt = float(loss.sai_train_loss(A, Z, torch.as_tensor(M @ Z)))
+    assert abs(Lt - L1) <= 1e-12 * L1
