@@ -40,15 +40,21 @@ def cell_xyz(nx: int, ny: int, nz: int, lex: np.ndarray) -> np.ndarray:
     return np.stack([lex % nx, (lex // nx) % ny, lex // (nx * ny)], axis=-1)
 
 
-def assemble_lex(nx: int, ny: int, nz: int, rho: np.ndarray) -> sp.csr_matrix:
-    """Cell-centred 7-point variable-coefficient Poisson operator in
-    lexicographic order.
+def assemble_lex(nx: int, ny: int, nz: int, rho: np.ndarray, neumann: bool = False) -> sp.csr_matrix:
+    """Cell-centred variable-coefficient Poisson operator (7-point; 5-point
+    when nz = 1) in lexicographic order, spacing h = 1.
 
     Paper, Sec. 7.1 / Supplementary "Operator assembly": A_ii = sum_j w_ij,
-    A_ij = -w_ij over cell-cell faces.  Face weight w_ij = 2/(rho_i+rho_j),
-    the harmonic mean of 1/rho.  Zero-flux boundaries everywhere except the
-    top face (z = nz-1), which carries p = 0 through a ghost cell one spacing
-    away: A_ii += 1/rho_i.  Spacing h = 1.
+    A_ij = -w_ij over cell-cell faces.
+
+    neumann=False (the 3D workload): face weight w_ij = 2/(rho_i+rho_j), the
+    harmonic mean of 1/rho; zero flux on every face except the top (z = nz-1),
+    which carries p = 0 through a ghost cell one spacing away: A_ii += 1/rho_i.
+
+    neumann=True (the paper's benchmark operator as printed): face weight
+    w_ij = 2 rho_i rho_j/(rho_i+rho_j), the harmonic mean of rho, and zero
+    flux on every boundary face, so A 1 = 0 (A is singular; the paper leaves
+    the constant mode to CG with a consistent right-hand side).
     """
     n = nx * ny * nz
     rows, cols, vals = [], [], []
@@ -66,13 +72,16 @@ def assemble_lex(nx: int, ny: int, nz: int, rho: np.ndarray) -> sp.csr_matrix:
                     if xx >= nx or yy >= ny or zz >= nz:
                         continue
                     j = lid(xx, yy, zz)
-                    w = 2.0 / (rho[i] + rho[j])
+                    if neumann:
+                        w = 2.0 * rho[i] * rho[j] / (rho[i] + rho[j])
+                    else:
+                        w = 2.0 / (rho[i] + rho[j])
                     rows += [i, j]
                     cols += [j, i]
                     vals += [-w, -w]
                     diag[i] += w
                     diag[j] += w
-                if z == nz - 1:
+                if z == nz - 1 and not neumann:
                     diag[i] += 1.0 / rho[i]
     rows += list(range(n))
     cols += list(range(n))
@@ -80,16 +89,16 @@ def assemble_lex(nx: int, ny: int, nz: int, rho: np.ndarray) -> sp.csr_matrix:
     return sp.csr_matrix((np.array(vals), (np.array(rows), np.array(cols))), shape=(n, n))
 
 
-def assemble(nx: int, ny: int, nz: int, rho_lex: np.ndarray) -> sp.csr_matrix:
+def assemble(nx: int, ny: int, nz: int, rho_lex: np.ndarray, neumann: bool = False) -> sp.csr_matrix:
     """The operator in Morton order: A_m = P A P^T with P the Morton perm."""
     perm = morton_perm(nx, ny, nz)
-    A = assemble_lex(nx, ny, nz, rho_lex)
+    A = assemble_lex(nx, ny, nz, rho_lex, neumann)
     Am = A[perm][:, perm].tocsr()
     Am.sort_indices()
     return Am
 
 
-def features(nx: int, ny: int, nz: int, rho_lex: np.ndarray) -> np.ndarray:
+def features(nx: int, ny: int, nz: int, rho_lex: np.ndarray, neumann: bool = False) -> np.ndarray:
     """Per-node encoder input [N, 20] in Morton order.
 
     The paper (Sec. 4.1, Supplementary "Encoder") lists density, position and
@@ -102,11 +111,13 @@ def features(nx: int, ny: int, nz: int, rho_lex: np.ndarray) -> np.ndarray:
               heavy fraction (log rho above the mid-point of its range),
               mean/std/min/max of log A_ii, nx/32, ny/32, nz/32
     Standard deviations are population (divide by N).  Pressure is absent:
-    the frames have no previous time step.
+    the frames have no previous time step.  The flags are geometric: on a 2D
+    grid (nz = 1) every cell is both top and bottom layer.  A_ii comes from
+    the operator the frame uses (neumann, as in assemble_lex).
     """
     n = nx * ny * nz
     perm = morton_perm(nx, ny, nz)
-    A = assemble_lex(nx, ny, nz, rho_lex)
+    A = assemble_lex(nx, ny, nz, rho_lex, neumann)
     dA = A.diagonal()
     xyz = cell_xyz(nx, ny, nz, np.arange(n))
     x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]

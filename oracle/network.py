@@ -70,12 +70,13 @@ class FrameSys:
     """Fixed per-frame inputs of the network: operator, features, geometry,
     partition, and the two edge-descriptor tables."""
 
-    def __init__(self, nx: int, ny: int, nz: int, rho_lex: np.ndarray, leaf: int, rank: int):
+    def __init__(self, nx: int, ny: int, nz: int, rho_lex: np.ndarray, leaf: int, rank: int,
+                 neumann: bool = False):
         self.nx, self.ny, self.nz = nx, ny, nz
         self.n = nx * ny * nz
-        self.A = grid.assemble(nx, ny, nz, rho_lex)
+        self.A = grid.assemble(nx, ny, nz, rho_lex, neumann)
         self.diagA = self.A.diagonal().copy()
-        self.feats = grid.features(nx, ny, nz, rho_lex)
+        self.feats = grid.features(nx, ny, nz, rho_lex, neumann)
         self.pos = grid.positions(nx, ny, nz)
         self.part = partition.build(self.n, leaf, rank)
         self._descriptors()

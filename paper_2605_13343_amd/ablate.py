@@ -93,10 +93,10 @@ def main(argv=None) -> int:
                "final_loss": r["history"]["loss"][-1], "n8192": m8, "n4096": m4}
         print(json.dumps(rec), flush=True)
         out["variants"].append(rec)
-    if a.out:
-        os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
-        with open(a.out, "w") as f:
-            json.dump(out, f, indent=1)
+        if a.out:  # after every variant, so a long run keeps what it finished
+            os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+            with open(a.out, "w") as f:
+                json.dump(out, f, indent=1)
     return 0
 
 

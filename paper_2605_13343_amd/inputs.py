@@ -12,6 +12,11 @@ cell-centred grid: a light background density rho=1 with heavy inclusions
 (seeded spheres, optionally a heavy bottom layer) and a uniform right-hand
 side.  All grid arrays are in lexicographic cell order, id = x + nx*(y + ny*z),
 with z the vertical axis (z = nz-1 is the top layer).
+
+The paper's own benchmark (Sec. 7.1 "Benchmark"; Supplementary "Multiphase
+Poisson Benchmark Generation") is drawn by the "paper2d_<N>" recipes: a 2D grid
+(nz = 1) whose heavy cells are 1-3 rectangular barriers with gaps, density
+noise, zero flux on every face and a mean-zero Gaussian right-hand side.
 """
 from __future__ import annotations
 
@@ -43,7 +48,7 @@ GRID_OF_N = {
     16384: (32, 32, 16),
 }
 
-RECIPES: Dict[str, FrameRecipe] = {
+RECIPES: Dict[str, "FrameRecipe | BarrierRecipe"] = {
     # N=1,024, 3 spheres at 100:1
     "plain1024": FrameRecipe(grids=(GRID_OF_N[1024],), spheres=(3, 3), contrast=(100.0, 100.0)),
     # N=8,192, 8 spheres at 100:1
@@ -59,24 +64,87 @@ RECIPES: Dict[str, FrameRecipe] = {
 }
 
 
+@dataclasses.dataclass(frozen=True)
+class BarrierRecipe:
+    """The paper's 2D frames (Supplementary "Multiphase Poisson Benchmark
+    Generation"): rho_heavy log-uniform in `contrast`, rho_light = 1, 1-3
+    barriers, each a band across the whole domain (vertical or horizontal,
+    equally likely) with its centre uniform in [0.2, 0.8] and its thickness
+    uniform in [0.05, 0.20] along the cross axis (unit-square coordinates),
+    and one of four gap topologies: a gap at the high end of the band ("top"),
+    at the low end ("bottom"), in its middle ("middle_hole"), or none
+    ("closed").  A cell is heavy if any band covers it.  Every density is
+    then multiplied by 1 + N(0, 0.05^2).  b ~ N(0, I) minus its mean."""
+    grid: Tuple[int, int]                     # (W, H) = (nx, ny); nz = 1
+    contrast: Tuple[float, float] = (5.0, 100.0)
+    barriers: Tuple[int, int] = (1, 3)
+    centre: Tuple[float, float] = (0.2, 0.8)
+    thickness: Tuple[float, float] = (0.05, 0.20)
+    gap: float = 0.2                          # gap length, fraction of the band's length
+    noise: float = 0.05
+
+
+GAP_TOPOLOGIES = ("top", "bottom", "middle_hole", "closed")
+
+# W x H: powers of two, as close to square as powers of two allow, so that
+# W * H = N and the Morton truncation to the first N cells keeps every cell.
+GRID2D_OF_N = {1024: (32, 32), 2048: (64, 32), 4096: (64, 64), 8192: (128, 64), 16384: (128, 128)}
+
+for _n, _wh in GRID2D_OF_N.items():
+    RECIPES[f"paper2d_{_n}"] = BarrierRecipe(grid=_wh)
+
+
 @dataclasses.dataclass
 class Frame:
     nx: int
     ny: int
     nz: int
     rho: np.ndarray   # float64 [N], lexicographic
-    b: np.ndarray     # float64 [N], lexicographic, uniform in [-1, 1)
+    b: np.ndarray     # float64 [N], lexicographic, uniform in [-1, 1) (mean-zero Gaussian for 2D barriers)
     seed: int
+    neumann: bool = False   # zero flux on every face, conductance the harmonic mean of rho (the paper's operator)
 
     @property
     def n(self) -> int:
         return self.nx * self.ny * self.nz
 
 
-def make_frame(recipe: str | FrameRecipe, seed: int) -> Frame:
-    """Draw one frame.  Draw order: grid, sphere count, contrast, spheres
-    (cx, cy, cz, r each), then b cell by cell."""
+def _make_barrier_frame(rc: BarrierRecipe, seed: int) -> Frame:
+    """Draw order: rho_heavy, barrier count, per barrier (orientation, centre,
+    thickness, gap topology), the density noise cell by cell, then b."""
+    rng = np.random.default_rng(seed)
+    nx, ny = rc.grid
+    heavy = float(np.exp(rng.uniform(np.log(rc.contrast[0]), np.log(rc.contrast[1]))))
+    nb = int(rng.integers(rc.barriers[0], rc.barriers[1] + 1))
+    y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    u, v = (x.ravel() + 0.5) / nx, (y.ravel() + 0.5) / ny      # unit-square cell centres
+    inside = np.zeros(nx * ny, dtype=bool)
+    for _ in range(nb):
+        vertical = bool(rng.integers(2))
+        c = float(rng.uniform(*rc.centre))
+        t = float(rng.uniform(*rc.thickness))
+        topo = GAP_TOPOLOGIES[int(rng.integers(len(GAP_TOPOLOGIES)))]
+        across, along = (u, v) if vertical else (v, u)
+        band = np.abs(across - c) <= 0.5 * t
+        if topo == "top":
+            band &= along < 1.0 - rc.gap
+        elif topo == "bottom":
+            band &= along >= rc.gap
+        elif topo == "middle_hole":
+            band &= np.abs(along - 0.5) >= 0.5 * rc.gap
+        inside |= band
+    rho = np.where(inside, heavy, 1.0) * (1.0 + rc.noise * rng.standard_normal(nx * ny))
+    b = rng.standard_normal(nx * ny)
+    b -= b.mean()
+    return Frame(nx=nx, ny=ny, nz=1, rho=rho.astype(np.float64), b=b, seed=seed, neumann=True)
+
+
+def make_frame(recipe: str | FrameRecipe | BarrierRecipe, seed: int) -> Frame:
+    """Draw one frame.  Sphere recipes draw, in order: grid, sphere count,
+    contrast, spheres (cx, cy, cz, r each), then b cell by cell."""
     rc = RECIPES[recipe] if isinstance(recipe, str) else recipe
+    if isinstance(rc, BarrierRecipe):
+        return _make_barrier_frame(rc, seed)
     rng = np.random.default_rng(seed)
     nx, ny, nz = rc.grids[int(rng.integers(len(rc.grids)))] if len(rc.grids) > 1 else rc.grids[0]
     ns = int(rng.integers(rc.spheres[0], rc.spheres[1] + 1))
