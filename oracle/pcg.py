@@ -52,7 +52,7 @@ def pcg(A, b: np.ndarray, M: Optional[Callable] = None, tol: float = 1e-6,
     p = z.copy()
     k, flags = 0, 0
     force = False
-    last_window = hist[0]
+    last_window = math.sqrt(r @ r)       # ||r_0||: the first window's reference
     while True:
         if k >= max_iter:
             flags = MAXITER

@@ -164,3 +164,19 @@ def test_fallback_on_stagnation_and_iteration_cap():
     x, it, fl, _ = pcg.solve_with_fallback(A, b, M, tol=1e-6, max_iter=120, stagnation=False)
     assert fl == pcg.MAXITER | pcg.FELL_BACK | pcg.CONVERGED and 120 < it <= 240
     assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) <= 1e-6
+
+
+@pytest.mark.parametrize("scale", [1e-3, 1.0, 1e3])
+def test_pcg_is_invariant_to_the_scale_of_b(scale):
+    """PCG is linear in b: scaling b by c scales every iterate and residual by
+    c, so iterations and flags (convergence, the stagnation windows, which
+    compare ||r_k|| with ||r_(k-100)||) do not depend on c.  A frame of the
+    paper's 2D benchmark with Jacobi to 1e-8 crosses the k = 100 window."""
+    fr = inputs.make_frame("paper2d_1024", 9100)
+    A = grid.assemble(fr.nx, fr.ny, fr.nz, fr.rho, neumann=True)
+    b = fr.b[grid.morton_perm(fr.nx, fr.ny, fr.nz)]
+    x1, k1, f1, _ = pcg.pcg(A, b, pcg.jacobi(A), tol=1e-8)
+    xs, ks, fs, _ = pcg.pcg(A, scale * b, pcg.jacobi(A), tol=1e-8)
+    assert k1 > 100 and f1 == pcg.CONVERGED
+    assert (ks, fs) == (k1, f1)
+    assert np.allclose(xs, scale * x1, rtol=1e-9, atol=1e-12 * scale * np.abs(x1).max())
