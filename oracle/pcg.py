@@ -20,6 +20,13 @@ Sec. 5 solve loop) with this build's run-time policy:
 The stagnation window and the Jacobi fallback (on any of NOT_SPD, STAGNATED,
 MAXITER) are this build's additions: the paper enforces no SPD property on M
 and has no fallback.
+
+fp32_vectors=True follows the paper's precision split (Sec. 6.3; Supplementary
+"Precision"): the vectors r, z, p and q are held in float32 (each computed in
+float64 from float32 operands and rounded once), while x, every inner product,
+norm and step size stay float64.  At tight tolerances the rounded vectors
+cost iterations (Krylov orthogonality decays sooner); the default is float64
+throughout.
 """
 from __future__ import annotations
 
@@ -33,12 +40,15 @@ CONVERGED, NOT_SPD, STAGNATED, MAXITER, FELL_BACK = 1, 2, 4, 8, 16
 
 def pcg(A, b: np.ndarray, M: Optional[Callable] = None, tol: float = 1e-6,
         max_iter: int = 10000, recompute_every: int = 25, x0: Optional[np.ndarray] = None,
-        stagnation: bool = True, bnorm: Optional[float] = None):
+        stagnation: bool = True, bnorm: Optional[float] = None, fp32_vectors: bool = False):
     """Returns (x, iterations, flags, relres history)."""
     b = np.asarray(b, dtype=np.float64)
-    Mf = (lambda r: r.copy()) if M is None else M
+    v = (lambda a: np.asarray(a, np.float64).astype(np.float32).astype(np.float64)) if fp32_vectors \
+        else (lambda a: a)
+    M0 = (lambda r: r.copy()) if M is None else M
+    Mf = lambda r: v(M0(r))
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
-    r = b - A @ x
+    r = v(b - A @ x)
     if bnorm is None:
         bnorm = float(np.sqrt(b @ b))
     target = tol * bnorm
@@ -57,14 +67,14 @@ def pcg(A, b: np.ndarray, M: Optional[Callable] = None, tol: float = 1e-6,
         if k >= max_iter:
             flags = MAXITER
             break
-        q = A @ p
+        q = v(A @ p)
         alpha = rho / float(p @ q)
         x = x + alpha * p
-        r = r - alpha * q
+        r = v(r - alpha * q)
         k += 1
         replaced = force or bool(recompute_every and k % recompute_every == 0)
         if replaced:
-            r = b - A @ x
+            r = v(b - A @ x)
         force = False
         rn = math.sqrt(float(r @ r))
         hist.append(rn / bnorm)
@@ -88,7 +98,7 @@ def pcg(A, b: np.ndarray, M: Optional[Callable] = None, tol: float = 1e-6,
             break
         beta = rho_new / rho
         rho = rho_new
-        p = z + beta * p
+        p = v(z + beta * p)
     return x, k, flags, hist
 
 
@@ -99,16 +109,17 @@ def jacobi(A) -> Callable:
 
 
 def solve_with_fallback(A, b, M: Callable, tol: float = 1e-6, max_iter: int = 10000,
-                        recompute_every: int = 25, stagnation: bool = True):
+                        recompute_every: int = 25, stagnation: bool = True, fp32_vectors: bool = False):
     """Learned-M PCG; a frame that did not converge (NOT_SPD, STAGNATED or
     MAXITER: positivity lost, less than a 2x drop of ||r|| over 100
     iterations, or the iteration cap) restarts as Jacobi-PCG warm-started from
     the current x, to the same target tol * ||b||, with the same cap and no
     stagnation check.  Iterations add up; the flags of both passes are kept."""
-    x, k, flags, hist = pcg(A, b, M, tol, max_iter, recompute_every, stagnation=stagnation)
+    x, k, flags, hist = pcg(A, b, M, tol, max_iter, recompute_every, stagnation=stagnation,
+                            fp32_vectors=fp32_vectors)
     if not flags & CONVERGED:
         bn = float(np.sqrt(b @ b))
         x, k2, f2, h2 = pcg(A, b, jacobi(A), tol, max_iter, recompute_every, x0=x,
-                            stagnation=False, bnorm=bn)
+                            stagnation=False, bnorm=bn, fp32_vectors=fp32_vectors)
         return x, k + k2, f2 | FELL_BACK | flags, hist + h2[1:]
     return x, k, flags, hist

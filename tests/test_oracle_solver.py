@@ -180,3 +180,25 @@ def test_pcg_is_invariant_to_the_scale_of_b(scale):
     assert k1 > 100 and f1 == pcg.CONVERGED
     assert (ks, fs) == (k1, f1)
     assert np.allclose(xs, scale * x1, rtol=1e-9, atol=1e-12 * scale * np.abs(x1).max())
+
+
+def test_fp32_vector_pcg_tracks_fp64_then_still_meets_the_true_residual():
+    """The precision split (float32 r, z, p, q; float64 x and scalars): the
+    first iterates equal the float64 ones to float32 accuracy (no residual
+    replacement), and a full solve still stops on a float64 true residual
+    below the target, in at most a few more iterations."""
+    fr = inputs.make_frame("paper2d_1024", 9100)
+    A = grid.assemble(fr.nx, fr.ny, fr.nz, fr.rho, neumann=True)
+    b = fr.b[grid.morton_perm(fr.nx, fr.ny, fr.nz)]
+    M = pcg.jacobi(A)
+    for k in (1, 3, 10):
+        x64, _, _, _ = pcg.pcg(A, b, M, tol=0.0, max_iter=k, recompute_every=0, stagnation=False)
+        x32, _, _, _ = pcg.pcg(A, b, M, tol=0.0, max_iter=k, recompute_every=0, stagnation=False,
+                               fp32_vectors=True)
+        assert np.linalg.norm(x32 - x64) / np.linalg.norm(x64) <= 4 * k * 2.0 ** -24, k
+        assert not np.array_equal(x32, x64)        # the rounding does act
+    x64, k64, f64, _ = pcg.pcg(A, b, None, tol=1e-8, max_iter=5000, stagnation=False)
+    x32, k32, f32_, _ = pcg.pcg(A, b, None, tol=1e-8, max_iter=5000, stagnation=False, fp32_vectors=True)
+    assert f64 == f32_ == pcg.CONVERGED
+    assert np.linalg.norm(b - A @ x32) <= 1e-8 * np.linalg.norm(b)
+    assert k64 <= k32 <= 1.2 * k64
