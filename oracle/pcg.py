@@ -21,12 +21,15 @@ The stagnation window and the Jacobi fallback (on any of NOT_SPD, STAGNATED,
 MAXITER) are this build's additions: the paper enforces no SPD property on M
 and has no fallback.
 
-fp32_vectors=True follows the paper's precision split (Sec. 6.3; Supplementary
-"Precision"): the vectors r, z, p and q are held in float32 (each computed in
-float64 from float32 operands and rounded once), while x, every inner product,
-norm and step size stay float64.  At tight tolerances the rounded vectors
-cost iterations (Krylov orthogonality decays sooner); the default is float64
-throughout.
+fp32_iteration=True follows the paper's precision split (Sec. 6.3;
+Supplementary "Precision"): the iteration's operator and vectors are float32
+and only its scalars float64.  q = A p uses A with every entry rounded to
+float32; r, z, p and q are held in float32 (each computed in float64 from
+float32 operands and rounded once); x, every inner product, norm and step
+size stay float64, and the replaced (true) residual b - A x uses the float64
+operator.  At tight tolerances the split costs iterations, mostly through
+the rounded operator: the recurrence follows A rounded to float32 while the
+stop is judged on the float64 A.  The default is float64 throughout.
 """
 from __future__ import annotations
 
@@ -34,17 +37,25 @@ import math
 from typing import Callable, Optional
 
 import numpy as np
+import scipy.sparse as sp
 
 CONVERGED, NOT_SPD, STAGNATED, MAXITER, FELL_BACK = 1, 2, 4, 8, 16
 
 
 def pcg(A, b: np.ndarray, M: Optional[Callable] = None, tol: float = 1e-6,
         max_iter: int = 10000, recompute_every: int = 25, x0: Optional[np.ndarray] = None,
-        stagnation: bool = True, bnorm: Optional[float] = None, fp32_vectors: bool = False):
+        stagnation: bool = True, bnorm: Optional[float] = None, fp32_iteration: bool = False):
     """Returns (x, iterations, flags, relres history)."""
     b = np.asarray(b, dtype=np.float64)
-    v = (lambda a: np.asarray(a, np.float64).astype(np.float32).astype(np.float64)) if fp32_vectors \
+    v = (lambda a: np.asarray(a, np.float64).astype(np.float32).astype(np.float64)) if fp32_iteration \
         else (lambda a: a)
+    Aq = A
+    if fp32_iteration:
+        if sp.issparse(A):
+            Aq = A.copy()
+            Aq.data = Aq.data.astype(np.float32).astype(np.float64)
+        else:
+            Aq = np.asarray(A, np.float64).astype(np.float32).astype(np.float64)
     M0 = (lambda r: r.copy()) if M is None else M
     Mf = lambda r: v(M0(r))
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
@@ -67,7 +78,7 @@ def pcg(A, b: np.ndarray, M: Optional[Callable] = None, tol: float = 1e-6,
         if k >= max_iter:
             flags = MAXITER
             break
-        q = v(A @ p)
+        q = v(Aq @ p)
         alpha = rho / float(p @ q)
         x = x + alpha * p
         r = v(r - alpha * q)
@@ -109,17 +120,17 @@ def jacobi(A) -> Callable:
 
 
 def solve_with_fallback(A, b, M: Callable, tol: float = 1e-6, max_iter: int = 10000,
-                        recompute_every: int = 25, stagnation: bool = True, fp32_vectors: bool = False):
+                        recompute_every: int = 25, stagnation: bool = True, fp32_iteration: bool = False):
     """Learned-M PCG; a frame that did not converge (NOT_SPD, STAGNATED or
     MAXITER: positivity lost, less than a 2x drop of ||r|| over 100
     iterations, or the iteration cap) restarts as Jacobi-PCG warm-started from
     the current x, to the same target tol * ||b||, with the same cap and no
     stagnation check.  Iterations add up; the flags of both passes are kept."""
     x, k, flags, hist = pcg(A, b, M, tol, max_iter, recompute_every, stagnation=stagnation,
-                            fp32_vectors=fp32_vectors)
+                            fp32_iteration=fp32_iteration)
     if not flags & CONVERGED:
         bn = float(np.sqrt(b @ b))
         x, k2, f2, h2 = pcg(A, b, jacobi(A), tol, max_iter, recompute_every, x0=x,
-                            stagnation=False, bnorm=bn, fp32_vectors=fp32_vectors)
+                            stagnation=False, bnorm=bn, fp32_iteration=fp32_iteration)
         return x, k + k2, f2 | FELL_BACK | flags, hist + h2[1:]
     return x, k, flags, hist

@@ -194,11 +194,11 @@ def test_fp32_vector_pcg_tracks_fp64_then_still_meets_the_true_residual():
     for k in (1, 3, 10):
         x64, _, _, _ = pcg.pcg(A, b, M, tol=0.0, max_iter=k, recompute_every=0, stagnation=False)
         x32, _, _, _ = pcg.pcg(A, b, M, tol=0.0, max_iter=k, recompute_every=0, stagnation=False,
-                               fp32_vectors=True)
+                               fp32_iteration=True)
         assert np.linalg.norm(x32 - x64) / np.linalg.norm(x64) <= 4 * k * 2.0 ** -24, k
         assert not np.array_equal(x32, x64)        # the rounding does act
     x64, k64, f64, _ = pcg.pcg(A, b, None, tol=1e-8, max_iter=5000, stagnation=False)
-    x32, k32, f32_, _ = pcg.pcg(A, b, None, tol=1e-8, max_iter=5000, stagnation=False, fp32_vectors=True)
+    x32, k32, f32_, _ = pcg.pcg(A, b, None, tol=1e-8, max_iter=5000, stagnation=False, fp32_iteration=True)
     assert f64 == f32_ == pcg.CONVERGED
     assert np.linalg.norm(b - A @ x32) <= 1e-8 * np.linalg.norm(b)
     assert k64 <= k32 <= 1.2 * k64
