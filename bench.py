@@ -22,6 +22,9 @@ JSON line carries these legs:
   * streaming: SpMV and the single-right-hand-side apply on batches whose
     algorithmic working set exceeds 1 GB (the precision frames replicated),
     in GB/s of algorithmic bytes;
+  * the paper's own 2D benchmark at its five scales and rtol 1e-8: CG,
+    Jacobi-PCG and the method with 2D-trained weights, ms/frame and
+    iterations (the setting of the paper's Table 4);
   * cpu_baseline: the float64 oracle as it stands on the 20 headline frames,
     which also gives each GPU leg's solution error against the oracle.
 
@@ -47,9 +50,9 @@ PEAK_HBM_GBS = 8000.0    # MI355X HBM3E, published
 PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 MFMA, published
 
 
-def _weights(cfg):
+def _weights(cfg, name=None):
     from paper_2605_13343_amd import inputs
-    path = os.path.join(ROOT, "paper_2605_13343_amd", "weights", f"trained_L{cfg.leaf}.npz")
+    path = os.path.join(ROOT, "paper_2605_13343_amd", "weights", name or f"trained_L{cfg.leaf}.npz")
     if os.path.exists(path):
         z = np.load(path, allow_pickle=False)
         return {k: z[k] for k in z.files}, "trained"
@@ -59,10 +62,11 @@ def _weights(cfg):
 class Inputs:
     """One batch of frames with its inputs resident in HBM."""
 
-    def __init__(self, cfg, frames, stream, batch=None):
+    def __init__(self, cfg, frames, stream, batch=None, ops=0):
         import torch
         from paper_2605_13343_amd import hp
         self.frames = frames
+        self.ops = ops
         self.dims = [(f.nx, f.ny, f.nz) for f in frames]
         cache = {}
         for d in self.dims:
@@ -75,7 +79,7 @@ class Inputs:
         self.b = torch.tensor(np.concatenate([f.b[p] for f, p in zip(frames, self.perms)]).astype(np.float32),
                               device="cuda")
         self.sys = self.B.new_sys()
-        self.B.assemble(self.rho, self.sys)
+        self.B.assemble(self.rho, self.sys, ops)
         self.x = torch.zeros(self.B.ntot, dtype=torch.float64, device="cuda")
 
     def x_frames(self):
@@ -305,6 +309,7 @@ def main() -> int:
         legs["largest_16384"] = _largest_leg(cfg, wt, stream)
         legs["batching_64_mixed"] = _batching_leg(cfg, wt, stream)
         legs["streaming"] = _streaming_leg(cfg, frames, stream)
+        legs["paper2d_rtol1e-8"] = _paper2d_leg(cfg, stream)
 
     # ---------------------------------------------------------------- CPU oracle baseline
     cpu = None
@@ -455,6 +460,48 @@ def _largest_leg(cfg, wt, stream):
             "pcg_update_gbs": pr["update"]["achieved"], "pcg_update_us": pr["update"]["avg_launch_us"],
             "pcg_spmv_gbs": pr["spmv"]["achieved"], "pcg_spmv_us": pr["spmv"]["avg_launch_us"],
             "frames": len(frames), "n": 16384, "seeds": "5000..5019"}
+
+
+def _paper2d_leg(cfg, stream, scales=(1024, 2048, 4096, 8192, 16384)):
+    """The paper's own benchmark (Sec. 7.1, Table 4's setting): 20 test frames
+    per scale (seeds 21000..21019) of the 2D barrier generator, the zero-flux
+    operator, relative residual 1e-8.  Per scale: unpreconditioned CG and
+    Jacobi-PCG (no stagnation check; graph-replayed chunks) and the method
+    with the 2D-trained weights (BF16 inference and apply, the captured step,
+    fallback on).  ms/frame of batched solves over the 20 frames."""
+    import torch
+    from paper_2605_13343_amd import hp, inputs
+    w, kind = _weights(cfg, f"trained_paper2d_L{cfg.leaf}.npz")
+    wt = torch.tensor(hp.pack_weights(cfg, w), device="cuda")
+    out = {"weights": kind, "rtol": 1e-8, "frames_per_scale": 20, "seeds": "21000..21019"}
+    for n in scales:
+        frames = [inputs.make_frame(f"paper2d_{n}", 21000 + f) for f in range(20)]
+        I = Inputs(cfg, frames, stream, ops=hp.ASM_PAPER)
+        row = {}
+        for name, pc in (("cg", hp.PRECOND_NONE), ("jacobi", hp.PRECOND_JACOBI)):
+            def solve(k, pc=pc):
+                I.x.zero_()
+                return I.B.pcg_solve(I.sys, None, I.b, I.x, pc, tol=1e-8, max_iter=20000, stagnation=False,
+                                     use_graph=True)
+            solve(0)
+            res, _, ms = _timed(stream, solve, 2)
+            row[name] = {"ms_per_frame": round(ms / len(frames), 4), **_iter_stats(res),
+                         "converged": sum(1 for r in res if r[1] & hp.CONVERGED)}
+        fac = I.B.new_factors(hp.HP_BF16)
+        I.B.infer_factors(wt, I.rho, I.sys, fac, hp.HP_BF16)
+
+        def ours(k):
+            I.x.zero_()
+            return I.B.solve_step(wt, I.rho, I.sys, fac, I.b, I.x, hp.HP_BF16, tol=1e-8, max_iter=20000)
+        ours(0)
+        res, _, ms = _timed(stream, ours, 3)
+        row["ours_bf16"] = {"ms_per_frame": round(ms / len(frames), 4), **_iter_stats(res),
+                            "converged": sum(1 for r in res if r[1] & hp.CONVERGED),
+                            "fell_back": sum(1 for r in res if r[1] & hp.FELL_BACK),
+                            "max_true_relres": float(max(r[2] for r in res))}
+        out[str(n)] = row
+        del I, fac
+    return out
 
 
 def _batching_leg(cfg, wt, stream):

@@ -28,8 +28,11 @@
  * with N = nx ny nz unknowns in Morton order (bit b of x, y, z at bits 3b,
  * 3b+1, 3b+2).  The library requires power-of-two dims whose Morton codes are
  * exactly 0..N-1 (log2 nx, log2 ny in {log2 nz, log2 nz + 1}, nx >= ny), so a
- * cell's Morton code is its row index.  Leaves are the K = N / L contiguous
- * index ranges of length L (paper Sec. 4); K must be a power of two.
+ * cell's Morton code is its row index.  A one-layer grid (nz = 1, the
+ * paper's 2D benchmark) interleaves x and y only (bit b of x, y at bits 2b,
+ * 2b+1; ny <= nx <= 2 ny); its z faces are all boundary faces, so the 7-point
+ * stencil is the 5-point one.  Leaves are the K = N / L contiguous index
+ * ranges of length L (paper Sec. 4); K must be a power of two.
  *
  * Batch layout.  The frames of a batch are concatenated: frame f's nodes are
  * rows [n0_f, n0_f + N_f) of every per-node array, its leaves [k0_f, ...),
@@ -58,6 +61,10 @@ enum {
 
 enum { HP_F32 = 0, HP_BF16 = 1 };                  /* factor / compute precision */
 enum { HP_PRECOND_NONE = 0, HP_PRECOND_JACOBI = 1, HP_PRECOND_HMAT = 2 };
+enum {                                             /* hp_assemble_ops bits */
+  HP_ASM_NEUMANN = 1,         /* zero flux on every face (no Dirichlet top layer) */
+  HP_ASM_RHO_CONDUCTANCE = 2  /* face weight: harmonic mean of rho (else of 1/rho) */
+};
 enum {                                             /* per-frame solve flags */
   HP_CONVERGED = 1, HP_NOT_SPD = 2, HP_STAGNATED = 4, HP_MAXITER = 8, HP_FELL_BACK = 16
 };
@@ -140,6 +147,15 @@ hp_status hp_batch_offsets(hp_batch b, int64_t* n0, int64_t* k0, int64_t* m0);
  *                 boundary), likewise wy, wz.  Computed in FP64; the FP32
  *                 copies are rounded once. */
 hp_status hp_assemble(hp_batch b, const float* d_rho, float* d_sys);
+
+/* hp_assemble with the operator chosen by ops (HP_ASM_* bits; 0 is
+ * hp_assemble).  The paper's benchmark operator (Sec. 7.1 "Benchmark",
+ * Supplementary "Operator assembly") is HP_ASM_NEUMANN | HP_ASM_RHO_CONDUCTANCE:
+ * w_ij = 2 rho_i rho_j / (rho_i + rho_j) and zero flux on every boundary face,
+ * so A 1 = 0 and A is singular; PCG needs a right-hand side with zero sum
+ * (the paper leaves the constant mode to CG).  Same output layout;
+ * HP_E_INVALID for unknown bits. */
+hp_status hp_assemble_ops(hp_batch b, const float* d_rho, float* d_sys, int32_t ops);
 
 /* q = A p for every frame (FP32, 7-point stencil in Morton order). */
 hp_status hp_spmv(hp_batch b, const float* d_sys, const float* d_p, float* d_q);

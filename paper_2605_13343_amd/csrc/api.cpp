@@ -249,7 +249,14 @@ extern "C" hp_status hp_batch_offsets(hp_batch b, int64_t* n0, int64_t* k0, int6
 
 extern "C" hp_status hp_assemble(hp_batch b, const float* d_rho, float* d_sys) {
   if (!b || !d_rho || !d_sys) return set_error(HP_E_INVALID, "hp_assemble: NULL argument");
-  return launch_assemble(b->geom(), d_rho, d_sys);
+  return launch_assemble(b->geom(), d_rho, d_sys, 0);
+}
+
+extern "C" hp_status hp_assemble_ops(hp_batch b, const float* d_rho, float* d_sys, int32_t ops) {
+  if (!b || !d_rho || !d_sys) return set_error(HP_E_INVALID, "hp_assemble_ops: NULL argument");
+  if (ops & ~(HP_ASM_NEUMANN | HP_ASM_RHO_CONDUCTANCE))
+    return set_error(HP_E_INVALID, "hp_assemble_ops: unknown bits in ops=%d", ops);
+  return launch_assemble(b->geom(), d_rho, d_sys, ops);
 }
 
 extern "C" hp_status hp_spmv(hp_batch b, const float* d_sys, const float* d_p, float* d_q) {

@@ -155,7 +155,7 @@ void factor_offsets_n(int64_t ktot, int64_t mtot, int64_t ntot, int L, int LS, i
                       int64_t* total);
 
 // solver.hip
-hp_status launch_assemble(const LaunchGeom& g, const float* rho, float* sys);
+hp_status launch_assemble(const LaunchGeom& g, const float* rho, float* sys, int ops);
 hp_status launch_spmv(const LaunchGeom& g, const float* sys, const float* p, float* q);
 hp_status launch_apply(const LaunchGeom& g, int L, int LS, int fdtype, const float* sys, const void* fac,
                        const int64_t* offs, const float* r, float* y, float* uh, float* vh, float* Tr, float* Tc);

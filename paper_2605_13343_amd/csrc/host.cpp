@@ -32,11 +32,19 @@ static int ilog2_exact(int v) {
 
 // Morton codes of the grid are exactly 0..N-1 iff the interleave x,y,z,x,y,z,...
 // fills the low bits without gaps: log2 nx, log2 ny in {lz, lz+1}, ly <= lx.
+// A 2D grid (nz = 1) interleaves x,y,x,y,...: ly <= lx <= ly + 1.
 bool admissible_grid(int nx, int ny, int nz, std::string* why) {
   int lx = ilog2_exact(nx), ly = ilog2_exact(ny), lz = ilog2_exact(nz);
   if (lx < 0 || ly < 0 || lz < 0) {
     if (why) *why = "grid dims must be powers of two";
     return false;
+  }
+  if (nz == 1) {
+    if (!(ly <= lx && lx <= ly + 1)) {
+      if (why) *why = "2D grid dims must satisfy ny <= nx <= 2 ny";
+      return false;
+    }
+    return true;
   }
   if (!(ly <= lx && lx <= lz + 1 && ly >= lz)) {
     if (why) *why = "grid dims must satisfy nz <= ny <= nx <= 2 nz with ny in {nz, 2 nz}";
@@ -51,7 +59,22 @@ static uint64_t spread3(uint64_t v) {
   return r;
 }
 
+static uint64_t spread2(uint64_t v) {
+  uint64_t r = 0;
+  for (int b = 0; b < 32; ++b) r |= ((v >> b) & 1ull) << (2 * b);
+  return r;
+}
+
+// Bits of the Morton rank that hold each coordinate.  Sorting the 3D codes of
+// a one-layer grid gives the 2D interleave, so there z has no bits (mask 0:
+// every z face is a boundary face).
 void morton_masks(int nx, int ny, int nz, unsigned* xm, unsigned* ym, unsigned* zm) {
+  if (nz == 1) {
+    *xm = (unsigned)spread2((uint64_t)nx - 1);
+    *ym = (unsigned)(spread2((uint64_t)ny - 1) << 1);
+    *zm = 0u;
+    return;
+  }
   *xm = (unsigned)spread3((uint64_t)nx - 1);
   *ym = (unsigned)(spread3((uint64_t)ny - 1) << 1);
   *zm = (unsigned)(spread3((uint64_t)nz - 1) << 2);

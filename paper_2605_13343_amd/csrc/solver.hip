@@ -117,23 +117,29 @@ __device__ inline double resid_f64(const SysPtr& s, const FrameDesc& F, unsigned
 
 // ------------------------------------------------------------------ assembly
 
-__global__ void k_assemble(const FrameDesc* fr, const int* blk2f, const float* rho, float* sys, int64_t ntot) {
+// ops: HP_ASM_NEUMANN drops the Dirichlet term of the top layer (zero flux on
+// every face); HP_ASM_RHO_CONDUCTANCE takes the harmonic mean of rho as face
+// conductance, 2 rho_i rho_j / (rho_i + rho_j), instead of that of 1/rho.
+__global__ void k_assemble(const FrameDesc* fr, const int* blk2f, const float* rho, float* sys, int64_t ntot,
+                           int ops) {
   const FrameDesc F = fr[blk2f[blockIdx.x]];
   int c = (blockIdx.x - F.b0) * NODE_BLOCK + threadIdx.x;
   if (c >= F.n) return;
   int64_t i = F.n0 + c;
   double ri = rho[i];
+  const bool rho_cond = (ops & HP_ASM_RHO_CONDUCTANCE) != 0;
+  auto face = [&](double rj) -> double { return rho_cond ? 2.0 * ri * rj / (ri + rj) : 2.0 / (ri + rj); };
   auto wplus = [&](unsigned m) -> double {
     if ((c & m) == m) return 0.0;
-    return 2.0 / (ri + (double)rho[F.n0 + mstep_plus(c, m)]);
+    return face((double)rho[F.n0 + mstep_plus(c, m)]);
   };
   auto wminus = [&](unsigned m) -> double {
     if ((c & m) == 0) return 0.0;
-    return 2.0 / (ri + (double)rho[F.n0 + mstep_minus(c, m)]);
+    return face((double)rho[F.n0 + mstep_minus(c, m)]);
   };
   double wpx = wplus(F.xm), wpy = wplus(F.ym), wpz = wplus(F.zm);
   double d = wpx + wminus(F.xm) + wpy + wminus(F.ym) + wpz + wminus(F.zm);
-  if ((c & F.zm) == F.zm) d += 1.0 / ri;
+  if (!(ops & HP_ASM_NEUMANN) && (c & F.zm) == F.zm) d += 1.0 / ri;
   sys[i] = (float)d;
   sys[ntot + i] = (float)wpx;
   sys[2 * ntot + i] = (float)wpy;
@@ -920,8 +926,8 @@ __global__ void k_finalize_x(const FrameDesc* fr, const int* blk2f, const FrameS
 
 
 
-hp_status launch_assemble(const LaunchGeom& g, const float* rho, float* sys) {
-  hipLaunchKernelGGL(k_assemble, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, rho, sys, g.ntot);
+hp_status launch_assemble(const LaunchGeom& g, const float* rho, float* sys, int ops) {
+  hipLaunchKernelGGL(k_assemble, dim3(g.nblk), dim3(NODE_BLOCK), 0, g.stream, g.fr, g.blk2f, rho, sys, g.ntot, ops);
   HP_HIP(hipGetLastError());
   return HP_OK;
 }

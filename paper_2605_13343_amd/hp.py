@@ -16,6 +16,8 @@ _lib = None
 HP_F32, HP_BF16 = 0, 1
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_HMAT = 0, 1, 2
 CONVERGED, NOT_SPD, STAGNATED, MAXITER, FELL_BACK = 1, 2, 4, 8, 16
+ASM_NEUMANN, ASM_RHO_CONDUCTANCE = 1, 2
+ASM_PAPER = ASM_NEUMANN | ASM_RHO_CONDUCTANCE   # the paper's benchmark operator
 
 
 class HPError(RuntimeError):
@@ -72,6 +74,7 @@ EXPORTS = {
     "hp_batch_info": ([C.c_void_p, C.c_int32, C.POINTER(BatchInfo)], C.c_int32),
     "hp_batch_offsets": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
     "hp_assemble": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
+    "hp_assemble_ops": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32], C.c_int32),
     "hp_spmv": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
     "hp_apply": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32], C.c_int32),
     "hp_apply_static": ([C.c_int32] * 5 + [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
@@ -262,8 +265,12 @@ class Batch:
         }
 
     # -- calls
-    def assemble(self, rho, sys):
-        _check(lib().hp_assemble(self.h, _ptr(rho), _ptr(sys)))
+    def assemble(self, rho, sys, ops: int = 0):
+        """ops: ASM_* bits (ASM_PAPER for the paper's 2D benchmark frames)."""
+        if ops:
+            _check(lib().hp_assemble_ops(self.h, _ptr(rho), _ptr(sys), ops))
+        else:
+            _check(lib().hp_assemble(self.h, _ptr(rho), _ptr(sys)))
 
     def spmv(self, sys, p, q):
         _check(lib().hp_spmv(self.h, _ptr(sys), _ptr(p), _ptr(q)))

@@ -30,15 +30,19 @@ class Side:
         self.rho = torch.tensor(rho, device="cuda")
         self.b = torch.tensor(b, device="cuda")
         self.sys = self.B.new_sys()
-        self.B.assemble(self.rho, self.sys)
+        kinds = {f.neumann for f in self.frames}
+        assert len(kinds) == 1, "one operator per batch"
+        self.neumann = kinds.pop()
+        self.ops = hp.ASM_PAPER if self.neumann else 0
+        self.B.assemble(self.rho, self.sys, self.ops)
         # oracle side (FP32-rounded inputs, FP64 arithmetic)
         self.A, self.bo, self.fs = [], [], []
         for f in self.frames:
             rr = f32(f.rho)
-            self.A.append(grid.assemble(f.nx, f.ny, f.nz, rr))
+            self.A.append(grid.assemble(f.nx, f.ny, f.nz, rr, f.neumann))
             self.bo.append(f32(f.b)[grid.morton_perm(f.nx, f.ny, f.nz)])
             if with_net:
-                self.fs.append(network.FrameSys(f.nx, f.ny, f.nz, rr, cfg.leaf, cfg.rank))
+                self.fs.append(network.FrameSys(f.nx, f.ny, f.nz, rr, cfg.leaf, cfg.rank, f.neumann))
         self.parts = [partition.build(f.n, cfg.leaf, cfg.rank) for f in self.frames]
 
     def rows(self, f):

@@ -57,6 +57,10 @@ def _oracle(cfg, s, f, w, trace=None):
     (dataclasses.replace(PLAIN, layers=1, highways=False), "plain1024", 1002),
     (dataclasses.replace(PLAIN, layers=1, offdiag=False), "plain1024", 1003),
     (DEF, "precision8192", 2000),
+    # the paper's 2D benchmark frames (one layer: z has no Morton bits)
+    (DEF, "paper2d_1024", 9000),
+    (DEF, "paper2d_8192", 9001),
+    (PLAIN, "paper2d_2048", 9002),
 ])
 def test_forward_fp32_matches_oracle(cfg, recipe, seed):
     w = test_weights(cfg)

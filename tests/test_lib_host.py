@@ -43,7 +43,7 @@ def test_binding_argument_counts_match_header():
         assert len(args) == ar[name], (name, len(args), ar[name])
 
 
-@pytest.mark.parametrize("dims", [(16, 8, 8), (16, 16, 8), (32, 16, 16), (5, 3, 2), (1, 1, 1)])
+@pytest.mark.parametrize("dims", [(16, 8, 8), (16, 16, 8), (32, 16, 16), (5, 3, 2), (1, 1, 1), (32, 32, 1), (128, 64, 1)])
 def test_morton_order_bit_exact(dims):
     assert np.array_equal(hp.morton_order(*dims), grid.morton_perm(*dims))
 
