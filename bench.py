@@ -366,7 +366,7 @@ def _rooflines(B, I, wt, fac, max_iters):
     gemm_tf = gemm_flops / (gemm_ms * 1e-3) / 1e12
     gemm_gbs = gemm_bytes / (gemm_ms_b * 1e-3) / 1e9
     hbm_bound = gemm_bytes / (PEAK_HBM_GBS * 1e9) >= gemm_flops / (PEAK_BF16_TFLOPS * 1e12)
-    gemm_kernel = "k_gemm_dl<..> / k_gemm_bt<..> / k_gemm<bf16> (MFMA 32x32x16, FP32 accumulation)"
+    gemm_kernel = "k_gemm_dl<..> / k_gemm_bt<..> / k_gemm<bf16> and k_ffn_fused (MFMA 32x32x16, FP32 accumulation)"
     gemm_common = {"traffic": None, "kernel": gemm_kernel, "launches": n_gemm,
                    "avg_launch_us": round(gemm_ms * 1e3 / max(n_gemm, 1), 2), "ms_per_inference": round(gemm_ms, 4),
                    "flops_per_inference": gemm_flops, "bytes_per_inference": gemm_bytes,
@@ -377,7 +377,8 @@ def _rooflines(B, I, wt, fac, max_iters):
     else:
         gemm_roof = {"bound": "mfma", "achieved": round(gemm_tf, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(gemm_tf / PEAK_BF16_TFLOPS, 4), **gemm_common}
-    # the fused FFN kernels alone (part of the family above)
+    # the fused FFN kernels alone (part of the family above; the GEMM family's
+    # figures include them)
     B.profile_enable("ffn")
     B.infer_factors(wt, I.rho, I.sys, fac, hp.HP_BF16)
     n_ffn, ffn_ms, ffn_flops = B.profile_read()
@@ -400,15 +401,20 @@ def _rooflines(B, I, wt, fac, max_iters):
                     {"bound": "mfma", "achieved": round(ffn_tf, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(ffn_tf / PEAK_BF16_TFLOPS, 4), **ffn_common})
     pcg_roofs = _pcg_rooflines(B, I, fac)
-    # the dominant kernel of a step: GEMM time per inference against the
-    # update kernel's time over the step's iterations
+    # the dominant kernel of a step by time: the fused FFN (ms per inference),
+    # the other GEMM launches together, or the update kernel over the step's
+    # iterations
     upd_ms_step = pcg_roofs["update"]["avg_launch_us"] * 1e-3 * float(max_iters)
     for r in [gemm_roof] + list(pcg_roofs.values()):
         r["traffic"] = _traffic(r["kernel"])
-    roofline = dict(gemm_roof) if gemm_ms >= upd_ms_step else dict(pcg_roofs["update"])
-    roofline["others"] = {"gemm": gemm_roof, "pcg_update": pcg_roofs["update"], "pcg_spmv": pcg_roofs["spmv"]}
     if ffn_roof:
         ffn_roof["traffic"] = _traffic(ffn_roof["kernel"])
+    cands = [(upd_ms_step, pcg_roofs["update"]), (gemm_ms - (ffn_ms if ffn_roof else 0.0), gemm_roof)]
+    if ffn_roof:
+        cands.append((ffn_ms, ffn_roof))
+    roofline = dict(max(cands, key=lambda c: c[0])[1])
+    roofline["others"] = {"gemm": gemm_roof, "pcg_update": pcg_roofs["update"], "pcg_spmv": pcg_roofs["spmv"]}
+    if ffn_roof:
         roofline["others"]["ffn_fused"] = ffn_roof
     roofline["others"] = {k: v for k, v in roofline["others"].items() if v["kernel"] != roofline["kernel"]}
     return roofline
