@@ -22,6 +22,8 @@ JSON line carries these legs:
   * streaming: SpMV and the single-right-hand-side apply on batches whose
     algorithmic working set exceeds 1 GB (the precision frames replicated),
     in GB/s of algorithmic bytes;
+  * training: one step of the training workload (32 systems of N = 4,096),
+    ms per step;
   * the paper's own 2D benchmark at its five scales and rtol 1e-8: CG,
     Jacobi-PCG and the method with 2D-trained weights, ms/frame and
     iterations (the setting of the paper's Table 4);
@@ -310,6 +312,7 @@ def main() -> int:
         legs["batching_64_mixed"] = _batching_leg(cfg, wt, stream)
         legs["streaming"] = _streaming_leg(cfg, frames, stream)
         legs["paper2d_rtol1e-8"] = _paper2d_leg(cfg, stream)
+        legs["training_4096x32"] = _training_leg(cfg, stream)
 
     # ---------------------------------------------------------------- CPU oracle baseline
     cpu = None
@@ -508,6 +511,35 @@ def _paper2d_leg(cfg, stream, scales=(1024, 2048, 4096, 8192, 16384)):
         out[str(n)] = row
         del I, fac
     return out
+
+
+def _training_leg(cfg, stream, steps: int = 5):
+    """One training step of the training workload (32 systems of N = 4,096,
+    16 Rademacher probes each, BF16 compute, FP32 master weights, AdamW):
+    hp_train_step (probe smoothing, forward with saves, cosine-Hutchinson
+    loss, reverse pass with per-layer recomputation, AdamW) on resident
+    inputs, ms per step over `steps` steps after one warm-up step."""
+    import torch
+    from paper_2605_13343_amd import hp, inputs
+    frames = [inputs.make_frame("train4096", 3_000_000 + i) for i in range(32)]
+    I = Inputs(cfg, frames, stream)
+    w = inputs.init_weights(cfg, 7)
+    flat = torch.tensor(hp.pack_weights(cfg, w), device="cuda")
+    grad, m, v = torch.zeros_like(flat), torch.zeros_like(flat), torch.zeros_like(flat)
+    zr = torch.tensor(np.concatenate([inputs.rademacher(4096, 16, 3_000_000 + i + 7_000_000) for i in range(32)]),
+                      device="cuda")
+    losses = []
+
+    def step(k):
+        lo, gn = I.B.train_step(flat, grad, m, v, I.rho, I.sys, zr, k + 1, hp.HP_BF16, lr=2e-4)
+        losses.append(lo)
+        return lo
+
+    step(0)
+    _, per, ms = _timed(stream, lambda k: step(k + 1), steps)
+    return {"ms_per_step": round(ms, 3), "systems_per_step": 32, "n": 4096, "probes": 16,
+            "ms_per_step_min": round(min(per), 3), "steps_timed": steps,
+            "note": "seeded initialisation, the same batch every step; the step drains the stream for its loss"}
 
 
 def _batching_leg(cfg, wt, stream):
