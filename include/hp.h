@@ -396,7 +396,10 @@ hp_status hp_train_step(hp_batch b, float* d_weights, float* d_grad, float* d_m,
  * For tests; HP_E_INVALID on an unknown name or a size beyond the buffer. */
 hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, int64_t bytes);
 
-/* Test switches of one batch.  "infer_graph" (0/1, default 0): replay
+/* Test switches of one batch.  Every call synchronises the batch stream and
+ * drops the batch's captured inference and solve-step graphs (they hold the
+ * kernels chosen when they were captured); the next call recaptures.
+ * "infer_graph" (0/1, default 0): replay
  * inferences from a captured hipGraph after the first (see
  * hp_infer_factors); "keep_stages" (0/1, default 0): keep the
  * encoder output and the pooled off-diagonal tokens of each inference for
@@ -419,7 +422,11 @@ hp_status hp_debug_copy(hp_batch b, const char* name, void* d_dst, int64_t bytes
  * dl256x128x32s3, 13: dl128x256x32s3;
  * other GEMMs on variant 0), -1 lets the autotuner choose (the tests
  * compare the variants); "gemm_small_tiles" (0/1): the same as gemm_variant
- * 0 / -1; "ffn_fused" (0/1, default 1): with BF16 compute outside training,
+ * 0 / -1; "attn_fused" (0/1, default 1): with BF16 compute outside
+ * training, L = 64 and 4 heads, run the diagonal stack's attention sublayer
+ * (LN1, QKV, the edge-biased leaf attention, the output projection and the
+ * residual) as one kernel per leaf, with the same arithmetic per value, so
+ * the results equal the separate launches bit for bit; "ffn_fused" (0/1, default 1): with BF16 compute outside training,
  * run each FFN as one fused kernel (hidden activations kept on chip; the
  * same MFMA sequence, GELU and rounding per element, so the results equal
  * the two-GEMM FFN bit for bit) instead of two GEMMs; "gemm_autotune" (0/1, default 1): time every variant on the first

@@ -650,6 +650,15 @@ extern "C" hp_status hp_frame_times(hp_batch b, double* h_stop_ms, double* h_sol
 extern "C" hp_status hp_debug_set(hp_batch b, const char* name, int32_t value) {
   if (!b || !name) return set_error(HP_E_INVALID, "hp_debug_set: NULL argument");
   const std::string n = name;
+  // captured inference and solve-step graphs hold the kernels the switches
+  // chose when they were captured: drop them, so the next call recaptures
+  if (!b->infer_graphs.empty() || !b->step_graphs.empty()) {
+    HP_HIP(hipStreamSynchronize(b->stream));
+    for (auto& kv : b->infer_graphs) hipGraphExecDestroy(kv.second);
+    for (auto& kv : b->step_graphs) hipGraphExecDestroy(kv.second);
+    b->infer_graphs.clear();
+    b->step_graphs.clear();
+  }
   if (n == "attention_valu") {
     b->attn_valu = value != 0;
     return HP_OK;
@@ -660,6 +669,10 @@ extern "C" hp_status hp_debug_set(hp_batch b, const char* name, int32_t value) {
   }
   if (n == "keep_stages") {
     b->keep_stages = value != 0;
+    return HP_OK;
+  }
+  if (n == "attn_fused") {
+    b->attn_fused = value != 0;
     return HP_OK;
   }
   if (n == "ffn_fused") {

@@ -121,6 +121,7 @@ struct Batch {
   int attn_valu = 0;                    // diagnostics: BF16 leaf attention on the vector ALUs
   int gemm_variant = -1;                // diagnostics: BF16 GEMMs forced onto one tile variant (-1: autotuned)
   int ffn_fused = 1;                    // BF16 inference: the FFN as one fused kernel (0: two GEMMs; same results)
+  int attn_fused = 1;                   // BF16 inference, L = 64: the diagonal attention sublayer as one kernel (same results)
   int keep_stages = 0;                  // diagnostics: keep the encoder output and pooled tokens for hp_debug_copy
   int gemm_autotune = 1;                // time both tile kernels on a shape's first call
   std::map<std::tuple<int, int, int64_t>, GemmPick> gemm_pick;

@@ -9,6 +9,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <array>
 #include <type_traits>
 
 #include "batch.h"
@@ -1384,6 +1385,254 @@ __global__ __launch_bounds__(256) void k_attention_mfma(const uint16_t* qkv, uin
     for (int i = 0; i < 4; ++i)
       *(uint2*)(orow + 8 * i + 4 * hh) =
           make_uint2(pack_bf16x2(O[4 * i] * inv, O[4 * i + 1] * inv), pack_bf16x2(O[4 * i + 2] * inv, O[4 * i + 3] * inv));
+  }
+}
+
+// The diagonal attention sublayer of one leaf in one block (BF16 inference,
+// L = 64 tokens, 4 heads of 32, d = 128): X += O Wo^T + bo with
+// O = MHA(LN1(X)) and the edge-biased attention of k_attention_mfma, so that
+// neither the normalised tokens nor Q, K, V nor O leave the chip.  Four waves:
+//   1. LN1 of the leaf's 64 rows (each wave 16, four at a time, the lanes and
+//      DPP sums of k_layernorm128) into a BF16 tile in LDS;
+//   2. wave h forms head h's Q, K and V (two 32 x 32 fragments each, W as the
+//      first MFMA operand, k steps of 16 in order, bias then BF16 rounding:
+//      the QKV GEMM's chain and epilogue).  Q and K become the attention's
+//      MFMA operands in registers (each lane swaps two of its four groups with
+//      the lane 32 away); V goes to LDS transposed;
+//   3. the attention of k_attention_mfma, its BF16 output into the LDS tile;
+//   4. the output projection (wave h: features 32 h .. + 31 of all 64 tokens),
+//      epilogue (acc + bo) + X, as the O GEMM.
+// Each value sees the arithmetic of the four separate launches, so the results
+// equal them bit for bit.  LDS 70.6 KB: two blocks per CU.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void k_attn_sublayer64(float* X, const float* __restrict__ g1, const float* __restrict__ be1,
+                       const uint16_t* __restrict__ Wqkv, const float* __restrict__ bqkv,
+                       const uint16_t* __restrict__ Wo, const float* __restrict__ bo, const float* T0,
+                       const float* corr, const uint8_t* nbr) {
+  constexpr int T = 64, DH = 32, H = 4, D = H * DH, NT = T / 32, VP = T + 8, AP = D + 8;
+  __shared__ __attribute__((aligned(16))) uint16_t sA[T][AP];  // LN1(X), later O
+  __shared__ __attribute__((aligned(16))) uint16_t sVt[H][DH][VP];
+  __shared__ __attribute__((aligned(16))) float sC[H][32][T + 4];
+  const int h = threadIdx.x >> 6, lane = threadIdx.x & 63, hh = lane >> 5, c32 = lane & 31;
+  const int64_t row0 = (int64_t)blockIdx.x * T;
+  auto wave_lds_fence = [] { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); };
+  // 1. LN1 (the wave's 16 rows requested together)
+  {
+    const int c0 = 8 * (lane & 15);
+    float4 xv[4][2];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const float* xr = X + (row0 + 16 * h + 4 * it + (lane >> 4)) * D + c0;
+      xv[it][0] = ((const float4*)xr)[0];
+      xv[it][1] = ((const float4*)xr)[1];
+    }
+    float gm[8], bt[8];
+    load8(g1 + c0, gm);
+    load8(be1 + c0, bt);
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int r = 16 * h + 4 * it + (lane >> 4);
+      const float x[8] = {xv[it][0].x, xv[it][0].y, xv[it][0].z, xv[it][0].w,
+                          xv[it][1].x, xv[it][1].y, xv[it][1].z, xv[it][1].w};
+      float mu = 0.f;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) mu += x[q];
+      mu = row16_sum(mu) * (1.f / 128.f);
+      float var = 0.f;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) var += (x[q] - mu) * (x[q] - mu);
+      const float rs = rsqrtf(row16_sum(var) * (1.f / 128.f) + 1e-5f);
+      float y[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) y[q] = (x[q] - mu) * rs * gm[q] + bt[q];
+      store8<uint16_t>(&sA[r][c0], y);
+    }
+  }
+  // this wave's operands of part j's weight rows (j D + 32 h + c32, k 8 hh
+  // of every k step), shared by both token blocks
+  auto load_w = [&](const uint16_t* Wt, int wrow, bf16x8_t* w) {
+    const uint16_t* src = Wt + (int64_t)wrow * D + 8 * hh;
+#pragma unroll
+    for (int s = 0; s < D / 16; ++s) w[s] = __builtin_bit_cast(bf16x8_t, *(const uint4*)(src + 16 * s));
+  };
+  bf16x8_t wcur[D / 16], wnext[D / 16];
+  load_w(Wqkv, 32 * h + c32, wcur);
+  __syncthreads();
+  // 2. head h's Q, K, V: fragment (token block rb, part j) over features
+  // j D + 32 h .. + 31; the regrouping of a fragment's BF16 values into the
+  // MFMA operand layout of k steps 0 and 1 (features 16 s + 8 hh .. + 7)
+  auto frag = [&](int j, int rb, const bf16x8_t* w) {
+    f32x16_t acc;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.f;
+#pragma unroll
+    for (int s = 0; s < D / 16; ++s) {
+      const bf16x8_t xb = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sA[32 * rb + c32][16 * s + 8 * hh]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[s], xb, acc, 0, 0, 0);
+    }
+    const int cb = j * D + 32 * h + 4 * hh;
+    uint32_t d[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      // biases by scalar loads: a bias's offset in the weight vector need not be 16-byte aligned
+      const float* bq = bqkv + cb + 8 * q;
+      d[2 * q] = pack_bf16x2(acc[4 * q] + bq[0], acc[4 * q + 1] + bq[1]);
+      d[2 * q + 1] = pack_bf16x2(acc[4 * q + 2] + bq[2], acc[4 * q + 3] + bq[3]);
+    }
+    return std::array<uint32_t, 8>{d[0], d[1], d[2], d[3], d[4], d[5], d[6], d[7]};
+  };
+  auto regroup = [&](const std::array<uint32_t, 8>& d, bf16x8_t* op) {
+    uint32_t x[4];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      x[2 * e] = (uint32_t)__shfl_xor((int)(hh ? d[4 * e] : d[4 * e + 2]), 32);
+      x[2 * e + 1] = (uint32_t)__shfl_xor((int)(hh ? d[4 * e + 1] : d[4 * e + 3]), 32);
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      op[e] = __builtin_bit_cast(bf16x8_t, hh ? make_uint4(x[2 * e], x[2 * e + 1], d[4 * e + 2], d[4 * e + 3])
+                                               : make_uint4(d[4 * e], d[4 * e + 1], x[2 * e], x[2 * e + 1]));
+  };
+  bf16x8_t qop[NT][2], kopT[NT][2];  // [token block][k step]
+  // Q (the K rows load meanwhile)
+  load_w(Wqkv, D + 32 * h + c32, wnext);
+#pragma unroll
+  for (int rb = 0; rb < NT; ++rb) regroup(frag(0, rb, wcur), qop[rb]);
+  // K (the V rows load meanwhile)
+  load_w(Wqkv, 2 * D + 32 * h + c32, wcur);
+#pragma unroll
+  for (int rb = 0; rb < NT; ++rb) regroup(frag(1, rb, wnext), kopT[rb]);
+  // V, transposed into LDS: this lane's key 32 rb + c32, head features
+  // 8 q + 4 hh + 0..3
+#pragma unroll
+  for (int rb = 0; rb < NT; ++rb) {
+    const std::array<uint32_t, 8> v = frag(2, rb, wcur);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int f0 = 8 * q + 4 * hh;
+      sVt[h][f0][32 * rb + c32] = (uint16_t)(v[2 * q] & 0xffff);
+      sVt[h][f0 + 1][32 * rb + c32] = (uint16_t)(v[2 * q] >> 16);
+      sVt[h][f0 + 2][32 * rb + c32] = (uint16_t)(v[2 * q + 1] & 0xffff);
+      sVt[h][f0 + 3][32 * rb + c32] = (uint16_t)(v[2 * q + 1] >> 16);
+    }
+  }
+  __syncthreads();  // every wave is done reading LN1(X): the tile takes O next; V^T is in place
+  // 3. attention (k_attention_mfma's arithmetic)
+  const float scale = 0.17677669529663687f;  // 1/sqrt(32)
+#pragma unroll
+  for (int b = 0; b < NT; ++b) {
+    const int q = 32 * b + c32;
+    const int64_t row = row0 + q;
+    if (b == NT - 1) load_w(Wo, 32 * h + c32, wnext);  // the output projection's rows, under the last tile
+    int lj[4];
+    float cv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = 4 * hh + u;
+      lj[u] = 255;
+      cv[u] = 0.f;
+      if (e < 7) {
+        lj[u] = nbr[row * 7 + e];
+        cv[u] = corr[(row * 7 + e) * H + h];
+      }
+    }
+    const float* bt = T0 + ((int64_t)h * T + q) * T;
+    float4 bvv[NT][4];
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) bvv[a][i] = *(const float4*)(bt + 32 * a + 8 * i + 4 * hh);
+    f32x16_t S[NT];
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+      for (int q2 = 0; q2 < 16; ++q2) S[a][q2] = 0.f;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int a = 0; a < NT; ++a) S[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kopT[a][s], qop[b][s], S[a], 0, 0, 0);
+#pragma unroll
+    for (int z = 0; z < T / 8; ++z) *(float4*)&sC[h][c32][hh * (T / 2) + 4 * z] = make_float4(0.f, 0.f, 0.f, 0.f);
+    wave_lds_fence();
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (lj[u] != 255) sC[h][c32][lj[u]] = cv[u];
+    wave_lds_fence();
+    float mx = -3.4e38f;
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k0 = 32 * a + 8 * i + 4 * hh;
+        const float4 bv = bvv[a][i];
+        const float4 cw = *(const float4*)&sC[h][c32][k0];
+        const float bj[4] = {bv.x + cw.x, bv.y + cw.y, bv.z + cw.z, bv.w + cw.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float v = fmaf(S[a][4 * i + j], scale, bj[j]);
+          S[a][4 * i + j] = v;
+          mx = fmaxf(mx, v);
+        }
+      }
+    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    float sum = 0.f;
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+      for (int q2 = 0; q2 < 16; ++q2) {
+        const float p = __expf(S[a][q2] - mx);  // P is rounded to BF16 for the product below
+        S[a][q2] = p;
+        sum += p;
+      }
+    sum += __shfl_xor(sum, 32, 64);
+    f32x16_t O;
+#pragma unroll
+    for (int q2 = 0; q2 < 16; ++q2) O[q2] = 0.f;
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        bf16x8_t pb, vb;
+        const int kb = 32 * a + 16 * s + 4 * hh;
+        uint16_t vv[8];
+        *(uint2*)&vv[0] = *(const uint2*)&sVt[h][c32][kb];
+        *(uint2*)&vv[4] = *(const uint2*)&sVt[h][c32][kb + 8];
+        vb = __builtin_bit_cast(bf16x8_t, *(const uint4*)vv);
+        const uint4 pw = make_uint4(pack_bf16x2(S[a][8 * s], S[a][8 * s + 1]), pack_bf16x2(S[a][8 * s + 2], S[a][8 * s + 3]),
+                                    pack_bf16x2(S[a][8 * s + 4], S[a][8 * s + 5]),
+                                    pack_bf16x2(S[a][8 * s + 6], S[a][8 * s + 7]));
+        pb = __builtin_bit_cast(bf16x8_t, pw);
+        O = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vb, pb, O, 0, 0, 0);
+      }
+    const float inv = 1.f / sum;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      *(uint2*)&sA[q][h * DH + 8 * i + 4 * hh] =
+          make_uint2(pack_bf16x2(O[4 * i] * inv, O[4 * i + 1] * inv), pack_bf16x2(O[4 * i + 2] * inv, O[4 * i + 3] * inv));
+  }
+  __syncthreads();  // O of every head in the tile
+  // 4. X += O Wo^T + bo: wave h, output features 32 h .. + 31, token blocks 0, 1
+#pragma unroll
+  for (int tb = 0; tb < NT; ++tb) {
+    f32x16_t acc;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.f;
+#pragma unroll
+    for (int s = 0; s < D / 16; ++s) {
+      const bf16x8_t ob = __builtin_bit_cast(bf16x8_t, *(const uint4*)&sA[32 * tb + c32][16 * s + 8 * hh]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wnext[s], ob, acc, 0, 0, 0);
+    }
+    const int cb = 32 * h + 4 * hh;
+    float* xr = X + (row0 + 32 * tb + c32) * D;
+    float4 rv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rv[q] = *(const float4*)(xr + cb + 8 * q);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float* bq = bo + cb + 8 * q;
+      *(float4*)(xr + cb + 8 * q) = make_float4((acc[4 * q] + bq[0]) + rv[q].x, (acc[4 * q + 1] + bq[1]) + rv[q].y,
+                                                (acc[4 * q + 2] + bq[2]) + rv[q].z, (acc[4 * q + 3] + bq[3]) + rv[q].w);
+    }
   }
 }
 
@@ -2844,6 +3093,17 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
     void* a = sidx ? N.ao128 : N.a128;
     void* q = sidx ? N.qkvo : N.qkv;
     void* o = sidx ? N.bo128 : N.b128;
+    if (sidx == 0 && sizeof(AT) == 2 && b.attn_fused && !b.attn_valu && !ls && L == 64 && H == 4 && d == 128 &&
+        P.qkv[0][l].N == 384 && P.qkv[0][l].K == 128 && P.o[0][l].N == 128 && P.o[0][l].K == 128) {
+      // the whole sublayer in one launch (LN1, QKV, attention, output projection)
+      if (!N.pre) edge_tables<AT>(b, W, l, sidx, tabs, st);
+      else if (N.pre_side) HP_HIP(hipStreamWaitEvent(st, b.side_ev[l], 0));
+      const uint16_t* wa = (const uint16_t*)N.warena;
+      hipLaunchKernelGGL(k_attn_sublayer64, dim3((unsigned)b.ktot), dim3(256), 0, st, X, wp(p + "ln1.g"),
+                         wp(p + "ln1.b"), wa + P.qkv[0][l].off, wp(p + "qkv.b"), wa + P.o[0][l].off, wp(p + "o.b"),
+                         (const float*)tabs.T0, (const float*)tabs.corr, (const uint8_t*)N.nbr);
+      continue;
+    }
     hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((M + 15) / 16)), dim3(256), 0, st, (const float*)X,
                        wp(p + "ln1.g"), wp(p + "ln1.b"), (AT*)a, (int)M);
     gemm<AT>(b, a, d, N, P.qkv[sidx][l], wp(p + "qkv.b"), nullptr, 0, nullptr, 0, q, 3 * d, M, 0);

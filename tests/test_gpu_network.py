@@ -306,6 +306,31 @@ def test_bf16_fused_ffn_matches_two_gemm_ffn(cfg, recipe, seed):
     assert torch.equal(out[1][2], out[0][2])
 
 
+@pytest.mark.parametrize("recipes", [[("precision8192", 2000)], [("paper2d_8192", 9001)],
+                                     [("batch_mixed", 4001), ("batch_mixed", 4002), ("train4096", 3000001)]])
+def test_bf16_fused_attention_sublayer_matches_separate_launches(recipes):
+    """The diagonal attention sublayer as one kernel per leaf (LN1, QKV,
+    edge-biased attention, output projection and residual) runs every value's
+    arithmetic as the four separate launches do, so the whole BF16 forward is
+    bit-identical with it on or off: residual streams and every factor."""
+    import torch
+    cfg = DEF
+    w = test_weights(cfg)
+    frames = [inputs.make_frame(r, sd) for r, sd in recipes]
+    s = Side(cfg, frames, with_net=True)
+    wt = torch.tensor(hp.pack_weights(cfg, w), device="cuda")
+    out = {}
+    for fused in (0, 1):
+        s.B.debug_set("attn_fused", fused)
+        fac = s.B.new_factors(hp.HP_BF16)
+        s.B.infer_factors(wt, s.rho, s.sys, fac, hp.HP_BF16)
+        torch.cuda.synchronize()
+        out[fused] = (_dbg(s, "xd", (s.B.ntot, cfg.d)), fac.clone())
+    print("fused vs separate attention sublayer: max |dxd|", float(np.abs(out[1][0] - out[0][0]).max()))
+    assert np.array_equal(out[1][0], out[0][0])
+    assert torch.equal(out[1][1], out[0][1])
+
+
 N_GEMM_VARIANTS = 14  # tile variants the library header lists for "gemm_variant"
 
 
