@@ -1403,7 +1403,10 @@ __global__ __launch_bounds__(256) void k_attention_mfma(const uint16_t* qkv, uin
 //   4. the output projection (wave h: features 32 h .. + 31 of all 64 tokens),
 //      epilogue (acc + bo) + X, as the O GEMM.
 // Each value sees the arithmetic of the four separate launches, so the results
-// equal them bit for bit.  LDS 70.6 KB: two blocks per CU.
+// equal them bit for bit.  The stencil corrections of the attention logits are
+// selected in registers (each lane compares its keys with its query's seven
+// neighbours) instead of going through a dense LDS row: 35 KB of LDS, no
+// register spills at two waves per SIMD.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void k_attn_sublayer64(float* X, const float* __restrict__ g1, const float* __restrict__ be1,
                        const uint16_t* __restrict__ Wqkv, const float* __restrict__ bqkv,
@@ -1412,10 +1415,8 @@ void k_attn_sublayer64(float* X, const float* __restrict__ g1, const float* __re
   constexpr int T = 64, DH = 32, H = 4, D = H * DH, NT = T / 32, VP = T + 8, AP = D + 8;
   __shared__ __attribute__((aligned(16))) uint16_t sA[T][AP];  // LN1(X), later O
   __shared__ __attribute__((aligned(16))) uint16_t sVt[H][DH][VP];
-  __shared__ __attribute__((aligned(16))) float sC[H][32][T + 4];
   const int h = threadIdx.x >> 6, lane = threadIdx.x & 63, hh = lane >> 5, c32 = lane & 31;
   const int64_t row0 = (int64_t)blockIdx.x * T;
-  auto wave_lds_fence = [] { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); };
   // 1. LN1 (the wave's 16 rows requested together)
   {
     const int c0 = 8 * (lane & 15);
@@ -1521,20 +1522,16 @@ void k_attn_sublayer64(float* X, const float* __restrict__ g1, const float* __re
   const float scale = 0.17677669529663687f;  // 1/sqrt(32)
 #pragma unroll
   for (int b = 0; b < NT; ++b) {
+    if (b > 0) __builtin_amdgcn_sched_barrier(0);  // keep the tiles' register lifetimes apart
     const int q = 32 * b + c32;
     const int64_t row = row0 + q;
-    if (b == NT - 1) load_w(Wo, 32 * h + c32, wnext);  // the output projection's rows, under the last tile
-    int lj[4];
-    float cv[4];
+    // the query's 7 stencil neighbours (key, correction); 255: none
+    int lj[7];
+    float cv[7];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = 4 * hh + u;
-      lj[u] = 255;
-      cv[u] = 0.f;
-      if (e < 7) {
-        lj[u] = nbr[row * 7 + e];
-        cv[u] = corr[(row * 7 + e) * H + h];
-      }
+    for (int e = 0; e < 7; ++e) {
+      lj[e] = nbr[row * 7 + e];
+      cv[e] = corr[(row * 7 + e) * H + h];
     }
     const float* bt = T0 + ((int64_t)h * T + q) * T;
     float4 bvv[NT][4];
@@ -1551,13 +1548,8 @@ void k_attn_sublayer64(float* X, const float* __restrict__ g1, const float* __re
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int a = 0; a < NT; ++a) S[a] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kopT[a][s], qop[b][s], S[a], 0, 0, 0);
-#pragma unroll
-    for (int z = 0; z < T / 8; ++z) *(float4*)&sC[h][c32][hh * (T / 2) + 4 * z] = make_float4(0.f, 0.f, 0.f, 0.f);
-    wave_lds_fence();
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (lj[u] != 255) sC[h][c32][lj[u]] = cv[u];
-    wave_lds_fence();
+    // k_attention_mfma adds a dense row of corrections (the neighbour's value
+    // at its key, 0 elsewhere); here each lane selects it for its keys
     float mx = -3.4e38f;
 #pragma unroll
     for (int a = 0; a < NT; ++a)
@@ -1565,8 +1557,12 @@ void k_attn_sublayer64(float* X, const float* __restrict__ g1, const float* __re
       for (int i = 0; i < 4; ++i) {
         const int k0 = 32 * a + 8 * i + 4 * hh;
         const float4 bv = bvv[a][i];
-        const float4 cw = *(const float4*)&sC[h][c32][k0];
-        const float bj[4] = {bv.x + cw.x, bv.y + cw.y, bv.z + cw.z, bv.w + cw.w};
+        float cw[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+          for (int e = 0; e < 7; ++e) cw[jj] = lj[e] == k0 + jj ? cv[e] : cw[jj];
+        const float bj[4] = {bv.x + cw[0], bv.y + cw[1], bv.z + cw[2], bv.w + cw[3]};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const float v = fmaf(S[a][4 * i + j], scale, bj[j]);
@@ -1610,6 +1606,7 @@ void k_attn_sublayer64(float* X, const float* __restrict__ g1, const float* __re
       *(uint2*)&sA[q][h * DH + 8 * i + 4 * hh] =
           make_uint2(pack_bf16x2(O[4 * i] * inv, O[4 * i + 1] * inv), pack_bf16x2(O[4 * i + 2] * inv, O[4 * i + 3] * inv));
   }
+  load_w(Wo, 32 * h + c32, wnext);  // the output projection's rows, while the other waves finish
   __syncthreads();  // O of every head in the tile
   // 4. X += O Wo^T + bo: wave h, output features 32 h .. + 31, token blocks 0, 1
 #pragma unroll
