@@ -87,6 +87,20 @@ typedef struct {
  * perm has N entries, host memory.  Any positive dims are accepted. */
 hp_status hp_morton_order(int32_t nx, int32_t ny, int32_t nz, int32_t* perm);
 
+/* Padded frames (paper Sec. 8: the partition is sized to a maximum N, and a
+ * smaller frame is padded to it; Supplementary "Grid and ordering": the
+ * benchmark's W x H grid, close to square with W H >= N, is cut to the first
+ * N cells in Morton order).  A frame keeps the power-of-two box nx x ny x nz
+ * that hp_batch_create admits, and region = (W, H, D, n) names its own cells:
+ * the first n cells, in Morton order, of the W x H x D grid at the box origin
+ * (1 <= W <= nx, 1 <= H <= ny, 1 <= D <= nz, 1 <= n <= W H D).  Every other
+ * cell of the box is padding.
+ * hp_region_mask: mask[c] = 1 if the box's c-th cell in Morton order is one
+ * of the frame's cells, else 0; N = nx ny nz entries, host memory.  Host only,
+ * bit-exact.  HP_E_SHAPE for a box hp_batch_create rejects or a region that
+ * does not fit it. */
+hp_status hp_region_mask(int32_t nx, int32_t ny, int32_t nz, const int32_t* region, uint8_t* mask);
+
 typedef struct {
   int32_t n, leaf, rank;   /* N, L, L_s */
   int32_t K, J, MH;        /* leaves, levels (log2 K), unique off-diagonal tiles (K - 1) */
@@ -129,6 +143,19 @@ typedef struct {
 hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes, const int32_t* dims,
                           void* hip_stream, hp_batch* out);
 hp_status hp_batch_destroy(hp_batch b);
+/* Sets every frame's region (see hp_region_mask): regions[4f .. 4f+3] =
+ * (W, H, D, n) for frame f (host), NULL = every frame is its whole box (the
+ * state after hp_batch_create).  From the next hp_assemble / hp_assemble_ops
+ * on, a padding cell's row of A is the identity row with no faces, a face
+ * between a frame cell and padding is a zero-flux boundary face, and the
+ * Dirichlet term of hp_assemble sits on the top layer of the frame's grid
+ * (z = D-1).  A is then the frame's operator on its own cells, direct-summed
+ * with I on the padding; with a right-hand side that is zero on the padding
+ * the solution is zero there and the frame's own solution elsewhere.  The
+ * network and the solver run on the whole box, padding included (the
+ * partition is the box's).  Waits for the batch stream; HP_E_SHAPE (nothing
+ * changed) if a region does not fit its frame's box. */
+hp_status hp_batch_set_regions(hp_batch b, const int32_t* regions);
 /* Sizes; factor offsets are given for dtype (HP_F32 or HP_BF16). */
 hp_status hp_batch_info(hp_batch b, int32_t dtype, hp_batch_info_t* info);
 /* Per-frame offsets (host arrays of nframes entries, any may be NULL). */

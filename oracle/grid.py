@@ -40,7 +40,56 @@ def cell_xyz(nx: int, ny: int, nz: int, lex: np.ndarray) -> np.ndarray:
     return np.stack([lex % nx, (lex // nx) % ny, lex // (nx * ny)], axis=-1)
 
 
-def assemble_lex(nx: int, ny: int, nz: int, rho: np.ndarray, neumann: bool = False) -> sp.csr_matrix:
+def region_mask_lex(nx: int, ny: int, nz: int, region=None) -> np.ndarray:
+    """Which cells of the nx x ny x nz box belong to the frame, lexicographic
+    boolean [nx ny nz].
+
+    A frame whose grid is not a power-of-two box (paper Sec. 8: the partition
+    is sized to a maximum N; Supplementary "Grid and ordering": a W x H grid,
+    close to square, with W H >= N, whose cells are sorted by Morton code and
+    cut to the first N) sits in the smallest box the partition accepts.
+    region = (W, H, D, n): the frame's cells are the first n cells, in Morton
+    order, of the W x H x D grid at the box origin; every other cell of the
+    box is padding.  region None: every cell is the frame's.
+    """
+    mask = np.zeros(nx * ny * nz, dtype=bool)
+    if region is None:
+        mask[:] = True
+        return mask
+    W, H, D, n = (int(t) for t in region)
+    if not (1 <= W <= nx and 1 <= H <= ny and 1 <= D <= nz and 1 <= n <= W * H * D):
+        raise ValueError(f"region {region} does not fit the {nx} x {ny} x {nz} box")
+    cells = sorted((morton_code(x, y, z), x + nx * (y + ny * z))
+                   for z in range(D) for y in range(H) for x in range(W))
+    for _, lid in cells[:n]:
+        mask[lid] = True
+    return mask
+
+
+def region_rhs(nx: int, ny: int, nz: int, b_lex: np.ndarray, region=None, neumann: bool = False) -> np.ndarray:
+    """Right-hand side of a padded frame, lexicographic: b on the frame's
+    cells and 0 on the padding (so the solution is 0 there); for the
+    zero-flux operator also minus its mean over the frame's cells, which
+    makes it orthogonal to the null space of the frame's block (the constant
+    on its cells; connected frames).  region None: b unchanged."""
+    b_lex = np.asarray(b_lex, dtype=np.float64)
+    if region is None:
+        return b_lex.copy()
+    real = region_mask_lex(nx, ny, nz, region)
+    out = np.where(real, b_lex, 0.0)
+    if neumann:
+        out[real] -= out[real].mean()
+    return out
+
+
+def region_top(nz: int, region=None) -> int:
+    """The layer that carries the Dirichlet condition: the top layer of the
+    frame's grid (z = D-1), the box's top (z = nz-1) without a region."""
+    return nz - 1 if region is None else int(region[2]) - 1
+
+
+def assemble_lex(nx: int, ny: int, nz: int, rho: np.ndarray, neumann: bool = False,
+                 region=None) -> sp.csr_matrix:
     """Cell-centred variable-coefficient Poisson operator (7-point; 5-point
     when nz = 1) in lexicographic order, spacing h = 1.
 
@@ -55,8 +104,16 @@ def assemble_lex(nx: int, ny: int, nz: int, rho: np.ndarray, neumann: bool = Fal
     w_ij = 2 rho_i rho_j/(rho_i+rho_j), the harmonic mean of rho, and zero
     flux on every boundary face, so A 1 = 0 (A is singular; the paper leaves
     the constant mode to CG with a consistent right-hand side).
+
+    region (see region_mask_lex): faces join two cells of the frame only, a
+    face towards padding is a zero-flux boundary face, the Dirichlet term
+    sits on the frame grid's top layer, and a padding cell's row is the
+    identity row (A_ii = 1, decoupled), so the frame's block is the operator
+    of its own cells and the padding block is I.
     """
     n = nx * ny * nz
+    real = region_mask_lex(nx, ny, nz, region)
+    ztop = region_top(nz, region)
     rows, cols, vals = [], [], []
     diag = np.zeros(n)
 
@@ -67,11 +124,16 @@ def assemble_lex(nx: int, ny: int, nz: int, rho: np.ndarray, neumann: bool = Fal
         for y in range(ny):
             for x in range(nx):
                 i = lid(x, y, z)
+                if not real[i]:
+                    diag[i] = 1.0
+                    continue
                 for (dx, dy, dz) in ((1, 0, 0), (0, 1, 0), (0, 0, 1)):
                     xx, yy, zz = x + dx, y + dy, z + dz
                     if xx >= nx or yy >= ny or zz >= nz:
                         continue
                     j = lid(xx, yy, zz)
+                    if not real[j]:
+                        continue
                     if neumann:
                         w = 2.0 * rho[i] * rho[j] / (rho[i] + rho[j])
                     else:
@@ -81,7 +143,7 @@ def assemble_lex(nx: int, ny: int, nz: int, rho: np.ndarray, neumann: bool = Fal
                     vals += [-w, -w]
                     diag[i] += w
                     diag[j] += w
-                if z == nz - 1 and not neumann:
+                if z == ztop and not neumann:
                     diag[i] += 1.0 / rho[i]
     rows += list(range(n))
     cols += list(range(n))
@@ -89,16 +151,18 @@ def assemble_lex(nx: int, ny: int, nz: int, rho: np.ndarray, neumann: bool = Fal
     return sp.csr_matrix((np.array(vals), (np.array(rows), np.array(cols))), shape=(n, n))
 
 
-def assemble(nx: int, ny: int, nz: int, rho_lex: np.ndarray, neumann: bool = False) -> sp.csr_matrix:
+def assemble(nx: int, ny: int, nz: int, rho_lex: np.ndarray, neumann: bool = False,
+             region=None) -> sp.csr_matrix:
     """The operator in Morton order: A_m = P A P^T with P the Morton perm."""
     perm = morton_perm(nx, ny, nz)
-    A = assemble_lex(nx, ny, nz, rho_lex, neumann)
+    A = assemble_lex(nx, ny, nz, rho_lex, neumann, region)
     Am = A[perm][:, perm].tocsr()
     Am.sort_indices()
     return Am
 
 
-def features(nx: int, ny: int, nz: int, rho_lex: np.ndarray, neumann: bool = False) -> np.ndarray:
+def features(nx: int, ny: int, nz: int, rho_lex: np.ndarray, neumann: bool = False,
+             region=None) -> np.ndarray:
     """Per-node encoder input [N, 20] in Morton order.
 
     The paper (Sec. 4.1, Supplementary "Encoder") lists density, position and
@@ -113,11 +177,13 @@ def features(nx: int, ny: int, nz: int, rho_lex: np.ndarray, neumann: bool = Fal
     Standard deviations are population (divide by N).  Pressure is absent:
     the frames have no previous time step.  The flags are geometric: on a 2D
     grid (nz = 1) every cell is both top and bottom layer.  A_ii comes from
-    the operator the frame uses (neumann, as in assemble_lex).
+    the operator the frame uses (neumann, region, as in assemble_lex).  With a
+    region the network sees the whole box: positions, flags and the summary
+    are those of the box, padding cells included (A_ii = 1 there).
     """
     n = nx * ny * nz
     perm = morton_perm(nx, ny, nz)
-    A = assemble_lex(nx, ny, nz, rho_lex, neumann)
+    A = assemble_lex(nx, ny, nz, rho_lex, neumann, region)
     dA = A.diagonal()
     xyz = cell_xyz(nx, ny, nz, np.arange(n))
     x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]

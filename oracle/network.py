@@ -71,12 +71,12 @@ class FrameSys:
     partition, and the two edge-descriptor tables."""
 
     def __init__(self, nx: int, ny: int, nz: int, rho_lex: np.ndarray, leaf: int, rank: int,
-                 neumann: bool = False):
+                 neumann: bool = False, region=None):
         self.nx, self.ny, self.nz = nx, ny, nz
         self.n = nx * ny * nz
-        self.A = grid.assemble(nx, ny, nz, rho_lex, neumann)
+        self.A = grid.assemble(nx, ny, nz, rho_lex, neumann, region)
         self.diagA = self.A.diagonal().copy()
-        self.feats = grid.features(nx, ny, nz, rho_lex, neumann)
+        self.feats = grid.features(nx, ny, nz, rho_lex, neumann, region)
         self.pos = grid.positions(nx, ny, nz)
         self.part = partition.build(self.n, leaf, rank)
         self._descriptors()

@@ -124,6 +124,10 @@ extern "C" hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes
     F.nz = nz;
     F.nx = nx;
     F.ny = ny;
+    F.rx = nx;
+    F.ry = ny;
+    F.rz = nz;
+    F.rthr = (unsigned)n;
     morton_masks(nx, ny, nz, &F.xm, &F.ym, &F.zm);
     F.nb = (n + NODE_BLOCK - 1) / NODE_BLOCK;
     F.b0 = nb0;
@@ -204,6 +208,32 @@ extern "C" hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes
     return s;
   }
   *out = b;
+  return HP_OK;
+}
+
+extern "C" hp_status hp_batch_set_regions(hp_batch b, const int32_t* regions) {
+  if (!b) return set_error(HP_E_INVALID, "hp_batch_set_regions: bad arguments");
+  std::vector<FrameDesc> fr = b->fr;
+  std::string why;
+  for (int f = 0; f < b->nframes; ++f) {
+    FrameDesc& F = fr[f];
+    const int nx = F.nx, ny = F.ny, nz = F.nz;
+    const int32_t whole[4] = {nx, ny, nz, F.n};
+    const int32_t* reg = regions ? regions + 4 * f : whole;
+    unsigned thr;
+    if (!region_threshold(nx, ny, nz, reg, &thr, &why))
+      return set_error(HP_E_SHAPE, "hp_batch_set_regions: frame %d (%d x %d x %d box): %s", f, nx, ny, nz, why.c_str());
+    F.rx = reg[0];
+    F.ry = reg[1];
+    F.rz = reg[2];
+    F.rthr = thr;
+    F.padded = !(reg[0] == nx && reg[1] == ny && reg[2] == nz && reg[3] == F.n);
+  }
+  // the stream's work may still read the descriptors
+  if (hipStreamSynchronize(b->stream) != hipSuccess ||
+      hipMemcpy(b->d_fr, fr.data(), sizeof(FrameDesc) * b->nframes, hipMemcpyHostToDevice) != hipSuccess)
+    return set_error(HP_E_HIP, "hp_batch_set_regions: upload failed");
+  b->fr = fr;
   return HP_OK;
 }
 

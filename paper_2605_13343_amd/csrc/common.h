@@ -39,6 +39,11 @@ struct FrameDesc {
   unsigned xm, ym, zm;  // Morton bit masks of x, y, z within the code
   int nb, b0;       // node blocks (of NODE_BLOCK rows) and first node block
   int nx, ny;       // grid width and depth
+  // The frame's own cells when its grid is smaller than the box (padded):
+  // cell c belongs to the frame iff its coordinates lie in rx x ry x rz and
+  // c < rthr; every other cell of the box is padding (an identity row).
+  int rx, ry, rz, padded;
+  unsigned rthr;
 };
 
 constexpr int NODE_BLOCK = 128;   // rows per node block
@@ -191,6 +196,11 @@ __device__ inline unsigned mstep_plus(unsigned c, unsigned mask) {
 __device__ inline unsigned mstep_minus(unsigned c, unsigned mask) {
   return (((c & mask) - 1u) & mask) | (c & ~mask);
 }
+// Whether cell c (box rank) is one of the frame's own cells (see FrameDesc).
+__device__ inline int mcoord(unsigned c, unsigned mask);
+__device__ inline bool in_region(const FrameDesc& F, unsigned c) {
+  return c < F.rthr && mcoord(c, F.xm) < F.rx && mcoord(c, F.ym) < F.ry && mcoord(c, F.zm) < F.rz;
+}
 __device__ inline int mcoord(unsigned c, unsigned mask) {
   int v = 0, b = 0;
   while (mask) {
@@ -205,6 +215,9 @@ __device__ inline int mcoord(unsigned c, unsigned mask) {
 // ---------------------------------------------------------------- host helpers
 bool admissible_grid(int nx, int ny, int nz, std::string* why);
 void morton_masks(int nx, int ny, int nz, unsigned* xm, unsigned* ym, unsigned* zm);
+// Region (W, H, D, n) of a frame inside its nx x ny x nz box: checks it and
+// returns the rank threshold of FrameDesc::rthr.
+bool region_threshold(int nx, int ny, int nz, const int32_t* reg, unsigned* thr, std::string* why);
 
 struct WeightEntry {
   std::string name;

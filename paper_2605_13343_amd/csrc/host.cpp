@@ -80,6 +80,45 @@ void morton_masks(int nx, int ny, int nz, unsigned* xm, unsigned* ym, unsigned* 
   *zm = (unsigned)(spread3((uint64_t)nz - 1) << 2);
 }
 
+// Box rank of a coordinate: its bits deposited, lowest first, into the bits of mask.
+static unsigned deposit_bits(unsigned v, unsigned mask) {
+  unsigned r = 0;
+  for (unsigned m = mask; m; m &= m - 1u, v >>= 1)
+    if (v & 1u) r |= m & (~m + 1u);
+  return r;
+}
+
+// The frame's cells are the first n cells of the W x H x D grid in Morton
+// order.  Box ranks follow the same order, so they are the grid cells whose
+// rank lies below that of the grid's (n+1)-th cell (every grid cell when n is
+// all of them: then the threshold is the box size).
+bool region_threshold(int nx, int ny, int nz, const int32_t* reg, unsigned* thr, std::string* why) {
+  const int W = reg[0], H = reg[1], D = reg[2], n = reg[3];
+  if (W < 1 || W > nx || H < 1 || H > ny || D < 1 || D > nz) {
+    if (why) *why = "the region's grid must fit the box";
+    return false;
+  }
+  const int64_t cells = (int64_t)W * H * D;
+  if (n < 1 || n > cells) {
+    if (why) *why = "the region's cell count must lie in [1, W H D]";
+    return false;
+  }
+  if (n == cells) {
+    *thr = (unsigned)((int64_t)nx * ny * nz);
+    return true;
+  }
+  unsigned xm, ym, zm;
+  morton_masks(nx, ny, nz, &xm, &ym, &zm);
+  std::vector<unsigned> r;
+  r.reserve((size_t)cells);
+  for (int z = 0; z < D; ++z)
+    for (int y = 0; y < H; ++y)
+      for (int x = 0; x < W; ++x) r.push_back(deposit_bits(x, xm) | deposit_bits(y, ym) | deposit_bits(z, zm));
+  std::nth_element(r.begin(), r.begin() + n, r.end());
+  *thr = r[n];
+  return true;
+}
+
 // ------------------------------------------------------------------ weights
 // Order and shapes of every tensor of the network; see hp_weight_info.
 std::vector<WeightEntry> weight_layout(const hp_model_config& c) {
@@ -153,6 +192,28 @@ extern "C" hp_status hp_morton_order(int32_t nx, int32_t ny, int32_t nz, int32_t
   std::iota(idx.begin(), idx.end(), 0);
   std::sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return code[a] < code[b]; });
   memcpy(perm, idx.data(), n * sizeof(int32_t));
+  return HP_OK;
+}
+
+extern "C" hp_status hp_region_mask(int32_t nx, int32_t ny, int32_t nz, const int32_t* region, uint8_t* mask) {
+  if (!region || !mask) return set_error(HP_E_INVALID, "hp_region_mask: bad arguments");
+  std::string why;
+  if (!admissible_grid(nx, ny, nz, &why)) return set_error(HP_E_SHAPE, "hp_region_mask: %s", why.c_str());
+  unsigned thr;
+  if (!region_threshold(nx, ny, nz, region, &thr, &why)) return set_error(HP_E_SHAPE, "hp_region_mask: %s", why.c_str());
+  unsigned xm, ym, zm;
+  morton_masks(nx, ny, nz, &xm, &ym, &zm);
+  auto coord = [](unsigned c, unsigned m) {
+    int v = 0, b = 0;
+    for (; m; m &= m - 1u, ++b)
+      if (c & m & (~m + 1u)) v |= 1 << b;
+    return v;
+  };
+  const int64_t n = (int64_t)nx * ny * nz;
+  for (int64_t c = 0; c < n; ++c) {
+    const unsigned u = (unsigned)c;
+    mask[c] = (uint8_t)(u < thr && coord(u, xm) < region[0] && coord(u, ym) < region[1] && coord(u, zm) < region[2]);
+  }
   return HP_OK;
 }
 

@@ -127,19 +127,30 @@ __global__ void k_assemble(const FrameDesc* fr, const int* blk2f, const float* r
   if (c >= F.n) return;
   int64_t i = F.n0 + c;
   double ri = rho[i];
+  // a padded frame: padding cells get identity rows and no faces, a face
+  // towards padding is a zero-flux face, the Dirichlet layer is the top of
+  // the frame's grid
+  const bool pad = F.padded != 0;
+  const bool own = !pad || in_region(F, (unsigned)c);
   const bool rho_cond = (ops & HP_ASM_RHO_CONDUCTANCE) != 0;
   auto face = [&](double rj) -> double { return rho_cond ? 2.0 * ri * rj / (ri + rj) : 2.0 / (ri + rj); };
   auto wplus = [&](unsigned m) -> double {
-    if ((c & m) == m) return 0.0;
-    return face((double)rho[F.n0 + mstep_plus(c, m)]);
+    if (!own || (c & m) == m) return 0.0;
+    const unsigned j = mstep_plus(c, m);
+    if (pad && !in_region(F, j)) return 0.0;
+    return face((double)rho[F.n0 + j]);
   };
   auto wminus = [&](unsigned m) -> double {
-    if ((c & m) == 0) return 0.0;
-    return face((double)rho[F.n0 + mstep_minus(c, m)]);
+    if (!own || (c & m) == 0) return 0.0;
+    const unsigned j = mstep_minus(c, m);
+    if (pad && !in_region(F, j)) return 0.0;
+    return face((double)rho[F.n0 + j]);
   };
   double wpx = wplus(F.xm), wpy = wplus(F.ym), wpz = wplus(F.zm);
   double d = wpx + wminus(F.xm) + wpy + wminus(F.ym) + wpz + wminus(F.zm);
-  if (!(ops & HP_ASM_NEUMANN) && (c & F.zm) == F.zm) d += 1.0 / ri;
+  const bool top = pad ? mcoord((unsigned)c, F.zm) == F.rz - 1 : (c & F.zm) == F.zm;
+  if (!(ops & HP_ASM_NEUMANN) && own && top) d += 1.0 / ri;
+  if (!own) d = 1.0;
   sys[i] = (float)d;
   sys[ntot + i] = (float)wpx;
   sys[2 * ntot + i] = (float)wpy;

@@ -66,6 +66,8 @@ class SolveResult(C.Structure):
 EXPORTS = {
     "hp_last_error": ([], C.c_char_p),
     "hp_morton_order": ([C.c_int32, C.c_int32, C.c_int32, C.c_void_p], C.c_int32),
+    "hp_region_mask": ([C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p], C.c_int32),
+    "hp_batch_set_regions": ([C.c_void_p, C.c_void_p], C.c_int32),
     "hp_build_partition": ([C.c_int32, C.c_int32, C.c_int32, C.POINTER(PartitionInfo)] + [C.c_void_p] * 6,
                            C.c_int32),
     "hp_batch_create": ([C.POINTER(ModelConfigC), C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)],
@@ -138,6 +140,15 @@ def morton_order(nx: int, ny: int, nz: int) -> np.ndarray:
     perm = np.zeros(nx * ny * nz, dtype=np.int32)
     _check(lib().hp_morton_order(nx, ny, nz, perm.ctypes.data))
     return perm
+
+
+def region_mask(nx: int, ny: int, nz: int, region) -> np.ndarray:
+    """Boolean [nx ny nz], Morton order of the box: the frame's own cells of
+    region (W, H, D, n) (hp_region_mask)."""
+    reg = np.array(region, dtype=np.int32)
+    mask = np.zeros(nx * ny * nz, dtype=np.uint8)
+    _check(lib().hp_region_mask(nx, ny, nz, reg.ctypes.data, mask.ctypes.data))
+    return mask.astype(bool)
 
 
 def build_partition(n: int, leaf: int, rank: int, tables: bool = True):
@@ -238,6 +249,13 @@ class Batch:
                 self.h = None
         except Exception:
             pass
+
+    def set_regions(self, regions):
+        """regions: one (W, H, D, n) or None (the whole box) per frame
+        (hp_batch_set_regions)."""
+        rows = [r if r is not None else (d[0], d[1], d[2], d[0] * d[1] * d[2]) for r, d in zip(regions, self.dims)]
+        arr = np.array(rows, dtype=np.int32).reshape(-1)
+        _check(lib().hp_batch_set_regions(self.h, arr.ctypes.data))
 
     # -- buffers
     def new_sys(self):

@@ -77,6 +77,8 @@ class BarrierRecipe:
     then multiplied by 1 + N(0, 0.05^2).  b ~ N(0, I) minus its mean."""
     grid: Tuple[int, int]                     # (W, H) = (nx, ny); nz = 1
     contrast: Tuple[float, float] = (5.0, 100.0)
+    box: Optional[Tuple[int, int]] = None     # padded frames: the power-of-two box holding the W x H grid
+    cells: Optional[int] = None               # padded frames: N, the grid cut to its first N cells in Morton order
     barriers: Tuple[int, int] = (1, 3)
     centre: Tuple[float, float] = (0.2, 0.8)
     thickness: Tuple[float, float] = (0.05, 0.20)
@@ -93,6 +95,15 @@ GRID2D_OF_N = {1024: (32, 32), 2048: (64, 32), 4096: (64, 64), 8192: (128, 64), 
 for _n, _wh in GRID2D_OF_N.items():
     RECIPES[f"paper2d_{_n}"] = BarrierRecipe(grid=_wh)
 
+# The paper's own grid choice for N that is not a product of two close powers
+# of two: W x H as close to square as possible with W H >= N (W = ceil(sqrt N),
+# H = ceil(N / W)), cut to the first N cells in Morton order.  Such a frame is
+# padded to the smallest power-of-two box the library's partition accepts.
+TRUNC2D_OF_N = {2048: ((46, 45), (64, 64)), 8192: ((91, 91), (128, 128))}
+
+for _n, (_wh, _box) in TRUNC2D_OF_N.items():
+    RECIPES[f"paper2d_trunc_{_n}"] = BarrierRecipe(grid=_wh, box=_box, cells=_n)
+
 
 @dataclasses.dataclass
 class Frame:
@@ -103,21 +114,36 @@ class Frame:
     b: np.ndarray     # float64 [N], lexicographic, uniform in [-1, 1) (mean-zero Gaussian for 2D barriers)
     seed: int
     neumann: bool = False   # zero flux on every face, conductance the harmonic mean of rho (the paper's operator)
+    # Padded frames: (W, H, D, cells), the frame's own cells are the first
+    # `cells` cells, in Morton order, of the W x H x D grid at the origin of
+    # the nx x ny x nz box; the rest of the box is padding.  b is then the raw
+    # draw over the box: the right-hand side is b on the frame's cells (minus
+    # its mean there for the zero-flux operator) and 0 on the padding, which
+    # each side forms from its own cell mask.
+    region: Optional[Tuple[int, int, int, int]] = None
 
     @property
     def n(self) -> int:
+        """Unknowns of the box (the partition's N)."""
         return self.nx * self.ny * self.nz
+
+    @property
+    def cells(self) -> int:
+        """The frame's own cells."""
+        return self.n if self.region is None else int(self.region[3])
 
 
 def _make_barrier_frame(rc: BarrierRecipe, seed: int) -> Frame:
     """Draw order: rho_heavy, barrier count, per barrier (orientation, centre,
     thickness, gap topology), the density noise cell by cell, then b."""
     rng = np.random.default_rng(seed)
-    nx, ny = rc.grid
+    W, H = rc.grid
+    nx, ny = rc.box if rc.box is not None else rc.grid
     heavy = float(np.exp(rng.uniform(np.log(rc.contrast[0]), np.log(rc.contrast[1]))))
     nb = int(rng.integers(rc.barriers[0], rc.barriers[1] + 1))
     y, x = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
-    u, v = (x.ravel() + 0.5) / nx, (y.ravel() + 0.5) / ny      # unit-square cell centres
+    u, v = (x.ravel() + 0.5) / W, (y.ravel() + 0.5) / H        # unit-square centres of the W x H grid
+    in_grid = (x.ravel() < W) & (y.ravel() < H)
     inside = np.zeros(nx * ny, dtype=bool)
     for _ in range(nb):
         vertical = bool(rng.integers(2))
@@ -132,11 +158,16 @@ def _make_barrier_frame(rc: BarrierRecipe, seed: int) -> Frame:
             band &= along >= rc.gap
         elif topo == "middle_hole":
             band &= np.abs(along - 0.5) >= 0.5 * rc.gap
-        inside |= band
+        inside |= band & in_grid
     rho = np.where(inside, heavy, 1.0) * (1.0 + rc.noise * rng.standard_normal(nx * ny))
     b = rng.standard_normal(nx * ny)
-    b -= b.mean()
-    return Frame(nx=nx, ny=ny, nz=1, rho=rho.astype(np.float64), b=b, seed=seed, neumann=True)
+    if rc.box is None:
+        b -= b.mean()
+        return Frame(nx=nx, ny=ny, nz=1, rho=rho.astype(np.float64), b=b, seed=seed, neumann=True)
+    rho = np.where(in_grid, rho, 1.0)       # the box outside the grid: light, noise-free
+    cells = rc.cells if rc.cells is not None else W * H
+    return Frame(nx=nx, ny=ny, nz=1, rho=rho.astype(np.float64), b=b, seed=seed, neumann=True,
+                 region=(W, H, 1, cells))
 
 
 def make_frame(recipe: str | FrameRecipe | BarrierRecipe, seed: int) -> Frame:
@@ -172,6 +203,15 @@ def make_frame_grid(nx: int, ny: int, nz: int, seed: int, spheres: int = 3,
     """A frame on an arbitrary grid with the plain recipe's inclusion law."""
     return make_frame(FrameRecipe(grids=((nx, ny, nz),), spheres=(spheres, spheres),
                                   contrast=(contrast, contrast)), seed)
+
+
+def make_padded_frame(box: Tuple[int, int, int], region: Tuple[int, int, int, int], seed: int,
+                      spheres: int = 3, contrast: float = 100.0) -> Frame:
+    """A 3D frame of the plain recipe's inclusion law on the box, whose own
+    cells are `region` (W, H, D, cells); b stays the raw draw (see Frame)."""
+    fr = make_frame_grid(*box, seed, spheres=spheres, contrast=contrast)
+    fr.region = tuple(int(t) for t in region)
+    return fr
 
 
 # ----------------------------------------------------------------------------

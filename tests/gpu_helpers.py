@@ -25,8 +25,11 @@ class Side:
         self.frames = list(frames)
         self.B = hp.Batch(cfg, [(f.nx, f.ny, f.nz) for f in self.frames])
         self.perms = [hp.morton_order(f.nx, f.ny, f.nz) for f in self.frames]
+        self.padded = any(f.region is not None for f in self.frames)
+        if self.padded:
+            self.B.set_regions([f.region for f in self.frames])
         rho = np.concatenate([f.rho[p] for f, p in zip(self.frames, self.perms)]).astype(np.float32)
-        b = np.concatenate([f.b[p] for f, p in zip(self.frames, self.perms)]).astype(np.float32)
+        b = np.concatenate([device_rhs(f)[p] for f, p in zip(self.frames, self.perms)]).astype(np.float32)
         self.rho = torch.tensor(rho, device="cuda")
         self.b = torch.tensor(b, device="cuda")
         self.sys = self.B.new_sys()
@@ -39,10 +42,11 @@ class Side:
         self.A, self.bo, self.fs = [], [], []
         for f in self.frames:
             rr = f32(f.rho)
-            self.A.append(grid.assemble(f.nx, f.ny, f.nz, rr, f.neumann))
-            self.bo.append(f32(f.b)[grid.morton_perm(f.nx, f.ny, f.nz)])
+            self.A.append(grid.assemble(f.nx, f.ny, f.nz, rr, f.neumann, f.region))
+            bl = grid.region_rhs(f.nx, f.ny, f.nz, f.b, f.region, f.neumann)
+            self.bo.append(f32(bl)[grid.morton_perm(f.nx, f.ny, f.nz)])
             if with_net:
-                self.fs.append(network.FrameSys(f.nx, f.ny, f.nz, rr, cfg.leaf, cfg.rank, f.neumann))
+                self.fs.append(network.FrameSys(f.nx, f.ny, f.nz, rr, cfg.leaf, cfg.rank, f.neumann, f.region))
         self.parts = [partition.build(f.n, cfg.leaf, cfg.rank) for f in self.frames]
 
     def rows(self, f):
@@ -85,6 +89,22 @@ class Side:
                 v["G"][k0:k0 + p["K"]], v["B"][m0:m0 + p["MH"]], v["Ut"][n0:n0 + p["n"]],
                 v["Vt"][n0:n0 + p["n"]], v["lam"][n0:n0 + p["n"]])))
         return out
+
+
+def device_rhs(fr) -> np.ndarray:
+    """The right-hand side the device gets, lexicographic: for a padded
+    frame b on the frame's cells (minus its mean there for the zero-flux
+    operator) and 0 on the padding, the cells taken from the library's own
+    mask (hp_region_mask), the arithmetic in the oracle's order."""
+    if fr.region is None:
+        return np.asarray(fr.b, dtype=np.float64)
+    perm = hp.morton_order(fr.nx, fr.ny, fr.nz)
+    real = np.zeros(fr.n, dtype=bool)
+    real[perm] = hp.region_mask(fr.nx, fr.ny, fr.nz, fr.region)
+    out = np.where(real, np.asarray(fr.b, dtype=np.float64), 0.0)
+    if fr.neumann:
+        out[real] -= out[real].mean()
+    return out
 
 
 def rand_factors(part, seed, b_scale=0.05, shift=0.0):
