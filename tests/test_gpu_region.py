@@ -170,36 +170,49 @@ def test_padded_forward_fp32_matches_oracle(which):
             assert v <= 1e-4, (f, k, v)
 
 
-def test_padded_hmat_pcg_with_inferred_factors_matches_oracle():
-    """Inference (FP32, seeded weights) then PCG with the learned M on padded
-    3D frames to 1e-6: flags and iterations against the oracle's PCG with the
-    factors as the device holds them; the frame's own residual meets the
-    tolerance (A has no coupling between frame cells and padding, so the
-    frame's residual is part of the whole one)."""
+@pytest.mark.parametrize("which,weights,tol", [("3d", "seeded", 1e-6), ("2d", "trained_paper2d_L64.npz", 1e-8)])
+def test_padded_hmat_pcg_with_inferred_factors_matches_oracle(which, weights, tol):
+    """Inference (FP32) then PCG with the learned M on padded frames: flags
+    and iterations against the oracle's PCG with the factors as the device
+    holds them, and the frame's own residual within the tolerance (A has no
+    coupling between frame cells and padding, so the frame's residual is
+    part of the whole one).  3D frames with the seeded test weights (their M
+    falls back to Jacobi) at 1e-6; the paper's truncated 2D grids with the
+    2D-trained weights (no fallback) at the benchmark's 1e-8."""
+    import os
     import torch
-    frames = _frames3d()
+    # (the 2D case takes the two truncated frames: at N = 1,024 these weights
+    # meet the rounding breakdown of the singular systems near 1e-8)
+    frames = _frames3d() if which == "3d" else _frames2d()[:2]
     s = Side(DEF, frames)
-    w = _test_weights(DEF)
+    if weights == "seeded":
+        w = _test_weights(DEF)
+    else:
+        z = np.load(os.path.join(os.path.dirname(hp.__file__), "weights", weights), allow_pickle=False)
+        w = {k: z[k] for k in z.files}
     wt = torch.tensor(hp.pack_weights(DEF, w), device="cuda")
     fac = s.B.new_factors(hp.HP_F32)
     s.B.infer_factors(wt, s.rho, s.sys, fac, hp.HP_F32)
     x = torch.zeros(s.B.ntot, dtype=torch.float64, device="cuda")
-    res = s.B.pcg_solve(s.sys, fac, s.b, x, hp.PRECOND_HMAT, fdtype=hp.HP_F32, tol=1e-6)
+    res = s.B.pcg_solve(s.sys, fac, s.b, x, hp.PRECOND_HMAT, fdtype=hp.HP_F32, tol=tol, max_iter=20000)
     held = s.download_factors(fac, hp.HP_F32)
     for f, xf in enumerate(s.split(x)):
         fr, A, b = s.frames[f], s.A[f], s.bo[f]
         G, Bm, Ut, Vt, lam = held[f]
         Mf = lambda v, f=f, G=G, Bm=Bm, Ut=Ut, Vt=Vt, lam=lam: hmatrix.apply(s.parts[f], G, Bm, Ut, Vt, lam,
                                                                               A.diagonal(), v)
-        xo, ko, flo, _ = opcg.solve_with_fallback(A, b, Mf, tol=1e-6)
-        _, k32, fl32, _ = opcg.solve_with_fallback(A, b, Mf, tol=1e-6, fp32_iteration=True)
+        xo, ko, flo, _ = opcg.solve_with_fallback(A, b, Mf, tol=tol, max_iter=20000)
+        _, k32, fl32, _ = opcg.solve_with_fallback(A, b, Mf, tol=tol, max_iter=20000, fp32_iteration=True)
         it, fl, _ = res[f]
         r = b - A @ xf
         real = np.ones(fr.n, bool) if fr.region is None else hp.region_mask(fr.nx, fr.ny, fr.nz, fr.region)
         own = np.linalg.norm(r[real]) / np.linalg.norm(b[real])
-        print(f"frame {f} region {fr.region}: gpu {it} flags {fl} oracle fp32-iteration {k32} fp64 {ko} "
+        print(f"{which} frame {f} region {fr.region}: gpu {it} flags {fl} oracle fp32-iteration {k32} fp64 {ko} "
               f"flags {flo} own relres {own:.2e}")
         assert fl == flo == fl32, (f, fl, flo, fl32)
         assert abs(it - k32) <= max(3, int(0.05 * k32)), (f, it, k32)
-        assert own <= 1e-6 and np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b)
-        assert relerr(xf[real], xo[real]) <= 1e-5
+        assert own <= tol and np.linalg.norm(r) <= tol * np.linalg.norm(b)
+        if not fr.neumann:
+            assert relerr(xf[real], xo[real]) <= 1e-5
+        if weights != "seeded":
+            assert not fl & hp.FELL_BACK, (f, fl)
