@@ -55,6 +55,9 @@ RECIPES: Dict[str, "FrameRecipe | BarrierRecipe"] = {
     "precision8192": FrameRecipe(grids=(GRID_OF_N[8192],), spheres=(8, 8), contrast=(100.0, 100.0)),
     # N=4,096 training systems: 2-8 spheres, contrast uniform in [10, 100]
     "train4096": FrameRecipe(grids=(GRID_OF_N[4096],), spheres=(2, 8), contrast=(10.0, 100.0)),
+    # the same law on the two smaller grids of the mixed batches
+    "train1024": FrameRecipe(grids=(GRID_OF_N[1024],), spheres=(2, 8), contrast=(10.0, 100.0)),
+    "train2048": FrameRecipe(grids=(GRID_OF_N[2048],), spheres=(2, 8), contrast=(10.0, 100.0)),
     # batching: N drawn uniformly from {1,024, 2,048, 4,096, 8,192}
     "batch_mixed": FrameRecipe(grids=tuple(GRID_OF_N[n] for n in (1024, 2048, 4096, 8192)),
                                spheres=(2, 8), contrast=(10.0, 100.0)),

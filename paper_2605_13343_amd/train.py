@@ -116,6 +116,7 @@ class Validator:
 # Seed bases of the training draws per recipe (disjoint from every
 # validation and benchmark seed).
 SEED_BASE = {"train4096": 3_000_000, "precision8192": 5_000_000, "largest16384": 6_000_000,
+             "train1024": 16_000_000, "train2048": 17_000_000,
              "plain1024": 8_000_000, "paper2d_1024": 11_000_000, "paper2d_2048": 12_000_000,
              "paper2d_4096": 13_000_000, "paper2d_8192": 14_000_000, "paper2d_16384": 15_000_000}
 
