@@ -55,12 +55,34 @@ def unpack(cfg, flat: np.ndarray) -> Dict[str, np.ndarray]:
 
 
 def recipe_grid(rc):
-    """(nx, ny, nz) of a one-grid recipe."""
+    """(nx, ny, nz) of a one-grid recipe: the box for padded frames."""
     if isinstance(rc, inputs.BarrierRecipe):
-        return (rc.grid[0], rc.grid[1], 1)
+        g = rc.box if rc.box is not None else rc.grid
+        return (g[0], g[1], 1)
     if len(rc.grids) != 1:
         raise ValueError("training batches use one grid shape per recipe")
     return rc.grids[0]
+
+
+def recipe_region(rc):
+    """(W, H, D, cells) of a padded recipe's frames (see inputs.Frame), else None."""
+    if isinstance(rc, inputs.BarrierRecipe) and rc.box is not None:
+        return (rc.grid[0], rc.grid[1], 1, rc.cells if rc.cells is not None else rc.grid[0] * rc.grid[1])
+    return None
+
+
+def frame_rhs(fr, perm) -> np.ndarray:
+    """The frame's right-hand side in Morton order: for a padded frame b on
+    its own cells (the library's mask), minus its mean there for the
+    zero-flux operator, and 0 on the padding."""
+    bm = np.asarray(fr.b, dtype=np.float64)[perm]
+    if fr.region is None:
+        return bm
+    real = hp.region_mask(fr.nx, fr.ny, fr.nz, fr.region)
+    bm = np.where(real, bm, 0.0)
+    if fr.neumann:
+        bm[real] -= bm[real].mean()
+    return bm
 
 
 def recipe_ops(rc) -> int:
@@ -88,9 +110,11 @@ class Validator:
         dims = [(f.nx, f.ny, f.nz) for f in frames]
         perms = [hp.morton_order(*d) for d in dims]
         self.B = hp.Batch(cfg, dims, stream)
+        if any(f.region is not None for f in frames):
+            self.B.set_regions([f.region for f in frames])
         self.rho = torch.tensor(np.concatenate([f.rho[p] for f, p in zip(frames, perms)]).astype(np.float32),
                                 device="cuda")
-        self.b = torch.tensor(np.concatenate([f.b[p] for f, p in zip(frames, perms)]).astype(np.float32),
+        self.b = torch.tensor(np.concatenate([frame_rhs(f, p) for f, p in zip(frames, perms)]).astype(np.float32),
                               device="cuda")
         self.sys = self.B.new_sys()
         self.B.assemble(self.rho, self.sys, self.ops)
@@ -117,6 +141,7 @@ class Validator:
 # validation and benchmark seed).
 SEED_BASE = {"train4096": 3_000_000, "precision8192": 5_000_000, "largest16384": 6_000_000,
              "train1024": 16_000_000, "train2048": 17_000_000,
+             "paper2d_trunc_2048": 18_000_000, "paper2d_trunc_8192": 19_000_000,
              "plain1024": 8_000_000, "paper2d_1024": 11_000_000, "paper2d_2048": 12_000_000,
              "paper2d_4096": 13_000_000, "paper2d_8192": 14_000_000, "paper2d_16384": 15_000_000}
 
@@ -136,6 +161,8 @@ def train(cfg=inputs.MODEL_DEFAULT, steps: int = 2000, mix=(("train4096", 32),),
         rc = inputs.RECIPES[recipe]
         g = recipe_grid(rc)
         B = hp.Batch(cfg, [g] * batch)
+        if recipe_region(rc) is not None:       # padded frames: the partition of the box
+            B.set_regions([recipe_region(rc)] * batch)
         if loss == "sai":
             B.debug_set("sai_loss", 1)
         trainers.append({"recipe": recipe, "rc": rc, "batch": batch, "B": B, "sys": B.new_sys(),
