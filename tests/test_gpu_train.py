@@ -57,6 +57,9 @@ def _oracle(cfg, s, w, zraw):
 @pytest.mark.parametrize("cfg,recipes", [(PLAIN, [("plain1024", 1000), ("plain1024", 1001)]),
                                          (DEF, [("train4096", 3000000)]),
                                          (DEF, [("batch_mixed", 4001), ("train4096", 3000001)]),
+                                         # a padded frame: the paper's 46 x 45 grid cut to 2,048 cells
+                                         # in its 64 x 64 box (training on the box's partition)
+                                         (DEF, [("paper2d_trunc_2048", 9400)]),
                                          # the ablation variants' reverse passes
                                          (dataclasses.replace(DEF, layers=2, highways=False),
                                           [("train4096", 3000002)]),
