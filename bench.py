@@ -162,6 +162,8 @@ def main() -> int:
                     help="headline, rooflines, FP32 and Jacobi legs only (no largest, batching, streaming legs)")
     ap.add_argument("--method-only", action="store_true",
                     help="time only the BF16 batched method (for counter runs under rocprofv3)")
+    ap.add_argument("--streaming-only", action="store_true",
+                    help="run only the streaming SpMV / apply leg (for counter runs under rocprofv3)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -188,6 +190,9 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.streaming_only:
+        print(json.dumps({"metric": "streaming SpMV / apply (counter run)", "streaming": _streaming_leg(cfg, frames, stream)}))
+        return 0
 
     # ---------------------------------------------------------------- batched BF16 method (headline)
     I = Inputs(cfg, frames, stream)
