@@ -81,23 +81,6 @@ struct SysPtr {
         wz8(dg8 + 3 * ntot) {}
 };
 
-// (A v)_i in FP32 with v read through a functor (7-point stencil, Morton).
-template <typename V>
-__device__ inline float stencil_f32(const SysPtr& s, const FrameDesc& F, unsigned c, V v) {
-  int64_t i = F.n0 + c;
-  int64_t xp = F.n0 + mstep_plus(c, F.xm), xn = F.n0 + mstep_minus(c, F.xm);
-  int64_t yp = F.n0 + mstep_plus(c, F.ym), yn = F.n0 + mstep_minus(c, F.ym);
-  int64_t zp = F.n0 + mstep_plus(c, F.zm), zn = F.n0 + mstep_minus(c, F.zm);
-  float a = s.dg[i] * v(i);
-  a = fmaf(-s.wx[i], v(xp), a);
-  a = fmaf(-s.wx[xn], v(xn), a);
-  a = fmaf(-s.wy[i], v(yp), a);
-  a = fmaf(-s.wy[yn], v(yn), a);
-  a = fmaf(-s.wz[i], v(zp), a);
-  a = fmaf(-s.wz[zn], v(zn), a);
-  return a;
-}
-
 // b_i - (A v)_i in FP64 with the FP64 coefficients (v is FP32, exact in FP64).
 template <typename V>
 __device__ inline double resid_f64(const SysPtr& s, const FrameDesc& F, unsigned c, double bi, V v) {
@@ -169,8 +152,25 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_spmv(const FrameDesc* fr, const 
   const FrameDesc F = fr[blk2f[bid]];
   int c = (bid - F.b0) * NODE_BLOCK + threadIdx.x;
   if (c >= F.n) return;
+  // (A p)_i in FP32: the diagonal term, then the faces +x, -x, +y, -y, +z, -z
+  // as FMAs in that order.  The node's own coefficients are read once and q
+  // written once: streaming (non-temporal) accesses keep them from evicting
+  // the p values that the neighbours read again
   SysPtr s(sys, ntot);
-  q[F.n0 + c] = stencil_f32(s, F, c, [&](int64_t j) { return p[j]; });
+  const int64_t i = F.n0 + c;
+  const int64_t xp = F.n0 + mstep_plus(c, F.xm), xn = F.n0 + mstep_minus(c, F.xm);
+  const int64_t yp = F.n0 + mstep_plus(c, F.ym), yn = F.n0 + mstep_minus(c, F.ym);
+  const int64_t zp = F.n0 + mstep_plus(c, F.zm), zn = F.n0 + mstep_minus(c, F.zm);
+  const float dgi = __builtin_nontemporal_load(s.dg + i), wxi = __builtin_nontemporal_load(s.wx + i);
+  const float wyi = __builtin_nontemporal_load(s.wy + i), wzi = __builtin_nontemporal_load(s.wz + i);
+  float a = dgi * p[i];
+  a = fmaf(-wxi, p[xp], a);
+  a = fmaf(-s.wx[xn], p[xn], a);
+  a = fmaf(-wyi, p[yp], a);
+  a = fmaf(-s.wy[yn], p[yn], a);
+  a = fmaf(-wzi, p[zp], a);
+  a = fmaf(-s.wz[zn], p[zn], a);
+  __builtin_nontemporal_store(a, q + i);
 }
 
 // ------------------------------------------------------------------ H-matrix stages
@@ -615,7 +615,8 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_spmv_p(const FrameDesc* fr, cons
   const float beta = (float)S.beta;
   double pq = 0.0;
   if (own) {
-    // the same operation order as stencil_f32 with p = z + beta p_old
+    // the same operation order as k_spmv (diagonal, then +x, -x, +y, -y, +z,
+    // -z) with p = z + beta p_old
     float P[7];
 #pragma unroll
     for (int e = 0; e < 7; ++e) P[e] = fmaf(beta, pv[e], zv[e]);
