@@ -190,7 +190,9 @@ hp_status hp_spmv(hp_batch b, const float* d_sys, const float* d_p, float* d_q);
 /* Packed factors of M, per batch (paper Sec. 4.4 "All factors pack into a
  * single tensor"): byte sections [G: ktot L L][B: mtot Ls Ls][Ut: ntot Ls]
  * [Vt: ntot Ls] in the factor dtype, then [lam: ntot] FP32, each section
- * 256-byte aligned at the offsets hp_batch_info reports.  G_k = F_k F_k^T is
+ * 256-byte aligned at the offsets hp_batch_info reports.  The buffer itself
+ * must be 16-byte aligned (the kernels read it in 16-byte loads); the calls
+ * that read it return HP_E_INVALID otherwise.  G_k = F_k F_k^T is
  * stored (the diagonal block of M, Sec. 4.2), B_m = U_m V_m^T.  Within a
  * section frames follow each other, so a one-frame batch holds exactly the
  * paper's per-frame packing [K L^2][M_H L_s^2][N L_s][N L_s][N].

@@ -300,6 +300,7 @@ static hp_status apply_args(hp_batch b, const float* d_sys, const void* d_factor
   if (!b || !d_sys || !d_factors || !d_r || !d_y) return set_error(HP_E_INVALID, "%s: NULL argument", who);
   if (ncols < 1) return set_error(HP_E_INVALID, "%s: ncols must be >= 1", who);
   if (fdtype != HP_F32 && fdtype != HP_BF16) return set_error(HP_E_INVALID, "%s: bad fdtype", who);
+  if ((uintptr_t)d_factors & 15) return set_error(HP_E_INVALID, "%s: factors must be 16-byte aligned", who);
   const uintptr_t r0 = (uintptr_t)d_r, y0 = (uintptr_t)d_y, len = (uintptr_t)(4 * b->ntot * (int64_t)ncols);
   if (r0 < y0 + len && y0 < r0 + len) return set_error(HP_E_INVALID, "%s: r and y must not overlap", who);
   int64_t tot;
@@ -465,6 +466,8 @@ static hp_status check_solve(hp_batch b, const float* d_sys, const void* d_facto
   const hp_solve_opts& o = *opts;
   if (o.precond < 0 || o.precond > 2) return set_error(HP_E_INVALID, "%s: bad precond", who);
   if (o.precond == HP_PRECOND_HMAT && !d_factors) return set_error(HP_E_INVALID, "%s: factors required for HMAT", who);
+  if (o.precond == HP_PRECOND_HMAT && ((uintptr_t)d_factors & 15))
+    return set_error(HP_E_INVALID, "%s: factors must be 16-byte aligned", who);
   if (o.precond == HP_PRECOND_HMAT && o.fdtype != HP_F32 && o.fdtype != HP_BF16)
     return set_error(HP_E_INVALID, "%s: bad fdtype", who);
   if (!(o.tol >= 0) || o.max_iter < 0 || o.recompute_every < 0)

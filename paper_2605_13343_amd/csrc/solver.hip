@@ -187,7 +187,20 @@ struct Factors {
 // Load n consecutive factor values as floats (vectorised).
 template <typename FT, int N>
 __device__ inline void load_vec(const FT* p, float* out) {
-  if constexpr (sizeof(FT) == 2) {
+  if constexpr (sizeof(FT) == 2 && N % 8 == 0) {
+    // 16-byte loads (every caller's range starts on a multiple of 8 elements)
+    const uint4* q = reinterpret_cast<const uint4*>(p);
+#pragma unroll
+    for (int i = 0; i < N / 8; ++i) {
+      const uint4 u = q[i];
+      const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        out[8 * i + 2 * h] = bf16_to_f32((uint16_t)(w[h] & 0xffff));
+        out[8 * i + 2 * h + 1] = bf16_to_f32((uint16_t)(w[h] >> 16));
+      }
+    }
+  } else if constexpr (sizeof(FT) == 2) {
     static_assert(N % 4 == 0, "bf16 vector loads come in fours");
     const uint2* q = reinterpret_cast<const uint2*>(p);
 #pragma unroll
@@ -459,9 +472,11 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_apply_leaf(const FrameDesc* fr
   const int64_t kg = blockIdx.x;
   const FrameDesc F = fr[leaf2f[kg]];
   const int64_t row0 = F.n0 + (kg - F.k0) * L;
+  LeafPre<L, LS, FT> pre;
+  pre.load(kg, row0, fac, sys + 4 * ntot);  // G, Ut, Vt and the gate ahead of the barrier
   for (int l = threadIdx.x; l < L; l += blockDim.x) rs[l] = r[row0 + l];
   __syncthreads();
-  leaf_stage<L, LS, FT>(kg, row0, rs, fac, sys + 4 * ntot, y, uh, vh, red);
+  pre.apply(kg, row0, rs, y, uh, vh, red);
 }
 
 // One block per coarse block (a tile, or a placeholder for a frame without
@@ -1050,6 +1065,7 @@ extern "C" hp_status hp_apply_static(int32_t nx, int32_t ny, int32_t nz, int32_t
   if (!d_sys || !d_factors || !d_r || !d_y) return set_error(HP_E_INVALID, "hp_apply_static: NULL argument");
   if (ncols < 1) return set_error(HP_E_INVALID, "hp_apply_static: ncols must be >= 1");
   if (fdtype != HP_F32 && fdtype != HP_BF16) return set_error(HP_E_INVALID, "hp_apply_static: bad fdtype");
+  if ((uintptr_t)d_factors & 15) return set_error(HP_E_INVALID, "hp_apply_static: factors must be 16-byte aligned");
   if (!((leaf == 64 && rank == 16) || (leaf == 32 && rank == 8)))
     return set_error(HP_E_SHAPE, "hp_apply_static: supported (leaf, rank): (64, 16), (32, 8)");
   if (nx <= 0 || ny <= 0 || nz <= 0 || !admissible_grid(nx, ny, nz, nullptr))
