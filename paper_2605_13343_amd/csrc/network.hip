@@ -3278,11 +3278,6 @@ static hp_status forward(Batch& b, const float* W, const float* rho, const float
     HP_HIP(hipStreamWaitEvent(b.offs, b.off_ev[0], 0));
   }
   for (int l = 0; l < b.cfg.layers; ++l) HP_TRY(layer_fwd<AT>(b, W, sys, l, nullptr));
-  if (N.par) {  // the heads read the off stack's last output
-    HP_HIP(hipEventRecord(b.off_ev[1], b.offs));
-    HP_HIP(hipStreamWaitEvent(b.stream, b.off_ev[1], 0));
-  }
-  if (N.pre_side) HP_HIP(hipStreamWaitEvent(b.stream, b.side_done, 0));  // every side launch joined
   const NetPlan& P = N.plan;
   const hp_model_config& c = b.cfg;
   hipStream_t st = b.stream;
@@ -3313,6 +3308,14 @@ static hp_status forward(Batch& b, const float* W, const float* rho, const float
   else
     hipLaunchKernelGGL((k_pack_nodes<FT, 8>), dim3((unsigned)((Nd + 255) / 256)), dim3(256), 0, st,
                        (const float*)N.NH, Nd, (FT*)(base + offs[2]), (FT*)(base + offs[3]), (float*)(base + offs[4]));
+  // the diagonal tokens' heads above need only this stream's work; the
+  // off-diagonal head reads the off stack's last output, so the streams join
+  // here (the off stack's last layer ran beside the heads above)
+  if (N.par) {
+    HP_HIP(hipEventRecord(b.off_ev[1], b.offs));
+    HP_HIP(hipStreamWaitEvent(b.stream, b.off_ev[1], 0));
+  }
+  if (N.pre_side) HP_HIP(hipStreamWaitEvent(b.stream, b.side_done, 0));  // every side launch joined
   if (b.mtot > 0) {
     if (use_off) {
       hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((No + 15) / 16)), dim3(256), 0, st, (const float*)N.Xo,

@@ -348,3 +348,24 @@ def test_solve_step_graph_equals_separate_calls(torch_cuda):
     print("iterations", [r[0] for r in r0], "after the change", [r[0] for r in r3])
     assert r2 == r3 and torch.equal(x2, x3) and torch.equal(f2, f3)
     assert all(r[1] & hp.CONVERGED for r in r3)
+
+
+def test_factor_buffers_must_be_16_byte_aligned(torch_cuda):
+    """The factor-reading calls reject a buffer that is not 16-byte aligned
+    (their kernels read it in 16-byte pieces) before launching anything."""
+    import torch
+    s = Side(DEF, [inputs.make_frame("plain1024", 1000)])
+    fac, _ = s.upload_factors([rand_factors(s.parts[0], 60, b_scale=2e-4, shift=1.0)], hp.HP_BF16)
+    big = torch.zeros(fac.numel() + 16, dtype=torch.uint8, device="cuda")
+    off = big[8:8 + fac.numel()]
+    off.copy_(fac)
+    r = torch.ones_like(s.b)
+    y = torch.zeros_like(s.b)
+    with pytest.raises(RuntimeError, match="16-byte aligned"):
+        s.B.apply(s.sys, off, hp.HP_BF16, r, y)
+    x = torch.zeros(s.B.ntot, dtype=torch.float64, device="cuda")
+    with pytest.raises(RuntimeError, match="16-byte aligned"):
+        s.B.pcg_solve(s.sys, off, s.b, x, hp.PRECOND_HMAT, fdtype=hp.HP_BF16)
+    s.B.apply(s.sys, fac, hp.HP_BF16, r, y)   # the aligned buffer still works
+    torch.cuda.synchronize()
+    assert torch.isfinite(y).all()
