@@ -131,6 +131,11 @@ extern "C" hp_status hp_batch_create(const hp_model_config* cfg, int32_t nframes
     morton_masks(nx, ny, nz, &F.xm, &F.ym, &F.zm);
     F.nb = (n + NODE_BLOCK - 1) / NODE_BLOCK;
     F.b0 = nb0;
+    // the leaf kernels take a leaf's first row as (global leaf) x L
+    if ((int64_t)F.n0 != (int64_t)F.k0 * L || (int64_t)F.n != (int64_t)F.K * L) {
+      delete b;
+      return set_error(HP_E_SHAPE, "hp_batch_create: frame %d is not a whole number of leaves", f);
+    }
     b->fr.push_back(F);
     b->dims.push_back({nx, ny, nz});
     n0 += n;
