@@ -437,20 +437,14 @@ __device__ inline void gather_leaf(const FrameDesc& F, int64_t kg, int s, const 
   float a = 0.f, c = 0.f;
   constexpr int JMAX = 16;  // every level's load in flight at once (up to 2^16 leaves)
   if (F.J <= JMAX) {
-    if (F.J == 0) {  // a frame of one leaf has no tiles
-      Tr = 0.f;
-      Tc = 0.f;
-      return;
-    }
-    // one unconditional load per level, levels past J reading level J - 1
-    // again (loads inside the conditions made each level wait for the last)
     float tv[JMAX];
 #pragma unroll
     for (int j = 0; j < JMAX; ++j) {
-      const int jj = j < F.J ? j : F.J - 1;
-      const int64_t m = (int64_t)F.m0 + K - (K >> jj) + (k >> (jj + 1));
-      const float* src = ((k >> jj) & 1) == 0 ? tr : tc;
-      tv[j] = src[m * LS + s];
+      tv[j] = 0.f;
+      if (j < F.J) {
+        const int64_t m = (int64_t)F.m0 + K - (K >> j) + (k >> (j + 1));
+        tv[j] = ((k >> j) & 1) == 0 ? tr[m * LS + s] : tc[m * LS + s];
+      }
     }
 #pragma unroll
     for (int j = 0; j < JMAX; ++j)
@@ -819,32 +813,27 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_prolong(const FrameDesc* fr, c
   __shared__ float trs[LS], tcs[LS];
   __shared__ double dred[LEAF_THREADS / 64];
   const int64_t kg = blockIdx.x;
-  const int64_t row0 = kg * L;  // n0 = k0 L: the leaf's rows do not wait for its frame
   const int f = leaf2f[kg];
+  const FrameDesc F = fr[f];
+  if (B_.st[2 * f].done) return;
+  const int64_t row0 = F.n0 + (kg - F.k0) * L;
   constexpr int TPR = LEAF_THREADS / L;
   const int row = threadIdx.x / TPR;
   const bool lead = threadIdx.x % TPR == 0;
   ProlongPre<L, LS, FT> pre;
   pre.load(row0, fac);
-  // every lane loads its row's z and r (no divergent branch, whose join
-  // would wait for the loads); the row's lead lane keeps them
-  const float zall = B_.z[row0 + row], rall = B_.r[row0 + row];
-  float zr = lead ? zall : 0.f;
-  const float rr = lead ? rall : 0.f;
-  const FrameDesc F = fr[f];
-  // a stopped frame's blocks run through and store nothing (an early return
-  // would let the compiler sink the loads above behind the state's)
-  const bool done = B_.st[2 * f].done != 0;
+  float zr = lead ? B_.z[row0 + row] : 0.f;
+  const float rr = lead ? B_.r[row0 + row] : 0.f;
   if (threadIdx.x < LS) gather_leaf<LS>(F, kg, threadIdx.x, B_.Tr, B_.Tc, trs[threadIdx.x], tcs[threadIdx.x]);
   __syncthreads();
   zr = pre.apply(trs, tcs, zr);
   double rz = 0.0;
   if (lead) {
-    if (!done) B_.z[row0 + row] = zr;
+    B_.z[row0 + row] = zr;
     rz = (double)rr * (double)zr;
   }
   double bs = block_sum(rz, dred);
-  if (threadIdx.x == 0 && !done) B_.part_rz[kg] = bs;
+  if (threadIdx.x == 0) B_.part_rz[kg] = bs;
 }
 
 // Setup for the learned preconditioner (leaf blocks): r = b - A x0 in FP64,
