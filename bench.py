@@ -61,27 +61,13 @@ def _weights(cfg, name=None):
     return inputs.init_weights(cfg, 7), "seeded-init"
 
 
-def _rhs(fr, perm):
-    """The frame's right-hand side in Morton order.  A padded frame's is b on
-    its own cells (the library's mask), minus its mean there for the
-    zero-flux operator, and 0 on the padding."""
-    from paper_2605_13343_amd import hp
-    bm = np.asarray(fr.b, dtype=np.float64)[perm]
-    if fr.region is None:
-        return bm
-    real = hp.region_mask(fr.nx, fr.ny, fr.nz, fr.region)
-    bm = np.where(real, bm, 0.0)
-    if fr.neumann:
-        bm[real] -= bm[real].mean()
-    return bm
-
-
 class Inputs:
     """One batch of frames with its inputs resident in HBM."""
 
     def __init__(self, cfg, frames, stream, batch=None, ops=0):
         import torch
         from paper_2605_13343_amd import hp
+        from paper_2605_13343_amd.train import frame_rhs
         self.frames = frames
         self.ops = ops
         self.dims = [(f.nx, f.ny, f.nz) for f in frames]
@@ -95,7 +81,7 @@ class Inputs:
             self.B.set_regions([f.region for f in frames])
         self.rho = torch.tensor(np.concatenate([f.rho[p] for f, p in zip(frames, self.perms)]).astype(np.float32),
                                 device="cuda")
-        self.b = torch.tensor(np.concatenate([_rhs(f, p) for f, p in zip(frames, self.perms)]).astype(np.float32),
+        self.b = torch.tensor(np.concatenate([frame_rhs(f, p) for f, p in zip(frames, self.perms)]).astype(np.float32),
                               device="cuda")
         self.sys = self.B.new_sys()
         self.B.assemble(self.rho, self.sys, ops)
