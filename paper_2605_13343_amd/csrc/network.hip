@@ -1072,7 +1072,8 @@ struct DescChunk {
 __global__ __launch_bounds__(256) void k_off_desc_part(const FrameDesc* fr, const int* tile2f, const DescChunk* ch,
                                                        const float* sys, int64_t ntot, int L, int LS, double* part) {
   __shared__ double sval[DESC_CHUNK * DESC_MAX_LEAF][6];
-  __shared__ int8_t sgrp[DESC_CHUNK * DESC_MAX_LEAF][6];
+  __shared__ __align__(8) uint8_t sgrp[DESC_CHUNK * DESC_MAX_LEAF][8];  // 6 used: one 8-byte read a node
+  __shared__ int scrd[2][DESC_CHUNK][DESC_MAX_LEAF / 4][3];  // token coordinate sums: row, column strip
   const DescChunk c = ch[blockIdx.x];
   const FrameDesc F = fr[tile2f[c.tile]];
   const int m = c.tile - F.m0, K = F.K;
@@ -1088,7 +1089,7 @@ __global__ __launch_bounds__(256) void k_off_desc_part(const FrameDesc* fr, cons
     for (int a = 0; a < 3; ++a) {
       for (int sgn = 0; sgn < 2; ++sgn) {
         const int e = 2 * a + sgn;
-        int8_t g = -1;
+        uint8_t g = 255;  // none
         double v = 0.0;
         const bool edge = sgn == 0 ? (ci & masks[a]) == masks[a] : (ci & masks[a]) == 0;
         if (!edge) {
@@ -1096,7 +1097,7 @@ __global__ __launch_bounds__(256) void k_off_desc_part(const FrameDesc* fr, cons
           const int kj = cj / L;
           if (kj >= c0 && kj < c0 + S) {
             const double w = sgn == 0 ? w8[a][F.n0 + ci] : w8[a][F.n0 + cj];
-            g = (int8_t)((cj % L) / p);
+            g = (uint8_t)((cj % L) / p);
             v = -w / sqrt(d8[F.n0 + ci] * d8[F.n0 + cj]);
           }
         }
@@ -1105,21 +1106,36 @@ __global__ __launch_bounds__(256) void k_off_desc_part(const FrameDesc* fr, cons
       }
     }
   }
+  // Coordinate sums of every token of the chunk, once per (strip, leaf,
+  // token, axis).  A token's p cells are consecutive and its first is a
+  // multiple of p, so they are first | i (i < p), and the sum over them is
+  // p mcoord(first) + the sum of mcoord(i) (only the mask's bits below p
+  // matter there).  The sums are integers: exact in FP64 in any order.
+  const int nk = c.k1 - c.k0;
+  for (int q = threadIdx.x; q < 2 * nk * LS * 3; q += blockDim.x) {
+    const int a = q % 3, tok = (q / 3) % LS, kk = (q / (3 * LS)) % nk, side = q / (3 * LS * nk);
+    const unsigned first = (unsigned)(((side ? c0 : r0) + c.k0 + kk) * L + tok * p);
+    const unsigned lm = masks[a] & (unsigned)(p - 1);
+    int lo = 0;
+    for (int u = 0; u < p; ++u) lo += mcoord((unsigned)u, lm);
+    scrd[side][kk][tok][a] = p * mcoord(first, masks[a]) + lo;
+  }
   __syncthreads();
   const int t = threadIdx.x / LS, t2 = threadIdx.x % LS;
   if (t >= LS) return;
   double cI[3] = {0, 0, 0}, cJ[3] = {0, 0, 0}, acc = 0.0;
   for (int k = c.k0; k < c.k1; ++k) {
-    for (int l = t * p; l < (t + 1) * p; ++l) {
-      const unsigned ci = (unsigned)((r0 + k) * L + l);
-      for (int a = 0; a < 3; ++a) cI[a] += mcoord(ci, masks[a]);
-      const int n = (k - c.k0) * L + l;
-      for (int e = 0; e < 6; ++e)
-        if (sgrp[n][e] == t2) acc += sval[n][e];
+    const int kk = k - c.k0;
+    for (int a = 0; a < 3; ++a) {
+      cI[a] += (double)scrd[0][kk][t][a];
+      cJ[a] += (double)scrd[1][kk][t2][a];
     }
-    for (int l = t2 * p; l < (t2 + 1) * p; ++l) {
-      const unsigned cj = (unsigned)((c0 + k) * L + l);
-      for (int a = 0; a < 3; ++a) cJ[a] += mcoord(cj, masks[a]);
+    for (int l = t * p; l < (t + 1) * p; ++l) {
+      const int n = (k - c.k0) * L + l;
+      const uint2 gw = *reinterpret_cast<const uint2*>(&sgrp[n][0]);
+#pragma unroll
+      for (int e = 0; e < 6; ++e)
+        if ((((e < 4 ? gw.x : gw.y) >> (8 * (e & 3))) & 0xffu) == (unsigned)t2) acc += sval[n][e];
     }
   }
   double* o = part + ((int64_t)blockIdx.x * LS * LS + t * LS + t2) * 7;
