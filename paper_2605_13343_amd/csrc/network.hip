@@ -1056,8 +1056,9 @@ __global__ __launch_bounds__(256) void k_edge_corr(EdgeW w, const float* slots, 
 //   (centroid(J_m^t') - centroid(I_m^t)) / 4,  mean of Ahat over I_m^t x J_m^t'.
 // The strip pairs of a tile are split into chunks of at most DESC_CHUNK
 // leaves a side (a big tile's serial loop would otherwise dominate): one
-// block per chunk, FP64 partial sums [chunk][t][t'][cI x, y, z | cJ x, y, z |
-// sum Ahat]; a second kernel adds a tile's chunks in order.  Within a block,
+// block per chunk, FP64 partial sums per chunk (the Ahat sum of every token
+// pair, the coordinate sums of every row and column token); a second kernel
+// adds a tile's chunks in order.  Within a block,
 // one thread per row-strip node first finds its stencil entries that land
 // in the column strip (the group t' of each and its Ahat, once per entry);
 // thread (t, t') then adds those of group t whose target is in group t', in
@@ -1138,12 +1139,15 @@ __global__ __launch_bounds__(256) void k_off_desc_part(const FrameDesc* fr, cons
         if ((((e < 4 ? gw.x : gw.y) >> (8 * (e & 3))) & 0xffu) == (unsigned)t2) acc += sval[n][e];
     }
   }
-  double* o = part + ((int64_t)blockIdx.x * LS * LS + t * LS + t2) * 7;
-  for (int a = 0; a < 3; ++a) {
-    o[a] = cI[a];
-    o[3 + a] = cJ[a];
-  }
-  o[6] = acc;
+  // chunk record: [Ahat sums, LS x LS | row-token coordinate sums, LS x 3 |
+  // column-token coordinate sums, LS x 3] (a row token's sums do not depend on
+  // t', nor a column token's on t)
+  double* o = part + (int64_t)blockIdx.x * (LS * LS + 6 * LS);
+  o[t * LS + t2] = acc;
+  if (t2 == 0)
+    for (int a = 0; a < 3; ++a) o[LS * LS + t * 3 + a] = cI[a];
+  if (t == 0)
+    for (int a = 0; a < 3; ++a) o[LS * LS + 3 * LS + t2 * 3 + a] = cJ[a];
 }
 
 // desc of tile (block) mg from its chunks [chunk0[mg], chunk0[mg + 1]).
@@ -1159,8 +1163,12 @@ __global__ __launch_bounds__(256) void k_off_desc_final(const FrameDesc* fr, con
   if (t >= LS) return;
   double v[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int c = chunk0[mg]; c < chunk0[mg + 1]; ++c) {
-    const double* o = part + ((int64_t)c * LS * LS + t * LS + t2) * 7;
-    for (int q = 0; q < 7; ++q) v[q] += o[q];
+    const double* o = part + (int64_t)c * (LS * LS + 6 * LS);
+    for (int a = 0; a < 3; ++a) {
+      v[a] += o[LS * LS + t * 3 + a];
+      v[3 + a] += o[LS * LS + 3 * LS + t2 * 3 + a];
+    }
+    v[6] += o[t * LS + t2];
   }
   const double inv = 1.0 / (double)(S * p);
   float* out = desc + (((int64_t)mg * LS + t) * LS + t2) * 4;
@@ -2478,7 +2486,7 @@ static hp_status network_alloc_impl(Batch& b) {
   N->ndesc_chunks = (int)dch.size();
   A(&N->desc_chunks, std::max<size_t>(dch.size(), 1) * sizeof(DescChunk));
   A(&N->desc_chunk0, dch0.size() * sizeof(int));
-  A(&N->desc_part, std::max<size_t>(dch.size(), 1) * c.rank * c.rank * 7 * sizeof(double));
+  A(&N->desc_part, std::max<size_t>(dch.size(), 1) * (c.rank * c.rank + 6 * c.rank) * sizeof(double));
   A(&N->chunks, ch.size() * sizeof(SumChunk));
   A(&N->gpart, ch.size() * 128 * 4);
   if (s != HP_OK) return s;
