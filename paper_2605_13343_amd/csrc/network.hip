@@ -885,6 +885,13 @@ struct EdgeW {
   const float *w1, *b1, *w2, *b2;
   int E, H;
 };
+// The edge MLPs of up to EDGE_LAYERS layers, layer blockIdx.y of a launch:
+// the inference computes every layer's tables in one launch per kernel, each
+// layer into its own buffer (outputs advance by a per-layer stride).
+constexpr int EDGE_LAYERS = 8;
+struct EdgeWs {
+  EdgeW w[EDGE_LAYERS];
+};
 
 // The edge MLP's parameters [W1 (4E) | b1 (E) | W2 (E H) | b2 (H)] are
 // contiguous in the weight vector; each block stages them in LDS once.
@@ -962,9 +969,12 @@ __device__ inline void edge_slot_consts(const float* sw, int E, int H, float* ou
 // Every leaf has the same shape, so one table per layer serves all leaves.
 // The block after the table's blocks writes the stencil-slot constants.
 template <bool FAST>
-__global__ __launch_bounds__(256) void k_edge_table(EdgeW w, int L, unsigned xm, unsigned ym, unsigned zm, float* T0,
-                                                    float* slots) {
+__global__ __launch_bounds__(256) void k_edge_table(EdgeWs ws, int L, unsigned xm, unsigned ym, unsigned zm, float* T0,
+                                                    float* slots, int64_t t0_stride, int slot_stride) {
   __shared__ float sw[EDGE_MAX_FLOATS];
+  const EdgeW w = ws.w[blockIdx.y];
+  T0 += blockIdx.y * t0_stride;
+  slots += blockIdx.y * slot_stride;
   edge_stage(w, sw);
   if (blockIdx.x == gridDim.x - 1) {
     edge_slot_consts<FAST>(sw, w.E, w.H, slots);
@@ -1017,10 +1027,13 @@ __global__ void k_leaf_stencil(const FrameDesc* fr, const int* node2f, const flo
 // slot) pair, the same operations as edge_mlp with the first three input
 // terms taken from the slot constants; grid-stride over pairs.
 template <bool FAST, int HK = 0, int EK = 0>
-__global__ __launch_bounds__(256) void k_edge_corr(EdgeW w, const float* slots, const uint8_t* nbr, const float* ahat,
-                                                   int64_t ntot, float* corr) {
+__global__ __launch_bounds__(256) void k_edge_corr(EdgeWs ws, const float* slots, const uint8_t* nbr, const float* ahat,
+                                                   int64_t ntot, float* corr, int slot_stride, int64_t corr_stride) {
   __shared__ float cst[EDGE_CST];
   __shared__ float sw[EDGE_MAX_FLOATS];
+  const EdgeW w = ws.w[blockIdx.y];
+  slots += blockIdx.y * slot_stride;
+  corr += blockIdx.y * corr_stride;
   for (int q = threadIdx.x; q < EDGE_CST; q += blockDim.x) cst[q] = slots[q];
   edge_stage(w, sw);  // ends with a barrier
   const int E = EK ? EK : w.E, H = HK ? HK : w.H;
@@ -1178,8 +1191,11 @@ __global__ __launch_bounds__(256) void k_off_desc_final(const FrameDesc* fr, con
 
 // Off-diagonal bias per layer: bias[m][h][t][t'] = MLP_e(desc[m][t][t']).
 template <bool FAST, int HK = 0, int EK = 0>
-__global__ __launch_bounds__(256) void k_edge_off(EdgeW w, const float* desc, int64_t npairs, int LS, float* bias) {
+__global__ __launch_bounds__(256) void k_edge_off(EdgeWs ws, const float* desc, int64_t npairs, int LS, float* bias,
+                                                  int64_t bias_stride) {
   __shared__ float sw[EDGE_MAX_FLOATS];
+  const EdgeW w = ws.w[blockIdx.y];
+  bias += blockIdx.y * bias_stride;
   edge_stage(w, sw);
   const int H = HK ? HK : w.H;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npairs; p += (int64_t)gridDim.x * blockDim.x) {
@@ -2989,37 +3005,48 @@ static EdgeTabs edge_tabs(const Batch& b, const NetBufs& N, int l) {
           N.boffl + (size_t)l * std::max<int64_t>(b.mtot, 1) * c.heads * c.rank * c.rank};
 }
 
-// Layer l's edge-bias tables of one stack (sidx 0: the within-leaf table T0,
-// the slot constants and the stencil corrections; 1: the off-diagonal pair
-// biases), from the edge MLP's FP32 weights.
+// Edge-bias tables of layers [l0, l0 + nl) of one stack (sidx 0: the
+// within-leaf table T0, the slot constants and the stencil corrections; 1:
+// the off-diagonal pair biases), from the edge MLP's FP32 weights, one launch
+// per kernel with the layer as blockIdx.y.  Several layers at once need the
+// inference's per-layer buffers (N.pre), whose layers lie a fixed stride apart.
 template <typename AT>
-static void edge_tables(Batch& b, const float* W, int l, int sidx, const EdgeTabs& t, hipStream_t st) {
+static void edge_tables(Batch& b, const float* W, int l0, int nl, int sidx, hipStream_t st) {
   NetBufs& N = *nb_of(b);
   const NetPlan& P = N.plan;
   const hp_model_config& c = b.cfg;
   const int64_t Nd = N.Nd, L = c.leaf, LS = c.rank, H = c.heads;
-  const std::string p = std::string(sidx ? "off" : "diag") + std::to_string(l) + ".";
   auto wp = [&](const std::string& n) { return W + woff(P, n); };
-  EdgeW ew{wp(p + "e1.w"), wp(p + "e1.b"), wp(p + "e2.w"), wp(p + "e2.b"), c.edge_hidden, (int)H};
+  EdgeWs ws{};
+  for (int q = 0; q < nl; ++q) {
+    const std::string p = std::string(sidx ? "off" : "diag") + std::to_string(l0 + q) + ".";
+    ws.w[q] = EdgeW{wp(p + "e1.w"), wp(p + "e1.b"), wp(p + "e2.w"), wp(p + "e2.b"), c.edge_hidden, (int)H};
+  }
+  const EdgeTabs t = edge_tabs(b, N, l0), t1 = nl > 1 ? edge_tabs(b, N, l0 + 1) : t;
+  const int64_t t0_stride = t1.T0 - t.T0, corr_stride = t1.corr - t.corr, boff_stride = t1.boff - t.boff;
+  const int slot_stride = (int)(t1.eslots - t.eslots);
   if (sidx == 0) {
     const unsigned lowmask = (unsigned)(L - 1);
     const FrameDesc& F0 = b.fr[0];
-    hipLaunchKernelGGL(k_edge_table<sizeof(AT) == 2>, dim3((unsigned)((L * L + 255) / 256 + 1)), dim3(256), 0, st, ew,
-                       (int)L, F0.xm & lowmask, F0.ym & lowmask, F0.zm & lowmask, t.T0, t.eslots);
+    hipLaunchKernelGGL(k_edge_table<sizeof(AT) == 2>, dim3((unsigned)((L * L + 255) / 256 + 1), (unsigned)nl),
+                       dim3(256), 0, st, ws, (int)L, F0.xm & lowmask, F0.ym & lowmask, F0.zm & lowmask, t.T0,
+                       t.eslots, t0_stride, slot_stride);
     if (H == 4 && c.edge_hidden == 32)  // the paper's widths: compile-time loops
-      hipLaunchKernelGGL((k_edge_corr<sizeof(AT) == 2, 4, 32>), dim3((unsigned)((Nd * 7 + 255) / 256)), dim3(256), 0,
-                         st, ew, (const float*)t.eslots, (const uint8_t*)N.nbr, (const float*)N.ahat, Nd, t.corr);
+      hipLaunchKernelGGL((k_edge_corr<sizeof(AT) == 2, 4, 32>), dim3((unsigned)((Nd * 7 + 255) / 256), (unsigned)nl),
+                         dim3(256), 0, st, ws, (const float*)t.eslots, (const uint8_t*)N.nbr, (const float*)N.ahat,
+                         Nd, t.corr, slot_stride, corr_stride);
     else
-      hipLaunchKernelGGL(k_edge_corr<sizeof(AT) == 2>, dim3((unsigned)((Nd * 7 + 255) / 256)), dim3(256), 0, st, ew,
-                         (const float*)t.eslots, (const uint8_t*)N.nbr, (const float*)N.ahat, Nd, t.corr);
+      hipLaunchKernelGGL(k_edge_corr<sizeof(AT) == 2>, dim3((unsigned)((Nd * 7 + 255) / 256), (unsigned)nl),
+                         dim3(256), 0, st, ws, (const float*)t.eslots, (const uint8_t*)N.nbr, (const float*)N.ahat,
+                         Nd, t.corr, slot_stride, corr_stride);
   } else {
     const int64_t npairs = b.mtot * LS * LS;
     if (H == 4 && c.edge_hidden == 32)
-      hipLaunchKernelGGL((k_edge_off<sizeof(AT) == 2, 4, 32>), dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0,
-                         st, ew, (const float*)N.desc, npairs, (int)LS, t.boff);
+      hipLaunchKernelGGL((k_edge_off<sizeof(AT) == 2, 4, 32>), dim3((unsigned)((npairs + 255) / 256), (unsigned)nl),
+                         dim3(256), 0, st, ws, (const float*)N.desc, npairs, (int)LS, t.boff, boff_stride);
     else
-      hipLaunchKernelGGL(k_edge_off<sizeof(AT) == 2>, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, ew,
-                         (const float*)N.desc, npairs, (int)LS, t.boff);
+      hipLaunchKernelGGL(k_edge_off<sizeof(AT) == 2>, dim3((unsigned)((npairs + 255) / 256), (unsigned)nl),
+                         dim3(256), 0, st, ws, (const float*)N.desc, npairs, (int)LS, t.boff, boff_stride);
   }
 }
 
@@ -3117,7 +3144,7 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
     if (sidx == 0 && sizeof(AT) == 2 && b.attn_fused && !b.attn_valu && !ls && L == 64 && H == 4 && d == 128 &&
         P.qkv[0][l].N == 384 && P.qkv[0][l].K == 128 && P.o[0][l].N == 128 && P.o[0][l].K == 128) {
       // the whole sublayer in one launch (LN1, QKV, attention, output projection)
-      if (!N.pre) edge_tables<AT>(b, W, l, sidx, tabs, st);
+      if (!N.pre) edge_tables<AT>(b, W, l, 1, sidx, st);
       else if (N.pre_side) HP_HIP(hipStreamWaitEvent(st, b.side_ev[l], 0));
       const uint16_t* wa = (const uint16_t*)N.warena;
       hipLaunchKernelGGL(k_attn_sublayer64, dim3((unsigned)b.ktot), dim3(256), 0, st, X, wp(p + "ln1.g"),
@@ -3128,7 +3155,7 @@ static hp_status layer_fwd(Batch& b, const float* W, const float* sys, int l, La
     hipLaunchKernelGGL(k_layernorm128<AT>, dim3((unsigned)((M + 15) / 16)), dim3(256), 0, st, (const float*)X,
                        wp(p + "ln1.g"), wp(p + "ln1.b"), (AT*)a, (int)M);
     gemm<AT>(b, a, d, N, P.qkv[sidx][l], wp(p + "qkv.b"), nullptr, 0, nullptr, 0, q, 3 * d, M, 0);
-    if (!N.pre) edge_tables<AT>(b, W, l, sidx, tabs, st);
+    if (!N.pre) edge_tables<AT>(b, W, l, 1, sidx, st);
     else if (N.pre_side && (sidx == 0 || N.par)) HP_HIP(hipStreamWaitEvent(st, b.side_ev[l], 0));
     if (sidx == 0) {
       if (sizeof(AT) == 2 && !b.attn_valu) {
@@ -3276,11 +3303,14 @@ static hp_status tables_ahead(Batch& b, const float* W, const float* sys) {
     }
   }
   stencil_desc(b, sys, st);
-  for (int l = 0; l < b.cfg.layers; ++l) {
-    const EdgeTabs t = edge_tabs(b, N, l);
-    edge_tables<AT>(b, W, l, 0, t, st);
-    if (use_off) edge_tables<AT>(b, W, l, 1, t, st);
-    if (N.pre_side) HP_HIP(hipEventRecord(b.side_ev[l], st));
+  // every layer's tables in one launch per kernel (fewer, fuller launches on
+  // the side stream, whose chain runs ahead of the encoder)
+  for (int l0 = 0; l0 < b.cfg.layers; l0 += EDGE_LAYERS) {
+    const int nl = std::min(EDGE_LAYERS, b.cfg.layers - l0);
+    edge_tables<AT>(b, W, l0, nl, 0, st);
+    if (use_off) edge_tables<AT>(b, W, l0, nl, 1, st);
+    if (N.pre_side)
+      for (int l = l0; l < l0 + nl; ++l) HP_HIP(hipEventRecord(b.side_ev[l], st));
   }
   if (N.pre_side) HP_HIP(hipEventRecord(b.side_done, st));
   HP_HIP(hipGetLastError());
