@@ -968,19 +968,17 @@ __device__ inline void edge_slot_consts(const float* sw, int E, int H, float* ou
 // Within-leaf bias table with A_ij = 0: T0[h][i][j] = MLP_e((pos j - pos i)/4, 0).
 // Every leaf has the same shape, so one table per layer serves all leaves.
 // The block after the table's blocks writes the stencil-slot constants.
+// Block bx of nbx (the last one writes the slot constants) of one layer.
 template <bool FAST>
-__global__ __launch_bounds__(256) void k_edge_table(EdgeWs ws, int L, unsigned xm, unsigned ym, unsigned zm, float* T0,
-                                                    float* slots, int64_t t0_stride, int slot_stride) {
+__device__ inline void edge_table_block(const EdgeW& w, int bx, int nbx, int L, unsigned xm, unsigned ym, unsigned zm,
+                                        float* T0, float* slots) {
   __shared__ float sw[EDGE_MAX_FLOATS];
-  const EdgeW w = ws.w[blockIdx.y];
-  T0 += blockIdx.y * t0_stride;
-  slots += blockIdx.y * slot_stride;
   edge_stage(w, sw);
-  if (blockIdx.x == gridDim.x - 1) {
+  if (bx == nbx - 1) {
     edge_slot_consts<FAST>(sw, w.E, w.H, slots);
     return;
   }
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = bx * blockDim.x + threadIdx.x;
   if (p >= L * L) return;
   const int i = p / L, j = p % L;
   float e[4] = {(mcoord(j, xm) - mcoord(i, xm)) * 0.25f, (mcoord(j, ym) - mcoord(i, ym)) * 0.25f,
@@ -990,12 +988,18 @@ __global__ __launch_bounds__(256) void k_edge_table(EdgeWs ws, int L, unsigned x
   for (int h = 0; h < w.H; ++h) T0[(h * L + i) * L + j] = o[h];
 }
 
+template <bool FAST>
+__global__ __launch_bounds__(256) void k_edge_table(EdgeWs ws, int L, unsigned xm, unsigned ym, unsigned zm, float* T0,
+                                                    float* slots, int64_t t0_stride, int slot_stride) {
+  edge_table_block<FAST>(ws.w[blockIdx.y], blockIdx.x, gridDim.x, L, xm, ym, zm, T0 + blockIdx.y * t0_stride,
+                         slots + blockIdx.y * slot_stride);
+}
+
 // Stencil entries of node i inside its own leaf (self and up to 6 faces):
 // nbr[i][e] = local index of j in the leaf (255: none), ahat[i][e] =
 // A_ij / sqrt(A_ii A_jj), delta code in dir[i][e] (0 self, 1..6 = +x,-x,+y,-y,+z,-z).
-__global__ void k_leaf_stencil(const FrameDesc* fr, const int* node2f, const float* sys, int64_t ntot, int L,
-                               uint8_t* nbr, float* ahat) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void leaf_stencil_node(int64_t i, const FrameDesc* fr, const int* node2f, const float* sys,
+                                         int64_t ntot, int L, uint8_t* nbr, float* ahat) {
   if (i >= ntot) return;
   const FrameDesc F = fr[node2f[i]];
   const unsigned c = (unsigned)(i - F.n0);
@@ -1019,6 +1023,11 @@ __global__ void k_leaf_stencil(const FrameDesc* fr, const int* node2f, const flo
       ahat[i * 7 + e] = (float)(-w / sqrt(d8[i] * d8[F.n0 + cj]));
     }
   }
+}
+
+__global__ void k_leaf_stencil(const FrameDesc* fr, const int* node2f, const float* sys, int64_t ntot, int L,
+                               uint8_t* nbr, float* ahat) {
+  leaf_stencil_node((int64_t)blockIdx.x * blockDim.x + threadIdx.x, fr, node2f, sys, ntot, L, nbr, ahat);
 }
 
 // Per-layer corrections of the diagonal bias at the stencil entries:
@@ -1083,12 +1092,12 @@ struct DescChunk {
   int k0, k1; // leaf range [k0, k1) inside the strips
 };
 
-__global__ __launch_bounds__(256) void k_off_desc_part(const FrameDesc* fr, const int* tile2f, const DescChunk* ch,
-                                                       const float* sys, int64_t ntot, int L, int LS, double* part) {
+__device__ inline void off_desc_chunk(int bx, const FrameDesc* fr, const int* tile2f, const DescChunk* ch,
+                                      const float* sys, int64_t ntot, int L, int LS, double* part) {
   __shared__ double sval[DESC_CHUNK * DESC_MAX_LEAF][6];
   __shared__ __align__(8) uint8_t sgrp[DESC_CHUNK * DESC_MAX_LEAF][8];  // 6 used: one 8-byte read a node
   __shared__ int scrd[2][DESC_CHUNK][DESC_MAX_LEAF / 4][3];  // token coordinate sums: row, column strip
-  const DescChunk c = ch[blockIdx.x];
+  const DescChunk c = ch[bx];
   const FrameDesc F = fr[tile2f[c.tile]];
   const int m = c.tile - F.m0, K = F.K;
   int j = 0;
@@ -1155,12 +1164,44 @@ __global__ __launch_bounds__(256) void k_off_desc_part(const FrameDesc* fr, cons
   // chunk record: [Ahat sums, LS x LS | row-token coordinate sums, LS x 3 |
   // column-token coordinate sums, LS x 3] (a row token's sums do not depend on
   // t', nor a column token's on t)
-  double* o = part + (int64_t)blockIdx.x * (LS * LS + 6 * LS);
+  double* o = part + (int64_t)bx * (LS * LS + 6 * LS);
   o[t * LS + t2] = acc;
   if (t2 == 0)
     for (int a = 0; a < 3; ++a) o[LS * LS + t * 3 + a] = cI[a];
   if (t == 0)
     for (int a = 0; a < 3; ++a) o[LS * LS + 3 * LS + t2 * 3 + a] = cJ[a];
+}
+
+__global__ __launch_bounds__(256) void k_off_desc_part(const FrameDesc* fr, const int* tile2f, const DescChunk* ch,
+                                                       const float* sys, int64_t ntot, int L, int LS, double* part) {
+  off_desc_chunk(blockIdx.x, fr, tile2f, ch, sys, ntot, L, LS, part);
+}
+
+// The head of the inference's side chain in one launch, three independent
+// parts as block ranges: [0, nd) descriptor chunks (k_off_desc_part), the
+// next ns blocks the leaf stencils (k_leaf_stencil), then nl layers of nt
+// blocks of edge tables (k_edge_table).  One launch instead of three keeps
+// the chain that runs ahead of the encoder short.
+template <bool FAST>
+__global__ __launch_bounds__(256) void k_side_head(const FrameDesc* fr, const int* tile2f, const DescChunk* ch,
+                                                   const float* sys, int64_t ntot, int L, int LS, double* part, int nd,
+                                                   const int* node2f, uint8_t* nbr, float* ahat, int ns, EdgeWs ws,
+                                                   unsigned xm, unsigned ym, unsigned zm, float* T0, float* slots,
+                                                   int64_t t0_stride, int slot_stride, int nt) {
+  int bx = blockIdx.x;
+  if (bx < nd) {
+    off_desc_chunk(bx, fr, tile2f, ch, sys, ntot, L, LS, part);
+    return;
+  }
+  bx -= nd;
+  if (bx < ns) {
+    leaf_stencil_node((int64_t)bx * blockDim.x + threadIdx.x, fr, node2f, sys, ntot, L, nbr, ahat);
+    return;
+  }
+  bx -= ns;
+  const int l = bx / nt;
+  bx -= l * nt;
+  edge_table_block<FAST>(ws.w[l], bx, nt, L, xm, ym, zm, T0 + l * t0_stride, slots + l * slot_stride);
 }
 
 // desc of tile (block) mg from its chunks [chunk0[mg], chunk0[mg + 1]).
@@ -3010,27 +3051,35 @@ static EdgeTabs edge_tabs(const Batch& b, const NetBufs& N, int l) {
 // the off-diagonal pair biases), from the edge MLP's FP32 weights, one launch
 // per kernel with the layer as blockIdx.y.  Several layers at once need the
 // inference's per-layer buffers (N.pre), whose layers lie a fixed stride apart.
-template <typename AT>
-static void edge_tables(Batch& b, const float* W, int l0, int nl, int sidx, hipStream_t st) {
-  NetBufs& N = *nb_of(b);
-  const NetPlan& P = N.plan;
-  const hp_model_config& c = b.cfg;
-  const int64_t Nd = N.Nd, L = c.leaf, LS = c.rank, H = c.heads;
+static EdgeWs edge_ws(Batch& b, const float* W, int l0, int nl, int sidx) {
+  const NetPlan& P = nb_of(b)->plan;
   auto wp = [&](const std::string& n) { return W + woff(P, n); };
   EdgeWs ws{};
   for (int q = 0; q < nl; ++q) {
     const std::string p = std::string(sidx ? "off" : "diag") + std::to_string(l0 + q) + ".";
-    ws.w[q] = EdgeW{wp(p + "e1.w"), wp(p + "e1.b"), wp(p + "e2.w"), wp(p + "e2.b"), c.edge_hidden, (int)H};
+    ws.w[q] = EdgeW{wp(p + "e1.w"), wp(p + "e1.b"), wp(p + "e2.w"), wp(p + "e2.b"), b.cfg.edge_hidden, b.cfg.heads};
   }
+  return ws;
+}
+
+// with_table false: the within-leaf tables and slot constants were written
+// already (by k_side_head).
+template <typename AT>
+static void edge_tables(Batch& b, const float* W, int l0, int nl, int sidx, hipStream_t st, bool with_table = true) {
+  NetBufs& N = *nb_of(b);
+  const hp_model_config& c = b.cfg;
+  const int64_t Nd = N.Nd, L = c.leaf, LS = c.rank, H = c.heads;
+  const EdgeWs ws = edge_ws(b, W, l0, nl, sidx);
   const EdgeTabs t = edge_tabs(b, N, l0), t1 = nl > 1 ? edge_tabs(b, N, l0 + 1) : t;
   const int64_t t0_stride = t1.T0 - t.T0, corr_stride = t1.corr - t.corr, boff_stride = t1.boff - t.boff;
   const int slot_stride = (int)(t1.eslots - t.eslots);
   if (sidx == 0) {
     const unsigned lowmask = (unsigned)(L - 1);
     const FrameDesc& F0 = b.fr[0];
-    hipLaunchKernelGGL(k_edge_table<sizeof(AT) == 2>, dim3((unsigned)((L * L + 255) / 256 + 1), (unsigned)nl),
-                       dim3(256), 0, st, ws, (int)L, F0.xm & lowmask, F0.ym & lowmask, F0.zm & lowmask, t.T0,
-                       t.eslots, t0_stride, slot_stride);
+    if (with_table)
+      hipLaunchKernelGGL(k_edge_table<sizeof(AT) == 2>, dim3((unsigned)((L * L + 255) / 256 + 1), (unsigned)nl),
+                         dim3(256), 0, st, ws, (int)L, F0.xm & lowmask, F0.ym & lowmask, F0.zm & lowmask, t.T0,
+                         t.eslots, t0_stride, slot_stride);
     if (H == 4 && c.edge_hidden == 32)  // the paper's widths: compile-time loops
       hipLaunchKernelGGL((k_edge_corr<sizeof(AT) == 2, 4, 32>), dim3((unsigned)((Nd * 7 + 255) / 256), (unsigned)nl),
                          dim3(256), 0, st, ws, (const float*)t.eslots, (const uint8_t*)N.nbr, (const float*)N.ahat,
@@ -3301,6 +3350,32 @@ static hp_status tables_ahead(Batch& b, const float* W, const float* sys) {
       HP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       b.off_ev.push_back(e);
     }
+  }
+  if (b.cfg.layers <= EDGE_LAYERS) {
+    // descriptor chunks, leaf stencils and every layer's within-leaf table in
+    // one launch, then the descriptors, then every layer's stencil
+    // corrections and pair biases (one launch each)
+    const hp_model_config& c = b.cfg;
+    const int64_t L = c.leaf, LS = c.rank, Nd = N.Nd;
+    const int nl = c.layers, nd = use_off ? (int)N.ndesc_chunks : 0, ns = (int)((Nd + 255) / 256);
+    const int nt = (int)((L * L + 255) / 256 + 1);
+    const EdgeTabs t = edge_tabs(b, N, 0), t1 = nl > 1 ? edge_tabs(b, N, 1) : t;
+    const unsigned lowmask = (unsigned)(L - 1);
+    const FrameDesc& F0 = b.fr[0];
+    hipLaunchKernelGGL(k_side_head<sizeof(AT) == 2>, dim3((unsigned)(nd + ns + nl * nt)), dim3(256), 0, st, b.d_fr,
+                       N.tile2f, (const DescChunk*)N.desc_chunks, sys, b.ntot, (int)L, (int)LS, N.desc_part, nd,
+                       N.node2f, N.nbr, N.ahat, ns, edge_ws(b, W, 0, nl, 0), F0.xm & lowmask, F0.ym & lowmask,
+                       F0.zm & lowmask, t.T0, t.eslots, (int64_t)(t1.T0 - t.T0), (int)(t1.eslots - t.eslots), nt);
+    if (use_off)
+      hipLaunchKernelGGL(k_off_desc_final, dim3((unsigned)b.mtot), dim3(256), 0, st, b.d_fr, N.tile2f,
+                         (const int*)N.desc_chunk0, (const double*)N.desc_part, (int)L, (int)LS, N.desc);
+    edge_tables<AT>(b, W, 0, nl, 0, st, false);
+    if (use_off) edge_tables<AT>(b, W, 0, nl, 1, st);
+    if (N.pre_side)
+      for (int l = 0; l < nl; ++l) HP_HIP(hipEventRecord(b.side_ev[l], st));
+    if (N.pre_side) HP_HIP(hipEventRecord(b.side_done, st));
+    HP_HIP(hipGetLastError());
+    return HP_OK;
   }
   stencil_desc(b, sys, st);
   // every layer's tables in one launch per kernel (fewer, fuller launches on
